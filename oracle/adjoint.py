@@ -1,0 +1,356 @@
+"""Reverse mode through the substep and through a checkpointed rollout.
+
+Section 3.3: gradients flow through the whole trajectory; the forward pass
+keeps one state per segment, and the backward pass re-runs each segment
+forward from its checkpoint before back-propagating through it.  The paper
+gets the per-step reverse pass from Taichi's autodiff; here every substep has
+a hand-written vector-Jacobian product, differentiating the branch that the
+forward pass took (min(exp, 1) at d >= 0, a clamped closest-point parameter
+and a sticking friction branch have zero derivative).
+
+Parameters with gradients: the per-action grasp velocities u, the bending
+stiffness b and the yield curvature sigma_y of each rod, and the initial
+positions and velocities.
+"""
+import numpy as np
+
+from .geometry import dot, cross, curvature_binormal, edges
+from .forward import substep, step, PLANE, SPHERE, CAPSULE
+from .model import State
+from . import selfcontact
+
+
+# --------------------------------------------------------------------------
+# building blocks
+# --------------------------------------------------------------------------
+
+def edges_vjp(ell, t, t_b, ell_b):
+    """Adjoint of (x) -> (|e^j|, t^j): e_b = (t_b - t (t.t_b))/|e| + ell_b t,
+    then x_{j+1} += e_b, x_j -= e_b."""
+    eb = (t_b - t * dot(t, t_b)[..., None]) / ell[..., None] + ell_b[..., None] * t
+    xb = np.zeros(t.shape[:-2] + (t.shape[-2] + 1, 3))
+    xb[..., 1:, :] += eb
+    xb[..., :-1, :] -= eb
+    return xb
+
+
+def transport_vjp(v, ta, tb, y_b):
+    """Adjoint of y = c v + b x v + b (b.v)/(1+c), b = ta x tb, c = ta.tb."""
+    b = cross(ta, tb)
+    c = dot(ta, tb)
+    bv, by = dot(b, v), dot(b, y_b)
+    opc = 1.0 + c
+    v_b = c[..., None] * y_b - cross(b, y_b) + b * (by / opc)[..., None]
+    c_b = dot(v, y_b) - bv * by / opc ** 2
+    b_b = cross(v, y_b) + (bv[..., None] * y_b + by[..., None] * v) / opc[..., None]
+    ta_b = cross(tb, b_b) + c_b[..., None] * tb
+    tb_b = cross(b_b, ta) + c_b[..., None] * ta
+    return v_b, ta_b, tb_b
+
+
+def curvature_vjp(t, d1, kappa_b):
+    """Adjoint of kappa = (kb.a1, kb.a2) w.r.t. the tangents t and the
+    directors d1 (a1 from d2 = t x d1, a2 from d1)."""
+    t0, t1 = t[..., :-1, :], t[..., 1:, :]
+    kbv, chi = curvature_binormal(t)
+    d2 = cross(t, d1)
+    a1 = 0.5 * (d2[..., :-1, :] + d2[..., 1:, :])
+    a2 = 0.5 * (d1[..., :-1, :] + d1[..., 1:, :])
+    k1b, k2b = kappa_b[..., 1:-1, 0], kappa_b[..., 1:-1, 1]
+    kbv_b = k1b[..., None] * a1 + k2b[..., None] * a2
+    a1_b = k1b[..., None] * kbv
+    a2_b = k2b[..., None] * kbv
+    t_b, d1_b, d2_b = np.zeros_like(t), np.zeros_like(d1), np.zeros_like(d1)
+    _kb_vjp(t0, t1, kbv, chi, kbv_b, 0.0, t_b)
+    d2_b[..., :-1, :] += 0.5 * a1_b
+    d2_b[..., 1:, :] += 0.5 * a1_b
+    d1_b[..., :-1, :] += 0.5 * a2_b
+    d1_b[..., 1:, :] += 0.5 * a2_b
+    t_b += cross(d1, d2_b)
+    d1_b += cross(d2_b, t)
+    return t_b, d1_b
+
+
+def _kb_vjp(t0, t1, kbv, chi, kbv_b, chi_b, t_b):
+    """Adjoint of kb = 2 (t0 x t1)/chi, chi = 1 + t0.t1 (accumulates into
+    t_b [.., E, 3]); chi_b is an extra adjoint already collected for chi."""
+    chi_b = chi_b - dot(kbv, kbv_b) / chi
+    n_b = 2.0 * kbv_b / chi[..., None]
+    t_b[..., :-1, :] += cross(t1, n_b) + chi_b[..., None] * t1
+    t_b[..., 1:, :] += cross(n_b, t0) + chi_b[..., None] * t0
+
+
+def bending_force_vjp(rods, t, ell, d1, d2, kb, F_b):
+    """Adjoint of bending_force: returns (t_b, ell_b, d1_b, d2_b, kb_b, b_b)."""
+    t0, t1 = t[..., :-1, :], t[..., 1:, :]
+    l0, l1 = ell[..., :-1], ell[..., 1:]
+    kbv, chi = curvature_binormal(t)
+    a1 = 0.5 * (d2[..., :-1, :] + d2[..., 1:, :])
+    a2 = 0.5 * (d1[..., :-1, :] + d1[..., 1:, :])
+    k1, k2 = dot(kbv, a1), dot(kbv, a2)
+    coef = rods.b[:, None] / rods.lbar
+    dk1, dk2 = k1 - kb[..., 1:-1, 0], k2 - kb[..., 1:-1, 1]
+    c1, c2 = coef * dk1, coef * dk2
+    s = c1 * k1 + c2 * k2
+    A = (2.0 / chi)[..., None] * (c1[..., None] * a1 + c2[..., None] * a2)
+    tt = (t0 + t1) / chi[..., None]
+    g0 = (-s[..., None] * tt + cross(t1, A)) / l0[..., None]
+    g1 = (-s[..., None] * tt - cross(t0, A)) / l1[..., None]
+
+    g0_b = F_b[..., :-2, :] - F_b[..., 1:-1, :]
+    g1_b = F_b[..., 1:-1, :] - F_b[..., 2:, :]
+    G0_b = g0_b / l0[..., None]
+    G1_b = g1_b / l1[..., None]
+    l0_b = -dot(g0, g0_b) / l0
+    l1_b = -dot(g1, g1_b) / l1
+    Gs_b = G0_b + G1_b
+    s_b = -dot(tt, Gs_b)
+    tt_b = -s[..., None] * Gs_b
+    t0_b = -cross(A, G1_b) + tt_b / chi[..., None]
+    t1_b = cross(A, G0_b) + tt_b / chi[..., None]
+    A_b = cross(G0_b, t1) - cross(G1_b, t0)
+    chi_b = -dot(tt, tt_b) / chi
+    c1_b = (2.0 / chi) * dot(a1, A_b) + k1 * s_b
+    c2_b = (2.0 / chi) * dot(a2, A_b) + k2 * s_b
+    a1_b = ((2.0 / chi) * c1)[..., None] * A_b
+    a2_b = ((2.0 / chi) * c2)[..., None] * A_b
+    chi_b = chi_b - dot(A, A_b) / chi
+    k1_b = c1 * s_b + coef * c1_b
+    k2_b = c2 * s_b + coef * c2_b
+    kb_b = np.zeros_like(kb)
+    kb_b[..., 1:-1, 0] = -coef * c1_b
+    kb_b[..., 1:-1, 1] = -coef * c2_b
+    b_b = np.sum((c1_b * dk1 + c2_b * dk2) / rods.lbar, axis=-1)
+    kbv_b = k1_b[..., None] * a1 + k2_b[..., None] * a2
+    a1_b = a1_b + k1_b[..., None] * kbv
+    a2_b = a2_b + k2_b[..., None] * kbv
+
+    t_b = np.zeros_like(t)
+    t_b[..., :-1, :] += t0_b
+    t_b[..., 1:, :] += t1_b
+    _kb_vjp(t0, t1, kbv, chi, kbv_b, chi_b, t_b)
+    ell_b = np.zeros_like(ell)
+    ell_b[..., :-1] += l0_b
+    ell_b[..., 1:] += l1_b
+    d1_b, d2_b = np.zeros_like(d1), np.zeros_like(d2)
+    d2_b[..., :-1, :] += 0.5 * a1_b
+    d2_b[..., 1:, :] += 0.5 * a1_b
+    d1_b[..., :-1, :] += 0.5 * a2_b
+    d1_b[..., 1:, :] += 0.5 * a2_b
+    return t_b, ell_b, d1_b, d2_b, kb_b, b_b
+
+
+def stretch_force_vjp(rods, t, ell, F_b):
+    """Adjoint of stretch_force: q = k_s eps t on x_j, -q on x_{j+1}."""
+    fs = rods.ks * (ell / rods.rest - 1.0)
+    q_b = F_b[..., :-1, :] - F_b[..., 1:, :]
+    fs_b = dot(q_b, t)
+    return fs[..., None] * q_b, rods.ks * fs_b / rods.rest
+
+
+def project_edges_vjp(rods, p_b, parity, D):
+    """Adjoint of one inextensibility pass.  With q = (|D| - r) t = D - r D/|D|
+    the pass is p_j += (w_j/W) q, p_{j+1} -= (w_{j+1}/W) q, and
+    dq/dD = I - (r/|D|)(I - t t^T)."""
+    j = np.arange(parity, rods.E, 2)
+    ell = np.sqrt(dot(D, D))
+    t = D / ell[..., None]
+    wj, wk = rods.w[:, j], rods.w[:, j + 1]
+    W = wj + wk
+    act = W > 0.0
+    Ws = np.where(act, W, 1.0)
+    aj, ak = p_b[:, j], p_b[:, j + 1]
+    q_b = (wj[..., None] * aj - wk[..., None] * ak) / Ws[..., None]
+    r = rods.rest[:, j]
+    D_b = q_b - (r / ell)[..., None] * (q_b - t * dot(t, q_b)[..., None])
+    D_b = np.where(act[..., None], D_b, 0.0)
+    p_b = p_b.copy()
+    p_b[:, j] = aj - D_b
+    p_b[:, j + 1] = ak + D_b
+    return p_b
+
+
+def sdf_vjp(c, sdf_b, n_b):
+    """Adjoint of (sdf, n)(x) for one primitive, one rod's vertices."""
+    kind = c["prim"][0]
+    n = c["n"]
+    if kind == PLANE:
+        return sdf_b[:, None] * n
+    nq = c["sdf"] + c["prim"][3]
+    perp = n_b - n * dot(n, n_b)[:, None]
+    xb = sdf_b[:, None] * n + perp / nq[:, None]
+    if kind == CAPSULE:
+        a, b = c["prim"][1], c["prim"][2]
+        u = (b - a) / np.sqrt(dot(b - a, b - a))
+        corr = (perp / nq[:, None]) @ u
+        xb = xb - np.where(c["interior"], corr, 0.0)[:, None] * u[None, :]
+    return xb
+
+
+def rigid_contact_vjp(rods, sim, crec, v_b, x_b):
+    """Adjoint of rigid_contact, primitives in reverse order."""
+    v_b = v_b.copy()
+    for c in reversed(crec["contact"]):
+        bi = c["bi"]
+        act = c["act"]
+        e, mu = c["e"], c["mu"]
+        vo_b = v_b[bi]
+        f, vin, n = c["f"], c["vin"], c["n"]
+        vn, vt, vtn, s, vres = c["vn"], c["vt"], c["vtn"], c["s"], c["vres"]
+        vi_b = (1.0 - f)[:, None] * vo_b
+        vres_b = f[:, None] * vo_b
+        f_b = dot(vres - vin, vo_b)
+        vn_b = -e * dot(n, vres_b)
+        n_b = (-e * vn)[:, None] * vres_b
+        s_b = dot(vt, vres_b)
+        vt_b = s[:, None] * vres_b
+        slide = c["slide"]
+        dvn_b = np.where(slide, -mu * s_b / vtn, 0.0)
+        vtn_b = np.where(slide, mu * c["dvn"] * s_b / vtn ** 2, 0.0)
+        vn_b = vn_b - (1.0 + e) * dvn_b
+        vt_b = vt_b + (vtn_b / vtn)[:, None] * vt
+        vi_b = vi_b + vt_b
+        vn_b = vn_b - dot(n, vt_b)
+        n_b = n_b - vn[:, None] * vt_b
+        vi_b = vi_b + vn_b[:, None] * n
+        n_b = n_b + vn_b[:, None] * vin
+        d_b = np.where(c["d"] < 0.0, f_b * f / sim.eps_s, 0.0)
+        xb = sdf_vjp(c, -d_b, n_b)
+        v_b[bi] = np.where(act[:, None], vi_b, vo_b)
+        x_b[bi] += np.where(act[:, None], xb, 0.0)
+    return v_b
+
+
+# --------------------------------------------------------------------------
+# the substep adjoint
+# --------------------------------------------------------------------------
+
+def substep_vjp(rods, sim, rec, bar):
+    """Given adjoints `bar` = (x_b, v_b, kb_b, d1_b) of the substep's output
+    state and the forward record `rec`, return the adjoints of its input state
+    and (u_b [B,G,3], b_b [B], sigma_b [B])."""
+    xb1, vb3, kbb1, d1nb = bar
+    h = sim.h
+    B = rods.B
+    t, ell, t1, ell1 = rec["t"], rec["ell"], rec["t1"], rec["ell1"]
+    d1, d1n, d2 = rec["d1"], rec["d1n"], rec["d2"]
+    kb_b = np.array(kbb1, dtype=np.float64)
+    d1n_b = np.array(d1nb, dtype=np.float64)
+    t1_b = np.zeros_like(t1)
+    sig_b = np.zeros(B)
+    # S11 plasticity: kb1 = kb + phi kel, phi = r_c (1 - thr/|kel|) on yield
+    if rods.plastic:
+        pr = rec["prec"]
+        kel, nrm, thr, yld, phi = pr["kel"], pr["nrm"], pr["thr"], pr["yld"], pr["phi"]
+        kbo_b = kbb1[..., 1:-1, :]
+        kel_b = phi[..., None] * kbo_b
+        phi_b = np.where(yld, dot(kel, kbo_b), 0.0)
+        rc = rods.r_c[:, None]
+        nrm_b = rc * thr / nrm ** 2 * phi_b
+        thr_b = -rc / nrm * phi_b
+        sig_b += np.sum(rods.lbar * thr_b, axis=-1)
+        kel_b = kel_b + (nrm_b / nrm)[..., None] * kel
+        kel_b = np.where(yld[..., None], kel_b, 0.0)
+        kb_b[..., 1:-1, :] -= kel_b
+        kappa_b = np.zeros_like(kbb1)
+        kappa_b[..., 1:-1, :] = kel_b
+        tb, d1b = curvature_vjp(t1, d1n, kappa_b)
+        t1_b += tb
+        d1n_b += d1b
+    # S10 transport
+    d1_b, t_b, tb = transport_vjp(d1, t, t1, d1n_b)
+    t1_b += tb
+    x1_b = xb1 + edges_vjp(ell1, t1, t1_b, np.zeros_like(ell1))
+    # S9 self-friction
+    if rec["pairs"] is not None:
+        vb3, xf_b = selfcontact.friction_vjp(rods, sim, rec, vb3)
+        x1_b = x1_b + xf_b
+    # S8 v3 = v2 + (p - p0)/h, x1 = p
+    p_b = x1_b + vb3 / h
+    v2_b = vb3.copy()
+    p0_b = -vb3 / h
+    # S7 projections, in reverse
+    for item in reversed(rec["ptape"]):
+        if item[0] == "edge":
+            p_b = project_edges_vjp(rods, p_b, item[1], item[2])
+        else:
+            p_b = selfcontact.project_pairs_vjp(rods, p_b, item)
+    p0_b = p0_b + p_b
+    # S5 p0 = x + h v2
+    x_b = p0_b.copy()
+    v2_b = v2_b + h * p0_b
+    # S4 rigid contact
+    if rec["crec"] is not None and rec["crec"].get("contact"):
+        v1_b = rigid_contact_vjp(rods, sim, rec["crec"], v2_b, x_b)
+    else:
+        v1_b = v2_b
+    # S3 velocity update / kinematic vertices
+    free = (rods.w > 0.0)[..., None]
+    v_b = np.where(free, v1_b, 0.0)
+    F_b = np.where(free, h * rods.w[..., None] * v1_b, 0.0)
+    u_b = np.zeros((B, rods.gidx.shape[1], 3))
+    for bi in range(B):
+        for g, vi in enumerate(rods.gidx[bi]):
+            if vi >= 0:
+                u_b[bi, g] += v1_b[bi, vi]
+    # S2 forces
+    tb, ellb, d1b, d2b, kbb, b_b = bending_force_vjp(rods, t, ell, d1, d2, rec["kb"], F_b)
+    t_b = t_b + tb
+    d1_b = d1_b + d1b
+    kb_b = kb_b + kbb
+    if not rods.inextensible:
+        tb, eb = stretch_force_vjp(rods, t, ell, F_b)
+        t_b = t_b + tb
+        ellb = ellb + eb
+    t_b = t_b + cross(d1, d2b)
+    d1_b = d1_b + cross(d2b, t)
+    x_b = x_b + edges_vjp(ell, t, t_b, ellb)
+    return State(x_b, v_b, kb_b, d1_b), u_b, b_b, sig_b
+
+
+# --------------------------------------------------------------------------
+# checkpointed rollout backward and the loss
+# --------------------------------------------------------------------------
+
+def backward(rods, sim, ckpts, U, n_steps, ckpt_every, xT_b, vT_b=None):
+    """Reverse pass through a rollout that kept a state every ckpt_every
+    steps.  Each segment is re-run forward from its checkpoint (keeping the
+    substep-start states), then its substeps are reversed.  Returns
+    (x0_b, v0_b, u_b [A,B,G,3], b_b [B], sigma_b [B])."""
+    B, N = rods.B, rods.N
+    bar = State(np.array(xT_b, np.float64),
+                np.zeros((B, N, 3)) if vT_b is None else np.array(vT_b, np.float64),
+                np.zeros((B, N, 2)), np.zeros((B, N - 1, 3)))
+    u_b = np.zeros_like(U, dtype=np.float64)
+    b_b = np.zeros(B)
+    sig_b = np.zeros(B)
+    spa = sim.steps_per_action
+    n_seg = len(ckpts)
+    for seg in reversed(range(n_seg)):
+        s0 = seg * ckpt_every
+        s1 = min(n_steps, s0 + ckpt_every)
+        starts = []
+        st = ckpts[seg]
+        for s in range(s0, s1):
+            a = s // spa
+            for _ in range(sim.n_sub):
+                starts.append((a, st))
+                st = substep(rods, sim, st, U[a])
+        for a, st in reversed(starts):
+            rec = {}
+            substep(rods, sim, st, U[a], rec)
+            bar, ub, bb, sb = substep_vjp(rods, sim, rec, bar)
+            u_b[a] += ub
+            b_b += bb
+            sig_b += sb
+    return bar.x, bar.v, u_b, b_b, sig_b
+
+
+def loss_mse(x, target, n_rods_total, sizes=None):
+    """L = (1/R) sum_r (1/N_r) sum_i |x_i - x*_i|^2 over the rods of the
+    batch (R = number of rods of the whole workload); returns (L_part,
+    dL/dx) for the rods given as [B,N,3]."""
+    B, N, _ = x.shape
+    diff = x - target
+    L = np.sum(diff * diff) / (n_rods_total * N)
+    return L, 2.0 * diff / (n_rods_total * N)

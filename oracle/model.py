@@ -1,0 +1,156 @@
+"""Static description of a batch of equally sized rods, and the state tuple.
+
+Discrete elastic rod data (Appendix A.1, "DLO Representation"): N_v vertices
+with mass m_i and radius r_i, N_e = N_v - 1 edges with rest lengths |e_bar^j|.
+Inverse masses w_i = 1/m_i are inputs; a vertex with w_i = 0 is kinematic
+(pinned, or held by a grasp whose velocity is prescribed).
+"""
+from dataclasses import dataclass
+from typing import List, NamedTuple
+
+import numpy as np
+
+FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF = 1, 2, 4
+
+
+class State(NamedTuple):
+    x: np.ndarray        # [B,N,3] vertex positions
+    v: np.ndarray        # [B,N,3] vertex velocities
+    kb: np.ndarray       # [B,N,2] rest curvature kappa_bar (ends unused, zero)
+    d1: np.ndarray       # [B,E,3] first reference director per edge (d2 = t x d1)
+
+
+@dataclass
+class Sim:
+    dt: float
+    n_sub: int
+    n_iters: int
+    gravity: np.ndarray
+    eps_s: float
+    f_thresh: float
+    self_margin: float
+    k_exclude: int
+    steps_per_action: int
+
+    @property
+    def h(self):
+        return self.dt / self.n_sub
+
+
+@dataclass
+class Rods:
+    """B rods with N vertices each."""
+    N: int
+    rest: np.ndarray     # [B,E]   rest edge lengths |e_bar^j|
+    w: np.ndarray        # [B,N]   inverse masses, 0 on pinned and grasped vertices
+    radius: np.ndarray   # [B,N]
+    gidx: np.ndarray     # [B,G]   grasped vertex (local index) per grasp slot, -1 none
+    K: np.ndarray        # [B]     stretching modulus (Pa)
+    b: np.ndarray        # [B]     bending stiffness, B_i = b I_2 (N m^2)
+    sigma_y: np.ndarray  # [B]     yield curvature (1/m)
+    r_c: np.ndarray      # [B]     creep rate
+    mu: np.ndarray       # [B]     Coulomb friction coefficient
+    restitution: np.ndarray  # [B]
+    flags: int
+    prims: List[list]    # per rod: list of (type, a[3], b[3], radius)
+
+    @property
+    def B(self):
+        return self.rest.shape[0]
+
+    @property
+    def E(self):
+        return self.N - 1
+
+    @property
+    def inextensible(self):
+        return bool(self.flags & FLAG_INEXT)
+
+    @property
+    def plastic(self):
+        return bool(self.flags & FLAG_PLASTIC)
+
+    @property
+    def self_contact(self):
+        return bool(self.flags & FLAG_SELF)
+
+    @property
+    def ks(self):
+        """Stretching stiffness k_s^j = K A^j with A^j = pi rbar_j^2 and rbar_j
+        the mean radius of the edge's two vertices (App. A.1, Stretching)."""
+        rbar = 0.5 * (self.radius[:, :-1] + self.radius[:, 1:])
+        return self.K[:, None] * np.pi * rbar ** 2
+
+    @property
+    def lbar(self):
+        """Voronoi length l_bar_i = (|e_bar^{i-1}| + |e_bar^i|)/2 of the
+        interior vertices i = 1..N-2 (App. A.1, Bending), shape [B,N-2]."""
+        return 0.5 * (self.rest[:, :-1] + self.rest[:, 1:])
+
+    @property
+    def grasp_slot(self):
+        """[B,N] grasp slot of each vertex, -1 if not grasped."""
+        s = np.full((self.B, self.N), -1, np.int64)
+        for bi in range(self.B):
+            for g, vi in enumerate(self.gidx[bi]):
+                if vi >= 0:
+                    s[bi, vi] = g
+        return s
+
+
+def rods_from_workload(wl, rods):
+    """Oracle view of workload rods `rods` (all must have the same size)."""
+    rods = [int(r) for r in rods]
+    sizes = {wl.rod_range(r)[1] - wl.rod_range(r)[0] for r in rods}
+    assert len(sizes) == 1, "oracle batches need equal rod sizes"
+    N = sizes.pop()
+    sl = [slice(*wl.rod_range(r)) for r in rods]
+    rest = np.stack([wl.rest_len[s][:-1] for s in sl])
+    w = np.stack([wl.inv_mass[s] for s in sl]).copy()
+    gidx = wl.grasp_idx[rods].astype(np.int64)
+    for bi in range(len(rods)):
+        for vi in gidx[bi]:
+            if vi >= 0:
+                w[bi, vi] = 0.0
+    p = wl.rod_params[rods]
+    flags = {int(f) for f in p[:, 0]}
+    assert len(flags) == 1, "oracle batches need equal flags"
+    prims = []
+    for r in rods:
+        lst = []
+        for k in range(wl.prim_offsets[r], wl.prim_offsets[r + 1]):
+            lst.append((int(wl.prim_type[k]), wl.prim_a[k].copy(), wl.prim_b[k].copy(),
+                        float(wl.prim_r[k])))
+        prims.append(lst)
+    return Rods(N=N, rest=rest, w=w, radius=np.stack([wl.radius[s] for s in sl]),
+                gidx=gidx, K=p[:, 1].copy(), b=p[:, 2].copy(), sigma_y=p[:, 3].copy(),
+                r_c=p[:, 4].copy(), mu=p[:, 5].copy(), restitution=p[:, 6].copy(),
+                flags=flags.pop(), prims=prims)
+
+
+def sim_from_workload(wl):
+    s = wl.sim
+    return Sim(dt=s.dt, n_sub=s.n_sub, n_iters=s.n_iters,
+               gravity=np.array(s.gravity, np.float64), eps_s=s.eps_s,
+               f_thresh=s.f_thresh, self_margin=s.self_margin, k_exclude=s.k_exclude,
+               steps_per_action=s.steps_per_action)
+
+
+def state_from_workload(wl, rods, kb=None, d1=None):
+    """Initial state of the listed rods; frames by the initial-frame rule and
+    zero rest curvature unless given."""
+    from .geometry import init_frames
+    rods = [int(r) for r in rods]
+    sl = [slice(*wl.rod_range(r)) for r in rods]
+    x = np.stack([wl.x0[s] for s in sl])
+    v = np.stack([wl.v0[s] for s in sl])
+    if d1 is None:
+        d1 = init_frames(x)
+    if kb is None:
+        kb = np.zeros(x.shape[:2] + (2,))
+    return State(x, v, kb, d1)
+
+
+def actions_for(wl, rods):
+    """[A,B,G,3] grasp velocities of the listed rods."""
+    return wl.actions[:, [int(r) for r in rods]]
