@@ -1,0 +1,193 @@
+/*
+ * rods.h - C ABI of the batched discrete-rod step and its adjoint (MI355X).
+ *
+ * The operations follow the discrete elastic rod simulator of DLO-Lab
+ * (arXiv 2606.04206): Section 3.1 (rod state, forces from the energy
+ * derivatives, symplectic Euler, bending plasticity), Section 3.2 "Rigid
+ * Body" (soft SDF contact), Section 3.3 (gradients through a checkpointed
+ * rollout) and Appendix A.1 (stretching and bending energies,
+ * inextensibility projection, plastic creep update, self-collision and
+ * friction).
+ *
+ * Conventions
+ *  - Rods are stored back to back (CSR): rod r owns vertices
+ *    vert_offsets[r] .. vert_offsets[r+1]-1.  A rod has N_r >= 2 vertices
+ *    and N_r - 1 edges.  Per-edge arrays use the same rows as vertices: edge
+ *    j of rod r is row vert_offsets[r] + j, and the row of the rod's last
+ *    vertex is padding (ignored on input, written as zero on output).
+ *  - "real" is float when the handle precision is 4 and double when it is 8.
+ *    Every device array passed to a call is in that precision.
+ *  - Host pointers are marked (host); all other pointers are device pointers
+ *    on the handle's device, contiguous, owned by the caller.  The library
+ *    never keeps a caller pointer beyond the call.
+ *  - Calls are asynchronous on the given stream unless stated otherwise.  A
+ *    handle is bound to one device, is not thread safe, and must be used
+ *    from one stream at a time.
+ *  - Return value: 0 on success, a negative ROD_E* code otherwise.  No
+ *    exception crosses the ABI.  Faults inside kernels and non-finite rod
+ *    states surface through rods_status.
+ */
+#ifndef RODS_H
+#define RODS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* rods_stream_t;   /* a hipStream_t (0 = null stream) */
+typedef struct RodsHandle RodsHandle;
+
+enum {
+  ROD_OK = 0,
+  ROD_EINVAL = -1,   /* bad argument: sizes, offsets, flags, null pointer */
+  ROD_ENOMEM = -2,   /* device allocation failed in rods_create */
+  ROD_EHIP = -3,     /* a HIP runtime call failed */
+  ROD_ESTATE = -4,   /* call out of order (backward without a recorded rollout,
+                        n_steps beyond max_steps, ...) */
+  ROD_EDTYPE = -5    /* unsupported precision */
+};
+
+/* rod_params row layout, one row of ROD_NPARAM doubles per rod */
+enum {
+  ROD_P_FLAGS = 0,   /* bit0 inextensible (projection replaces stretching energy),
+                        bit1 bending plasticity, bit2 self-contact */
+  ROD_P_K = 1,       /* stretching modulus K (Pa); k_s = K A, A = pi r^2 (App. A.1) */
+  ROD_P_B = 2,       /* bending stiffness b (N m^2): B_i = b I_2 (App. A.1) */
+  ROD_P_SIGMA = 3,   /* yield curvature sigma_y (1/m) (App. A.1, Bending Plasticity) */
+  ROD_P_RC = 4,      /* creep rate r_c */
+  ROD_P_MU = 5,      /* Coulomb friction coefficient (rigid and self contact) */
+  ROD_P_REST = 6,    /* restitution coefficient (rigid contact) */
+  ROD_NPARAM = 7
+};
+#define ROD_FLAG_INEXT 1
+#define ROD_FLAG_PLASTIC 2
+#define ROD_FLAG_SELF 4
+
+enum { ROD_PRIM_PLANE = 0, ROD_PRIM_SPHERE = 1, ROD_PRIM_CAPSULE = 2 };
+
+/* A static rigid primitive seen as a signed distance field (Section 3.2).
+ * plane: a = point on the plane, b = unit normal.  sphere: a = centre,
+ * radius.  capsule: segment a-b, radius. */
+typedef struct {
+  int32_t type;
+  double a[3], b[3], radius;
+} RodsPrim;
+
+typedef struct {
+  int32_t n_rods;             /* R >= 1 */
+  int32_t n_grasp;            /* G >= 0: grasp slots per rod */
+  int32_t precision;          /* 4 (float) or 8 (double) */
+  const int32_t* vert_offsets;/* (host) [R+1], increasing, N_r >= 2 */
+  const int32_t* grasp_idx;   /* (host) [R][G] local vertex index per slot, or -1;
+                                 may be NULL when G == 0 */
+  const double* rod_params;   /* (host) [R][ROD_NPARAM] */
+  const double* radius;       /* (host) [V] vertex radius r_i (m) */
+  const double* inv_mass;     /* (host) [V] w_i = 1/m_i; 0 pins the vertex */
+  const double* rest_len;     /* (host) [V] rest length of edge j in row j */
+  const RodsPrim* prims;      /* (host) [P] primitives; may be NULL when P == 0 */
+  const int32_t* prim_offsets;/* (host) [R+1] rod r's scene = prims[po[r]..po[r+1]);
+                                 may be NULL when there are no primitives */
+  double dt;                  /* step (frame) time (s) */
+  double gravity[3];          /* (m/s^2) */
+  double eps_s;               /* contact softness epsilon_s (m) */
+  double f_thresh;            /* contact influence threshold (0.1 in the paper) */
+  double self_margin;         /* self-contact candidate margin delta_c (m) */
+  int32_t n_sub;              /* substeps per step, h = dt / n_sub */
+  int32_t n_iters;            /* constraint iterations N_C per substep (1..32) */
+  int32_t k_exclude;          /* self-contact: edges i, j are candidates only if |i-j| > k_exclude */
+  int32_t steps_per_action;   /* steps that share one grasp velocity in rods_rollout */
+  int32_t ckpt_every;         /* K: checkpoint interval of recorded rollouts (steps) */
+  int32_t max_steps;          /* longest recorded rollout; sizes the checkpoints */
+} RodsDesc;
+
+/* Validates the description, copies the static data to the device and
+ * allocates every buffer the handle will ever use (state, checkpoints,
+ * backward tape, work lists): no call below allocates device memory.
+ * The state starts as x = 0 and must be set with rods_set_state. */
+int rods_create(const RodsDesc* desc, RodsHandle** out);
+void rods_destroy(RodsHandle* h);
+const char* rods_strerror(int code);
+
+/* Current state S = (x, x_dot, r) of Section 4.1 plus the reference frames.
+ * x, v: [V][3].  kappa_bar: [V][2] rest curvature (rows of end vertices
+ * ignored), NULL = zeros.  d1: [V][3] first reference director of each edge
+ * (edge rows as above), NULL = the initial-frame rule: d1 of the first edge
+ * is z (or x when the edge is within 1e-6 of parallel to z) projected
+ * orthogonal to the edge and normalised, then parallel transport along the
+ * rod.  Clears the recorded rollout. */
+int rods_set_state(RodsHandle* h, const void* x, const void* v, const void* kappa_bar,
+                   const void* d1, rods_stream_t stream);
+/* Copies the current state out; any pointer may be NULL to skip it. */
+int rods_get_state(RodsHandle* h, void* x, void* v, void* kappa_bar, void* d1,
+                   rods_stream_t stream);
+
+/* Overrides the per-rod bending stiffness b and yield curvature sigma_y with
+ * device arrays [R] (either may be NULL).  Clears the recorded rollout. */
+int rods_set_params(RodsHandle* h, const void* b, const void* sigma_y, rods_stream_t stream);
+
+/* Material curvature kappa_i (App. A.1, Bending) of the shape x [V][3] with
+ * frames d1 [V][3] (NULL = initial-frame rule), written to kappa [V][2].
+ * Passing the result to rods_set_state makes that shape the rest shape. */
+int rods_curvature(RodsHandle* h, const void* x, const void* d1, void* kappa,
+                   rods_stream_t stream);
+
+/* Advances the state by one step dt (n_sub substeps) with grasp velocities
+ * grasp_vel [R][G][3]: grasped vertices move with the given velocity.
+ * Does not record.  Safe to capture in a HIP graph. */
+int rods_step(RodsHandle* h, const void* grasp_vel, rods_stream_t stream);
+
+/* Advances by n_steps; step s uses grasp_vel[s / steps_per_action] with
+ * grasp_vel of shape [ceil(n_steps/steps_per_action)][R][G][3].  x_final
+ * [V][3] receives the final positions (NULL to skip).  With record != 0 the
+ * state at every ckpt_every-th step and a copy of the actions are kept for
+ * rods_backward (ROD_ESTATE if n_steps > max_steps). */
+int rods_rollout(RodsHandle* h, int32_t n_steps, const void* grasp_vel, void* x_final,
+                 int32_t record, rods_stream_t stream);
+
+/* Reverse pass of the last recorded rollout (Section 3.3): replays each
+ * segment from its checkpoint and back-propagates the cotangents dL_dxT
+ * [V][3] and dL_dvT [V][3] (NULL = 0) of the final state.  Writes (each
+ * may be NULL): dL_du [A][R][G][3], dL_db [R], dL_dsigma [R], dL_dx0 [V][3],
+ * dL_dv0 [V][3].  Outputs are overwritten.  ROD_ESTATE without a recorded
+ * rollout.  The recorded rollout stays valid (backward may run again). */
+int rods_backward(RodsHandle* h, const void* dL_dxT, const void* dL_dvT, void* dL_du,
+                  void* dL_db, void* dL_dsigma, void* dL_dx0, void* dL_dv0,
+                  rods_stream_t stream);
+
+/* Mean-squared-distance loss L = (1/R) sum_r (1/N_r) sum_i |x_i - target_i|^2
+ * of the positions x [V][3]; writes loss [1] and dL_dx [V][3] (either may be
+ * NULL). */
+int rods_loss_mse(RodsHandle* h, const void* x, const void* target, void* loss,
+                  void* dL_dx, rods_stream_t stream);
+
+/* Synchronises the stream and copies per-rod status words to flags (host)
+ * [R]: bit0 = non-finite state seen.  Returns ROD_EHIP if a kernel failed. */
+int rods_status(RodsHandle* h, int32_t* flags, rods_stream_t stream);
+
+/* Launch configuration per size bin: fills up to max_bins entries of
+ * (vertices per lane, waves per rod, rods in bin) into out (host) [3*max_bins]
+ * and returns the number of bins (negative on error). */
+int rods_bins(RodsHandle* h, int32_t* out, int32_t max_bins);
+
+/* Times every legal launch shape of every size bin on a short forward run
+ * and keeps the fastest (the results do not depend on the choice).  Saves
+ * and restores the state; synchronises the stream. */
+int rods_autotune(RodsHandle* h, int32_t n_steps, rods_stream_t stream);
+
+/* Plain path switch: with plain != 0, rods_rollout and rods_backward launch
+ * the same kernels once per rod and per step (a one-rod work list, no
+ * multi-step residency): the reference against which the batched path's
+ * speedup is measured.  Results are identical to the batched path. */
+int rods_set_plain(RodsHandle* h, int32_t plain);
+
+/* Checks the lane-exchange primitives of the kernels: writes, for each of
+ * 64 lanes, the lane id received from the next and from the previous lane
+ * into out (device) [2][64] as int32 (-1 where no neighbour exists). */
+int rods_selftest_exchange(void* out, rods_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RODS_H */

@@ -1,0 +1,203 @@
+// Device-side helpers: 3-vectors, lane exchange inside a rod's team of
+// lanes, and the kernel argument block.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rods {
+
+template <typename T>
+struct V3 {
+  T x, y, z;
+};
+
+template <typename T>
+__device__ __forceinline__ V3<T> mk(T a, T b, T c) { return V3<T>{a, b, c}; }
+template <typename T>
+__device__ __forceinline__ V3<T> zero3() { return V3<T>{T(0), T(0), T(0)}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator+(V3<T> a, V3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator-(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator-(V3<T> a) { return {-a.x, -a.y, -a.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator*(T s, V3<T> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T>& operator+=(V3<T>& a, V3<T> b) { a.x += b.x; a.y += b.y; a.z += b.z; return a; }
+template <typename T>
+__device__ __forceinline__ V3<T>& operator-=(V3<T>& a, V3<T> b) { a.x -= b.x; a.y -= b.y; a.z -= b.z; return a; }
+template <typename T>
+__device__ __forceinline__ T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T>
+__device__ __forceinline__ V3<T> cross(V3<T> a, V3<T> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ V3<T> sel(bool c, V3<T> a, V3<T> b) { return c ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Lane exchange.  A rod is owned by a team of 64*W lanes (W waves of one
+// workgroup); team lane l holds vertices l*C .. l*C+C-1.  Inside a wave the
+// neighbour exchange is a DPP wavefront shift (a VALU move, no LDS); at a
+// wave boundary the value goes through a small ping-pong LDS buffer with one
+// barrier per exchange group.  Every exchange must be reached by all lanes
+// of the workgroup (uniform control flow).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int dpp_from_next_i(int v) {
+  // wave_shl:1 -- lane i receives lane i+1; lane 63 receives 0
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_from_prev_i(int v) {
+  // wave_shr:1 -- lane i receives lane i-1; lane 0 receives 0
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float dpp_from_next(float v) {
+  return __int_as_float(dpp_from_next_i(__float_as_int(v)));
+}
+__device__ __forceinline__ float dpp_from_prev(float v) {
+  return __int_as_float(dpp_from_prev_i(__float_as_int(v)));
+}
+__device__ __forceinline__ double dpp_from_next(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = dpp_from_next_i((int)(b & 0xffffffffLL));
+  int hi = dpp_from_next_i((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double dpp_from_prev(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = dpp_from_prev_i((int)(b & 0xffffffffLL));
+  int hi = dpp_from_prev_i((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+constexpr int XK = 12;   // largest exchange group (values)
+
+template <typename T, int W>
+struct Team {
+  T* buf;    // LDS: 2 (ping-pong) x W x XK values, only used when W > 1
+  int pp;
+  int wave, lane;
+
+  __device__ void init(T* lds) {
+    buf = lds;
+    pp = 0;
+    wave = threadIdx.x >> 6;
+    lane = threadIdx.x & 63;
+  }
+  // v[k] <- value of team lane + 1 (0 past the team's end)
+  template <int K>
+  __device__ __forceinline__ void next(T (&v)[K]) {
+    T r[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = dpp_from_next(v[k]);
+    if constexpr (W > 1) {
+      T* b = buf + pp * (W * XK);
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) b[wave * XK + k] = v[k];
+      }
+      __syncthreads();
+      if (lane == 63 && wave + 1 < W) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) r[k] = b[(wave + 1) * XK + k];
+      }
+      pp ^= 1;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = r[k];
+  }
+  // v[k] <- value of team lane - 1 (0 before the team's start)
+  template <int K>
+  __device__ __forceinline__ void prev(T (&v)[K]) {
+    T r[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = dpp_from_prev(v[k]);
+    if constexpr (W > 1) {
+      T* b = buf + pp * (W * XK);
+      if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) b[wave * XK + k] = v[k];
+      }
+      __syncthreads();
+      if (lane == 0 && wave > 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) r[k] = b[(wave - 1) * XK + k];
+      }
+      pp ^= 1;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = r[k];
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void put3(T* a, int o, V3<T> v) { a[o] = v.x; a[o + 1] = v.y; a[o + 2] = v.z; }
+template <typename T>
+__device__ __forceinline__ V3<T> get3(const T* a, int o) { return V3<T>{a[o], a[o + 1], a[o + 2]}; }
+
+// ---------------------------------------------------------------------------
+// Kernel arguments (one block passed by value)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct RodArgs {
+  // topology and work list
+  const int32_t* voff;      // [R+1]
+  const int32_t* rods;      // rods of this launch, blockIdx.x -> rod
+  const int64_t* tape_off;  // [R] offset of the rod's block inside one tape slice
+  // per-rod parameters
+  const T* b;
+  const T* sigma;
+  const T* rc;
+  const T* mu;
+  const T* restit;
+  const T* K;
+  const int32_t* flags;
+  // per-vertex statics (CSR rows)
+  const T* w;               // inverse mass, 0 for pinned and grasped vertices
+  const T* rest;            // rest length of edge row j
+  const T* radius;
+  const int32_t* gslot;     // grasp slot of the vertex or -1
+  // rigid primitives
+  const int32_t* prim_off;  // [R+1]
+  const int32_t* prim_type;
+  const T* prim_a;          // [P][3]
+  const T* prim_b;          // [P][3]
+  const T* prim_r;          // [P]
+  // state (read at start, written at end)
+  T* x;
+  T* v;
+  T* kb;
+  T* d1;
+  // optional copy of the final state (checkpoint)
+  T* ck_x;
+  T* ck_v;
+  T* ck_kb;
+  T* ck_d1;
+  // substep tape: substep-start states of the launch's steps
+  T* tape;
+  int64_t tape_stride;      // values per tape slice (one substep, all rods)
+  // actions
+  const T* u;               // action a of rod r, slot g at u[a*act_stride + (r*G+g)*3]
+  int64_t act_stride;
+  int32_t G;
+  int32_t spa;              // steps per action
+  int32_t step_off;         // global index of the launch's first step
+  // adjoint state and outputs
+  T* lx;
+  T* lv;
+  T* lkb;
+  T* ld1;
+  T* dL_du;
+  double* acc_b;            // [V] per-vertex dL/db partials
+  double* acc_s;            // [V] per-vertex dL/dsigma partials
+  int32_t* status;          // [R]
+  // scalars
+  T h;
+  T gx, gy, gz;
+  T eps_s, f_thresh, self_margin;
+  int32_t n_sub, n_iters, n_steps, k_ex;
+};
+
+}  // namespace rods

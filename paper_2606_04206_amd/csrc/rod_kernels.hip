@@ -1,0 +1,1277 @@
+// HIP kernels of the batched discrete-rod step and its adjoint (gfx950).
+//
+// One workgroup of W waves owns one rod for a whole launch (a segment of
+// steps): the rod's state lives in VGPRs, team lane l holding the C
+// consecutive vertices l*C .. l*C+C-1 and the edges that start at them.
+// With C even, every even ("red") edge lies inside one lane and every odd
+// ("black") edge but the lane's last lies inside one lane too, so an
+// iteration of the inextensibility projection needs exactly one neighbour
+// exchange pair (positions to the left, corrections to the right).
+//
+// Physics (DLO-Lab, Section 3.1 and Appendix A.1): bending forces of the
+// discrete elastic rod with frames held fixed, stretching forces for
+// extensible rods, symplectic Euler, soft SDF rigid contact (Section 3.2),
+// N_C red-black inextensibility iterations, position-based velocity update,
+// parallel transport of the reference frames and the plastic rest-curvature
+// return map.  The adjoint kernel re-runs each substep from its stored start
+// state (projection iterates kept in LDS) and applies the hand-written
+// vector-Jacobian product of every sub-step in reverse.
+#include "rod_device.h"
+#include "rod_launch.h"
+
+namespace rods {
+
+constexpr int FLAG_INEXT = 1, FLAG_PLASTIC = 2, FLAG_SELF = 4;
+constexpr int NFIELD = 11;   // x(3) v(3) kappa_bar(2) d1(3) per vertex slot
+
+template <typename T>
+__device__ __forceinline__ T rcp(T a) { return T(1) / a; }
+
+template <typename T>
+__device__ __forceinline__ V3<T> transport(V3<T> v, V3<T> ta, V3<T> tb) {
+  V3<T> bb = cross(ta, tb);
+  T c = dot(ta, tb);
+  return c * v + cross(bb, v) + (dot(bb, v) / (T(1) + c)) * bb;
+}
+
+// Adjoint of transport: y = R(ta->tb) v.  Returns v_b; adds to ta_b, tb_b.
+template <typename T>
+__device__ __forceinline__ V3<T> transport_vjp(V3<T> v, V3<T> ta, V3<T> tb, V3<T> yb,
+                                               V3<T>& ta_b, V3<T>& tb_b) {
+  V3<T> bb = cross(ta, tb);
+  T c = dot(ta, tb);
+  T bv = dot(bb, v), by = dot(bb, yb);
+  T iopc = T(1) / (T(1) + c);
+  V3<T> vb = c * yb - cross(bb, yb) + (by * iopc) * bb;
+  T cb = dot(v, yb) - bv * by * iopc * iopc;
+  V3<T> bbb = cross(v, yb) + iopc * (bv * yb + by * v);
+  ta_b += cross(tb, bbb) + cb * tb;
+  tb_b += cross(bbb, ta) + cb * ta;
+  return vb;
+}
+
+// Bending stencil of an interior vertex (App. A.1, Bending), frames fixed:
+// g0 = dU_b/de^{i-1}, g1 = dU_b/de^i.
+template <typename T>
+struct BendIn {
+  V3<T> t0, t1, d1a, d1b, d2a, d2b;
+  T l0, l1, kr0, kr1, lbar;
+};
+
+template <typename T>
+__device__ __forceinline__ void bend_grad(const BendIn<T>& q, T b, V3<T>& g0, V3<T>& g1) {
+  T ichi = T(1) / (T(1) + dot(q.t0, q.t1));
+  V3<T> kbv = (T(2) * ichi) * cross(q.t0, q.t1);
+  V3<T> a1 = T(0.5) * (q.d2a + q.d2b);
+  V3<T> a2 = T(0.5) * (q.d1a + q.d1b);
+  T k1 = dot(kbv, a1), k2 = dot(kbv, a2);
+  T coef = b / q.lbar;
+  T c1 = coef * (k1 - q.kr0), c2 = coef * (k2 - q.kr1);
+  T s = c1 * k1 + c2 * k2;
+  V3<T> A = (T(2) * ichi) * (c1 * a1 + c2 * a2);
+  V3<T> tt = ichi * (q.t0 + q.t1);
+  g0 = (T(1) / q.l0) * (cross(q.t1, A) - s * tt);
+  g1 = (T(1) / q.l1) * (-(s * tt) - cross(q.t0, A));
+}
+
+template <typename T>
+struct BendBar {
+  V3<T> t0, t1, d1a, d1b, d2a, d2b;
+  T l0, l1, kr0, kr1, b;
+};
+
+// Adjoint of bend_grad given g0_b, g1_b.
+template <typename T>
+__device__ __forceinline__ void bend_vjp(const BendIn<T>& q, T b, V3<T> g0b, V3<T> g1b,
+                                         BendBar<T>& o) {
+  T chi = T(1) + dot(q.t0, q.t1);
+  T ichi = T(1) / chi;
+  V3<T> nn = cross(q.t0, q.t1);
+  V3<T> kbv = (T(2) * ichi) * nn;
+  V3<T> a1 = T(0.5) * (q.d2a + q.d2b);
+  V3<T> a2 = T(0.5) * (q.d1a + q.d1b);
+  T k1 = dot(kbv, a1), k2 = dot(kbv, a2);
+  T coef = b / q.lbar;
+  T dk1 = k1 - q.kr0, dk2 = k2 - q.kr1;
+  T c1 = coef * dk1, c2 = coef * dk2;
+  T s = c1 * k1 + c2 * k2;
+  V3<T> A = (T(2) * ichi) * (c1 * a1 + c2 * a2);
+  V3<T> tt = ichi * (q.t0 + q.t1);
+  T il0 = T(1) / q.l0, il1 = T(1) / q.l1;
+  V3<T> g0 = il0 * (cross(q.t1, A) - s * tt);
+  V3<T> g1 = il1 * (-(s * tt) - cross(q.t0, A));
+  // g = G / l
+  V3<T> G0b = il0 * g0b, G1b = il1 * g1b;
+  o.l0 = -dot(g0, g0b) * il0;
+  o.l1 = -dot(g1, g1b) * il1;
+  V3<T> Gsb = G0b + G1b;
+  T sb = -dot(tt, Gsb);
+  V3<T> ttb = (-s) * Gsb;
+  V3<T> t0b = ichi * ttb - cross(A, G1b);
+  V3<T> t1b = ichi * ttb + cross(A, G0b);
+  V3<T> Ab = cross(G0b, q.t1) - cross(G1b, q.t0);
+  T chib = -dot(tt, ttb) * ichi - dot(A, Ab) * ichi;
+  T c1b = T(2) * ichi * dot(a1, Ab) + k1 * sb;
+  T c2b = T(2) * ichi * dot(a2, Ab) + k2 * sb;
+  V3<T> a1b = (T(2) * ichi * c1) * Ab;
+  V3<T> a2b = (T(2) * ichi * c2) * Ab;
+  T k1b = c1 * sb + coef * c1b;
+  T k2b = c2 * sb + coef * c2b;
+  o.kr0 = -coef * c1b;
+  o.kr1 = -coef * c2b;
+  o.b = (c1b * dk1 + c2b * dk2) / q.lbar;
+  V3<T> kbvb = k1b * a1 + k2b * a2;
+  a1b += k1b * kbv;
+  a2b += k2b * kbv;
+  // kbv = 2 nn / chi, chi = 1 + t0.t1
+  chib -= dot(kbv, kbvb) * ichi;
+  V3<T> nb = (T(2) * ichi) * kbvb;
+  t0b += cross(q.t1, nb) + chib * q.t1;
+  t1b += cross(nb, q.t0) + chib * q.t0;
+  o.t0 = t0b;
+  o.t1 = t1b;
+  o.d2a = T(0.5) * a1b;
+  o.d2b = T(0.5) * a1b;
+  o.d1a = T(0.5) * a2b;
+  o.d1b = T(0.5) * a2b;
+}
+
+// Material curvature (kb.a1, kb.a2) at an interior vertex (App. A.1).
+template <typename T>
+__device__ __forceinline__ void curvature(V3<T> t0, V3<T> t1, V3<T> d1a, V3<T> d1b, T& k1, T& k2) {
+  T ichi = T(1) / (T(1) + dot(t0, t1));
+  V3<T> kbv = (T(2) * ichi) * cross(t0, t1);
+  V3<T> a1 = T(0.5) * (cross(t0, d1a) + cross(t1, d1b));
+  V3<T> a2 = T(0.5) * (d1a + d1b);
+  k1 = dot(kbv, a1);
+  k2 = dot(kbv, a2);
+}
+
+// Adjoint of curvature w.r.t. t0, t1, d1a, d1b (d2 = t x d1 inside).
+template <typename T>
+__device__ __forceinline__ void curvature_vjp(V3<T> t0, V3<T> t1, V3<T> d1a, V3<T> d1b, T k1b,
+                                              T k2b, V3<T>& t0b, V3<T>& t1b, V3<T>& d1ab,
+                                              V3<T>& d1bb) {
+  T chi = T(1) + dot(t0, t1);
+  T ichi = T(1) / chi;
+  V3<T> kbv = (T(2) * ichi) * cross(t0, t1);
+  V3<T> d2a = cross(t0, d1a), d2b = cross(t1, d1b);
+  V3<T> a1 = T(0.5) * (d2a + d2b);
+  V3<T> a2 = T(0.5) * (d1a + d1b);
+  V3<T> kbvb = k1b * a1 + k2b * a2;
+  V3<T> a1b = k1b * kbv, a2b = k2b * kbv;
+  T chib = -dot(kbv, kbvb) * ichi;
+  V3<T> nb = (T(2) * ichi) * kbvb;
+  t0b = cross(t1, nb) + chib * t1;
+  t1b = cross(nb, t0) + chib * t0;
+  V3<T> d2ab = T(0.5) * a1b;   // same for d2b
+  d1ab = T(0.5) * a2b + cross(d2ab, t0);
+  d1bb = T(0.5) * a2b + cross(d2ab, t1);
+  t0b += cross(d1a, d2ab);
+  t1b += cross(d1b, d2ab);
+}
+
+// One inextensibility projection of edge (pj, pk) (App. A.1): lambda = C/W,
+// pj += lambda wj t, pk -= lambda wk t.  Returns the edge vector D it saw.
+template <typename T>
+__device__ __forceinline__ V3<T> project_edge(V3<T>& pj, V3<T>& pk, T wj, T wk, T r) {
+  V3<T> D = pk - pj;
+  T W = wj + wk;
+  if (W > T(0)) {
+    T l = sqrt(dot(D, D));
+    T s = (l - r) / (W * l);
+    pj += (s * wj) * D;
+    pk -= (s * wk) * D;
+  }
+  return D;
+}
+
+// Adjoint of project_edge: returns D_b (pj_b -= D_b, pk_b += D_b).
+template <typename T>
+__device__ __forceinline__ V3<T> project_edge_vjp(V3<T> D, T wj, T wk, T r, V3<T> aj, V3<T> ak) {
+  T W = wj + wk;
+  if (!(W > T(0))) return zero3<T>();
+  T l = sqrt(dot(D, D));
+  T il = T(1) / l;
+  V3<T> t = il * D;
+  V3<T> qb = (T(1) / W) * (wj * aj - wk * ak);
+  return qb - (r * il) * (qb - dot(t, qb) * t);
+}
+
+// ---------------------------------------------------------------------------
+// rigid contact (Section 3.2): soft SDF impulses on free vertices
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Prim {
+  int type;
+  V3<T> a, b;
+  T r;
+};
+
+template <typename T>
+__device__ __forceinline__ Prim<T> load_prim(const RodArgs<T>& a, int k) {
+  Prim<T> p;
+  p.type = a.prim_type[k];
+  p.a = get3(a.prim_a, 3 * k);
+  p.b = get3(a.prim_b, 3 * k);
+  p.r = a.prim_r[k];
+  return p;
+}
+
+// signed distance, unit normal, and whether the capsule parameter is interior
+template <typename T>
+__device__ __forceinline__ T sdf_normal(const Prim<T>& p, V3<T> x, V3<T>& n, bool& interior,
+                                        T& nq) {
+  interior = false;
+  if (p.type == 0) {
+    n = p.b;
+    nq = T(0);
+    return dot(x - p.a, p.b);
+  }
+  V3<T> q;
+  if (p.type == 1) {
+    q = x - p.a;
+  } else {
+    V3<T> ab = p.b - p.a;
+    T s = dot(x - p.a, ab) / dot(ab, ab);
+    interior = (s > T(0)) && (s < T(1));
+    s = s < T(0) ? T(0) : (s > T(1) ? T(1) : s);
+    q = x - (p.a + s * ab);
+  }
+  nq = sqrt(dot(q, q));
+  n = (T(1) / nq) * q;
+  return nq - p.r;
+}
+
+template <typename T>
+__device__ __forceinline__ T exp_t(T a) { return exp(a); }
+
+// One primitive's response on v; returns true when active.
+template <typename T>
+__device__ __forceinline__ bool contact_one(const Prim<T>& p, V3<T> x, T rad, T mu, T e, T eps_s,
+                                            T f_thresh, V3<T>& v) {
+  V3<T> n;
+  bool interior;
+  T nq;
+  T sdf = sdf_normal(p, x, n, interior, nq);
+  T d = rad - sdf;
+  T f = d >= T(0) ? T(1) : exp_t(d / eps_s);
+  T vn = dot(v, n);
+  if (!(f > f_thresh && vn < T(0))) return false;
+  T dvn = -(T(1) + e) * vn;
+  V3<T> vt = v - vn * n;
+  T vtn = sqrt(dot(vt, vt));
+  T s = T(0);
+  if (vtn > T(0)) {
+    T sr = T(1) - mu * dvn / vtn;
+    s = sr > T(0) ? sr : T(0);
+  }
+  V3<T> vres = (-e * vn) * n + s * vt;
+  v = (T(1) - f) * v + f * vres;
+  return true;
+}
+
+// Adjoint of contact_one at input velocity vin (re-evaluated); vb is the
+// adjoint of the output velocity, updated in place to that of the input;
+// adds to xb.
+template <typename T>
+__device__ __forceinline__ void contact_one_vjp(const Prim<T>& p, V3<T> x, T rad, T mu, T e,
+                                                T eps_s, T f_thresh, V3<T> vin, V3<T>& vb,
+                                                V3<T>& xb) {
+  V3<T> n;
+  bool interior;
+  T nq;
+  T sdf = sdf_normal(p, x, n, interior, nq);
+  T d = rad - sdf;
+  T f = d >= T(0) ? T(1) : exp_t(d / eps_s);
+  T vn = dot(vin, n);
+  if (!(f > f_thresh && vn < T(0))) return;
+  T dvn = -(T(1) + e) * vn;
+  V3<T> vt = vin - vn * n;
+  T vtn = sqrt(dot(vt, vt));
+  T s = T(0);
+  bool slide = false;
+  if (vtn > T(0)) {
+    T sr = T(1) - mu * dvn / vtn;
+    slide = sr > T(0);
+    s = slide ? sr : T(0);
+  }
+  V3<T> vres = (-e * vn) * n + s * vt;
+  V3<T> vob = vb;
+  V3<T> vib = (T(1) - f) * vob;
+  V3<T> vresb = f * vob;
+  T fb = dot(vres - vin, vob);
+  T vnb = -e * dot(n, vresb);
+  V3<T> nb = (-e * vn) * vresb;
+  T sb = dot(vt, vresb);
+  V3<T> vtb = s * vresb;
+  if (slide) {
+    T dvnb = -mu * sb / vtn;
+    T vtnb = mu * dvn * sb / (vtn * vtn);
+    vnb += -(T(1) + e) * dvnb;
+    vtb += (vtnb / vtn) * vt;
+  }
+  vib += vtb;
+  vnb -= dot(n, vtb);
+  nb -= vn * vtb;
+  vib += vnb * n;
+  nb += vnb * vin;
+  T db = d < T(0) ? fb * f / eps_s : T(0);
+  T sdfb = -db;
+  if (p.type == 0) {
+    xb += sdfb * p.b;
+  } else {
+    V3<T> perp = (T(1) / nq) * (nb - dot(n, nb) * n);
+    V3<T> g = sdfb * n + perp;
+    if (p.type == 2 && interior) {
+      V3<T> ab = p.b - p.a;
+      V3<T> u = (T(1) / sqrt(dot(ab, ab))) * ab;
+      g -= dot(perp, u) * u;
+    }
+    xb += g;
+  }
+  vb = vib;
+}
+
+// ---------------------------------------------------------------------------
+// Per-lane rod state
+// ---------------------------------------------------------------------------
+template <typename T, int C>
+struct Rec {   // what the adjoint needs from one substep's forward run
+  V3<T> t[C], d1[C];
+  T ell[C], kr0[C], kr1[C];
+  V3<T> tp, d1p;
+  T lp;
+  V3<T> x[C], v1[C];
+  V3<T> t1[C], d1n[C];
+  T ell1[C];
+  V3<T> t1p, d1np;
+  T kel0[C], kel1[C], nrm[C], phi[C];
+  bool yld[C];
+};
+
+template <typename T, int C, int W>
+struct Rod {
+  static constexpr int TL = 64 * W;   // lanes per team
+  int rod, N, v0, tl, flags, p0, p1;
+  T b, sig, rc, mu, e, K;
+  T w[C], rest[C], lbar[C], ks[C], rad[C];
+  int gs[C];
+  T wn;
+  V3<T> x[C], v[C], d1[C];
+  T kr0[C], kr1[C];
+
+  __device__ __forceinline__ int gi(int c) const { return tl * C + c; }
+  __device__ __forceinline__ bool vvalid(int c) const { return gi(c) < N; }
+  __device__ __forceinline__ bool evalid(int c) const { return gi(c) < N - 1; }
+  __device__ __forceinline__ bool ivalid(int c) const { return gi(c) >= 1 && gi(c) <= N - 2; }
+
+  __device__ void load_static(const RodArgs<T>& a, Team<T, W>& X) {
+    rod = a.rods[blockIdx.x];
+    v0 = a.voff[rod];
+    N = a.voff[rod + 1] - v0;
+    tl = threadIdx.x;
+    flags = a.flags[rod];
+    b = a.b[rod];
+    sig = a.sigma[rod];
+    rc = a.rc[rod];
+    mu = a.mu[rod];
+    e = a.restit[rod];
+    K = a.K[rod];
+    p0 = a.prim_off ? a.prim_off[rod] : 0;
+    p1 = a.prim_off ? a.prim_off[rod + 1] : 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int g = gi(c);
+      bool vv = g < N;
+      w[c] = vv ? a.w[v0 + g] : T(0);
+      gs[c] = vv ? a.gslot[v0 + g] : -1;
+      rad[c] = vv ? a.radius[v0 + g] : T(0);
+      rest[c] = (g < N - 1) ? a.rest[v0 + g] : T(0);
+    }
+    T rp[1] = {rest[C - 1]};
+    X.prev(rp);
+    T rn[2] = {rad[0], w[0]};
+    X.next(rn);
+    wn = rn[1];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      lbar[c] = ivalid(c) ? T(0.5) * ((c ? rest[c - 1] : rp[0]) + rest[c]) : T(0);
+      T rb = T(0.5) * (rad[c] + (c < C - 1 ? rad[c + 1] : rn[0]));
+      ks[c] = evalid(c) ? K * T(3.14159265358979323846) * rb * rb : T(0);
+    }
+  }
+
+  __device__ void load_state(const T* X, const T* Vv, const T* KB, const T* D1) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int g = gi(c), r = v0 + g;
+      bool vv = g < N;
+      x[c] = vv ? get3(X, 3 * r) : zero3<T>();
+      v[c] = vv ? get3(Vv, 3 * r) : zero3<T>();
+      kr0[c] = ivalid(c) ? KB[2 * r] : T(0);
+      kr1[c] = ivalid(c) ? KB[2 * r + 1] : T(0);
+      d1[c] = evalid(c) ? get3(D1, 3 * r) : zero3<T>();
+    }
+  }
+
+  __device__ void store_state(T* X, T* Vv, T* KB, T* D1) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int g = gi(c), r = v0 + g;
+      if (g < N) {
+        put3(X, 3 * r, x[c]);
+        put3(Vv, 3 * r, v[c]);
+        KB[2 * r] = kr0[c];
+        KB[2 * r + 1] = kr1[c];
+        put3(D1, 3 * r, d1[c]);   // zero on the last vertex row
+      }
+    }
+  }
+
+  // tape layout of one rod block: value (field*C + c) of team lane l at
+  // [(field*C + c) * TL + l] -- every access is a 64-lane contiguous run
+  __device__ void store_tape(T* base) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      T vals[NFIELD] = {x[c].x, x[c].y, x[c].z, v[c].x, v[c].y, v[c].z,
+                        kr0[c], kr1[c], d1[c].x, d1[c].y, d1[c].z};
+#pragma unroll
+      for (int f = 0; f < NFIELD; ++f) base[(f * C + c) * TL + tl] = vals[f];
+    }
+  }
+  __device__ void load_tape(const T* base) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      T vals[NFIELD];
+#pragma unroll
+      for (int f = 0; f < NFIELD; ++f) vals[f] = base[(f * C + c) * TL + tl];
+      x[c] = mk(vals[0], vals[1], vals[2]);
+      v[c] = mk(vals[3], vals[4], vals[5]);
+      kr0[c] = vals[6];
+      kr1[c] = vals[7];
+      d1[c] = mk(vals[8], vals[9], vals[10]);
+    }
+  }
+
+  // grasp velocities of this lane's grasped vertices for action `act`
+  __device__ void load_actions(const RodArgs<T>& a, int act, V3<T> (&ug)[C]) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      ug[c] = zero3<T>();
+      if (gs[c] >= 0) ug[c] = get3(a.u, (int64_t)act * a.act_stride + (int64_t)(rod * a.G + gs[c]) * 3);
+    }
+  }
+
+  // edge vectors at positions p: tangents and lengths (invalid edges: t = 0, l = 1)
+  __device__ void edges(Team<T, W>& X, const V3<T> (&p)[C], V3<T> (&t)[C], T (&l)[C]) const {
+    T pn[3] = {p[0].x, p[0].y, p[0].z};
+    X.next(pn);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      V3<T> q = (c < C - 1) ? p[c + 1] : mk(pn[0], pn[1], pn[2]);
+      V3<T> D = q - p[c];
+      T ll = sqrt(dot(D, D));
+      bool ok = evalid(c);
+      l[c] = ok ? ll : T(1);
+      t[c] = ok ? (T(1) / ll) * D : zero3<T>();
+    }
+  }
+
+  // adjoint of edges(): adds the position adjoints to pb
+  __device__ void edges_vjp(Team<T, W>& X, const V3<T> (&t)[C], const T (&l)[C],
+                            const V3<T> (&tb)[C], const T (&lb)[C], V3<T> (&pb)[C]) const {
+    V3<T> eb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      eb[c] = evalid(c) ? (T(1) / l[c]) * (tb[c] - dot(t[c], tb[c]) * t[c]) + lb[c] * t[c]
+                        : zero3<T>();
+      pb[c] -= eb[c];
+      if (c < C - 1) pb[c + 1] += eb[c];
+    }
+    T s[3] = {eb[C - 1].x, eb[C - 1].y, eb[C - 1].z};
+    X.prev(s);
+    pb[0] += mk(s[0], s[1], s[2]);
+  }
+
+  __device__ __forceinline__ T* tape_at(T* lds_tape, int it, int c, int k) const {
+    return lds_tape + ((it * C + c) * 3 + k) * TL + tl;
+  }
+
+  // N_C iterations of red (even edges) then black (odd edges) projections
+  template <bool REC>
+  __device__ void project(const RodArgs<T>& a, Team<T, W>& X, V3<T> (&p)[C], T* lds_tape) {
+    for (int it = 0; it < a.n_iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < C; c += 2) {
+        V3<T> D = zero3<T>();
+        if (evalid(c)) D = project_edge(p[c], p[c + 1], w[c], w[c + 1], rest[c]);
+        if constexpr (REC) {
+          *tape_at(lds_tape, it, c, 0) = D.x;
+          *tape_at(lds_tape, it, c, 1) = D.y;
+          *tape_at(lds_tape, it, c, 2) = D.z;
+        }
+      }
+#pragma unroll
+      for (int c = 1; c < C - 1; c += 2) {
+        V3<T> D = zero3<T>();
+        if (evalid(c)) D = project_edge(p[c], p[c + 1], w[c], w[c + 1], rest[c]);
+        if constexpr (REC) {
+          *tape_at(lds_tape, it, c, 0) = D.x;
+          *tape_at(lds_tape, it, c, 1) = D.y;
+          *tape_at(lds_tape, it, c, 2) = D.z;
+        }
+      }
+      // the lane's last edge reaches into the next lane
+      T pn[3] = {p[0].x, p[0].y, p[0].z};
+      X.next(pn);
+      V3<T> q = mk(pn[0], pn[1], pn[2]);
+      V3<T> qn = q;
+      V3<T> D = zero3<T>();
+      if (evalid(C - 1)) D = project_edge(p[C - 1], q, w[C - 1], wn, rest[C - 1]);
+      if constexpr (REC) {
+        *tape_at(lds_tape, it, C - 1, 0) = D.x;
+        *tape_at(lds_tape, it, C - 1, 1) = D.y;
+        *tape_at(lds_tape, it, C - 1, 2) = D.z;
+      }
+      V3<T> dq = q - qn;
+      T s[3] = {dq.x, dq.y, dq.z};
+      X.prev(s);
+      p[0] += mk(s[0], s[1], s[2]);
+    }
+  }
+
+  __device__ void project_vjp(const RodArgs<T>& a, Team<T, W>& X, V3<T> (&pb)[C],
+                              const T* lds_tape) const {
+    for (int it = a.n_iters - 1; it >= 0; --it) {
+      // black pass, reversed
+      T an[3] = {pb[0].x, pb[0].y, pb[0].z};
+      X.next(an);
+      V3<T> Db = zero3<T>();
+      if (evalid(C - 1)) {
+        V3<T> D = mk(lds_tape[((it * C + C - 1) * 3 + 0) * TL + tl],
+                     lds_tape[((it * C + C - 1) * 3 + 1) * TL + tl],
+                     lds_tape[((it * C + C - 1) * 3 + 2) * TL + tl]);
+        Db = project_edge_vjp(D, w[C - 1], wn, rest[C - 1], pb[C - 1], mk(an[0], an[1], an[2]));
+        pb[C - 1] -= Db;
+      }
+      T s[3] = {Db.x, Db.y, Db.z};
+      X.prev(s);
+      pb[0] += mk(s[0], s[1], s[2]);
+#pragma unroll
+      for (int c = 1; c < C - 1; c += 2) {
+        if (evalid(c)) {
+          V3<T> D = mk(lds_tape[((it * C + c) * 3 + 0) * TL + tl],
+                       lds_tape[((it * C + c) * 3 + 1) * TL + tl],
+                       lds_tape[((it * C + c) * 3 + 2) * TL + tl]);
+          V3<T> db = project_edge_vjp(D, w[c], w[c + 1], rest[c], pb[c], pb[c + 1]);
+          pb[c] -= db;
+          pb[c + 1] += db;
+        }
+      }
+      // red pass, reversed
+#pragma unroll
+      for (int c = 0; c < C; c += 2) {
+        if (evalid(c)) {
+          V3<T> D = mk(lds_tape[((it * C + c) * 3 + 0) * TL + tl],
+                       lds_tape[((it * C + c) * 3 + 1) * TL + tl],
+                       lds_tape[((it * C + c) * 3 + 2) * TL + tl]);
+          V3<T> db = project_edge_vjp(D, w[c], w[c + 1], rest[c], pb[c], pb[c + 1]);
+          pb[c] -= db;
+          pb[c + 1] += db;
+        }
+      }
+    }
+  }
+
+  // gather the previous lane's last edge: tangent, length, d1
+  __device__ void prev_edge(Team<T, W>& X, const V3<T> (&t)[C], const T (&l)[C],
+                            const V3<T> (&dd)[C], V3<T>& tp, T& lp, V3<T>& dp) const {
+    T pv[7] = {t[C - 1].x, t[C - 1].y, t[C - 1].z, l[C - 1], dd[C - 1].x, dd[C - 1].y, dd[C - 1].z};
+    X.prev(pv);
+    tp = mk(pv[0], pv[1], pv[2]);
+    lp = pv[3];
+    dp = mk(pv[4], pv[5], pv[6]);
+  }
+
+  __device__ __forceinline__ BendIn<T> bend_in(int c, const V3<T> (&t)[C], const T (&l)[C],
+                                               const V3<T> (&dd1)[C], V3<T> tp, T lp,
+                                               V3<T> d1p) const {
+    BendIn<T> q;
+    q.t0 = c ? t[c - 1] : tp;
+    q.t1 = t[c];
+    q.l0 = c ? l[c - 1] : lp;
+    q.l1 = l[c];
+    q.d1a = c ? dd1[c - 1] : d1p;
+    q.d1b = dd1[c];
+    q.d2a = cross(q.t0, q.d1a);
+    q.d2b = cross(q.t1, q.d1b);
+    q.kr0 = kr0[c];
+    q.kr1 = kr1[c];
+    q.lbar = lbar[c];
+    return q;
+  }
+
+  // ---------------------------------------------------------------- substep
+  template <bool REC>
+  __device__ void substep(const RodArgs<T>& a, Team<T, W>& X, const V3<T> (&ug)[C],
+                          Rec<T, C>* rc_, T* lds_tape) {
+    const T h = a.h;
+    const T ih = T(1) / h;
+    const V3<T> g = mk(a.gx, a.gy, a.gz);
+    // S2 forces at x with frames fixed
+    V3<T> t[C];
+    T l[C];
+    edges(X, x, t, l);
+    V3<T> tp, d1p;
+    T lp;
+    prev_edge(X, t, l, d1, tp, lp, d1p);
+    V3<T> F[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) F[c] = zero3<T>();
+    V3<T> to_prev = zero3<T>(), to_next = zero3<T>();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (ivalid(c)) {
+        BendIn<T> q = bend_in(c, t, l, d1, tp, lp, d1p);
+        V3<T> g0, g1;
+        bend_grad(q, b, g0, g1);
+        F[c] += g1 - g0;
+        if (c > 0) F[c - 1] += g0; else to_prev += g0;
+        if (c < C - 1) F[c + 1] -= g1; else to_next -= g1;
+      }
+    }
+    if (!(flags & FLAG_INEXT)) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (evalid(c)) {
+          V3<T> q = (ks[c] * (l[c] / rest[c] - T(1))) * t[c];
+          F[c] += q;
+          if (c < C - 1) F[c + 1] -= q; else to_next -= q;
+        }
+      }
+    }
+    {
+      T s[3] = {to_prev.x, to_prev.y, to_prev.z};
+      X.next(s);
+      F[C - 1] += mk(s[0], s[1], s[2]);
+      T s2[3] = {to_next.x, to_next.y, to_next.z};
+      X.prev(s2);
+      F[0] += mk(s2[0], s2[1], s2[2]);
+    }
+    if constexpr (REC) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        rc_->t[c] = t[c];
+        rc_->ell[c] = l[c];
+        rc_->d1[c] = d1[c];
+        rc_->kr0[c] = kr0[c];
+        rc_->kr1[c] = kr1[c];
+        rc_->x[c] = x[c];
+      }
+      rc_->tp = tp;
+      rc_->lp = lp;
+      rc_->d1p = d1p;
+    }
+    // S3 velocity update and kinematic vertices
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      V3<T> vn;
+      if (gs[c] >= 0) vn = ug[c];
+      else if (w[c] > T(0)) vn = v[c] + h * (g + w[c] * F[c]);
+      else vn = zero3<T>();
+      v[c] = vn;
+      if constexpr (REC) rc_->v1[c] = vn;
+    }
+    // S4 rigid contact, primitives in order
+    if (p1 > p0) {
+      for (int k = p0; k < p1; ++k) {
+        Prim<T> pr = load_prim(a, k);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          if (w[c] > T(0)) contact_one(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, v[c]);
+      }
+    }
+    // S5 predict
+    V3<T> p[C], pp[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      p[c] = x[c] + h * v[c];
+      pp[c] = p[c];
+    }
+    // S7 projections
+    if (flags & FLAG_INEXT) project<REC>(a, X, p, lds_tape);
+    // S8 velocity update from the corrections
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      v[c] += ih * (p[c] - pp[c]);
+      x[c] = p[c];
+    }
+    // S10 frames by parallel transport in time
+    V3<T> t1[C];
+    T l1[C];
+    edges(X, x, t1, l1);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (evalid(c)) d1[c] = transport(d1[c], t[c], t1[c]);
+    if constexpr (REC) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        rc_->t1[c] = t1[c];
+        rc_->ell1[c] = l1[c];
+        rc_->d1n[c] = d1[c];
+        rc_->yld[c] = false;
+      }
+    }
+    // S11 plasticity
+    if (flags & FLAG_PLASTIC) {
+      V3<T> t1p, d1np;
+      T l1p;
+      prev_edge(X, t1, l1, d1, t1p, l1p, d1np);
+      if constexpr (REC) {
+        rc_->t1p = t1p;
+        rc_->d1np = d1np;
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (ivalid(c)) {
+          T k1, k2;
+          curvature(c ? t1[c - 1] : t1p, t1[c], c ? d1[c - 1] : d1np, d1[c], k1, k2);
+          T e0 = k1 - kr0[c], e1 = k2 - kr1[c];
+          T nrm = sqrt(e0 * e0 + e1 * e1);
+          T thr = sig * lbar[c];
+          bool y = nrm > thr;
+          T phi = y ? rc * (nrm - thr) / nrm : T(0);
+          if constexpr (REC) {
+            rc_->kel0[c] = e0;
+            rc_->kel1[c] = e1;
+            rc_->nrm[c] = y ? nrm : T(1);
+            rc_->phi[c] = phi;
+            rc_->yld[c] = y;
+          }
+          if (y) {
+            kr0[c] += phi * e0;
+            kr1[c] += phi * e1;
+          }
+        }
+      }
+    }
+  }
+
+  // ------------------------------------------------------------ substep VJP
+  // lx, lv, lk0, lk1, ld1: adjoints of the substep's output state on entry,
+  // of its input state on exit.
+  __device__ void substep_vjp(const RodArgs<T>& a, Team<T, W>& X, const Rec<T, C>& r,
+                              const T* lds_tape, V3<T> (&lx)[C], V3<T> (&lv)[C], T (&lk0)[C],
+                              T (&lk1)[C], V3<T> (&ld1)[C], double (&accb)[C],
+                              double (&accs)[C], V3<T> (&uacc)[C]) const {
+    const T h = a.h;
+    const T ih = T(1) / h;
+    // S11 plasticity: kr' = kr + phi kel on yield
+    V3<T> t1b[C], d1nb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      t1b[c] = zero3<T>();
+      d1nb[c] = ld1[c];
+    }
+    if (flags & FLAG_PLASTIC) {
+      V3<T> tpb = zero3<T>(), dpb = zero3<T>();
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (ivalid(c) && r.yld[c]) {
+          T o0 = lk0[c], o1 = lk1[c];
+          T phi = r.phi[c], nrm = r.nrm[c], thr = sig * lbar[c];
+          T phib = r.kel0[c] * o0 + r.kel1[c] * o1;
+          T nrmb = rc * thr / (nrm * nrm) * phib;
+          T thrb = -rc / nrm * phib;
+          accs[c] += (double)(lbar[c] * thrb);
+          T e0 = phi * o0 + (nrmb / nrm) * r.kel0[c];
+          T e1 = phi * o1 + (nrmb / nrm) * r.kel1[c];
+          lk0[c] -= e0;
+          lk1[c] -= e1;
+          V3<T> t0b, tcb, dab, dcb;
+          curvature_vjp(c ? r.t1[c - 1] : r.t1p, r.t1[c], c ? r.d1n[c - 1] : r.d1np, r.d1n[c], e0,
+                        e1, t0b, tcb, dab, dcb);
+          if (c > 0) {
+            t1b[c - 1] += t0b;
+            d1nb[c - 1] += dab;
+          } else {
+            tpb += t0b;
+            dpb += dab;
+          }
+          t1b[c] += tcb;
+          d1nb[c] += dcb;
+        }
+      }
+      T s[6] = {tpb.x, tpb.y, tpb.z, dpb.x, dpb.y, dpb.z};
+      X.next(s);
+      t1b[C - 1] += mk(s[0], s[1], s[2]);
+      d1nb[C - 1] += mk(s[3], s[4], s[5]);
+    }
+    // S10 transport
+    V3<T> tb[C], d1b[C];
+    T lb[C], l1b[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      tb[c] = zero3<T>();
+      lb[c] = T(0);
+      l1b[c] = T(0);
+      d1b[c] = zero3<T>();
+      if (evalid(c)) d1b[c] = transport_vjp(r.d1[c], r.t[c], r.t1[c], d1nb[c], tb[c], t1b[c]);
+    }
+    V3<T> pb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) pb[c] = lx[c];
+    edges_vjp(X, r.t1, r.ell1, t1b, l1b, pb);
+    // S8: v' = v2 + (p - p0)/h, x' = p
+    V3<T> v2b[C], p0b[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      pb[c] += ih * lv[c];
+      v2b[c] = lv[c];
+      p0b[c] = -(ih * lv[c]);
+    }
+    // S7
+    if (flags & FLAG_INEXT) project_vjp(a, X, pb, lds_tape);
+    // S5 p0 = x + h v2
+    V3<T> xb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      p0b[c] += pb[c];
+      xb[c] = p0b[c];
+      v2b[c] += h * p0b[c];
+    }
+    // S4 rigid contact, primitives in reverse (input velocities re-evaluated)
+    if (p1 > p0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (w[c] > T(0)) {
+          for (int k = p1 - 1; k >= p0; --k) {
+            V3<T> vin = r.v1[c];
+            for (int j = p0; j < k; ++j)
+              contact_one(load_prim(a, j), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vin);
+            contact_one_vjp(load_prim(a, k), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vin,
+                            v2b[c], xb[c]);
+          }
+        }
+      }
+    }
+    // S3
+    V3<T> Fb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (gs[c] >= 0) {
+        uacc[c] += v2b[c];
+        lv[c] = zero3<T>();
+        Fb[c] = zero3<T>();
+      } else if (w[c] > T(0)) {
+        lv[c] = v2b[c];
+        Fb[c] = (h * w[c]) * v2b[c];
+      } else {
+        lv[c] = zero3<T>();
+        Fb[c] = zero3<T>();
+      }
+    }
+    // S2 forces
+    T fp[3] = {Fb[C - 1].x, Fb[C - 1].y, Fb[C - 1].z};
+    X.prev(fp);
+    T fn[3] = {Fb[0].x, Fb[0].y, Fb[0].z};
+    X.next(fn);
+    V3<T> Fp = mk(fp[0], fp[1], fp[2]), Fn = mk(fn[0], fn[1], fn[2]);
+    V3<T> d2b[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) d2b[c] = zero3<T>();
+    V3<T> tpb = zero3<T>(), d1pb = zero3<T>(), d2pb = zero3<T>();
+    T lpb = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (ivalid(c)) {
+        BendIn<T> q = bend_in(c, r.t, r.ell, r.d1, r.tp, r.lp, r.d1p);
+        V3<T> Fm = c ? Fb[c - 1] : Fp;
+        V3<T> Fq = (c < C - 1) ? Fb[c + 1] : Fn;
+        BendBar<T> o;
+        bend_vjp(q, b, Fm - Fb[c], Fb[c] - Fq, o);
+        lk0[c] += o.kr0;
+        lk1[c] += o.kr1;
+        accb[c] += (double)o.b;
+        if (c > 0) {
+          tb[c - 1] += o.t0;
+          lb[c - 1] += o.l0;
+          d1b[c - 1] += o.d1a;
+          d2b[c - 1] += o.d2a;
+        } else {
+          tpb += o.t0;
+          lpb += o.l0;
+          d1pb += o.d1a;
+          d2pb += o.d2a;
+        }
+        tb[c] += o.t1;
+        lb[c] += o.l1;
+        d1b[c] += o.d1b;
+        d2b[c] += o.d2b;
+      }
+    }
+    if (!(flags & FLAG_INEXT)) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (evalid(c)) {
+          V3<T> Fq = (c < C - 1) ? Fb[c + 1] : Fn;
+          V3<T> qb = Fb[c] - Fq;
+          T fs = ks[c] * (r.ell[c] / rest[c] - T(1));
+          tb[c] += fs * qb;
+          lb[c] += ks[c] * dot(qb, r.t[c]) / rest[c];
+        }
+      }
+    }
+    {
+      T s[12] = {tpb.x, tpb.y, tpb.z, lpb, d1pb.x, d1pb.y, d1pb.z, d2pb.x, d2pb.y, d2pb.z, T(0), T(0)};
+      X.next(s);
+      tb[C - 1] += mk(s[0], s[1], s[2]);
+      lb[C - 1] += s[3];
+      d1b[C - 1] += mk(s[4], s[5], s[6]);
+      d2b[C - 1] += mk(s[7], s[8], s[9]);
+    }
+    // d2 = t x d1
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (evalid(c)) {
+        tb[c] += cross(r.d1[c], d2b[c]);
+        d1b[c] += cross(d2b[c], r.t[c]);
+      } else {
+        d1b[c] = zero3<T>();
+      }
+    }
+    edges_vjp(X, r.t, r.ell, tb, lb, xb);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      lx[c] = vvalid(c) ? xb[c] : zero3<T>();
+      ld1[c] = d1b[c];
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+template <typename T, int W>
+__device__ __forceinline__ size_t xchg_bytes() { return W > 1 ? 2 * W * XK * sizeof(T) : 0; }
+
+// Forward: n_steps steps of every rod of the work list, the rod resident in
+// registers the whole time.  TAPE: store every substep-start state.
+template <typename T, int C, int W, bool TAPE>
+__global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Team<T, W> X;
+  X.init(reinterpret_cast<T*>(smem));
+  Rod<T, C, W> R;
+  R.load_static(a, X);
+  R.load_state(a.x, a.v, a.kb, a.d1);
+  T* tape_rod = TAPE ? a.tape + a.tape_off[R.rod] : nullptr;
+  for (int s = 0; s < a.n_steps; ++s) {
+    V3<T> ug[C];
+    R.load_actions(a, (a.step_off + s) / a.spa, ug);
+    for (int k = 0; k < a.n_sub; ++k) {
+      if constexpr (TAPE) R.store_tape(tape_rod + (int64_t)(s * a.n_sub + k) * a.tape_stride);
+      R.template substep<false>(a, X, ug, nullptr, nullptr);
+    }
+  }
+  R.store_state(a.x, a.v, a.kb, a.d1);
+  if (a.ck_x) R.store_state(a.ck_x, a.ck_v, a.ck_kb, a.ck_d1);
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    T s = dot(R.x[c], R.x[c]) + dot(R.v[c], R.v[c]);
+    bad |= !(s == s) || s > T(1e30);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(a.status + R.rod, 1);
+}
+
+// Adjoint over the launch's steps, last to first, from the substep tape.
+template <typename T, int C, int W>
+__global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Team<T, W> X;
+  X.init(reinterpret_cast<T*>(smem));
+  T* lds_tape = reinterpret_cast<T*>(smem + xchg_bytes<T, W>());
+  Rod<T, C, W> R;
+  R.load_static(a, X);
+  V3<T> lx[C], lv[C], ld1[C], uacc[C];
+  T lk0[C], lk1[C];
+  double accb[C], accs[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    int g = R.gi(c), row = R.v0 + g;
+    bool vv = g < R.N;
+    lx[c] = vv ? get3(a.lx, 3 * row) : zero3<T>();
+    lv[c] = vv ? get3(a.lv, 3 * row) : zero3<T>();
+    lk0[c] = R.ivalid(c) ? a.lkb[2 * row] : T(0);
+    lk1[c] = R.ivalid(c) ? a.lkb[2 * row + 1] : T(0);
+    ld1[c] = R.evalid(c) ? get3(a.ld1, 3 * row) : zero3<T>();
+    accb[c] = 0.0;
+    accs[c] = 0.0;
+    uacc[c] = zero3<T>();
+  }
+  const T* tape_rod = a.tape + a.tape_off[R.rod];
+  Rec<T, C> rec;
+  for (int s = a.n_steps - 1; s >= 0; --s) {
+    const int act = (a.step_off + s) / a.spa;
+    V3<T> ug[C];
+    R.load_actions(a, act, ug);
+    for (int k = a.n_sub - 1; k >= 0; --k) {
+      R.load_tape(tape_rod + (int64_t)(s * a.n_sub + k) * a.tape_stride);
+      R.template substep<true>(a, X, ug, &rec, lds_tape);
+      R.substep_vjp(a, X, rec, lds_tape, lx, lv, lk0, lk1, ld1, accb, accs, uacc);
+    }
+    // grasp-velocity gradient of this step's action
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (R.gs[c] >= 0) {
+        T* o = a.dL_du + (int64_t)act * a.act_stride + (int64_t)(R.rod * a.G + R.gs[c]) * 3;
+        o[0] += uacc[c].x;
+        o[1] += uacc[c].y;
+        o[2] += uacc[c].z;
+        uacc[c] = zero3<T>();
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    int g = R.gi(c), row = R.v0 + g;
+    if (g < R.N) {
+      put3(a.lx, 3 * row, lx[c]);
+      put3(a.lv, 3 * row, lv[c]);
+      a.lkb[2 * row] = lk0[c];
+      a.lkb[2 * row + 1] = lk1[c];
+      put3(a.ld1, 3 * row, ld1[c]);
+      a.acc_b[row] += accb[c];
+      a.acc_s[row] += accs[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+
+// Initial-frame rule, one thread per rod walking its edges.
+template <typename T>
+__global__ void k_init_frames(const int32_t* voff, int R, const T* x, T* d1) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  int v0 = voff[r], N = voff[r + 1] - v0;
+  V3<T> e = get3(x, 3 * (v0 + 1)) - get3(x, 3 * v0);
+  V3<T> t = (T(1) / sqrt(dot(e, e))) * e;
+  V3<T> az = mk(T(0), T(0), T(1));
+  V3<T> c = cross(t, az);
+  V3<T> av = sqrt(dot(c, c)) < T(1e-6) ? mk(T(1), T(0), T(0)) : az;
+  V3<T> d = av - dot(av, t) * t;
+  d = (T(1) / sqrt(dot(d, d))) * d;
+  put3(d1, 3 * v0, d);
+  for (int j = 1; j < N - 1; ++j) {
+    V3<T> en = get3(x, 3 * (v0 + j + 1)) - get3(x, 3 * (v0 + j));
+    V3<T> tn = (T(1) / sqrt(dot(en, en))) * en;
+    d = transport(d, t, tn);
+    put3(d1, 3 * (v0 + j), d);
+    t = tn;
+  }
+  put3(d1, 3 * (v0 + N - 1), zero3<T>());
+}
+
+// Material curvature of a shape at every interior vertex.
+template <typename T>
+__global__ void k_curvature(const int32_t* voff, const int32_t* rod_of, int V, const T* x,
+                            const T* d1, T* kappa) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V) return;
+  int r = rod_of[i];
+  int v0 = voff[r], N = voff[r + 1] - v0, j = i - v0;
+  T k1 = T(0), k2 = T(0);
+  if (j >= 1 && j <= N - 2) {
+    V3<T> e0 = get3(x, 3 * i) - get3(x, 3 * (i - 1));
+    V3<T> e1 = get3(x, 3 * (i + 1)) - get3(x, 3 * i);
+    V3<T> t0 = (T(1) / sqrt(dot(e0, e0))) * e0, t1 = (T(1) / sqrt(dot(e1, e1))) * e1;
+    curvature(t0, t1, get3(d1, 3 * (i - 1)), get3(d1, 3 * i), k1, k2);
+  }
+  kappa[2 * i] = k1;
+  kappa[2 * i + 1] = k2;
+}
+
+// per-rod part of the MSE loss and dL/dx
+template <typename T>
+__global__ void k_loss(const int32_t* voff, int R, const T* x, const T* tgt, double* part,
+                       T* dldx) {
+  int r = blockIdx.x;
+  int v0 = voff[r], N = voff[r + 1] - v0;
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    V3<T> d = get3(x, 3 * (v0 + j)) - get3(tgt, 3 * (v0 + j));
+    s += (double)dot(d, d);
+    if (dldx) put3(dldx, 3 * (v0 + j), (T(2) / (T(R) * T(N))) * d);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[r] = red[0] / ((double)R * N);
+}
+
+// fixed-order sum of the per-rod loss parts (one thread)
+template <typename T>
+__global__ void k_loss_sum(const double* part, int R, T* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int r = 0; r < R; ++r) s += part[r];
+  out[0] = (T)s;
+}
+
+// per-rod fixed-order sum of per-vertex parameter partials
+template <typename T>
+__global__ void k_reduce_params(const int32_t* voff, int R, const double* acc_b,
+                                const double* acc_s, T* db, T* ds) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double sb = 0.0, ss = 0.0;
+  for (int i = voff[r]; i < voff[r + 1]; ++i) {
+    sb += acc_b[i];
+    ss += acc_s[i];
+  }
+  if (db) db[r] = (T)sb;
+  if (ds) ds[r] = (T)ss;
+}
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+
+template <typename T>
+__global__ void k_copy(T* dst, const T* src, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_selftest_exchange(int* out) {
+  int l = threadIdx.x;
+  int nx = dpp_from_next_i(l + 1) - 1;
+  int pv = dpp_from_prev_i(l + 1) - 1;
+  out[l] = nx;
+  out[64 + l] = pv;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+
+template <typename T, int C, int W>
+static size_t adj_lds(int n_iters) {
+  return (W > 1 ? 2 * W * XK * sizeof(T) : 0) + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
+}
+
+template <typename T, int C, int W>
+static hipError_t launch_shape(int which, const RodArgs<T>& a, int n_blocks, hipStream_t st) {
+  size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
+  if (which == 0)
+    hipLaunchKernelGGL((k_forward<T, C, W, false>), dim3(n_blocks), dim3(64 * W), xb, st, a);
+  else if (which == 1)
+    hipLaunchKernelGGL((k_forward<T, C, W, true>), dim3(n_blocks), dim3(64 * W), xb, st, a);
+  else {
+    size_t lds = adj_lds<T, C, W>(a.n_iters);
+    hipLaunchKernelGGL((k_adjoint<T, C, W>), dim3(n_blocks), dim3(64 * W), lds, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rods(int which, int C, int W, const RodArgs<T>& a, int n_blocks,
+                       hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+#define RODS_SHAPE(CC, WW) \
+  if (C == CC && W == WW) return launch_shape<T, CC, WW>(which, a, n_blocks, st);
+  RODS_SHAPE(2, 1)
+  RODS_SHAPE(2, 2)
+  RODS_SHAPE(2, 4)
+  RODS_SHAPE(2, 8)
+  RODS_SHAPE(4, 1)
+  RODS_SHAPE(4, 2)
+  RODS_SHAPE(4, 4)
+  RODS_SHAPE(4, 8)
+#undef RODS_SHAPE
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+size_t adjoint_lds_bytes(int C, int W, int n_iters) {
+  return (W > 1 ? 2 * W * XK * sizeof(T) : 0) + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
+}
+
+template <typename T>
+hipError_t launch_init_frames(const int32_t* voff, int R, const T* x, T* d1, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_frames<T>, dim3((R + 63) / 64), dim3(64), 0, st, voff, R, x, d1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_curvature(const int32_t* voff, const int32_t* rod_of, int V, const T* x,
+                            const T* d1, T* kappa, hipStream_t st) {
+  hipLaunchKernelGGL(k_curvature<T>, dim3((V + 255) / 256), dim3(256), 0, st, voff, rod_of, V, x,
+                     d1, kappa);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_loss(const int32_t* voff, int R, const T* x, const T* tgt, double* part,
+                       T* loss, T* dldx, hipStream_t st) {
+  hipLaunchKernelGGL(k_loss<T>, dim3(R), dim3(256), 0, st, voff, R, x, tgt, part, dldx);
+  if (loss) hipLaunchKernelGGL(k_loss_sum<T>, dim3(1), dim3(64), 0, st, part, R, loss);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reduce_params(const int32_t* voff, int R, const double* ab, const double* as,
+                                T* db, T* ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_params<T>, dim3((R + 63) / 64), dim3(64), 0, st, voff, R, ab, as,
+                     db, ds);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T val, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, val);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_selftest_exchange(int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_selftest_exchange, dim3(1), dim3(64), 0, st, out);
+  return hipGetLastError();
+}
+
+#define RODS_INST(T)                                                                          \
+  template hipError_t launch_rods<T>(int, int, int, const RodArgs<T>&, int, hipStream_t);     \
+  template size_t adjoint_lds_bytes<T>(int, int, int);                                         \
+  template hipError_t launch_init_frames<T>(const int32_t*, int, const T*, T*, hipStream_t);  \
+  template hipError_t launch_curvature<T>(const int32_t*, const int32_t*, int, const T*,      \
+                                          const T*, T*, hipStream_t);                         \
+  template hipError_t launch_loss<T>(const int32_t*, int, const T*, const T*, double*, T*, T*, \
+                                     hipStream_t);                                            \
+  template hipError_t launch_reduce_params<T>(const int32_t*, int, const double*,             \
+                                              const double*, T*, T*, hipStream_t);            \
+  template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                             \
+  template hipError_t launch_copy<T>(T*, const T*, int64_t, hipStream_t);
+RODS_INST(float)
+RODS_INST(double)
+template hipError_t launch_fill<int32_t>(int32_t*, int64_t, int32_t, hipStream_t);
+
+}  // namespace rods

@@ -1,0 +1,32 @@
+// Host-callable launchers of the rod kernels (defined in rod_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "rod_device.h"
+
+namespace rods {
+
+// which: 0 = forward, 1 = forward writing the substep tape, 2 = adjoint
+template <typename T>
+hipError_t launch_rods(int which, int C, int W, const RodArgs<T>& a, int n_blocks,
+                       hipStream_t st);
+template <typename T>
+size_t adjoint_lds_bytes(int C, int W, int n_iters);
+template <typename T>
+hipError_t launch_init_frames(const int32_t* voff, int R, const T* x, T* d1, hipStream_t st);
+template <typename T>
+hipError_t launch_curvature(const int32_t* voff, const int32_t* rod_of, int V, const T* x,
+                            const T* d1, T* kappa, hipStream_t st);
+template <typename T>
+hipError_t launch_loss(const int32_t* voff, int R, const T* x, const T* tgt, double* part,
+                       T* loss, T* dldx, hipStream_t st);
+template <typename T>
+hipError_t launch_reduce_params(const int32_t* voff, int R, const double* ab, const double* as,
+                                T* db, T* ds, hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T val, hipStream_t st);
+template <typename T>
+hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t st);
+hipError_t launch_selftest_exchange(int* out, hipStream_t st);
+
+}  // namespace rods

@@ -1,0 +1,692 @@
+// C ABI of the batched rod simulator: validation, device allocation (all of
+// it in rods_create), size bins and work lists, and the drivers of the
+// rollout (segment checkpoints) and of the checkpointed backward pass.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "rods.h"
+#include "rod_launch.h"
+
+using rods::RodArgs;
+
+namespace {
+
+constexpr int NF = 11;   // values per vertex of a full state (x 3, v 3, kappa_bar 2, d1 3)
+
+struct Bin {
+  int C, W;       // vertices per lane, waves per rod
+  int n, off;     // rods bin_rods[off .. off+n)
+};
+
+// legal launch shapes for a rod of n vertices, smallest team first
+static std::vector<std::pair<int, int>> shapes_for(int n, int prec) {
+  std::vector<std::pair<int, int>> out;
+  const int Cs[2] = {2, 4};
+  const int Ws[4] = {1, 2, 4, 8};
+  for (int C : Cs) {
+    if (prec == 8 && C != 2) continue;
+    for (int W : Ws) {
+      if (64 * W * C >= n) {
+        out.push_back({C, W});
+        break;
+      }
+    }
+  }
+  return out;
+}
+
+struct HandleBase {
+  virtual ~HandleBase() {}
+};
+
+#define HIPCHK(expr)                        \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return (int)ROD_EHIP; \
+  } while (0)
+
+template <typename T>
+struct Impl : HandleBase {
+  int R = 0, V = 0, G = 0, P = 0, prec = 4;
+  RodsDesc d{};
+  std::vector<int32_t> voff_h;
+  int n_ck = 0, n_act_max = 0;
+  int device = 0;
+
+  std::vector<void*> allocs;
+  int32_t *voff = nullptr, *rod_of = nullptr, *gslot = nullptr, *flags = nullptr,
+          *prim_off = nullptr, *prim_type = nullptr, *status = nullptr, *bin_rods = nullptr;
+  T *b = nullptr, *sigma = nullptr, *rc = nullptr, *mu = nullptr, *restit = nullptr, *K = nullptr;
+  T *w = nullptr, *rest = nullptr, *radius = nullptr, *prim_a = nullptr, *prim_b = nullptr,
+    *prim_r = nullptr;
+  T *x = nullptr, *v = nullptr, *kb = nullptr, *d1 = nullptr;
+  T *sx = nullptr, *sv = nullptr, *skb = nullptr, *sd1 = nullptr;
+  T* ck = nullptr;          // [n_ck][V*NF]
+  T* acts = nullptr;        // recorded actions [n_act_max][R][G][3]
+  T* du_scratch = nullptr;  // dL/du when the caller does not want it
+  T* tape = nullptr;
+  int64_t tape_stride = 0, tape_cap = 0;
+  int64_t* tape_off = nullptr;
+  T *lx = nullptr, *lv = nullptr, *lkb = nullptr, *ld1 = nullptr;
+  double *acc_b = nullptr, *acc_s = nullptr, *loss_part = nullptr;
+  std::vector<Bin> bins;
+  std::vector<int32_t> bin_rods_h;
+  bool recorded = false;
+  int n_rec = 0;
+  int plain = 0;
+
+  ~Impl() override {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+
+  template <typename U>
+  int alloc(U*& p, size_t n) {
+    void* q = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&q, n * sizeof(U)) != hipSuccess) return ROD_ENOMEM;
+    allocs.push_back(q);
+    p = static_cast<U*>(q);
+    return ROD_OK;
+  }
+  template <typename U>
+  int upload(U*& p, const std::vector<U>& h) {
+    int rc_ = alloc(p, h.size());
+    if (rc_) return rc_;
+    if (!h.empty()) HIPCHK(hipMemcpy(p, h.data(), h.size() * sizeof(U), hipMemcpyHostToDevice));
+    return ROD_OK;
+  }
+
+  T* ck_x(int k) const { return ck + (size_t)k * V * NF; }
+  T* ck_v(int k) const { return ck_x(k) + (size_t)V * 3; }
+  T* ck_kb(int k) const { return ck_x(k) + (size_t)V * 6; }
+  T* ck_d1(int k) const { return ck_x(k) + (size_t)V * 8; }
+
+  int create(const RodsDesc* dd) {
+    d = *dd;
+    R = d.n_rods;
+    G = d.n_grasp;
+    prec = d.precision;
+    HIPCHK(hipGetDevice(&device));
+    voff_h.assign(d.vert_offsets, d.vert_offsets + R + 1);
+    V = voff_h[R];
+    P = d.prim_offsets ? d.prim_offsets[R] : 0;
+    // ---- per-vertex statics
+    std::vector<T> w_h(V), rest_h(V), rad_h(V);
+    std::vector<int32_t> gslot_h(V, -1), rod_of_h(V);
+    for (int r = 0; r < R; ++r) {
+      for (int i = voff_h[r]; i < voff_h[r + 1]; ++i) {
+        rod_of_h[i] = r;
+        w_h[i] = (T)d.inv_mass[i];
+        rad_h[i] = (T)d.radius[i];
+        rest_h[i] = (i < voff_h[r + 1] - 1) ? (T)d.rest_len[i] : T(0);
+      }
+      for (int g = 0; g < G; ++g) {
+        int li = d.grasp_idx[r * G + g];
+        if (li >= 0) {
+          gslot_h[voff_h[r] + li] = g;
+          w_h[voff_h[r] + li] = T(0);   // grasped vertices are kinematic
+        }
+      }
+    }
+    // ---- per-rod parameters
+    std::vector<T> b_h(R), s_h(R), rc_h(R), mu_h(R), e_h(R), K_h(R);
+    std::vector<int32_t> fl_h(R);
+    for (int r = 0; r < R; ++r) {
+      const double* p = d.rod_params + (size_t)r * ROD_NPARAM;
+      fl_h[r] = (int32_t)p[ROD_P_FLAGS];
+      K_h[r] = (T)p[ROD_P_K];
+      b_h[r] = (T)p[ROD_P_B];
+      s_h[r] = (T)p[ROD_P_SIGMA];
+      rc_h[r] = (T)p[ROD_P_RC];
+      mu_h[r] = (T)p[ROD_P_MU];
+      e_h[r] = (T)p[ROD_P_REST];
+    }
+    // ---- primitives
+    std::vector<int32_t> pt_h(P), po_h(R + 1, 0);
+    std::vector<T> pa_h(3 * (size_t)P), pb_h(3 * (size_t)P), pr_h(P);
+    if (d.prim_offsets) po_h.assign(d.prim_offsets, d.prim_offsets + R + 1);
+    for (int k = 0; k < P; ++k) {
+      pt_h[k] = d.prims[k].type;
+      for (int c = 0; c < 3; ++c) {
+        pa_h[3 * k + c] = (T)d.prims[k].a[c];
+        pb_h[3 * k + c] = (T)d.prims[k].b[c];
+      }
+      pr_h[k] = (T)d.prims[k].radius;
+    }
+    // ---- size bins: smallest legal team per rod, largest rods first
+    std::vector<std::vector<int>> members;
+    std::vector<std::pair<int, int>> keys;
+    for (int r = 0; r < R; ++r) {
+      auto sh = shapes_for(voff_h[r + 1] - voff_h[r], prec);
+      if (sh.empty()) return ROD_EINVAL;
+      auto key = sh.front();
+      size_t k = 0;
+      while (k < keys.size() && keys[k] != key) ++k;
+      if (k == keys.size()) {
+        keys.push_back(key);
+        members.emplace_back();
+      }
+      members[k].push_back(r);
+    }
+    int64_t off = 0;
+    std::vector<int64_t> toff_h(R, 0);
+    for (size_t k = 0; k < keys.size(); ++k) {
+      auto& m = members[k];
+      std::stable_sort(m.begin(), m.end(), [&](int a, int b2) {
+        return (voff_h[a + 1] - voff_h[a]) > (voff_h[b2 + 1] - voff_h[b2]);
+      });
+      Bin bn{keys[k].first, keys[k].second, (int)m.size(), (int)bin_rods_h.size()};
+      bins.push_back(bn);
+      for (int r : m) {
+        bin_rods_h.push_back(r);
+        toff_h[r] = off;
+        off += (int64_t)NF * bn.C * 64 * bn.W;
+      }
+    }
+    tape_stride = off;
+    tape_cap = 2 * off;   // autotuned teams are at most twice the smallest legal one
+    n_ck = std::max(1, (d.max_steps + d.ckpt_every - 1) / d.ckpt_every);
+    n_act_max = std::max(1, (d.max_steps + d.steps_per_action - 1) / d.steps_per_action);
+
+    int e;
+    if ((e = upload(voff, voff_h)) || (e = upload(rod_of, rod_of_h)) || (e = upload(gslot, gslot_h)) ||
+        (e = upload(flags, fl_h)) || (e = upload(prim_off, po_h)) || (e = upload(prim_type, pt_h)) ||
+        (e = upload(b, b_h)) || (e = upload(sigma, s_h)) || (e = upload(rc, rc_h)) ||
+        (e = upload(mu, mu_h)) || (e = upload(restit, e_h)) || (e = upload(K, K_h)) ||
+        (e = upload(w, w_h)) || (e = upload(rest, rest_h)) || (e = upload(radius, rad_h)) ||
+        (e = upload(prim_a, pa_h)) || (e = upload(prim_b, pb_h)) || (e = upload(prim_r, pr_h)) ||
+        (e = upload(bin_rods, bin_rods_h)) || (e = upload(tape_off, toff_h)))
+      return e;
+    if ((e = alloc(x, 3 * (size_t)V)) || (e = alloc(v, 3 * (size_t)V)) ||
+        (e = alloc(kb, 2 * (size_t)V)) || (e = alloc(d1, 3 * (size_t)V)) ||
+        (e = alloc(sx, 3 * (size_t)V)) || (e = alloc(sv, 3 * (size_t)V)) ||
+        (e = alloc(skb, 2 * (size_t)V)) || (e = alloc(sd1, 3 * (size_t)V)) ||
+        (e = alloc(lx, 3 * (size_t)V)) || (e = alloc(lv, 3 * (size_t)V)) ||
+        (e = alloc(lkb, 2 * (size_t)V)) || (e = alloc(ld1, 3 * (size_t)V)) ||
+        (e = alloc(acc_b, (size_t)V)) || (e = alloc(acc_s, (size_t)V)) ||
+        (e = alloc(loss_part, (size_t)R)) || (e = alloc(status, (size_t)R)) ||
+        (e = alloc(ck, (size_t)n_ck * V * NF)) ||
+        (e = alloc(acts, (size_t)n_act_max * R * G * 3)) ||
+        (e = alloc(du_scratch, (size_t)n_act_max * R * G * 3)) ||
+        (e = alloc(tape, (size_t)std::min(d.ckpt_every, std::max(1, d.max_steps)) * d.n_sub * (size_t)tape_cap)))
+      return e;
+    HIPCHK(hipMemset(x, 0, 3 * sizeof(T) * V));
+    HIPCHK(hipMemset(v, 0, 3 * sizeof(T) * V));
+    HIPCHK(hipMemset(kb, 0, 2 * sizeof(T) * V));
+    HIPCHK(hipMemset(d1, 0, 3 * sizeof(T) * V));
+    HIPCHK(hipMemset(status, 0, sizeof(int32_t) * R));
+    HIPCHK(hipDeviceSynchronize());
+    return ROD_OK;
+  }
+
+  RodArgs<T> args(hipStream_t) const {
+    RodArgs<T> a{};
+    a.voff = voff;
+    a.tape_off = tape_off;
+    a.b = b; a.sigma = sigma; a.rc = rc; a.mu = mu; a.restit = restit; a.K = K;
+    a.flags = flags;
+    a.w = w; a.rest = rest; a.radius = radius; a.gslot = gslot;
+    a.prim_off = prim_off; a.prim_type = prim_type; a.prim_a = prim_a; a.prim_b = prim_b;
+    a.prim_r = prim_r;
+    a.x = x; a.v = v; a.kb = kb; a.d1 = d1;
+    a.tape_stride = tape_stride;
+    a.act_stride = (int64_t)R * G * 3;
+    a.G = G;
+    a.spa = d.steps_per_action;
+    a.lx = lx; a.lv = lv; a.lkb = lkb; a.ld1 = ld1;
+    a.acc_b = acc_b; a.acc_s = acc_s;
+    a.status = status;
+    a.h = (T)(d.dt / d.n_sub);
+    a.gx = (T)d.gravity[0]; a.gy = (T)d.gravity[1]; a.gz = (T)d.gravity[2];
+    a.eps_s = (T)d.eps_s; a.f_thresh = (T)d.f_thresh; a.self_margin = (T)d.self_margin;
+    a.n_sub = d.n_sub; a.n_iters = d.n_iters; a.k_ex = d.k_exclude;
+    return a;
+  }
+
+  // launch `which` for every bin (batched) or per rod (plain) over n_steps
+  int launch_all(int which, RodArgs<T> a, hipStream_t st) {
+    if (!plain) {
+      for (const Bin& bn : bins) {
+        a.rods = bin_rods + bn.off;
+        HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, a, bn.n, st));
+      }
+      return ROD_OK;
+    }
+    // plain path: one rod per launch, one step per launch
+    const int n_steps = a.n_steps;
+    const int step_off = a.step_off;
+    T* tape0 = a.tape;
+    for (const Bin& bn : bins) {
+      for (int i = 0; i < bn.n; ++i) {
+        RodArgs<T> b1 = a;
+        b1.rods = bin_rods + bn.off + i;
+        b1.n_steps = 1;
+        for (int s0 = 0; s0 < n_steps; ++s0) {
+          int s = (which == 2) ? (n_steps - 1 - s0) : s0;
+          b1.step_off = step_off + s;
+          if (tape0) b1.tape = tape0 + (int64_t)s * d.n_sub * tape_stride;
+          b1.ck_x = (s == n_steps - 1) ? a.ck_x : nullptr;
+          HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, b1, 1, st));
+        }
+      }
+    }
+    return ROD_OK;
+  }
+
+  int set_state(const T* x_, const T* v_, const T* kb_, const T* d1_, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(x, x_, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(v, v_, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    if (kb_) HIPCHK(hipMemcpyAsync(kb, kb_, sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(rods::launch_fill<T>(kb, 2 * (int64_t)V, T(0), st));
+    if (d1_) HIPCHK(hipMemcpyAsync(d1, d1_, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(rods::launch_init_frames<T>(voff, R, x, d1, st));
+    HIPCHK(rods::launch_fill<int32_t>(status, R, 0, st));
+    recorded = false;
+    return ROD_OK;
+  }
+
+  int rollout(int n_steps, const T* u, T* x_final, int record, hipStream_t st) {
+    if (n_steps < 0) return ROD_EINVAL;
+    if (record && n_steps > d.max_steps) return ROD_ESTATE;
+    recorded = false;
+    if (n_steps == 0) return ROD_OK;
+    const int spa = d.steps_per_action;
+    const int n_act = (n_steps + spa - 1) / spa;
+    RodArgs<T> a = args(st);
+    if (record) {
+      if (G > 0)
+        HIPCHK(hipMemcpyAsync(acts, u, sizeof(T) * (size_t)n_act * R * G * 3,
+                              hipMemcpyDeviceToDevice, st));
+      a.u = acts;
+      const int Kc = d.ckpt_every;
+      const int nseg = (n_steps + Kc - 1) / Kc;
+      HIPCHK(hipMemcpyAsync(ck_x(0), x, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(ck_v(0), v, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(ck_kb(0), kb, sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(ck_d1(0), d1, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+      for (int seg = 0; seg < nseg; ++seg) {
+        a.step_off = seg * Kc;
+        a.n_steps = std::min(Kc, n_steps - seg * Kc);
+        if (seg + 1 < nseg) {
+          a.ck_x = ck_x(seg + 1); a.ck_v = ck_v(seg + 1); a.ck_kb = ck_kb(seg + 1);
+          a.ck_d1 = ck_d1(seg + 1);
+        } else {
+          a.ck_x = a.ck_v = a.ck_kb = a.ck_d1 = nullptr;
+        }
+        int e = launch_all(0, a, st);
+        if (e) return e;
+      }
+      recorded = true;
+      n_rec = n_steps;
+    } else {
+      a.u = u;
+      a.step_off = 0;
+      a.n_steps = n_steps;
+      int e = launch_all(0, a, st);
+      if (e) return e;
+    }
+    if (x_final) HIPCHK(hipMemcpyAsync(x_final, x, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    return ROD_OK;
+  }
+
+  int step(const T* u, hipStream_t st) {
+    RodArgs<T> a = args(st);
+    a.u = u;
+    a.act_stride = 0;
+    a.spa = 1;
+    a.step_off = 0;
+    a.n_steps = 1;
+    recorded = false;
+    return launch_all(0, a, st);
+  }
+
+  int backward(const T* gxT, const T* gvT, T* du, T* db_, T* ds_, T* gx0, T* gv0,
+               hipStream_t st) {
+    if (!recorded) return ROD_ESTATE;
+    const int n = n_rec, Kc = d.ckpt_every, nseg = (n + Kc - 1) / Kc;
+    const int spa = d.steps_per_action;
+    const int n_act = (n + spa - 1) / spa;
+    T* dU = du ? du : du_scratch;
+    HIPCHK(hipMemcpyAsync(lx, gxT, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    if (gvT) HIPCHK(hipMemcpyAsync(lv, gvT, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(rods::launch_fill<T>(lv, 3 * (int64_t)V, T(0), st));
+    HIPCHK(rods::launch_fill<T>(lkb, 2 * (int64_t)V, T(0), st));
+    HIPCHK(rods::launch_fill<T>(ld1, 3 * (int64_t)V, T(0), st));
+    HIPCHK(rods::launch_fill<T>(dU, (int64_t)n_act * R * G * 3, T(0), st));
+    HIPCHK(rods::launch_fill<double>(acc_b, V, 0.0, st));
+    HIPCHK(rods::launch_fill<double>(acc_s, V, 0.0, st));
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+      const int s0 = seg * Kc, ns = std::min(Kc, n - s0);
+      HIPCHK(hipMemcpyAsync(sx, ck_x(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(sv, ck_v(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(skb, ck_kb(seg), sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(sd1, ck_d1(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+      RodArgs<T> a = args(st);
+      a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;
+      a.u = acts;
+      a.step_off = s0;
+      a.n_steps = ns;
+      a.tape = tape;
+      int e = launch_all(1, a, st);
+      if (e) return e;
+      a.dL_du = dU;
+      e = launch_all(2, a, st);
+      if (e) return e;
+    }
+    if (db_ || ds_) HIPCHK(rods::launch_reduce_params<T>(voff, R, acc_b, acc_s, db_, ds_, st));
+    if (gx0) HIPCHK(hipMemcpyAsync(gx0, lx, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    if (gv0) HIPCHK(hipMemcpyAsync(gv0, lv, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    return ROD_OK;
+  }
+
+  int autotune(int n_steps, hipStream_t st) {
+    // save state
+    HIPCHK(hipMemcpyAsync(sx, x, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(sv, v, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(skb, kb, sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(sd1, d1, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    std::vector<T> zeros((size_t)std::max(1, R * G * 3), T(0));
+    T* u0 = du_scratch;
+    HIPCHK(hipMemcpyAsync(u0, zeros.data(), sizeof(T) * zeros.size(), hipMemcpyHostToDevice, st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (Bin& bn : bins) {
+      int nmax = 0;
+      for (int i = 0; i < bn.n; ++i) {
+        int r = bin_rods_h[bn.off + i];
+        nmax = std::max(nmax, voff_h[r + 1] - voff_h[r]);
+      }
+      std::vector<std::pair<int, int>> cand;
+      const int Cs[2] = {2, 4};
+      const int Ws[4] = {1, 2, 4, 8};
+      const int team0 = 64 * bn.C * bn.W;   // smallest legal team of the bin
+      for (int C : Cs)
+        for (int W : Ws)
+          if (64 * W * C >= nmax && 64 * W * C <= 2 * team0 && !(prec == 8 && C != 2) &&
+              !(C == 4 && W == 8))
+            cand.push_back({C, W});
+      float best = 1e30f;
+      std::pair<int, int> bestk{bn.C, bn.W};
+      for (auto cw : cand) {
+        RodArgs<T> a = args(st);
+        a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;   // time on the scratch copy
+        a.u = u0; a.act_stride = 0; a.spa = 1; a.step_off = 0; a.n_steps = n_steps;
+        a.rods = bin_rods + bn.off;
+        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, a, bn.n, st));   // warm
+        HIPCHK(hipEventRecord(e0, st));
+        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, a, bn.n, st));
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; bestk = cw; }
+      }
+      bn.C = bestk.first;
+      bn.W = bestk.second;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // the tape layout depends on the shapes
+    std::vector<int64_t> toff_h(R, 0);
+    int64_t off = 0;
+    for (const Bin& bn : bins)
+      for (int i = 0; i < bn.n; ++i) {
+        toff_h[bin_rods_h[bn.off + i]] = off;
+        off += (int64_t)NF * bn.C * 64 * bn.W;
+      }
+    if (off > tape_cap) return ROD_EINVAL;   // cannot grow after create
+    tape_stride = off;
+    HIPCHK(hipMemcpy(tape_off, toff_h.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice));
+    HIPCHK(hipStreamSynchronize(st));
+    recorded = false;
+    return ROD_OK;
+  }
+};
+
+struct Holder {
+  int prec;
+  HandleBase* impl;
+};
+
+template <typename F>
+int dispatch(RodsHandle* h, F&& f) {
+  if (!h) return ROD_EINVAL;
+  Holder* H = reinterpret_cast<Holder*>(h);
+  if (H->prec == 4) return f(static_cast<Impl<float>*>(H->impl));
+  return f(static_cast<Impl<double>*>(H->impl));
+}
+
+static int validate(const RodsDesc* d) {
+  if (!d || d->n_rods < 1 || d->n_grasp < 0 || !d->vert_offsets || !d->rod_params ||
+      !d->radius || !d->inv_mass || !d->rest_len)
+    return ROD_EINVAL;
+  if (d->precision != 4 && d->precision != 8) return ROD_EDTYPE;
+  if (d->n_grasp > 0 && !d->grasp_idx) return ROD_EINVAL;
+  if (d->vert_offsets[0] != 0) return ROD_EINVAL;
+  for (int r = 0; r < d->n_rods; ++r) {
+    int n = d->vert_offsets[r + 1] - d->vert_offsets[r];
+    if (n < 2 || shapes_for(n, d->precision).empty()) return ROD_EINVAL;
+    for (int g = 0; g < d->n_grasp; ++g) {
+      int li = d->grasp_idx[r * d->n_grasp + g];
+      if (li < -1 || li >= n) return ROD_EINVAL;
+    }
+    int fl = (int)d->rod_params[(size_t)r * ROD_NPARAM + ROD_P_FLAGS];
+    if (fl < 0 || fl > 7) return ROD_EINVAL;
+  }
+  if (d->prim_offsets) {
+    if (d->prim_offsets[0] != 0) return ROD_EINVAL;
+    for (int r = 0; r < d->n_rods; ++r)
+      if (d->prim_offsets[r + 1] < d->prim_offsets[r]) return ROD_EINVAL;
+    int P = d->prim_offsets[d->n_rods];
+    if (P > 0 && !d->prims) return ROD_EINVAL;
+    for (int k = 0; k < P; ++k)
+      if (d->prims[k].type < 0 || d->prims[k].type > 2) return ROD_EINVAL;
+  }
+  if (!(d->dt > 0) || d->n_sub < 1 || d->n_iters < 0 || d->n_iters > 32 ||
+      d->steps_per_action < 1 || d->ckpt_every < 1 || d->max_steps < 0 || !(d->eps_s > 0))
+    return ROD_EINVAL;
+  return ROD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+struct RodsHandle {
+  Holder h;
+};
+
+int rods_create(const RodsDesc* desc, RodsHandle** out) {
+  if (!out) return ROD_EINVAL;
+  *out = nullptr;
+  int e = validate(desc);
+  if (e) return e;
+  RodsHandle* H = new (std::nothrow) RodsHandle;
+  if (!H) return ROD_ENOMEM;
+  H->h.prec = desc->precision;
+  if (desc->precision == 4) {
+    auto* I = new (std::nothrow) Impl<float>();
+    H->h.impl = I;
+    e = I ? I->create(desc) : ROD_ENOMEM;
+  } else {
+    auto* I = new (std::nothrow) Impl<double>();
+    H->h.impl = I;
+    e = I ? I->create(desc) : ROD_ENOMEM;
+  }
+  if (e) {
+    delete H->h.impl;
+    delete H;
+    return e;
+  }
+  *out = H;
+  return ROD_OK;
+}
+
+void rods_destroy(RodsHandle* h) {
+  if (!h) return;
+  delete h->h.impl;
+  delete h;
+}
+
+const char* rods_strerror(int code) {
+  switch (code) {
+    case ROD_OK: return "ok";
+    case ROD_EINVAL: return "invalid argument";
+    case ROD_ENOMEM: return "device allocation failed";
+    case ROD_EHIP: return "HIP runtime error";
+    case ROD_ESTATE: return "call out of order (no recorded rollout, or n_steps > max_steps)";
+    case ROD_EDTYPE: return "unsupported precision";
+    default: return "unknown error";
+  }
+}
+
+int rods_set_state(RodsHandle* h, const void* x, const void* v, const void* kappa_bar,
+                   const void* d1, rods_stream_t stream) {
+  if (!h || !x || !v) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    return I->set_state((const T*)x, (const T*)v, (const T*)kappa_bar, (const T*)d1,
+                        (hipStream_t)stream);
+  });
+}
+
+int rods_get_state(RodsHandle* h, void* x, void* v, void* kappa_bar, void* d1,
+                   rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    hipStream_t st = (hipStream_t)stream;
+    size_t V = I->V;
+    if (x) HIPCHK(hipMemcpyAsync(x, I->x, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    if (v) HIPCHK(hipMemcpyAsync(v, I->v, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    if (kappa_bar) HIPCHK(hipMemcpyAsync(kappa_bar, I->kb, sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, st));
+    if (d1) HIPCHK(hipMemcpyAsync(d1, I->d1, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    return (int)ROD_OK;
+  });
+}
+
+int rods_set_params(RodsHandle* h, const void* b, const void* sigma_y, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    hipStream_t st = (hipStream_t)stream;
+    if (b) HIPCHK(hipMemcpyAsync(I->b, b, sizeof(T) * I->R, hipMemcpyDeviceToDevice, st));
+    if (sigma_y) HIPCHK(hipMemcpyAsync(I->sigma, sigma_y, sizeof(T) * I->R, hipMemcpyDeviceToDevice, st));
+    I->recorded = false;
+    return (int)ROD_OK;
+  });
+}
+
+int rods_curvature(RodsHandle* h, const void* x, const void* d1, void* kappa,
+                   rods_stream_t stream) {
+  if (!h || !x || !kappa) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    hipStream_t st = (hipStream_t)stream;
+    const T* dd = (const T*)d1;
+    if (!dd) {
+      HIPCHK(rods::launch_init_frames<T>(I->voff, I->R, (const T*)x, I->sd1, st));
+      dd = I->sd1;
+    }
+    HIPCHK(rods::launch_curvature<T>(I->voff, I->rod_of, I->V, (const T*)x, dd, (T*)kappa, st));
+    return (int)ROD_OK;
+  });
+}
+
+int rods_step(RodsHandle* h, const void* grasp_vel, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    if (I->G > 0 && !grasp_vel) return (int)ROD_EINVAL;
+    return I->step((const T*)grasp_vel, (hipStream_t)stream);
+  });
+}
+
+int rods_rollout(RodsHandle* h, int32_t n_steps, const void* grasp_vel, void* x_final,
+                 int32_t record, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    if (I->G > 0 && n_steps > 0 && !grasp_vel) return (int)ROD_EINVAL;
+    return I->rollout(n_steps, (const T*)grasp_vel, (T*)x_final, record, (hipStream_t)stream);
+  });
+}
+
+int rods_backward(RodsHandle* h, const void* dL_dxT, const void* dL_dvT, void* dL_du,
+                  void* dL_db, void* dL_dsigma, void* dL_dx0, void* dL_dv0,
+                  rods_stream_t stream) {
+  if (!h || !dL_dxT) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    return I->backward((const T*)dL_dxT, (const T*)dL_dvT, (T*)dL_du, (T*)dL_db, (T*)dL_dsigma,
+                       (T*)dL_dx0, (T*)dL_dv0, (hipStream_t)stream);
+  });
+}
+
+int rods_loss_mse(RodsHandle* h, const void* x, const void* target, void* loss, void* dL_dx,
+                  rods_stream_t stream) {
+  if (!h || !x || !target) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    HIPCHK(rods::launch_loss<T>(I->voff, I->R, (const T*)x, (const T*)target, I->loss_part,
+                                (T*)loss, (T*)dL_dx, (hipStream_t)stream));
+    return (int)ROD_OK;
+  });
+}
+
+int rods_status(RodsHandle* h, int32_t* flags, rods_stream_t stream) {
+  if (!h || !flags) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    hipStream_t st = (hipStream_t)stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return (int)ROD_EHIP;
+    if (hipMemcpy(flags, I->status, sizeof(int32_t) * I->R, hipMemcpyDeviceToHost) != hipSuccess)
+      return (int)ROD_EHIP;
+    return (int)ROD_OK;
+  });
+}
+
+int rods_bins(RodsHandle* h, int32_t* out, int32_t max_bins) {
+  if (!h || !out) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    int n = 0;
+    for (const Bin& bn : I->bins) {
+      if (n < max_bins) {
+        out[3 * n] = bn.C;
+        out[3 * n + 1] = bn.W;
+        out[3 * n + 2] = bn.n;
+      }
+      ++n;
+    }
+    return n;
+  });
+}
+
+int rods_autotune(RodsHandle* h, int32_t n_steps, rods_stream_t stream) {
+  if (!h || n_steps < 1) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) { return I->autotune(n_steps, (hipStream_t)stream); });
+}
+
+int rods_set_plain(RodsHandle* h, int32_t plain) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    I->plain = plain ? 1 : 0;
+    return (int)ROD_OK;
+  });
+}
+
+int rods_selftest_exchange(void* out, rods_stream_t stream) {
+  if (!out) return ROD_EINVAL;
+  if (rods::launch_selftest_exchange((int*)out, (hipStream_t)stream) != hipSuccess) return ROD_EHIP;
+  return ROD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+"""Python binding of librods (ctypes).  Argument marshalling only: every step
+of the simulation runs in the HIP library; PyTorch supplies device memory and
+the current stream.  Raises if the library has not been built."""
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_void_p
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librods.so")
+
+ROD_NPARAM = 7
+FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF = 1, 2, 4
+ERRORS = {0: "ok", -1: "ROD_EINVAL", -2: "ROD_ENOMEM", -3: "ROD_EHIP", -4: "ROD_ESTATE",
+          -5: "ROD_EDTYPE"}
+
+
+class RodsPrim(ctypes.Structure):
+    _fields_ = [("type", c_int32), ("a", c_double * 3), ("b", c_double * 3), ("radius", c_double)]
+
+
+class RodsDesc(ctypes.Structure):
+    _fields_ = [("n_rods", c_int32), ("n_grasp", c_int32), ("precision", c_int32),
+                ("vert_offsets", POINTER(c_int32)), ("grasp_idx", POINTER(c_int32)),
+                ("rod_params", POINTER(c_double)), ("radius", POINTER(c_double)),
+                ("inv_mass", POINTER(c_double)), ("rest_len", POINTER(c_double)),
+                ("prims", POINTER(RodsPrim)), ("prim_offsets", POINTER(c_int32)),
+                ("dt", c_double), ("gravity", c_double * 3), ("eps_s", c_double),
+                ("f_thresh", c_double), ("self_margin", c_double),
+                ("n_sub", c_int32), ("n_iters", c_int32), ("k_exclude", c_int32),
+                ("steps_per_action", c_int32), ("ckpt_every", c_int32), ("max_steps", c_int32)]
+
+
+EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "rods_get_state",
+           "rods_set_params", "rods_curvature", "rods_step", "rods_rollout", "rods_backward",
+           "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_plain",
+           "rods_selftest_exchange"]
+
+_lib = None
+
+
+class RodsError(RuntimeError):
+    pass
+
+
+def load():
+    """Load librods.so (no GPU needed to load it)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RodsError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = c_void_p
+    sig = {
+        "rods_create": ([POINTER(RodsDesc), POINTER(vp)], c_int32),
+        "rods_destroy": ([vp], None),
+        "rods_strerror": ([c_int32], ctypes.c_char_p),
+        "rods_set_state": ([vp, vp, vp, vp, vp, vp], c_int32),
+        "rods_get_state": ([vp, vp, vp, vp, vp, vp], c_int32),
+        "rods_set_params": ([vp, vp, vp, vp], c_int32),
+        "rods_curvature": ([vp, vp, vp, vp, vp], c_int32),
+        "rods_step": ([vp, vp, vp], c_int32),
+        "rods_rollout": ([vp, c_int32, vp, vp, c_int32, vp], c_int32),
+        "rods_backward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], c_int32),
+        "rods_loss_mse": ([vp, vp, vp, vp, vp, vp], c_int32),
+        "rods_status": ([vp, POINTER(c_int32), vp], c_int32),
+        "rods_bins": ([vp, POINTER(c_int32), c_int32], c_int32),
+        "rods_autotune": ([vp, c_int32, vp], c_int32),
+        "rods_set_plain": ([vp, c_int32], c_int32),
+        "rods_selftest_exchange": ([vp, vp], c_int32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(code, what):
+    if code != 0:
+        raise RodsError(f"{what}: {ERRORS.get(code, code)}")
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require(t, shape, dtype, name):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype and tuple(t.shape) == tuple(shape)):
+        raise RodsError(f"{name}: need a contiguous {dtype} CUDA tensor of shape {tuple(shape)}, "
+                        f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+    return t
+
+
+class RodsHandle:
+    """One librods handle built from a synth.Workload-like description."""
+
+    def __init__(self, wl, precision=4, max_steps=None, ckpt_every=None, n_iters=None,
+                 n_sub=None):
+        lib = load()
+        sim = wl.sim
+        self.R = wl.n_rods
+        self.V = wl.n_vert
+        self.G = wl.n_grasp
+        self.precision = precision
+        self.dtype = torch.float32 if precision == 4 else torch.float64
+        self.spa = sim.steps_per_action
+        self.ckpt_every = ckpt_every or sim.ckpt_every
+        self.max_steps = max_steps if max_steps is not None else sim.steps
+        keep = []
+
+        def arr(a, ct):
+            a = np.ascontiguousarray(a, dtype=np.int32 if ct is c_int32 else np.float64)
+            keep.append(a)
+            return a.ctypes.data_as(POINTER(ct))
+
+        P = len(wl.prim_type)
+        prims = (RodsPrim * max(1, P))()
+        for k in range(P):
+            prims[k].type = int(wl.prim_type[k])
+            prims[k].a[:] = [float(v) for v in wl.prim_a[k]]
+            prims[k].b[:] = [float(v) for v in wl.prim_b[k]]
+            prims[k].radius = float(wl.prim_r[k])
+        d = RodsDesc()
+        d.n_rods, d.n_grasp, d.precision = self.R, self.G, precision
+        d.vert_offsets = arr(wl.vert_offsets, c_int32)
+        d.grasp_idx = arr(wl.grasp_idx.reshape(-1), c_int32) if self.G else None
+        d.rod_params = arr(wl.rod_params.reshape(-1), c_double)
+        d.radius = arr(wl.radius, c_double)
+        d.inv_mass = arr(wl.inv_mass, c_double)
+        d.rest_len = arr(wl.rest_len, c_double)
+        d.prims = prims if P else None
+        d.prim_offsets = arr(wl.prim_offsets, c_int32) if P else None
+        d.dt = sim.dt
+        d.gravity[:] = list(sim.gravity)
+        d.eps_s, d.f_thresh, d.self_margin = sim.eps_s, sim.f_thresh, sim.self_margin
+        d.n_sub = n_sub or sim.n_sub
+        d.n_iters = sim.n_iters if n_iters is None else n_iters
+        d.k_exclude = sim.k_exclude
+        d.steps_per_action = self.spa
+        d.ckpt_every = self.ckpt_every
+        d.max_steps = self.max_steps
+        h = c_void_p()
+        _check(lib.rods_create(ctypes.byref(d), ctypes.byref(h)), "rods_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.rods_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ helpers
+    def tensor(self, *shape):
+        return torch.empty(*shape, dtype=self.dtype, device="cuda")
+
+    def n_actions(self, n_steps):
+        return -(-n_steps // self.spa)
+
+    # ------------------------------------------------------------------ calls
+    def set_state(self, x, v, kappa_bar=None, d1=None):
+        V = self.V
+        _require(x, (V, 3), self.dtype, "x")
+        _require(v, (V, 3), self.dtype, "v")
+        _require(kappa_bar, (V, 2), self.dtype, "kappa_bar")
+        _require(d1, (V, 3), self.dtype, "d1")
+        _check(self._lib.rods_set_state(self._h, _ptr(x), _ptr(v), _ptr(kappa_bar), _ptr(d1),
+                                        _stream()), "rods_set_state")
+
+    def get_state(self):
+        V = self.V
+        x, v, kb, d1 = self.tensor(V, 3), self.tensor(V, 3), self.tensor(V, 2), self.tensor(V, 3)
+        _check(self._lib.rods_get_state(self._h, _ptr(x), _ptr(v), _ptr(kb), _ptr(d1),
+                                        _stream()), "rods_get_state")
+        return x, v, kb, d1
+
+    def set_params(self, b=None, sigma_y=None):
+        _require(b, (self.R,), self.dtype, "b")
+        _require(sigma_y, (self.R,), self.dtype, "sigma_y")
+        _check(self._lib.rods_set_params(self._h, _ptr(b), _ptr(sigma_y), _stream()),
+               "rods_set_params")
+
+    def curvature(self, x, d1=None):
+        _require(x, (self.V, 3), self.dtype, "x")
+        _require(d1, (self.V, 3), self.dtype, "d1")
+        k = self.tensor(self.V, 2)
+        _check(self._lib.rods_curvature(self._h, _ptr(x), _ptr(d1), _ptr(k), _stream()),
+               "rods_curvature")
+        return k
+
+    def step(self, u):
+        _require(u, (self.R, self.G, 3), self.dtype, "grasp_vel")
+        _check(self._lib.rods_step(self._h, _ptr(u), _stream()), "rods_step")
+
+    def rollout(self, n_steps, U, record=False, x_final=None):
+        _require(U, (self.n_actions(n_steps), self.R, self.G, 3), self.dtype, "grasp_vel")
+        _require(x_final, (self.V, 3), self.dtype, "x_final")
+        _check(self._lib.rods_rollout(self._h, int(n_steps), _ptr(U), _ptr(x_final),
+                                      1 if record else 0, _stream()), "rods_rollout")
+        return x_final
+
+    def backward(self, dxT, dvT=None, n_steps=None, want=("u", "b", "sigma", "x0", "v0")):
+        V, R, G = self.V, self.R, self.G
+        _require(dxT, (V, 3), self.dtype, "dL_dxT")
+        _require(dvT, (V, 3), self.dtype, "dL_dvT")
+        out = {}
+        if "u" in want:
+            out["u"] = self.tensor(self.n_actions(n_steps), R, G, 3)
+        for k, shape in (("b", (R,)), ("sigma", (R,)), ("x0", (V, 3)), ("v0", (V, 3))):
+            if k in want:
+                out[k] = self.tensor(*shape)
+        _check(self._lib.rods_backward(self._h, _ptr(dxT), _ptr(dvT), _ptr(out.get("u")),
+                                       _ptr(out.get("b")), _ptr(out.get("sigma")),
+                                       _ptr(out.get("x0")), _ptr(out.get("v0")), _stream()),
+               "rods_backward")
+        return out
+
+    def loss_mse(self, x, target):
+        _require(x, (self.V, 3), self.dtype, "x")
+        _require(target, (self.V, 3), self.dtype, "target")
+        loss, g = self.tensor(1), self.tensor(self.V, 3)
+        _check(self._lib.rods_loss_mse(self._h, _ptr(x), _ptr(target), _ptr(loss), _ptr(g),
+                                       _stream()), "rods_loss_mse")
+        return loss, g
+
+    def status(self):
+        flags = (c_int32 * self.R)()
+        _check(self._lib.rods_status(self._h, flags, _stream()), "rods_status")
+        return np.frombuffer(flags, dtype=np.int32).copy()
+
+    def bins(self):
+        out = (c_int32 * 48)()
+        n = self._lib.rods_bins(self._h, out, 16)
+        if n < 0:
+            _check(n, "rods_bins")
+        return [tuple(out[3 * i:3 * i + 3]) for i in range(min(n, 16))]
+
+    def autotune(self, n_steps=2):
+        _check(self._lib.rods_autotune(self._h, int(n_steps), _stream()), "rods_autotune")
+
+    def set_plain(self, plain=True):
+        _check(self._lib.rods_set_plain(self._h, 1 if plain else 0), "rods_set_plain")
+
+
+def selftest_exchange():
+    out = torch.zeros(2, 64, dtype=torch.int32, device="cuda")
+    _check(load().rods_selftest_exchange(_ptr(out), _stream()), "rods_selftest_exchange")
+    return out.cpu().numpy()
+
+
+class RodsRollout(torch.autograd.Function):
+    """x_T = rollout(x0, v0, U; b, sigma_y) through librods; backward runs the
+    library's checkpointed adjoint.  kappa_bar0 is a fixed input."""
+
+    @staticmethod
+    def forward(ctx, handle, n_steps, x0, v0, U, b, sigma_y, kappa_bar0=None):
+        handle.set_params(b.detach().contiguous(), sigma_y.detach().contiguous())
+        handle.set_state(x0.detach().contiguous(), v0.detach().contiguous(),
+                         None if kappa_bar0 is None else kappa_bar0.detach().contiguous())
+        xT = handle.tensor(handle.V, 3)
+        handle.rollout(n_steps, U.detach().contiguous(), record=True, x_final=xT)
+        ctx.handle = handle
+        ctx.n_steps = n_steps
+        return xT
+
+    @staticmethod
+    def backward(ctx, gx):
+        h = ctx.handle
+        g = h.backward(gx.contiguous(), n_steps=ctx.n_steps)
+        return None, None, g["x0"], g["v0"], g["u"], g["b"], g["sigma"], None

@@ -1,0 +1,64 @@
+"""Helpers shared by the GPU tests: run the library on a workload and run the
+oracle on the same (rounded) inputs."""
+from dataclasses import replace
+
+import numpy as np
+import torch
+
+from synth import make_workload
+from oracle.model import rods_from_workload, sim_from_workload, State
+from oracle.geometry import init_frames
+from paper_2606_04206_amd import RodsHandle
+
+DEV = "cuda"
+
+
+def to_dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def sub_workload(wl):
+    """Same workload with one substep per step (dt = h), for substep-level
+    teacher-forced parity."""
+    sim = replace(wl.sim, dt=wl.sim.dt / wl.sim.n_sub, n_sub=1)
+    return replace(wl, sim=sim)
+
+
+def rows(wl, rods):
+    return np.concatenate([np.arange(*wl.rod_range(r)) for r in rods])
+
+
+def oracle_state_rows(wl, rods, st):
+    """Scatter an oracle State of `rods` (equal sizes) into full-batch rows."""
+    out = []
+    for k, arr in enumerate(st):
+        B, n = arr.shape[:2]
+        if k == 3:   # d1 has N-1 rows per rod -> pad the last vertex row
+            pad = np.zeros((B, n + 1, 3))
+            pad[:, :n] = arr
+            arr = pad
+        out.append(arr.reshape(-1, arr.shape[-1]))
+    return out
+
+
+def gather_state(wl, rods, full):
+    """Full-batch arrays -> oracle State for `rods` (equal sizes)."""
+    n = wl.rod_range(rods[0])[1] - wl.rod_range(rods[0])[0]
+    idx = rows(wl, rods)
+    x, v, kb, d1 = (np.asarray(a, np.float64)[idx].reshape(len(rods), n, -1) for a in full)
+    return State(x, v, kb, d1[:, :-1])
+
+
+def initial_full_state(wl, dtype=np.float64):
+    """Initial full-batch state with frames from the oracle's initial-frame
+    rule and zero rest curvature."""
+    V = wl.n_vert
+    d1 = np.zeros((V, 3))
+    for r in range(wl.n_rods):
+        a, b = wl.rod_range(r)
+        d1[a:b - 1] = init_frames(wl.x0[a:b][None])[0]
+    return [wl.x0.astype(dtype), wl.v0.astype(dtype), np.zeros((V, 2), dtype), d1.astype(dtype)]
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))

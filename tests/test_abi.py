@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every function include/rods.h declares, rejects invalid descriptions before
+touching the device, and the ctypes structs match the C layout."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2606_04206_amd import rods as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "rods.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rods_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = R.load()
+    names = declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(R.EXPORTS) == names
+
+
+def test_struct_layouts(tmp_path):
+    """The ctypes mirrors have the C compiler's sizes and offsets."""
+    prog = tmp_path / "sz.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "rods.h"\n'
+                    'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(RodsDesc), '
+                    'sizeof(RodsPrim), offsetof(RodsDesc, dt), offsetof(RodsDesc, n_sub), '
+                    'offsetof(RodsDesc, max_steps)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    c = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                        check=True).stdout.split()]
+    py = [ctypes.sizeof(R.RodsDesc), ctypes.sizeof(R.RodsPrim), R.RodsDesc.dt.offset,
+          R.RodsDesc.n_sub.offset, R.RodsDesc.max_steps.offset]
+    assert c == py
+
+
+def test_strerror_and_invalid_descriptions():
+    lib = R.load()
+    assert lib.rods_strerror(-4).startswith(b"call out of order")
+    h = ctypes.c_void_p()
+    d = R.RodsDesc()
+    assert lib.rods_create(None, ctypes.byref(h)) == -1
+    assert lib.rods_create(ctypes.byref(d), ctypes.byref(h)) == -1   # n_rods = 0
+    offs = np.array([0, 1], np.int32)      # a 1-vertex rod is invalid
+    params = np.zeros(7)
+    vals = np.ones(1)
+    d.n_rods, d.precision = 1, 4
+    d.vert_offsets = offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.rod_params = params.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for f in ("radius", "inv_mass", "rest_len"):
+        setattr(d, f, vals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    d.dt, d.n_sub, d.n_iters, d.steps_per_action, d.ckpt_every, d.eps_s = 1e-3, 1, 1, 1, 1, 1e-3
+    assert lib.rods_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    d.precision = 2
+    offs[1] = 2
+    assert lib.rods_create(ctypes.byref(d), ctypes.byref(h)) == -5
+    assert lib.rods_backward(None, None, None, None, None, None, None, None, None) == -1
+    assert lib.rods_status(None, None, None) == -1
