@@ -182,6 +182,16 @@ int rods_autotune(RodsHandle* h, int32_t n_steps, rods_stream_t stream);
  * speedup is measured.  Results are identical to the batched path. */
 int rods_set_plain(RodsHandle* h, int32_t plain);
 
+/* Kernel timing for measurement: with on != 0 every batch of kernel launches
+ * (one per size bin) is bracketed by HIP events recorded on the launch
+ * stream.  Events are created here (no device memory). */
+int rods_set_profiling(RodsHandle* h, int32_t on);
+/* Synchronises the stream and writes out (host) [9]: for the forward, the
+ * forward writing the backward tape, and the adjoint kernels (in that
+ * order) the total milliseconds, the number of launch batches and the
+ * longest batch; then clears the record. */
+int rods_profile(RodsHandle* h, double* out, rods_stream_t stream);
+
 /* Checks the lane-exchange primitives of the kernels: writes, for each of
  * 64 lanes, the lane id received from the next and from the previous lane
  * into out (device) [2][64] as int32 (-1 where no neighbour exists). */

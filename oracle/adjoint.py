@@ -262,19 +262,26 @@ def substep_vjp(rods, sim, rec, bar):
     t1_b += tb
     x1_b = xb1 + edges_vjp(ell1, t1, t1_b, np.zeros_like(ell1))
     # S9 self-friction
+    d0_b = None
     if rec["pairs"] is not None:
-        vb3, xf_b = selfcontact.friction_vjp(rods, sim, rec, vb3)
+        vb3, xf_b, d0_b = selfcontact.friction_vjp(rods, sim, rec, vb3)
         x1_b = x1_b + xf_b
     # S8 v3 = v2 + (p - p0)/h, x1 = p
     p_b = x1_b + vb3 / h
     v2_b = vb3.copy()
     p0_b = -vb3 / h
     # S7 projections, in reverse
-    for item in reversed(rec["ptape"]):
+    tape = rec["ptape"]
+    first = next((k for k, it in enumerate(tape) if it[0] == "pairs"), None)
+    for k in range(len(tape) - 1, -1, -1):
+        item = tape[k]
         if item[0] == "edge":
             p_b = project_edges_vjp(rods, p_b, item[1], item[2])
         else:
-            p_b = selfcontact.project_pairs_vjp(rods, p_b, item)
+            p_in_b = selfcontact.project_pairs_vjp(rods, p_b, item)
+            if k == first and d0_b is not None:
+                p_in_b = p_in_b + selfcontact.depth0_vjp(rods, item, d0_b)
+            p_b = p_in_b
     p0_b = p0_b + p_b
     # S5 p0 = x + h v2
     x_b = p0_b.copy()

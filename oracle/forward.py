@@ -252,15 +252,18 @@ def substep(rods, sim, st, u, rec=None):
     # S6
     pairs = selfcontact.candidates(rods, sim, p0) if rods.self_contact else None
     # S7
-    ptape = [] if rec is not None else None
+    ptape = [] if (rec is not None or pairs is not None) else None
     p = project(rods, sim, p0, pairs, ptape)
     # S8
     v3 = v2 + (p - p0) / h
     x1 = p
+    v3_pre = v3
     # S9
     frec = {} if rec is not None else None
+    d0 = None
     if pairs is not None:
-        v3 = selfcontact.friction(rods, sim, x1, v3, pairs, frec)
+        d0 = selfcontact.first_pass_depths(ptape)
+        v3 = selfcontact.friction(rods, sim, x1, v3, pairs, d0, frec)
     # S10
     _, ell1, t1 = edges(x1)
     d1n = transport(d1, t, t1)
@@ -273,7 +276,7 @@ def substep(rods, sim, st, u, rec=None):
         kb1 = kb
     if rec is not None:
         rec.update(x=x, v=v, kb=kb, d1=d1, u=u, ell=ell, t=t, d2=d2, F=F, v1=v1,
-                   v2=v2, p0=p0, ptape=ptape, pairs=pairs, p=p, v3=v3, x1=x1,
+                   v2=v2, p0=p0, ptape=ptape, pairs=pairs, p=p, v3=v3, x1=x1, v3_pre=v3_pre, d0=d0,
                    ell1=ell1, t1=t1, d1n=d1n, prec=prec, crec=crec, frec=frec)
     return State(x1, v3, kb1, d1n)
 

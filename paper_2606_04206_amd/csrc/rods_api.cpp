@@ -82,9 +82,43 @@ struct Impl : HandleBase {
   bool recorded = false;
   int n_rec = 0;
   int plain = 0;
+  // kernel timing: event pairs around every launch batch, per kernel kind
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_used;   // (kind, index of the first event of a pair)
+  size_t ev_next = 0;
 
   ~Impl() override {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
+  }
+
+  int set_profiling(int on) {
+    profiling = on != 0;
+    if (profiling && ev_pool.empty()) {
+      ev_pool.resize(4096);
+      for (auto& e : ev_pool) HIPCHK(hipEventCreate(&e));
+    }
+    ev_used.clear();
+    ev_next = 0;
+    return ROD_OK;
+  }
+
+  // out[3*k + 0] = total ms, out[3*k + 1] = launch batches, out[3*k + 2] = max ms,
+  // for k = 0 forward, 1 forward writing the tape, 2 adjoint
+  int profile(double* out, hipStream_t st) {
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < 9; ++i) out[i] = 0.0;
+    for (auto& u : ev_used) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev_pool[u.second], ev_pool[u.second + 1]));
+      out[3 * u.first] += ms;
+      out[3 * u.first + 1] += 1.0;
+      out[3 * u.first + 2] = std::max(out[3 * u.first + 2], (double)ms);
+    }
+    ev_used.clear();
+    ev_next = 0;
+    return ROD_OK;
   }
 
   template <typename U>
@@ -253,6 +287,18 @@ struct Impl : HandleBase {
 
   // launch `which` for every bin (batched) or per rod (plain) over n_steps
   int launch_all(int which, RodArgs<T> a, hipStream_t st) {
+    const bool timed = profiling && ev_next + 2 <= ev_pool.size();
+    if (timed) HIPCHK(hipEventRecord(ev_pool[ev_next], st));
+    int e = launch_all_(which, a, st);
+    if (timed) {
+      HIPCHK(hipEventRecord(ev_pool[ev_next + 1], st));
+      ev_used.push_back({which, (int)ev_next});
+      ev_next += 2;
+    }
+    return e;
+  }
+
+  int launch_all_(int which, RodArgs<T> a, hipStream_t st) {
     if (!plain) {
       for (const Bin& bn : bins) {
         a.rods = bin_rods + bn.off;
@@ -681,6 +727,16 @@ int rods_set_plain(RodsHandle* h, int32_t plain) {
     I->plain = plain ? 1 : 0;
     return (int)ROD_OK;
   });
+}
+
+int rods_set_profiling(RodsHandle* h, int32_t on) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) { return I->set_profiling(on); });
+}
+
+int rods_profile(RodsHandle* h, double* out, rods_stream_t stream) {
+  if (!h || !out) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) { return I->profile(out, (hipStream_t)stream); });
 }
 
 int rods_selftest_exchange(void* out, rods_stream_t stream) {

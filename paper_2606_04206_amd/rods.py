@@ -36,7 +36,7 @@ class RodsDesc(ctypes.Structure):
 EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "rods_get_state",
            "rods_set_params", "rods_curvature", "rods_step", "rods_rollout", "rods_backward",
            "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_plain",
-           "rods_selftest_exchange"]
+           "rods_set_profiling", "rods_profile", "rods_selftest_exchange"]
 
 _lib = None
 
@@ -70,6 +70,8 @@ def load():
         "rods_bins": ([vp, POINTER(c_int32), c_int32], c_int32),
         "rods_autotune": ([vp, c_int32, vp], c_int32),
         "rods_set_plain": ([vp, c_int32], c_int32),
+        "rods_set_profiling": ([vp, c_int32], c_int32),
+        "rods_profile": ([vp, POINTER(c_double), vp], c_int32),
         "rods_selftest_exchange": ([vp, vp], c_int32),
     }
     for name, (args, res) in sig.items():
@@ -253,6 +255,17 @@ class RodsHandle:
 
     def autotune(self, n_steps=2):
         _check(self._lib.rods_autotune(self._h, int(n_steps), _stream()), "rods_autotune")
+
+    def set_profiling(self, on=True):
+        _check(self._lib.rods_set_profiling(self._h, 1 if on else 0), "rods_set_profiling")
+
+    def profile(self):
+        """{kind: (total_ms, launches, max_ms)} for 'forward', 'forward_tape',
+        'adjoint' since the last call."""
+        out = (c_double * 9)()
+        _check(self._lib.rods_profile(self._h, out, _stream()), "rods_profile")
+        return {k: (out[3 * i], int(out[3 * i + 1]), out[3 * i + 2])
+                for i, k in enumerate(("forward", "forward_tape", "adjoint"))}
 
     def set_plain(self, plain=True):
         _check(self._lib.rods_set_plain(self._h, 1 if plain else 0), "rods_set_plain")

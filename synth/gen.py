@@ -195,7 +195,11 @@ def _target_curve(rng, x_ref, rest_edges):
 
 # ----------------------------------------------------------------------------
 
-def make_workload(cid: int, steps: Optional[int] = None) -> Workload:
+def make_workload(cid: int, steps: Optional[int] = None,
+                  start_height: Optional[float] = None) -> Workload:
+    """start_height (configurations 2-4): height of the initial arc instead of
+    the configured one (tests use a height just above the ground to start in
+    contact)."""
     cfg = CONFIGS[cid]
     sim = cfg.sim if steps is None else replace(cfg.sim, steps=steps)
     spa = sim.steps_per_action
@@ -239,7 +243,8 @@ def make_workload(cid: int, steps: Optional[int] = None) -> Workload:
             edge = EDGE_LEN
             x_clean = arc_polyline(n, edge, 0.6)
             x_clean = _rot_z(x_clean, rng.uniform(0.0, 2.0 * np.pi))
-            x_clean[:, 2] += 0.5 if cid in (2, 3) else 0.3
+            x_clean[:, 2] += (start_height if start_height is not None
+                              else (0.5 if cid in (2, 3) else 0.3))
             x = x_clean.copy()
             xr = None
         else:

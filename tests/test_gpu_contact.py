@@ -1,0 +1,109 @@
+"""GPU parity under rigid contact: the uneven 4096-rod batch (N in [16, 512],
+ground plane + 1-8 spheres/capsules per rod), started just above the ground
+with a downward velocity so that every contact branch is exercised."""
+import numpy as np
+import pytest
+import torch
+
+from synth import make_workload
+from oracle import forward as ofw, adjoint as oadj
+from oracle.model import rods_from_workload, sim_from_workload, State
+from oracle.forward import sdf_normal
+from tests.gpukit import (to_dev, sub_workload, rows, oracle_state_rows, gather_state,
+                          initial_full_state, rel_err)
+
+pytestmark = pytest.mark.gpu
+
+
+def contact_workload(steps, full=True):
+    wl = make_workload(4, steps=steps, start_height=0.006)
+    rng = np.random.default_rng(44)
+    wl.v0[:, 2] = -0.3
+    wl.v0[:, :2] = rng.normal(0.0, 0.2, (wl.n_vert, 2))
+    return wl if full else wl.subset(wl.oracle_rods)
+
+
+def _handle(wl, precision=4, **kw):
+    from paper_2606_04206_amd import RodsHandle
+    return RodsHandle(wl, precision=precision, **kw)
+
+
+def test_contact_substep_teacher_forced_with_branch_agreement():
+    """One substep of the full uneven batch from the seeded contact state:
+    positions <= 1e-4 per oracle rod; at every vertex whose contact
+    decisions all have a margin (|f - 0.1| > 1e-4, |v.n| > 1e-4 |v|), the
+    velocity agrees to 1e-3 relative + 5e-3 m/s, far below the jump a
+    different branch would cause (>= 0.03 m/s here)."""
+    wl = contact_workload(2)
+    run = sub_workload(wl)
+    h = _handle(run, max_steps=2)
+    full = initial_full_state(wl)
+    h.set_state(*(to_dev(a) for a in full))
+    h.step(to_dev(wl.actions[0]))
+    gx, gv, gkb, gd1 = (t.double().cpu().numpy() for t in h.get_state())
+    assert not h.status().any()
+    n_sure = n_active = 0
+    for r in wl.oracle_rods:
+        st = gather_state(wl, [r], [a.astype(np.float32).astype(np.float64) for a in full])
+        orods, osim = rods_from_workload(run, [r]), sim_from_workload(run)
+        rec = {}
+        ref = ofw.substep(orods, osim, st, wl.actions[0][[r]], rec)
+        gpu = gather_state(wl, [r], [gx, gv, gkb, gd1])
+        assert rel_err(gpu.x, ref.x) <= 1e-4, r
+        sure = np.ones(orods.N, bool)
+        for c in rec["crec"]["contact"]:
+            vin = c["vin"]
+            sure &= np.abs(c["f"] - osim.f_thresh) > 1e-4
+            sure &= np.abs(c["vn"]) > 1e-4 * np.linalg.norm(vin, axis=-1)
+            n_active += int(c["act"].sum())
+        sure &= orods.w[0] > 0
+        dv = np.linalg.norm(gpu.v[0] - ref.v[0], axis=-1)
+        tol = 1e-3 * np.linalg.norm(ref.v[0], axis=-1) + 5e-3
+        assert np.all(dv[sure] <= tol[sure]), (r, dv[sure].max())
+        n_sure += int(sure.sum())
+    assert n_active > 100 and n_sure > 1000
+
+
+def _grads(precision, wl, n_steps, K):
+    h = _handle(wl, precision=precision, max_steps=n_steps, ckpt_every=K)
+    dt = torch.float32 if precision == 4 else torch.float64
+    h.set_state(*(to_dev(a, dt) for a in initial_full_state(wl)))
+    xT = h.tensor(wl.n_vert, 3)
+    h.rollout(n_steps, to_dev(wl.actions, dt), record=True, x_final=xT)
+    loss, g = h.loss_mse(xT, to_dev(wl.target, dt))
+    out = {k: v.double().cpu().numpy() for k, v in h.backward(g, n_steps=n_steps).items()}
+    out["loss"] = float(loss.item())
+    return out
+
+
+def _oracle_grads_uneven(wl, n_steps, K):
+    res = []
+    for r in range(wl.n_rods):
+        orods, osim = rods_from_workload(wl, [r]), sim_from_workload(wl)
+        st = gather_state(wl, [r], initial_full_state(wl))
+        U = wl.actions[:, [r]]
+        xT, ck = ofw.rollout(orods, osim, st, U, n_steps, K)
+        a, b = wl.rod_range(r)
+        L, gx = oadj.loss_mse(xT.x, wl.target[a:b][None], wl.n_rods)
+        x0b, v0b, Ub, bb, sb = oadj.backward(orods, osim, ck, U, n_steps, K, gx)
+        res.append(dict(loss=L, u=Ub[:, 0], b=bb[0], sigma=sb[0], x0=x0b[0], v0=v0b[0]))
+    return res
+
+
+@pytest.mark.parametrize("precision,tol,r_c", [(8, 1e-8, 0.5), (4, 1e-3, 1.0)])
+def test_contact_rollout_gradients(precision, tol, r_c):
+    """The 8 sampled rods (N = 16 .. 512, separate size bins), 6 steps in
+    contact, checkpoint every 4: gradients against the oracle."""
+    wl = contact_workload(6, full=False)
+    wl.rod_params[:, 4] = r_c
+    n, K = 6, 4
+    g = _grads(precision, wl, n, K)
+    ref = _oracle_grads_uneven(wl, n, K)
+    assert abs(g["loss"] - sum(r["loss"] for r in ref)) <= 1e-4 * sum(r["loss"] for r in ref)
+    for r, o in enumerate(ref):
+        a, b = wl.rod_range(r)
+        assert rel_err(g["u"][:, r], o["u"]) <= tol, ("u", r)
+        assert rel_err(g["x0"][a:b], o["x0"]) <= tol, ("x0", r)
+        assert rel_err(g["v0"][a:b], o["v0"]) <= tol, ("v0", r)
+    assert rel_err(g["b"], np.array([o["b"] for o in ref])) <= tol
+    assert rel_err(g["sigma"], np.array([o["sigma"] for o in ref])) <= tol
