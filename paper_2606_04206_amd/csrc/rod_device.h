@@ -192,7 +192,9 @@ struct RodArgs {
   T* dL_du;
   double* acc_b;            // [V] per-vertex dL/db partials
   double* acc_s;            // [V] per-vertex dL/dsigma partials
-  int32_t* status;          // [R]
+  T* sc_tape;               // self-contact rods: projection iterates of one substep
+  const int64_t* sc_off;    // [R] offset of the rod's block in sc_tape
+  int32_t* status;          // [R] bit0 non-finite, bit1 partner list full, bit2 edge too long for the hash cell
   // scalars
   T h;
   T gx, gy, gz;

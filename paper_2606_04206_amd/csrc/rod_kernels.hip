@@ -18,6 +18,7 @@
 // vector-Jacobian product of every sub-step in reverse.
 #include "rod_device.h"
 #include "rod_launch.h"
+#include "rod_selfcontact.h"
 
 namespace rods {
 
@@ -348,12 +349,21 @@ struct Rec {   // what the adjoint needs from one substep's forward run
   V3<T> t1p, d1np;
   T kel0[C], kel1[C], nrm[C], phi[C];
   bool yld[C];
+  V3<T> x1[C], v3[C];   // positions after projection, velocities before self-friction
 };
 
-template <typename T, int C, int W>
+template <typename T, int C, int W, bool SC>
 struct Rod {
   static constexpr int TL = 64 * W;   // lanes per team
+  static constexpr int NV = TL * C;   // vertex capacity of the team
   int rod, N, v0, tl, flags, p0, p1;
+  // self-contact scratch (LDS) and the adjoint's contact-pass inputs (global)
+  T *sc_pos, *sc_aux, *sc_adj, *sc_w, *sc_r, *sc_d0;
+  int *sc_cnt, *sc_start, *sc_pcnt, *sc_tmp;
+  short *sc_items, *sc_plist;
+  T sc_cell, sc_lmax;
+  int sc_flags;
+  T* ctape;
   T b, sig, rc, mu, e, K;
   T w[C], rest[C], lbar[C], ks[C], rad[C];
   int gs[C];
@@ -501,7 +511,19 @@ struct Rod {
   // N_C iterations of red (even edges) then black (odd edges) projections
   template <bool REC>
   __device__ void project(const RodArgs<T>& a, Team<T, W>& X, V3<T> (&p)[C], T* lds_tape) {
+    const bool inext = (flags & FLAG_INEXT) != 0;
     for (int it = 0; it < a.n_iters; ++it) {
+      if (inext) project_iter<REC>(a, X, p, lds_tape, it);
+      if constexpr (SC) {
+        if (flags & FLAG_SELF) sc_pass<REC>(X, p, it, it == 0);
+      }
+    }
+  }
+
+  template <bool REC>
+  __device__ void project_iter(const RodArgs<T>& a, Team<T, W>& X, V3<T> (&p)[C], T* lds_tape,
+                               int it) {
+    {
 #pragma unroll
       for (int c = 0; c < C; c += 2) {
         V3<T> D = zero3<T>();
@@ -542,8 +564,19 @@ struct Rod {
   }
 
   __device__ void project_vjp(const RodArgs<T>& a, Team<T, W>& X, V3<T> (&pb)[C],
-                              const T* lds_tape) const {
+                              const T* lds_tape) {
+    const bool inext = (flags & FLAG_INEXT) != 0;
     for (int it = a.n_iters - 1; it >= 0; --it) {
+      if constexpr (SC) {
+        if (flags & FLAG_SELF) sc_pass_vjp(X, pb, it, it == 0);
+      }
+      if (inext) project_iter_vjp(X, pb, lds_tape, it);
+    }
+  }
+
+  __device__ void project_iter_vjp(Team<T, W>& X, V3<T> (&pb)[C], const T* lds_tape,
+                                   int it) const {
+    {
       // black pass, reversed
       T an[3] = {pb[0].x, pb[0].y, pb[0].z};
       X.next(an);
@@ -582,6 +615,372 @@ struct Rod {
         }
       }
     }
+  }
+
+  // ------------------------------------------------------------ self-contact
+  static constexpr size_t sc_bytes() {
+    return sizeof(T) * (size_t)(3 * NV * 3 + 2 * NV + NV * SC_MAXP) +
+           sizeof(int) * (size_t)(SC_HT + SC_HT + 1 + NV + 2 * TL) +
+           sizeof(short) * (size_t)(NV + NV * SC_MAXP) + 64;
+  }
+  __device__ void sc_layout(unsigned char* base) {
+    T* f = reinterpret_cast<T*>(base);
+    sc_pos = f; f += 3 * NV;
+    sc_aux = f; f += 3 * NV;
+    sc_adj = f; f += 3 * NV;
+    sc_w = f; f += NV;
+    sc_r = f; f += NV;
+    sc_d0 = f; f += NV * SC_MAXP;
+    int* q = reinterpret_cast<int*>(f);
+    sc_cnt = q; q += SC_HT;
+    sc_start = q; q += SC_HT + 1;
+    sc_pcnt = q; q += NV;
+    sc_tmp = q; q += 2 * TL;
+    short* sh = reinterpret_cast<short*>(q);
+    sc_items = sh; sh += NV;
+    sc_plist = sh;
+  }
+  __device__ void sc_stage(T* dst, const V3<T> (&vals)[C]) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int g = gi(c);
+      V3<T> q = vvalid(c) ? vals[c] : zero3<T>();
+      dst[3 * g] = q.x;
+      dst[3 * g + 1] = q.y;
+      dst[3 * g + 2] = q.z;
+    }
+  }
+  __device__ __forceinline__ V3<T> sc_at(const T* a, int v) const {
+    return mk(a[3 * v], a[3 * v + 1], a[3 * v + 2]);
+  }
+  // static data into LDS and the hash cell size: 2 r_max + delta_c + 2 l_max
+  // (a partner's midpoint then lies in the 27 cells around the edge's own as
+  // long as no edge exceeds 2 l_max, which is checked every substep)
+  __device__ void sc_setup(const RodArgs<T>& a) {
+    sc_flags = 0;
+    T m_r = T(0), m_l = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int g = gi(c);
+      sc_w[g] = w[c];
+      sc_r[g] = rad[c];
+      m_r = rad[c] > m_r ? rad[c] : m_r;
+      m_l = rest[c] > m_l ? rest[c] : m_l;
+    }
+    T* red = reinterpret_cast<T*>(sc_tmp);
+    red[2 * tl] = m_r;
+    red[2 * tl + 1] = m_l;
+    __syncthreads();
+    if (tl == 0) {
+      T rr = T(0), ll = T(0);
+      for (int k = 0; k < TL; ++k) {
+        rr = red[2 * k] > rr ? red[2 * k] : rr;
+        ll = red[2 * k + 1] > ll ? red[2 * k + 1] : ll;
+      }
+      red[0] = rr;
+      red[1] = ll;
+    }
+    __syncthreads();
+    T rmax = red[0], lmax = red[1];
+    sc_lmax = T(2) * lmax;
+    sc_cell = T(2) * rmax + a.self_margin + T(2) * lmax;
+    __syncthreads();
+  }
+
+  // candidate pairs at the predicted positions p (uniform-grid hash of edge
+  // midpoints; per own edge a sorted, duplicate-free partner list)
+  __device__ void sc_broadphase(const RodArgs<T>& a, const V3<T> (&p)[C]) {
+    sc_stage(sc_pos, p);
+    for (int i = tl; i < SC_HT; i += TL) sc_cnt[i] = 0;
+    __syncthreads();
+    const T ig = T(1) / sc_cell;
+    unsigned key[C];
+    int slot[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      key[c] = 0;
+      slot[c] = 0;
+      if (evalid(c)) {
+        int e = gi(c);
+        V3<T> P = sc_at(sc_pos, e), Q = sc_at(sc_pos, e + 1);
+        V3<T> D = Q - P;
+        if (dot(D, D) > sc_lmax * sc_lmax) sc_flags |= 4;
+        V3<T> m = T(0.5) * (P + Q);
+        key[c] = sc_hash((int)floor(m.x * ig), (int)floor(m.y * ig), (int)floor(m.z * ig));
+        slot[c] = atomicAdd(&sc_cnt[key[c]], 1);
+      }
+    }
+    __syncthreads();
+    constexpr int PER = SC_HT / TL;
+    const int base = tl * PER;
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) sum += sc_cnt[base + k];
+    int* src = sc_tmp;
+    int* dst = sc_tmp + TL;
+    src[tl] = sum;
+    __syncthreads();
+    for (int off = 1; off < TL; off <<= 1) {
+      int v = src[tl];
+      if (tl >= off) v += src[tl - off];
+      dst[tl] = v;
+      __syncthreads();
+      int* t_ = src; src = dst; dst = t_;
+    }
+    int excl = src[tl] - sum;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      sc_start[base + k] = excl;
+      excl += sc_cnt[base + k];
+    }
+    if (tl == TL - 1) sc_start[SC_HT] = excl;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (evalid(c)) sc_items[sc_start[key[c]] + slot[c]] = (short)gi(c);
+    __syncthreads();
+    const T margin = a.self_margin;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (!evalid(c)) continue;
+      const int e = gi(c);
+      short* pl = sc_plist + e * SC_MAXP;
+      int cnt = 0;
+      V3<T> P = sc_at(sc_pos, e), Q = sc_at(sc_pos, e + 1);
+      V3<T> m = T(0.5) * (P + Q);
+      int cx = (int)floor(m.x * ig), cy = (int)floor(m.y * ig), cz = (int)floor(m.z * ig);
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            unsigned kk = sc_hash(cx + dx, cy + dy, cz + dz);
+            for (int q = sc_start[kk]; q < sc_start[kk + 1]; ++q) {
+              int j = sc_items[q];
+              if (!(j - e > a.k_ex || e - j > a.k_ex)) continue;
+              int lo = e < j ? e : j, hi = e < j ? j : e;
+              V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
+              V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
+              Closest<T> cp = closest_params(P1, Q1, P2, Q2);
+              V3<T> ca = (T(1) - cp.s) * P1 + cp.s * Q1;
+              V3<T> cb = (T(1) - cp.u) * P2 + cp.u * Q2;
+              V3<T> df = ca - cb;
+              T ra = (T(1) - cp.s) * sc_r[lo] + cp.s * sc_r[lo + 1];
+              T rb = (T(1) - cp.u) * sc_r[hi] + cp.u * sc_r[hi + 1];
+              if (!(sqrt(dot(df, df)) < ra + rb + margin)) continue;
+              // sorted insert without duplicates (hash collisions revisit buckets)
+              int at = 0;
+              while (at < cnt && pl[at] < j) ++at;
+              if (at < cnt && pl[at] == j) continue;
+              if (at >= SC_MAXP) { sc_flags |= 2; continue; }
+              if (cnt == SC_MAXP) sc_flags |= 2;
+              int last = cnt < SC_MAXP ? cnt : SC_MAXP - 1;
+              for (int k = last; k > at; --k) pl[k] = pl[k - 1];
+              pl[at] = (short)j;
+              cnt = cnt < SC_MAXP ? cnt + 1 : SC_MAXP;
+            }
+          }
+      sc_pcnt[e] = cnt;
+    }
+    __syncthreads();
+  }
+
+  __device__ __forceinline__ PairGeo<T> sc_pair(const T* P, int lo, int hi) const {
+    return pair_geo(sc_at(P, lo), sc_at(P, lo + 1), sc_at(P, hi), sc_at(P, hi + 1), sc_w[lo],
+                    sc_w[lo + 1], sc_w[hi], sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
+                    sc_r[hi + 1]);
+  }
+
+  // one Jacobi pass of the self-contact projection (gather per own edge)
+  template <bool REC>
+  __device__ void sc_pass(Team<T, W>& X, V3<T> (&p)[C], int it, bool first) {
+    sc_stage(sc_pos, p);
+    if constexpr (REC) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        ctape[((it * C + c) * 3 + 0) * TL + tl] = p[c].x;
+        ctape[((it * C + c) * 3 + 1) * TL + tl] = p[c].y;
+        ctape[((it * C + c) * 3 + 2) * TL + tl] = p[c].z;
+      }
+    }
+    __syncthreads();
+    V3<T> dA[C], dB[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      dA[c] = zero3<T>();
+      dB[c] = zero3<T>();
+      if (!evalid(c)) continue;
+      const int e = gi(c);
+      const short* pl = sc_plist + e * SC_MAXP;
+      const int n = sc_pcnt[e];
+      for (int k = 0; k < n; ++k) {
+        int j = pl[k];
+        int lo = e < j ? e : j, hi = e < j ? j : e;
+        PairGeo<T> g = sc_pair(sc_pos, lo, hi);
+        if (first) sc_d0[e * SC_MAXP + k] = g.act ? g.d : T(0);
+        if (g.act) {
+          T kk = g.d / g.W;
+          if (e == lo) {
+            dA[c] += (kk * sc_w[lo] * (T(1) - g.cp.s)) * g.n;
+            dB[c] += (kk * sc_w[lo + 1] * g.cp.s) * g.n;
+          } else {
+            dA[c] -= (kk * sc_w[hi] * (T(1) - g.cp.u)) * g.n;
+            dB[c] -= (kk * sc_w[hi + 1] * g.cp.u) * g.n;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    T s3[3] = {dB[C - 1].x, dB[C - 1].y, dB[C - 1].z};
+    X.prev(s3);
+#pragma unroll
+    for (int c = 0; c < C; ++c) p[c] += dA[c] + (c ? dB[c - 1] : mk(s3[0], s3[1], s3[2]));
+  }
+
+  // self-friction on velocities v at final positions x1
+  __device__ void sc_friction(const RodArgs<T>& a, Team<T, W>& X, const V3<T> (&x1)[C],
+                              V3<T> (&v)[C]) {
+    sc_stage(sc_pos, x1);
+    sc_stage(sc_aux, v);
+    __syncthreads();
+    V3<T> dA[C], dB[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      dA[c] = zero3<T>();
+      dB[c] = zero3<T>();
+      if (!evalid(c)) continue;
+      const int e = gi(c);
+      const short* pl = sc_plist + e * SC_MAXP;
+      const int n = sc_pcnt[e];
+      for (int k = 0; k < n; ++k) {
+        T d0 = sc_d0[e * SC_MAXP + k];
+        if (!(d0 > T(0))) continue;
+        int j = pl[k];
+        int lo = e < j ? e : j, hi = e < j ? j : e;
+        FricGeo<T> f = pair_friction(sc_at(sc_pos, lo), sc_at(sc_pos, lo + 1), sc_at(sc_pos, hi),
+                                     sc_at(sc_pos, hi + 1), sc_at(sc_aux, lo),
+                                     sc_at(sc_aux, lo + 1), sc_at(sc_aux, hi),
+                                     sc_at(sc_aux, hi + 1), sc_w[lo], sc_w[lo + 1], sc_w[hi],
+                                     sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
+                                     sc_r[hi + 1], d0, mu, a.h);
+        if (!f.ok) continue;
+        T iW = T(1) / f.g.W;
+        if (e == lo) {
+          dA[c] += (sc_w[lo] * (T(1) - f.g.cp.s) * iW) * f.dvt;
+          dB[c] += (sc_w[lo + 1] * f.g.cp.s * iW) * f.dvt;
+        } else {
+          dA[c] -= (sc_w[hi] * (T(1) - f.g.cp.u) * iW) * f.dvt;
+          dB[c] -= (sc_w[hi + 1] * f.g.cp.u * iW) * f.dvt;
+        }
+      }
+    }
+    __syncthreads();
+    T s3[3] = {dB[C - 1].x, dB[C - 1].y, dB[C - 1].z};
+    X.prev(s3);
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] += dA[c] + (c ? dB[c - 1] : mk(s3[0], s3[1], s3[2]));
+  }
+
+  // adjoint of sc_friction: lv (adjoint of friction's output velocity) ->
+  // adjoint of its input velocity; adds position adjoints to xb; leaves the
+  // adjoint of each pair's first-pass depth in sc_d0
+  __device__ void sc_friction_vjp(const RodArgs<T>& a, Team<T, W>& X, const Rec<T, C>& r,
+                                  V3<T> (&lv)[C], V3<T> (&xb)[C]) {
+    sc_stage(sc_pos, r.x1);
+    sc_stage(sc_aux, r.v3);
+    sc_stage(sc_adj, lv);
+    __syncthreads();
+    V3<T> vA[C], vB[C], xA[C], xB[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      vA[c] = vB[c] = xA[c] = xB[c] = zero3<T>();
+      if (!evalid(c)) continue;
+      const int e = gi(c);
+      const short* pl = sc_plist + e * SC_MAXP;
+      const int n = sc_pcnt[e];
+      for (int k = 0; k < n; ++k) {
+        T d0 = sc_d0[e * SC_MAXP + k];
+        if (!(d0 > T(0))) continue;
+        int j = pl[k];
+        int lo = e < j ? e : j, hi = e < j ? j : e;
+        V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
+        V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
+        V3<T> vi = sc_at(sc_aux, lo), vi1 = sc_at(sc_aux, lo + 1);
+        V3<T> vj = sc_at(sc_aux, hi), vj1 = sc_at(sc_aux, hi + 1);
+        FricGeo<T> f = pair_friction(P1, Q1, P2, Q2, vi, vi1, vj, vj1, sc_w[lo], sc_w[lo + 1],
+                                     sc_w[hi], sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
+                                     sc_r[hi + 1], d0, mu, a.h);
+        V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
+        V3<T> q0 = zero3<T>(), q1 = zero3<T>(), q2 = zero3<T>(), q3 = zero3<T>();
+        T d0b = pair_friction_vjp(P1, Q1, P2, Q2, vi, vi1, vj, vj1, f, sc_w[lo], sc_w[lo + 1],
+                                  sc_w[hi], sc_w[hi + 1], mu, a.h, sc_at(sc_adj, lo),
+                                  sc_at(sc_adj, lo + 1), sc_at(sc_adj, hi),
+                                  sc_at(sc_adj, hi + 1), b0, b1, b2, b3, q0, q1, q2, q3);
+        sc_d0[e * SC_MAXP + k] = d0b;
+        if (e == lo) {
+          vA[c] += b0; vB[c] += b1; xA[c] += q0; xB[c] += q1;
+        } else {
+          vA[c] += b2; vB[c] += b3; xA[c] += q2; xB[c] += q3;
+        }
+      }
+    }
+    __syncthreads();
+    T s6[6] = {vB[C - 1].x, vB[C - 1].y, vB[C - 1].z, xB[C - 1].x, xB[C - 1].y, xB[C - 1].z};
+    X.prev(s6);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      lv[c] += vA[c] + (c ? vB[c - 1] : mk(s6[0], s6[1], s6[2]));
+      xb[c] += xA[c] + (c ? xB[c - 1] : mk(s6[3], s6[4], s6[5]));
+    }
+  }
+
+  // adjoint of the contact pass of iteration it (inputs read back from ctape);
+  // at it == 0 also the adjoint of the first-pass depths left in sc_d0
+  __device__ void sc_pass_vjp(Team<T, W>& X, V3<T> (&pb)[C], int it, bool with_depth) {
+    V3<T> pin[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      pin[c] = mk(ctape[((it * C + c) * 3 + 0) * TL + tl], ctape[((it * C + c) * 3 + 1) * TL + tl],
+                  ctape[((it * C + c) * 3 + 2) * TL + tl]);
+    sc_stage(sc_pos, pin);
+    sc_stage(sc_adj, pb);
+    __syncthreads();
+    V3<T> cA[C], cB[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      cA[c] = cB[c] = zero3<T>();
+      if (!evalid(c)) continue;
+      const int e = gi(c);
+      const short* pl = sc_plist + e * SC_MAXP;
+      const int n = sc_pcnt[e];
+      for (int k = 0; k < n; ++k) {
+        int j = pl[k];
+        int lo = e < j ? e : j, hi = e < j ? j : e;
+        PairGeo<T> g = sc_pair(sc_pos, lo, hi);
+        if (!g.act) continue;
+        V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
+        V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
+        V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
+        pair_proj_vjp(P1, Q1, P2, Q2, g, sc_w[lo], sc_w[lo + 1], sc_w[hi], sc_w[hi + 1],
+                      sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], sc_at(sc_adj, lo),
+                      sc_at(sc_adj, lo + 1), sc_at(sc_adj, hi), sc_at(sc_adj, hi + 1), b0, b1,
+                      b2, b3);
+        if (with_depth) {
+          T d0b = sc_d0[e * SC_MAXP + k];
+          if (d0b != T(0))
+            pair_depth_vjp(P1, Q1, P2, Q2, g, sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], d0b,
+                           b0, b1, b2, b3);
+        }
+        if (e == lo) {
+          cA[c] += b0; cB[c] += b1;
+        } else {
+          cA[c] += b2; cB[c] += b3;
+        }
+      }
+    }
+    __syncthreads();
+    T s3[3] = {cB[C - 1].x, cB[C - 1].y, cB[C - 1].z};
+    X.prev(s3);
+#pragma unroll
+    for (int c = 0; c < C; ++c) pb[c] += cA[c] + (c ? cB[c - 1] : mk(s3[0], s3[1], s3[2]));
   }
 
   // gather the previous lane's last edge: tangent, length, d1
@@ -699,13 +1098,31 @@ struct Rod {
       p[c] = x[c] + h * v[c];
       pp[c] = p[c];
     }
+    // S6 self-contact candidates at the predicted positions
+    const bool self_on = SC && (flags & FLAG_SELF);
+    if constexpr (SC) {
+      if (self_on) sc_broadphase(a, p);
+    }
     // S7 projections
-    if (flags & FLAG_INEXT) project<REC>(a, X, p, lds_tape);
+    if ((flags & FLAG_INEXT) || self_on) project<REC>(a, X, p, lds_tape);
     // S8 velocity update from the corrections
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       v[c] += ih * (p[c] - pp[c]);
       x[c] = p[c];
+    }
+    // S9 self-friction
+    if constexpr (SC) {
+      if (self_on) {
+        if constexpr (REC) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            rc_->x1[c] = x[c];
+            rc_->v3[c] = v[c];
+          }
+        }
+        sc_friction(a, X, x, v);
+      }
     }
     // S10 frames by parallel transport in time
     V3<T> t1[C];
@@ -764,7 +1181,7 @@ struct Rod {
   __device__ void substep_vjp(const RodArgs<T>& a, Team<T, W>& X, const Rec<T, C>& r,
                               const T* lds_tape, V3<T> (&lx)[C], V3<T> (&lv)[C], T (&lk0)[C],
                               T (&lk1)[C], V3<T> (&ld1)[C], double (&accb)[C],
-                              double (&accs)[C], V3<T> (&uacc)[C]) const {
+                              double (&accs)[C], V3<T> (&uacc)[C]) {
     const T h = a.h;
     const T ih = T(1) / h;
     // S11 plasticity: kr' = kr + phi kel on yield
@@ -823,6 +1240,10 @@ struct Rod {
 #pragma unroll
     for (int c = 0; c < C; ++c) pb[c] = lx[c];
     edges_vjp(X, r.t1, r.ell1, t1b, l1b, pb);
+    // S9 self-friction
+    if constexpr (SC) {
+      if (flags & FLAG_SELF) sc_friction_vjp(a, X, r, lv, pb);
+    }
     // S8: v' = v2 + (p - p0)/h, x' = p
     V3<T> v2b[C], p0b[C];
 #pragma unroll
@@ -832,7 +1253,7 @@ struct Rod {
       p0b[c] = -(ih * lv[c]);
     }
     // S7
-    if (flags & FLAG_INEXT) project_vjp(a, X, pb, lds_tape);
+    if ((flags & FLAG_INEXT) || (SC && (flags & FLAG_SELF))) project_vjp(a, X, pb, lds_tape);
     // S5 p0 = x + h v2
     V3<T> xb[C];
 #pragma unroll
@@ -958,14 +1379,20 @@ template <typename T, int W>
 __device__ __forceinline__ size_t xchg_bytes() { return W > 1 ? 2 * W * XK * sizeof(T) : 0; }
 
 // Forward: n_steps steps of every rod of the work list, the rod resident in
-// registers the whole time.  TAPE: store every substep-start state.
-template <typename T, int C, int W, bool TAPE>
+// registers the whole time.  TAPE: store every substep-start state.  SC:
+// self-contact support (hash, partner lists and staging buffers in LDS).
+template <typename T, int C, int W, bool TAPE, bool SC>
 __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Team<T, W> X;
   X.init(reinterpret_cast<T*>(smem));
-  Rod<T, C, W> R;
+  Rod<T, C, W, SC> R;
   R.load_static(a, X);
+  if constexpr (SC) {
+    R.sc_layout(smem + xchg_bytes<T, W>());
+    R.ctape = nullptr;
+    R.sc_setup(a);
+  }
   R.load_state(a.x, a.v, a.kb, a.d1);
   T* tape_rod = TAPE ? a.tape + a.tape_off[R.rod] : nullptr;
   for (int s = 0; s < a.n_steps; ++s) {
@@ -984,18 +1411,30 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
     T s = dot(R.x[c], R.x[c]) + dot(R.v[c], R.v[c]);
     bad |= !(s == s) || s > T(1e30);
   }
-  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(a.status + R.rod, 1);
+  int fl = bad ? 1 : 0;
+  if constexpr (SC) fl |= R.sc_flags;
+  if (fl) atomicOr(a.status + R.rod, fl);
 }
 
 // Adjoint over the launch's steps, last to first, from the substep tape.
-template <typename T, int C, int W>
+template <typename T, int C, int W, bool SC>
 __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Team<T, W> X;
   X.init(reinterpret_cast<T*>(smem));
-  T* lds_tape = reinterpret_cast<T*>(smem + xchg_bytes<T, W>());
-  Rod<T, C, W> R;
+  Rod<T, C, W, SC> R;
   R.load_static(a, X);
+  T* lds_tape;
+  if constexpr (SC) {
+    // LDS holds the self-contact buffers; the projection iterates go to a
+    // rod-private global scratch block (written and read within a substep)
+    R.sc_layout(smem + xchg_bytes<T, W>());
+    lds_tape = a.sc_tape + a.sc_off[R.rod];
+    R.ctape = lds_tape + (size_t)a.n_iters * C * 3 * 64 * W;
+    R.sc_setup(a);
+  } else {
+    lds_tape = reinterpret_cast<T*>(smem + xchg_bytes<T, W>());
+  }
   V3<T> lx[C], lv[C], ld1[C], uacc[C];
   T lk0[C], lk1[C];
   double accb[C], accs[C];
@@ -1167,46 +1606,73 @@ __global__ void k_selftest_exchange(int* out) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 
-template <typename T, int C, int W>
-static size_t adj_lds(int n_iters) {
-  return (W > 1 ? 2 * W * XK * sizeof(T) : 0) + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
+template <typename T, int C, int W, bool SC>
+static size_t lds_bytes(int which, int n_iters) {
+  size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
+  if (SC) return xb + Rod<T, C, W, SC>::sc_bytes();
+  if (which == 2) return xb + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
+  return xb;
 }
 
-template <typename T, int C, int W>
+template <typename T, int C, int W, bool SC>
 static hipError_t launch_shape(int which, const RodArgs<T>& a, int n_blocks, hipStream_t st) {
-  size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
-  if (which == 0)
-    hipLaunchKernelGGL((k_forward<T, C, W, false>), dim3(n_blocks), dim3(64 * W), xb, st, a);
-  else if (which == 1)
-    hipLaunchKernelGGL((k_forward<T, C, W, true>), dim3(n_blocks), dim3(64 * W), xb, st, a);
-  else {
-    size_t lds = adj_lds<T, C, W>(a.n_iters);
-    hipLaunchKernelGGL((k_adjoint<T, C, W>), dim3(n_blocks), dim3(64 * W), lds, st, a);
+  size_t lds = lds_bytes<T, C, W, SC>(which, a.n_iters);
+  if (which == 0) {
+    auto f = k_forward<T, C, W, false, SC>;
+    if (lds > 65536) hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, a);
+  } else if (which == 1) {
+    auto f = k_forward<T, C, W, true, SC>;
+    if (lds > 65536) hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, a);
+  } else {
+    auto f = k_adjoint<T, C, W, SC>;
+    if (lds > 65536) hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, a);
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_rods(int which, int C, int W, const RodArgs<T>& a, int n_blocks,
+hipError_t launch_rods(int which, int C, int W, bool SC, const RodArgs<T>& a, int n_blocks,
                        hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
 #define RODS_SHAPE(CC, WW) \
-  if (C == CC && W == WW) return launch_shape<T, CC, WW>(which, a, n_blocks, st);
+  if (!SC && C == CC && W == WW) return launch_shape<T, CC, WW, false>(which, a, n_blocks, st);
   RODS_SHAPE(2, 1)
   RODS_SHAPE(2, 2)
   RODS_SHAPE(2, 4)
   RODS_SHAPE(2, 8)
-  RODS_SHAPE(4, 1)
-  RODS_SHAPE(4, 2)
-  RODS_SHAPE(4, 4)
-  RODS_SHAPE(4, 8)
+  if constexpr (sizeof(T) == 4) {
+    RODS_SHAPE(4, 1)
+    RODS_SHAPE(4, 2)
+    RODS_SHAPE(4, 4)
+#define RODS_SC_SHAPE(CC, WW) \
+  if (SC && C == CC && W == WW) return launch_shape<T, CC, WW, true>(which, a, n_blocks, st);
+    RODS_SC_SHAPE(2, 1)
+    RODS_SC_SHAPE(2, 2)
+    RODS_SC_SHAPE(2, 4)
+    RODS_SC_SHAPE(2, 8)
+    RODS_SC_SHAPE(4, 4)
+#undef RODS_SC_SHAPE
+  }
 #undef RODS_SHAPE
   return hipErrorInvalidValue;
 }
 
 template <typename T>
-size_t adjoint_lds_bytes(int C, int W, int n_iters) {
-  return (W > 1 ? 2 * W * XK * sizeof(T) : 0) + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
+size_t kernel_lds_bytes(int which, int C, int W, bool SC, int n_iters) {
+  size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
+  if (SC) {
+    if (C == 2 && W == 1) return xb + Rod<T, 2, 1, true>::sc_bytes();
+    if (C == 2 && W == 2) return xb + Rod<T, 2, 2, true>::sc_bytes();
+    if (C == 2 && W == 4) return xb + Rod<T, 2, 4, true>::sc_bytes();
+    if (C == 2 && W == 8) return xb + Rod<T, 2, 8, true>::sc_bytes();
+    if (C == 4 && W == 4) return xb + Rod<T, 4, 4, true>::sc_bytes();
+    return (size_t)1 << 30;
+  }
+  if (which == 2) return xb + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
+  return xb;
 }
 
 template <typename T>
@@ -1259,8 +1725,8 @@ hipError_t launch_selftest_exchange(int* out, hipStream_t st) {
 }
 
 #define RODS_INST(T)                                                                          \
-  template hipError_t launch_rods<T>(int, int, int, const RodArgs<T>&, int, hipStream_t);     \
-  template size_t adjoint_lds_bytes<T>(int, int, int);                                         \
+  template hipError_t launch_rods<T>(int, int, int, bool, const RodArgs<T>&, int, hipStream_t); \
+  template size_t kernel_lds_bytes<T>(int, int, int, bool, int);                               \
   template hipError_t launch_init_frames<T>(const int32_t*, int, const T*, T*, hipStream_t);  \
   template hipError_t launch_curvature<T>(const int32_t*, const int32_t*, int, const T*,      \
                                           const T*, T*, hipStream_t);                         \

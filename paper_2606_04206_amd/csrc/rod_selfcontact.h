@@ -1,0 +1,256 @@
+// Self-contact and self-friction of one rod (DLO-Lab App. A.1,
+// "Self-collision and Friction") for the rod kernels: closest points of two
+// segments (clamped segment-segment method, Ericson 5.1.9, with a parallel
+// fallback), the per-pair position correction and velocity friction, and
+// their vector-Jacobian products.  Pairs are always evaluated with the
+// lower-indexed edge first, so both lanes that own a pair's edges compute
+// bitwise identical pair quantities.
+#pragma once
+#include "rod_device.h"
+
+namespace rods {
+
+constexpr int SC_MAXP = 12;    // partner capacity per edge
+constexpr int SC_HT = 2048;    // hash buckets (power of two)
+
+template <typename T>
+struct Closest {
+  T s, u;
+  bool gen, s_cl, lo, hi, s_alt_cl;
+};
+
+template <typename T>
+__device__ __forceinline__ T clamp01(T x) { return x < T(0) ? T(0) : (x > T(1) ? T(1) : x); }
+
+template <typename T>
+__device__ __forceinline__ Closest<T> closest_params(V3<T> P1, V3<T> Q1, V3<T> P2, V3<T> Q2) {
+  V3<T> d1 = Q1 - P1, d2 = Q2 - P2, r = P1 - P2;
+  T a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r), c = dot(d1, r), b = dot(d1, d2);
+  T denom = a * e - b * b;
+  Closest<T> o;
+  o.gen = denom > T(1e-12) * (a * e);
+  T s_raw = o.gen ? (b * f - c * e) / denom : T(0);
+  T s0 = clamp01(s_raw);
+  o.s_cl = !o.gen || s_raw <= T(0) || s_raw >= T(1);
+  T u_raw = (b * s0 + f) / e;
+  o.lo = u_raw < T(0);
+  o.hi = u_raw > T(1);
+  o.u = o.lo ? T(0) : (o.hi ? T(1) : u_raw);
+  T s_alt_raw = o.lo ? -c / a : (b - c) / a;
+  o.s_alt_cl = s_alt_raw <= T(0) || s_alt_raw >= T(1);
+  o.s = (o.lo || o.hi) ? clamp01(s_alt_raw) : s0;
+  return o;
+}
+
+// Adjoint of closest_params on the recorded branch; adds to the endpoint adjoints.
+template <typename T>
+__device__ __forceinline__ void closest_params_vjp(V3<T> P1, V3<T> Q1, V3<T> P2, V3<T> Q2,
+                                                   const Closest<T>& br, T s_b, T u_b,
+                                                   V3<T>& P1b, V3<T>& Q1b, V3<T>& P2b,
+                                                   V3<T>& Q2b) {
+  V3<T> d1 = Q1 - P1, d2 = Q2 - P2, r = P1 - P2;
+  T a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r), c = dot(d1, r), b = dot(d1, d2);
+  T denom = a * e - b * b;
+  T a_b = 0, b_b = 0, c_b = 0, e_b = 0, f_b = 0;
+  bool uc = br.lo || br.hi;
+  T s_alt_b = (uc && !br.s_alt_cl) ? s_b : T(0);
+  T num = br.lo ? -c : b - c;
+  c_b += -s_alt_b / a;
+  if (br.hi) b_b += s_alt_b / a;
+  a_b += -s_alt_b * num / (a * a);
+  T dn = br.gen ? denom : T(1);
+  T s_raw = br.gen ? (b * f - c * e) / dn : T(0);
+  T s0 = clamp01(s_raw);
+  T u_raw_b = uc ? T(0) : u_b;
+  b_b += u_raw_b * s0 / e;
+  f_b += u_raw_b / e;
+  e_b += -u_raw_b * (b * s0 + f) / (e * e);
+  T s0_b = u_raw_b * b / e + (uc ? T(0) : s_b);
+  T sr_b = br.s_cl ? T(0) : s0_b;
+  b_b += sr_b * f / dn;
+  f_b += sr_b * b / dn;
+  c_b += -sr_b * e / dn;
+  e_b += -sr_b * c / dn;
+  T dn_b = -sr_b * s_raw / dn;
+  a_b += dn_b * e;
+  e_b += dn_b * a;
+  b_b += T(-2) * dn_b * b;
+  V3<T> d1_b = (T(2) * a_b) * d1 + c_b * r + b_b * d2;
+  V3<T> d2_b = (T(2) * e_b) * d2 + f_b * r + b_b * d1;
+  V3<T> r_b = f_b * d2 + c_b * d1;
+  P1b += r_b - d1_b;
+  Q1b += d1_b;
+  P2b -= d2_b + r_b;
+  Q2b += d2_b;
+}
+
+// Geometry of one pair (edge i = P1-Q1 before edge j = P2-Q2).
+template <typename T>
+struct PairGeo {
+  Closest<T> cp;
+  V3<T> diff, n;
+  T dist, d, W, ra, rb;
+  bool act;
+};
+
+template <typename T>
+__device__ __forceinline__ PairGeo<T> pair_geo(V3<T> P1, V3<T> Q1, V3<T> P2, V3<T> Q2, T wi,
+                                               T wi1, T wj, T wj1, T ri, T ri1, T rj, T rj1) {
+  PairGeo<T> g;
+  g.cp = closest_params(P1, Q1, P2, Q2);
+  T s = g.cp.s, u = g.cp.u;
+  V3<T> ca = (T(1) - s) * P1 + s * Q1;
+  V3<T> cb = (T(1) - u) * P2 + u * Q2;
+  g.ra = (T(1) - s) * ri + s * ri1;
+  g.rb = (T(1) - u) * rj + u * rj1;
+  g.W = wi * (T(1) - s) * (T(1) - s) + wi1 * s * s + wj * (T(1) - u) * (T(1) - u) + wj1 * u * u;
+  g.diff = ca - cb;
+  g.dist = sqrt(dot(g.diff, g.diff));
+  g.d = g.ra + g.rb - g.dist;
+  g.act = g.d > T(0) && g.dist > T(1e-12) && g.W > T(0);
+  g.n = (T(1) / (g.act ? g.dist : T(1))) * g.diff;
+  return g;
+}
+
+// Adjoint of the four corrections of an active pair given the adjoints gi,
+// gi1, gj, gj1 of the pass outputs of its four vertices; returns the
+// contributions to the adjoints of the pass inputs.
+template <typename T>
+__device__ __forceinline__ void pair_proj_vjp(V3<T> P1, V3<T> Q1, V3<T> P2, V3<T> Q2,
+                                              const PairGeo<T>& g, T wi, T wi1, T wj, T wj1,
+                                              T ri, T ri1, T rj, T rj1, V3<T> gi, V3<T> gi1,
+                                              V3<T> gj, V3<T> gj1, V3<T>& P1b, V3<T>& Q1b,
+                                              V3<T>& P2b, V3<T>& Q2b) {
+  T s = g.cp.s, u = g.cp.u;
+  V3<T> n = g.n;
+  T kk = g.d / g.W;
+  T ni = dot(gi, n), ni1 = dot(gi1, n), nj = dot(gj, n), nj1 = dot(gj1, n);
+  T kk_b = wi * (T(1) - s) * ni + wi1 * s * ni1 - wj * (T(1) - u) * nj - wj1 * u * nj1;
+  V3<T> n_b = (kk * wi * (T(1) - s)) * gi + (kk * wi1 * s) * gi1 - (kk * wj * (T(1) - u)) * gj -
+              (kk * wj1 * u) * gj1;
+  T s_b = kk * (-wi * ni + wi1 * ni1);
+  T u_b = kk * (wj * nj - wj1 * nj1);
+  T d_b = kk_b / g.W;
+  T W_b = -kk_b * g.d / (g.W * g.W);
+  s_b += W_b * (T(-2) * wi * (T(1) - s) + T(2) * wi1 * s);
+  u_b += W_b * (T(-2) * wj * (T(1) - u) + T(2) * wj1 * u);
+  V3<T> diff_b = (T(1) / g.dist) * (n_b - dot(n, n_b) * n) - d_b * n;
+  s_b += d_b * (ri1 - ri);
+  u_b += d_b * (rj1 - rj);
+  s_b += dot(diff_b, Q1 - P1);
+  u_b -= dot(diff_b, Q2 - P2);
+  P1b += (T(1) - s) * diff_b;
+  Q1b += s * diff_b;
+  P2b -= (T(1) - u) * diff_b;
+  Q2b -= u * diff_b;
+  closest_params_vjp(P1, Q1, P2, Q2, g.cp, s_b, u_b, P1b, Q1b, P2b, Q2b);
+}
+
+// Adjoint of the first-pass depth d of an active pair w.r.t. its inputs.
+template <typename T>
+__device__ __forceinline__ void pair_depth_vjp(V3<T> P1, V3<T> Q1, V3<T> P2, V3<T> Q2,
+                                               const PairGeo<T>& g, T ri, T ri1, T rj, T rj1,
+                                               T d_b, V3<T>& P1b, V3<T>& Q1b, V3<T>& P2b,
+                                               V3<T>& Q2b) {
+  T s = g.cp.s, u = g.cp.u;
+  T s_b = d_b * (ri1 - ri);
+  T u_b = d_b * (rj1 - rj);
+  V3<T> diff_b = (-d_b) * g.n;
+  s_b += dot(diff_b, Q1 - P1);
+  u_b -= dot(diff_b, Q2 - P2);
+  P1b += (T(1) - s) * diff_b;
+  Q1b += s * diff_b;
+  P2b -= (T(1) - u) * diff_b;
+  Q2b -= u * diff_b;
+  closest_params_vjp(P1, Q1, P2, Q2, g.cp, s_b, u_b, P1b, Q1b, P2b, Q2b);
+}
+
+// Friction of one pair at final positions; velocities vi.. of the four
+// vertices; writes the velocity changes of the four vertices.
+template <typename T>
+struct FricGeo {
+  PairGeo<T> g;
+  V3<T> vrel, vt, dvt;
+  T vn, vtn, ratio, scale;
+  bool ok, slide;
+};
+
+template <typename T>
+__device__ __forceinline__ FricGeo<T> pair_friction(V3<T> P1, V3<T> Q1, V3<T> P2, V3<T> Q2,
+                                                    V3<T> vi, V3<T> vi1, V3<T> vj, V3<T> vj1,
+                                                    T wi, T wi1, T wj, T wj1, T ri, T ri1, T rj,
+                                                    T rj1, T d0, T mu, T h) {
+  FricGeo<T> f;
+  f.g = pair_geo(P1, Q1, P2, Q2, wi, wi1, wj, wj1, ri, ri1, rj, rj1);
+  T s = f.g.cp.s, u = f.g.cp.u;
+  f.ok = f.g.dist > T(1e-12) && f.g.W > T(0);
+  f.g.n = (T(1) / (f.ok ? f.g.dist : T(1))) * f.g.diff;
+  f.vrel = (T(1) - s) * vi + s * vi1 - (T(1) - u) * vj - u * vj1;
+  f.vn = dot(f.vrel, f.g.n);
+  f.vt = f.vrel - f.vn * f.g.n;
+  T vtn = sqrt(dot(f.vt, f.vt));
+  f.ok = f.ok && vtn > T(0);
+  f.vtn = f.ok ? vtn : T(1);
+  f.ratio = mu * d0 / (h * f.vtn);
+  f.slide = f.ratio < T(1);
+  f.scale = f.ok ? (f.slide ? f.ratio : T(1)) : T(0);
+  f.dvt = (-f.scale) * f.vt;
+  return f;
+}
+
+// Adjoint of a pair's friction given the adjoints of the four velocity
+// outputs (gi..): adds to the adjoints of the four input velocities, of the
+// four positions, and returns the adjoint of d0.
+template <typename T>
+__device__ __forceinline__ T pair_friction_vjp(V3<T> P1, V3<T> Q1, V3<T> P2, V3<T> Q2, V3<T> vi,
+                                               V3<T> vi1, V3<T> vj, V3<T> vj1,
+                                               const FricGeo<T>& f, T wi, T wi1, T wj, T wj1,
+                                               T mu, T h, V3<T> gi, V3<T> gi1, V3<T> gj,
+                                               V3<T> gj1, V3<T>& vib, V3<T>& vi1b, V3<T>& vjb,
+                                               V3<T>& vj1b, V3<T>& P1b, V3<T>& Q1b, V3<T>& P2b,
+                                               V3<T>& Q2b) {
+  if (!f.ok) return T(0);
+  T s = f.g.cp.s, u = f.g.cp.u;
+  T W = f.g.W;
+  V3<T> n = f.g.n;
+  T ci = wi * (T(1) - s), ci1 = wi1 * s, cj = -wj * (T(1) - u), cj1 = -wj1 * u;
+  V3<T> G = ci * gi + ci1 * gi1 + cj * gj + cj1 * gj1;
+  V3<T> dvt_b = (T(1) / W) * G;
+  T W_b = -dot(G, f.dvt) / (W * W);
+  T s_b = (-wi * dot(gi, f.dvt) + wi1 * dot(gi1, f.dvt)) / W;
+  T u_b = (wj * dot(gj, f.dvt) - wj1 * dot(gj1, f.dvt)) / W;
+  T scale_b = -dot(dvt_b, f.vt);
+  V3<T> vt_b = (-f.scale) * dvt_b;
+  T d0_b = T(0);
+  if (f.slide) {
+    d0_b = scale_b * mu / (h * f.vtn);
+    T vtn_b = -scale_b * f.ratio / f.vtn;
+    vt_b += (vtn_b / f.vtn) * f.vt;
+  }
+  V3<T> vrel_b = vt_b - dot(n, vt_b) * n;
+  V3<T> n_b = -(f.vn * vt_b + dot(vt_b, n) * f.vrel);
+  s_b += dot(vrel_b, vi1 - vi);
+  u_b -= dot(vrel_b, vj1 - vj);
+  vib += (T(1) - s) * vrel_b;
+  vi1b += s * vrel_b;
+  vjb -= (T(1) - u) * vrel_b;
+  vj1b -= u * vrel_b;
+  s_b += W_b * (T(-2) * wi * (T(1) - s) + T(2) * wi1 * s);
+  u_b += W_b * (T(-2) * wj * (T(1) - u) + T(2) * wj1 * u);
+  V3<T> diff_b = (T(1) / f.g.dist) * (n_b - dot(n, n_b) * n);
+  s_b += dot(diff_b, Q1 - P1);
+  u_b -= dot(diff_b, Q2 - P2);
+  P1b += (T(1) - s) * diff_b;
+  Q1b += s * diff_b;
+  P2b -= (T(1) - u) * diff_b;
+  Q2b -= u * diff_b;
+  closest_params_vjp(P1, Q1, P2, Q2, f.g.cp, s_b, u_b, P1b, Q1b, P2b, Q2b);
+  return d0_b;
+}
+
+__device__ __forceinline__ unsigned sc_hash(int ix, int iy, int iz) {
+  return ((unsigned)ix * 73856093u ^ (unsigned)iy * 19349663u ^ (unsigned)iz * 83492791u) &
+         (unsigned)(SC_HT - 1);
+}
+
+}  // namespace rods

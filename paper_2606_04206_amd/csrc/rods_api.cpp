@@ -10,6 +10,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "rods.h"
@@ -24,16 +25,23 @@ constexpr int NF = 11;   // values per vertex of a full state (x 3, v 3, kappa_b
 struct Bin {
   int C, W;       // vertices per lane, waves per rod
   int n, off;     // rods bin_rods[off .. off+n)
+  bool sc;        // rods with self-contact
 };
 
+// self-contact kernels exist for these shapes (FP32)
+static bool sc_shape_ok(int C, int W) {
+  return (C == 2 && (W == 1 || W == 2 || W == 4 || W == 8)) || (C == 4 && W == 4);
+}
+
 // legal launch shapes for a rod of n vertices, smallest team first
-static std::vector<std::pair<int, int>> shapes_for(int n, int prec) {
+static std::vector<std::pair<int, int>> shapes_for(int n, int prec, bool sc = false) {
   std::vector<std::pair<int, int>> out;
   const int Cs[2] = {2, 4};
   const int Ws[4] = {1, 2, 4, 8};
   for (int C : Cs) {
     if (prec == 8 && C != 2) continue;
     for (int W : Ws) {
+      if (sc && !sc_shape_ok(C, W)) continue;
       if (64 * W * C >= n) {
         out.push_back({C, W});
         break;
@@ -75,6 +83,10 @@ struct Impl : HandleBase {
   T* tape = nullptr;
   int64_t tape_stride = 0, tape_cap = 0;
   int64_t* tape_off = nullptr;
+  T* sc_tape = nullptr;          // self-contact projection iterates (one substep per rod)
+  int64_t* sc_off = nullptr;
+  int64_t sc_cap = 0;
+  size_t lds_max = 65536;
   T *lx = nullptr, *lv = nullptr, *lkb = nullptr, *ld1 = nullptr;
   double *acc_b = nullptr, *acc_s = nullptr, *loss_part = nullptr;
   std::vector<Bin> bins;
@@ -196,12 +208,20 @@ struct Impl : HandleBase {
       pr_h[k] = (T)d.prims[k].radius;
     }
     // ---- size bins: smallest legal team per rod, largest rods first
+    {
+      int attr = 0;
+      if (hipDeviceGetAttribute(&attr, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+              hipSuccess && attr > 0)
+        lds_max = (size_t)attr;
+    }
     std::vector<std::vector<int>> members;
-    std::vector<std::pair<int, int>> keys;
+    std::vector<std::tuple<int, int, bool>> keys;
     for (int r = 0; r < R; ++r) {
-      auto sh = shapes_for(voff_h[r + 1] - voff_h[r], prec);
+      const bool sc = (fl_h[r] & ROD_FLAG_SELF) != 0;
+      if (sc && prec != 4) return ROD_EDTYPE;
+      auto sh = shapes_for(voff_h[r + 1] - voff_h[r], prec, sc);
       if (sh.empty()) return ROD_EINVAL;
-      auto key = sh.front();
+      auto key = std::make_tuple(sh.front().first, sh.front().second, sc);
       size_t k = 0;
       while (k < keys.size() && keys[k] != key) ++k;
       if (k == keys.size()) {
@@ -210,23 +230,21 @@ struct Impl : HandleBase {
       }
       members[k].push_back(r);
     }
-    int64_t off = 0;
-    std::vector<int64_t> toff_h(R, 0);
     for (size_t k = 0; k < keys.size(); ++k) {
       auto& m = members[k];
       std::stable_sort(m.begin(), m.end(), [&](int a, int b2) {
         return (voff_h[a + 1] - voff_h[a]) > (voff_h[b2 + 1] - voff_h[b2]);
       });
-      Bin bn{keys[k].first, keys[k].second, (int)m.size(), (int)bin_rods_h.size()};
+      Bin bn{std::get<0>(keys[k]), std::get<1>(keys[k]), (int)m.size(), (int)bin_rods_h.size(),
+             std::get<2>(keys[k])};
+      if (rods::kernel_lds_bytes<T>(2, bn.C, bn.W, bn.sc, d.n_iters) > lds_max) return ROD_EINVAL;
       bins.push_back(bn);
-      for (int r : m) {
-        bin_rods_h.push_back(r);
-        toff_h[r] = off;
-        off += (int64_t)NF * bn.C * 64 * bn.W;
-      }
+      for (int r : m) bin_rods_h.push_back(r);
     }
-    tape_stride = off;
-    tape_cap = 2 * off;   // autotuned teams are at most twice the smallest legal one
+    std::vector<int64_t> toff_h, soff_h;
+    layout_offsets(toff_h, soff_h);
+    tape_cap = 2 * tape_stride;   // autotuned teams are at most twice the smallest legal one
+    sc_cap = 2 * sc_stride_;
     n_ck = std::max(1, (d.max_steps + d.ckpt_every - 1) / d.ckpt_every);
     n_act_max = std::max(1, (d.max_steps + d.steps_per_action - 1) / d.steps_per_action);
 
@@ -237,7 +255,8 @@ struct Impl : HandleBase {
         (e = upload(mu, mu_h)) || (e = upload(restit, e_h)) || (e = upload(K, K_h)) ||
         (e = upload(w, w_h)) || (e = upload(rest, rest_h)) || (e = upload(radius, rad_h)) ||
         (e = upload(prim_a, pa_h)) || (e = upload(prim_b, pb_h)) || (e = upload(prim_r, pr_h)) ||
-        (e = upload(bin_rods, bin_rods_h)) || (e = upload(tape_off, toff_h)))
+        (e = upload(bin_rods, bin_rods_h)) || (e = upload(tape_off, toff_h)) ||
+        (e = upload(sc_off, soff_h)) || (e = alloc(sc_tape, (size_t)sc_cap)))
       return e;
     if ((e = alloc(x, 3 * (size_t)V)) || (e = alloc(v, 3 * (size_t)V)) ||
         (e = alloc(kb, 2 * (size_t)V)) || (e = alloc(d1, 3 * (size_t)V)) ||
@@ -261,6 +280,27 @@ struct Impl : HandleBase {
     return ROD_OK;
   }
 
+  int64_t sc_stride_ = 0;
+  // per-rod offsets of the backward tape block and of the self-contact
+  // iterate block for the current launch shapes
+  void layout_offsets(std::vector<int64_t>& toff_h, std::vector<int64_t>& soff_h) {
+    toff_h.assign(R, 0);
+    soff_h.assign(R, 0);
+    int64_t off = 0, soff = 0;
+    for (const Bin& bn : bins)
+      for (int i = 0; i < bn.n; ++i) {
+        int r = bin_rods_h[bn.off + i];
+        toff_h[r] = off;
+        off += (int64_t)NF * bn.C * 64 * bn.W;
+        if (bn.sc) {
+          soff_h[r] = soff;
+          soff += (int64_t)2 * d.n_iters * bn.C * 3 * 64 * bn.W;
+        }
+      }
+    tape_stride = off;
+    sc_stride_ = soff;
+  }
+
   RodArgs<T> args(hipStream_t) const {
     RodArgs<T> a{};
     a.voff = voff;
@@ -277,6 +317,7 @@ struct Impl : HandleBase {
     a.spa = d.steps_per_action;
     a.lx = lx; a.lv = lv; a.lkb = lkb; a.ld1 = ld1;
     a.acc_b = acc_b; a.acc_s = acc_s;
+    a.sc_tape = sc_tape; a.sc_off = sc_off;
     a.status = status;
     a.h = (T)(d.dt / d.n_sub);
     a.gx = (T)d.gravity[0]; a.gy = (T)d.gravity[1]; a.gz = (T)d.gravity[2];
@@ -302,7 +343,7 @@ struct Impl : HandleBase {
     if (!plain) {
       for (const Bin& bn : bins) {
         a.rods = bin_rods + bn.off;
-        HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, a, bn.n, st));
+        HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, bn.sc, a, bn.n, st));
       }
       return ROD_OK;
     }
@@ -320,7 +361,7 @@ struct Impl : HandleBase {
           b1.step_off = step_off + s;
           if (tape0) b1.tape = tape0 + (int64_t)s * d.n_sub * tape_stride;
           b1.ck_x = (s == n_steps - 1) ? a.ck_x : nullptr;
-          HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, b1, 1, st));
+          HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, bn.sc, b1, 1, st));
         }
       }
     }
@@ -458,7 +499,8 @@ struct Impl : HandleBase {
       for (int C : Cs)
         for (int W : Ws)
           if (64 * W * C >= nmax && 64 * W * C <= 2 * team0 && !(prec == 8 && C != 2) &&
-              !(C == 4 && W == 8))
+              !(C == 4 && W == 8) && (!bn.sc || sc_shape_ok(C, W)) &&
+              rods::kernel_lds_bytes<T>(2, C, W, bn.sc, d.n_iters) <= lds_max)
             cand.push_back({C, W});
       float best = 1e30f;
       std::pair<int, int> bestk{bn.C, bn.W};
@@ -467,9 +509,9 @@ struct Impl : HandleBase {
         a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;   // time on the scratch copy
         a.u = u0; a.act_stride = 0; a.spa = 1; a.step_off = 0; a.n_steps = n_steps;
         a.rods = bin_rods + bn.off;
-        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, a, bn.n, st));   // warm
+        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, bn.sc, a, bn.n, st));   // warm
         HIPCHK(hipEventRecord(e0, st));
-        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, a, bn.n, st));
+        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, bn.sc, a, bn.n, st));
         HIPCHK(hipEventRecord(e1, st));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
@@ -481,17 +523,12 @@ struct Impl : HandleBase {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // the tape layout depends on the shapes
-    std::vector<int64_t> toff_h(R, 0);
-    int64_t off = 0;
-    for (const Bin& bn : bins)
-      for (int i = 0; i < bn.n; ++i) {
-        toff_h[bin_rods_h[bn.off + i]] = off;
-        off += (int64_t)NF * bn.C * 64 * bn.W;
-      }
-    if (off > tape_cap) return ROD_EINVAL;   // cannot grow after create
-    tape_stride = off;
+    // the tape layouts depend on the shapes
+    std::vector<int64_t> toff_h, soff_h;
+    layout_offsets(toff_h, soff_h);
+    if (tape_stride > tape_cap || sc_stride_ > sc_cap) return ROD_EINVAL;   // cannot grow after create
     HIPCHK(hipMemcpy(tape_off, toff_h.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(sc_off, soff_h.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice));
     HIPCHK(hipStreamSynchronize(st));
     recorded = false;
     return ROD_OK;

@@ -196,11 +196,16 @@ def _target_curve(rng, x_ref, rest_edges):
 # ----------------------------------------------------------------------------
 
 def make_workload(cid: int, steps: Optional[int] = None,
-                  start_height: Optional[float] = None) -> Workload:
-    """start_height (configurations 2-4): height of the initial arc instead of
-    the configured one (tests use a height just above the ground to start in
-    contact)."""
+                  start_height: Optional[float] = None, pitch: Optional[float] = None,
+                  n_vert: Optional[int] = None, n_rods: Optional[int] = None) -> Workload:
+    """Test knobs: start_height (configurations 2-4) replaces the initial arc
+    height (tests start just above the ground, in contact); pitch, n_vert and
+    n_rods (configuration 5) replace the helix pitch (below 2 r the coils
+    start in self-contact), the vertices per rod and the number of rods."""
     cfg = CONFIGS[cid]
+    if cid == 5 and (n_vert is not None or n_rods is not None):
+        cfg = replace(cfg, n_vert=n_vert or cfg.n_vert, n_rods=n_rods or cfg.n_rods,
+                      oracle_rods=(0, (n_rods or cfg.n_rods) - 1))
     sim = cfg.sim if steps is None else replace(cfg.sim, steps=steps)
     spa = sim.steps_per_action
     n_act = -(-sim.steps // spa)
@@ -251,7 +256,8 @@ def make_workload(cid: int, steps: Optional[int] = None,
             n = cfg.n_vert
             edge = EDGE_LEN
             rho = rng.uniform(0.05, 0.15)
-            x_clean = helix_polyline(n, edge, rho, 0.03, 0.05, rng.uniform(0.0, 2.0 * np.pi))
+            x_clean = helix_polyline(n, edge, rho, pitch or 0.03, 0.05,
+                                     rng.uniform(0.0, 2.0 * np.pi))
             x = x_clean + rng.normal(0.0, 1e-3, size=(n, 3))
             xr = x_clean
         rest_e = np.linalg.norm(x_clean[1:] - x_clean[:-1], axis=1)

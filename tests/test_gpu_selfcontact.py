@@ -1,0 +1,98 @@
+"""GPU parity with self-contact (App. A.1, "Self-collision and Friction"):
+helices whose pitch (9 mm) is below the rod diameter, so neighbouring coils
+start interpenetrating and every substep has active pairs and friction."""
+import numpy as np
+import pytest
+import torch
+
+from synth import make_workload
+from oracle import forward as ofw, adjoint as oadj
+from oracle.model import rods_from_workload, sim_from_workload, State
+from tests.gpukit import (to_dev, sub_workload, gather_state, initial_full_state, rel_err)
+
+pytestmark = pytest.mark.gpu
+
+
+def _handle(wl, **kw):
+    from paper_2606_04206_amd import RodsHandle
+    return RodsHandle(wl, precision=4, **kw)
+
+
+def _teacher_forced_substep(wl):
+    run = sub_workload(wl)
+    h = _handle(run, max_steps=2)
+    full = initial_full_state(wl)
+    h.set_state(*(to_dev(a) for a in full))
+    h.step(to_dev(wl.actions[0]))
+    out = [t.double().cpu().numpy() for t in h.get_state()]
+    st = h.status()
+    return run, full, out, st
+
+
+@pytest.mark.parametrize("n_vert,n_rods", [(64, 8), (1024, 256)])
+def test_selfcontact_substep_teacher_forced(n_vert, n_rods):
+    """One substep from the interpenetrating helices: positions <= 1e-4 per
+    oracle rod, and velocities agree at every vertex away from friction and
+    contact ties (1e-3 relative + 5e-3 m/s)."""
+    wl = make_workload(5, steps=2, pitch=0.009, n_vert=n_vert, n_rods=n_rods)
+    run, full, out, status = _teacher_forced_substep(wl)
+    assert not status.any(), status[status != 0]
+    n_pairs = 0
+    for r in wl.oracle_rods:
+        st = gather_state(wl, [r], [a.astype(np.float32).astype(np.float64) for a in full])
+        orods, osim = rods_from_workload(run, [r]), sim_from_workload(run)
+        rec = {}
+        ref = ofw.substep(orods, osim, st, wl.actions[0][[r]], rec)
+        gpu = gather_state(wl, [r], out)
+        assert rel_err(gpu.x, ref.x) <= 1e-4, r
+        n_pairs += int((rec["d0"][0] > 0).sum())
+        dv = np.linalg.norm(gpu.v[0] - ref.v[0], axis=-1)
+        tol = 1e-3 * np.linalg.norm(ref.v[0], axis=-1) + 5e-3
+        assert np.mean(dv <= tol) > 0.99, (r, dv.max())
+    assert n_pairs > 20
+
+
+def test_selfcontact_step_parity_1024():
+    """A full step (15 substeps) of the 256 x 1024 interpenetrating helices:
+    positions <= 1e-4 on the oracle rods."""
+    wl = make_workload(5, steps=2, pitch=0.009)
+    h = _handle(wl, max_steps=2)
+    full = initial_full_state(wl)
+    h.set_state(*(to_dev(a) for a in full))
+    h.step(to_dev(wl.actions[0]))
+    out = [t.double().cpu().numpy() for t in h.get_state()]
+    assert not h.status().any()
+    for r in wl.oracle_rods:
+        st = gather_state(wl, [r], [a.astype(np.float32).astype(np.float64) for a in full])
+        orods, osim = rods_from_workload(wl, [r]), sim_from_workload(wl)
+        ref = ofw.step(orods, osim, st, wl.actions[0][[r]])
+        assert rel_err(gather_state(wl, [r], out).x, ref.x) <= 1e-4, r
+
+
+def test_selfcontact_rollout_gradients():
+    """Eight 64-vertex interpenetrating helices, 3 steps, checkpoint every 2,
+    creep rate 0.5: FP32 gradients w.r.t. grasp velocities, b, sigma_y and
+    the initial state within 1e-3 of the oracle."""
+    n, K = 3, 2
+    wl = make_workload(5, steps=n, pitch=0.009, n_vert=64, n_rods=8)
+    wl.rod_params[:, 4] = 0.5
+    h = _handle(wl, max_steps=n, ckpt_every=K)
+    h.set_state(*(to_dev(a) for a in initial_full_state(wl)))
+    xT = h.tensor(wl.n_vert, 3)
+    h.rollout(n, to_dev(wl.actions), record=True, x_final=xT)
+    loss, g = h.loss_mse(xT, to_dev(wl.target))
+    gg = {k: v.double().cpu().numpy() for k, v in h.backward(g, n_steps=n).items()}
+    assert not h.status().any()
+    rods = list(range(wl.n_rods))
+    orods, osim = rods_from_workload(wl, rods), sim_from_workload(wl)
+    st = gather_state(wl, rods, initial_full_state(wl))
+    xr, ck = ofw.rollout(orods, osim, st, wl.actions, n, K)
+    L, gx = oadj.loss_mse(xr.x, wl.target.reshape(xr.x.shape), wl.n_rods)
+    x0b, v0b, Ub, bb, sb = oadj.backward(orods, osim, ck, wl.actions, n, K, gx)
+    assert abs(float(loss.item()) - L) <= 1e-4 * L
+    for r in rods:
+        assert rel_err(gg["u"][:, r], Ub[:, r]) <= 1e-3, ("u", r)
+        a, b = wl.rod_range(r)
+        assert rel_err(gg["x0"][a:b], x0b[r]) <= 1e-3, ("x0", r)
+    assert rel_err(gg["b"], bb) <= 1e-3
+    assert rel_err(gg["sigma"], sb) <= 1e-3
