@@ -44,6 +44,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-autotune", action="store_true")
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="run one device copy of this many MiB before timing (a kernel of "
+                        "known traffic for scaling hardware byte counters)")
     return p.parse_args()
 
 
@@ -118,6 +121,13 @@ def main():
         loss, g = h.loss_mse(xT, tgt)
         return loss, h.backward(g, n_steps=n_steps)
 
+    if a.calib_copy_mib:
+        n = a.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(a.warmup):
         bench_step()
     torch.cuda.synchronize()

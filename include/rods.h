@@ -138,6 +138,12 @@ int rods_curvature(RodsHandle* h, const void* x, const void* d1, void* kappa,
  * Does not record.  Safe to capture in a HIP graph. */
 int rods_step(RodsHandle* h, const void* grasp_vel, rods_stream_t stream);
 
+/* Same as rods_step, replayed from a HIP graph of the step's kernel launches
+ * (captured on the first call and after rods_autotune or rods_set_plain; the
+ * graph works on the handle's own buffers).  The action is copied into the
+ * handle before the replay, outside the graph. */
+int rods_step_graph(RodsHandle* h, const void* grasp_vel, rods_stream_t stream);
+
 /* Advances by n_steps; step s uses grasp_vel[s / steps_per_action] with
  * grasp_vel of shape [ceil(n_steps/steps_per_action)][R][G][3].  x_final
  * [V][3] receives the final positions (NULL to skip).  With record != 0 the

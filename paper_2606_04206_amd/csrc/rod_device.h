@@ -36,6 +36,16 @@ __device__ __forceinline__ V3<T> cross(V3<T> a, V3<T> b) {
 template <typename T>
 __device__ __forceinline__ V3<T> sel(bool c, V3<T> a, V3<T> b) { return c ? a : b; }
 
+// Reciprocal, quotient and square root.  FP32 uses the hardware
+// instructions (v_rcp_f32, v_sqrt_f32: about 1 ulp) instead of the correctly
+// rounded multi-instruction sequences; FP64 keeps IEEE division and sqrt.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+template <typename T>
+__device__ __forceinline__ T fdiv(T a, T b) { return a * frcp(b); }
+
 // ---------------------------------------------------------------------------
 // Lane exchange.  A rod is owned by a team of 64*W lanes (W waves of one
 // workgroup); team lane l holds vertices l*C .. l*C+C-1.  Inside a wave the

@@ -32,7 +32,7 @@ template <typename T>
 __device__ __forceinline__ V3<T> transport(V3<T> v, V3<T> ta, V3<T> tb) {
   V3<T> bb = cross(ta, tb);
   T c = dot(ta, tb);
-  return c * v + cross(bb, v) + (dot(bb, v) / (T(1) + c)) * bb;
+  return c * v + cross(bb, v) + fdiv(dot(bb, v), T(1) + c) * bb;
 }
 
 // Adjoint of transport: y = R(ta->tb) v.  Returns v_b; adds to ta_b, tb_b.
@@ -42,7 +42,7 @@ __device__ __forceinline__ V3<T> transport_vjp(V3<T> v, V3<T> ta, V3<T> tb, V3<T
   V3<T> bb = cross(ta, tb);
   T c = dot(ta, tb);
   T bv = dot(bb, v), by = dot(bb, yb);
-  T iopc = T(1) / (T(1) + c);
+  T iopc = frcp(T(1) + c);
   V3<T> vb = c * yb - cross(bb, yb) + (by * iopc) * bb;
   T cb = dot(v, yb) - bv * by * iopc * iopc;
   V3<T> bbb = cross(v, yb) + iopc * (bv * yb + by * v);
@@ -61,18 +61,18 @@ struct BendIn {
 
 template <typename T>
 __device__ __forceinline__ void bend_grad(const BendIn<T>& q, T b, V3<T>& g0, V3<T>& g1) {
-  T ichi = T(1) / (T(1) + dot(q.t0, q.t1));
+  T ichi = frcp(T(1) + dot(q.t0, q.t1));
   V3<T> kbv = (T(2) * ichi) * cross(q.t0, q.t1);
   V3<T> a1 = T(0.5) * (q.d2a + q.d2b);
   V3<T> a2 = T(0.5) * (q.d1a + q.d1b);
   T k1 = dot(kbv, a1), k2 = dot(kbv, a2);
-  T coef = b / q.lbar;
+  T coef = fdiv(b, q.lbar);
   T c1 = coef * (k1 - q.kr0), c2 = coef * (k2 - q.kr1);
   T s = c1 * k1 + c2 * k2;
   V3<T> A = (T(2) * ichi) * (c1 * a1 + c2 * a2);
   V3<T> tt = ichi * (q.t0 + q.t1);
-  g0 = (T(1) / q.l0) * (cross(q.t1, A) - s * tt);
-  g1 = (T(1) / q.l1) * (-(s * tt) - cross(q.t0, A));
+  g0 = frcp(q.l0) * (cross(q.t1, A) - s * tt);
+  g1 = frcp(q.l1) * (-(s * tt) - cross(q.t0, A));
 }
 
 template <typename T>
@@ -86,19 +86,19 @@ template <typename T>
 __device__ __forceinline__ void bend_vjp(const BendIn<T>& q, T b, V3<T> g0b, V3<T> g1b,
                                          BendBar<T>& o) {
   T chi = T(1) + dot(q.t0, q.t1);
-  T ichi = T(1) / chi;
+  T ichi = frcp(chi);
   V3<T> nn = cross(q.t0, q.t1);
   V3<T> kbv = (T(2) * ichi) * nn;
   V3<T> a1 = T(0.5) * (q.d2a + q.d2b);
   V3<T> a2 = T(0.5) * (q.d1a + q.d1b);
   T k1 = dot(kbv, a1), k2 = dot(kbv, a2);
-  T coef = b / q.lbar;
+  T coef = fdiv(b, q.lbar);
   T dk1 = k1 - q.kr0, dk2 = k2 - q.kr1;
   T c1 = coef * dk1, c2 = coef * dk2;
   T s = c1 * k1 + c2 * k2;
   V3<T> A = (T(2) * ichi) * (c1 * a1 + c2 * a2);
   V3<T> tt = ichi * (q.t0 + q.t1);
-  T il0 = T(1) / q.l0, il1 = T(1) / q.l1;
+  T il0 = frcp(q.l0), il1 = frcp(q.l1);
   V3<T> g0 = il0 * (cross(q.t1, A) - s * tt);
   V3<T> g1 = il1 * (-(s * tt) - cross(q.t0, A));
   // g = G / l
@@ -120,7 +120,7 @@ __device__ __forceinline__ void bend_vjp(const BendIn<T>& q, T b, V3<T> g0b, V3<
   T k2b = c2 * sb + coef * c2b;
   o.kr0 = -coef * c1b;
   o.kr1 = -coef * c2b;
-  o.b = (c1b * dk1 + c2b * dk2) / q.lbar;
+  o.b = fdiv(c1b * dk1 + c2b * dk2, q.lbar);
   V3<T> kbvb = k1b * a1 + k2b * a2;
   a1b += k1b * kbv;
   a2b += k2b * kbv;
@@ -140,7 +140,7 @@ __device__ __forceinline__ void bend_vjp(const BendIn<T>& q, T b, V3<T> g0b, V3<
 // Material curvature (kb.a1, kb.a2) at an interior vertex (App. A.1).
 template <typename T>
 __device__ __forceinline__ void curvature(V3<T> t0, V3<T> t1, V3<T> d1a, V3<T> d1b, T& k1, T& k2) {
-  T ichi = T(1) / (T(1) + dot(t0, t1));
+  T ichi = frcp(T(1) + dot(t0, t1));
   V3<T> kbv = (T(2) * ichi) * cross(t0, t1);
   V3<T> a1 = T(0.5) * (cross(t0, d1a) + cross(t1, d1b));
   V3<T> a2 = T(0.5) * (d1a + d1b);
@@ -154,7 +154,7 @@ __device__ __forceinline__ void curvature_vjp(V3<T> t0, V3<T> t1, V3<T> d1a, V3<
                                               T k2b, V3<T>& t0b, V3<T>& t1b, V3<T>& d1ab,
                                               V3<T>& d1bb) {
   T chi = T(1) + dot(t0, t1);
-  T ichi = T(1) / chi;
+  T ichi = frcp(chi);
   V3<T> kbv = (T(2) * ichi) * cross(t0, t1);
   V3<T> d2a = cross(t0, d1a), d2b = cross(t1, d1b);
   V3<T> a1 = T(0.5) * (d2a + d2b);
@@ -179,8 +179,8 @@ __device__ __forceinline__ V3<T> project_edge(V3<T>& pj, V3<T>& pk, T wj, T wk, 
   V3<T> D = pk - pj;
   T W = wj + wk;
   if (W > T(0)) {
-    T l = sqrt(dot(D, D));
-    T s = (l - r) / (W * l);
+    T l = fsqrt(dot(D, D));
+    T s = fdiv(l - r, W * l);
     pj += (s * wj) * D;
     pk -= (s * wk) * D;
   }
@@ -192,10 +192,10 @@ template <typename T>
 __device__ __forceinline__ V3<T> project_edge_vjp(V3<T> D, T wj, T wk, T r, V3<T> aj, V3<T> ak) {
   T W = wj + wk;
   if (!(W > T(0))) return zero3<T>();
-  T l = sqrt(dot(D, D));
-  T il = T(1) / l;
+  T l = fsqrt(dot(D, D));
+  T il = frcp(l);
   V3<T> t = il * D;
-  V3<T> qb = (T(1) / W) * (wj * aj - wk * ak);
+  V3<T> qb = frcp(W) * (wj * aj - wk * ak);
   return qb - (r * il) * (qb - dot(t, qb) * t);
 }
 
@@ -234,13 +234,13 @@ __device__ __forceinline__ T sdf_normal(const Prim<T>& p, V3<T> x, V3<T>& n, boo
     q = x - p.a;
   } else {
     V3<T> ab = p.b - p.a;
-    T s = dot(x - p.a, ab) / dot(ab, ab);
+    T s = fdiv(dot(x - p.a, ab), dot(ab, ab));
     interior = (s > T(0)) && (s < T(1));
     s = s < T(0) ? T(0) : (s > T(1) ? T(1) : s);
     q = x - (p.a + s * ab);
   }
-  nq = sqrt(dot(q, q));
-  n = (T(1) / nq) * q;
+  nq = fsqrt(dot(q, q));
+  n = frcp(nq) * q;
   return nq - p.r;
 }
 
@@ -256,15 +256,15 @@ __device__ __forceinline__ bool contact_one(const Prim<T>& p, V3<T> x, T rad, T 
   T nq;
   T sdf = sdf_normal(p, x, n, interior, nq);
   T d = rad - sdf;
-  T f = d >= T(0) ? T(1) : exp_t(d / eps_s);
+  T f = d >= T(0) ? T(1) : exp_t(fdiv(d, eps_s));
   T vn = dot(v, n);
   if (!(f > f_thresh && vn < T(0))) return false;
   T dvn = -(T(1) + e) * vn;
   V3<T> vt = v - vn * n;
-  T vtn = sqrt(dot(vt, vt));
+  T vtn = fsqrt(dot(vt, vt));
   T s = T(0);
   if (vtn > T(0)) {
-    T sr = T(1) - mu * dvn / vtn;
+    T sr = T(1) - fdiv(mu * dvn, vtn);
     s = sr > T(0) ? sr : T(0);
   }
   V3<T> vres = (-e * vn) * n + s * vt;
@@ -284,16 +284,16 @@ __device__ __forceinline__ void contact_one_vjp(const Prim<T>& p, V3<T> x, T rad
   T nq;
   T sdf = sdf_normal(p, x, n, interior, nq);
   T d = rad - sdf;
-  T f = d >= T(0) ? T(1) : exp_t(d / eps_s);
+  T f = d >= T(0) ? T(1) : exp_t(fdiv(d, eps_s));
   T vn = dot(vin, n);
   if (!(f > f_thresh && vn < T(0))) return;
   T dvn = -(T(1) + e) * vn;
   V3<T> vt = vin - vn * n;
-  T vtn = sqrt(dot(vt, vt));
+  T vtn = fsqrt(dot(vt, vt));
   T s = T(0);
   bool slide = false;
   if (vtn > T(0)) {
-    T sr = T(1) - mu * dvn / vtn;
+    T sr = T(1) - fdiv(mu * dvn, vtn);
     slide = sr > T(0);
     s = slide ? sr : T(0);
   }
@@ -307,26 +307,26 @@ __device__ __forceinline__ void contact_one_vjp(const Prim<T>& p, V3<T> x, T rad
   T sb = dot(vt, vresb);
   V3<T> vtb = s * vresb;
   if (slide) {
-    T dvnb = -mu * sb / vtn;
-    T vtnb = mu * dvn * sb / (vtn * vtn);
+    T dvnb = fdiv(-mu * sb, vtn);
+    T vtnb = fdiv(mu * dvn * sb, vtn * vtn);
     vnb += -(T(1) + e) * dvnb;
-    vtb += (vtnb / vtn) * vt;
+    vtb += fdiv(vtnb, vtn) * vt;
   }
   vib += vtb;
   vnb -= dot(n, vtb);
   nb -= vn * vtb;
   vib += vnb * n;
   nb += vnb * vin;
-  T db = d < T(0) ? fb * f / eps_s : T(0);
+  T db = d < T(0) ? fdiv(fb * f, eps_s) : T(0);
   T sdfb = -db;
   if (p.type == 0) {
     xb += sdfb * p.b;
   } else {
-    V3<T> perp = (T(1) / nq) * (nb - dot(n, nb) * n);
+    V3<T> perp = frcp(nq) * (nb - dot(n, nb) * n);
     V3<T> g = sdfb * n + perp;
     if (p.type == 2 && interior) {
       V3<T> ab = p.b - p.a;
-      V3<T> u = (T(1) / sqrt(dot(ab, ab))) * ab;
+      V3<T> u = frcp(fsqrt(dot(ab, ab))) * ab;
       g -= dot(perp, u) * u;
     }
     xb += g;
@@ -481,10 +481,10 @@ struct Rod {
     for (int c = 0; c < C; ++c) {
       V3<T> q = (c < C - 1) ? p[c + 1] : mk(pn[0], pn[1], pn[2]);
       V3<T> D = q - p[c];
-      T ll = sqrt(dot(D, D));
+      T ll = fsqrt(dot(D, D));
       bool ok = evalid(c);
       l[c] = ok ? ll : T(1);
-      t[c] = ok ? (T(1) / ll) * D : zero3<T>();
+      t[c] = ok ? frcp(ll) * D : zero3<T>();
     }
   }
 
@@ -494,7 +494,7 @@ struct Rod {
     V3<T> eb[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      eb[c] = evalid(c) ? (T(1) / l[c]) * (tb[c] - dot(t[c], tb[c]) * t[c]) + lb[c] * t[c]
+      eb[c] = evalid(c) ? frcp(l[c]) * (tb[c] - dot(t[c], tb[c]) * t[c]) + lb[c] * t[c]
                         : zero3<T>();
       pb[c] -= eb[c];
       if (c < C - 1) pb[c + 1] += eb[c];
@@ -618,8 +618,13 @@ struct Rod {
   }
 
   // ------------------------------------------------------------ self-contact
+  // LDS: staging (positions, velocities), statics, first-pass depths, the
+  // hash (counts, starts, items) and the partner lists.  The adjoint's third
+  // staging buffer reuses the hash counts and starts, which are dead once the
+  // partner lists are built.
   static constexpr size_t sc_bytes() {
-    return sizeof(T) * (size_t)(3 * NV * 3 + 2 * NV + NV * SC_MAXP) +
+    static_assert(!SC || 2 * SC_HT * sizeof(int) >= 3 * NV * sizeof(T), "adjoint staging alias");
+    return sizeof(T) * (size_t)(2 * NV * 3 + 2 * NV + NV * SC_MAXP) +
            sizeof(int) * (size_t)(SC_HT + SC_HT + 1 + NV + 2 * TL) +
            sizeof(short) * (size_t)(NV + NV * SC_MAXP) + 64;
   }
@@ -627,13 +632,13 @@ struct Rod {
     T* f = reinterpret_cast<T*>(base);
     sc_pos = f; f += 3 * NV;
     sc_aux = f; f += 3 * NV;
-    sc_adj = f; f += 3 * NV;
     sc_w = f; f += NV;
     sc_r = f; f += NV;
     sc_d0 = f; f += NV * SC_MAXP;
     int* q = reinterpret_cast<int*>(f);
     sc_cnt = q; q += SC_HT;
     sc_start = q; q += SC_HT + 1;
+    sc_adj = reinterpret_cast<T*>(sc_cnt);
     sc_pcnt = q; q += NV;
     sc_tmp = q; q += 2 * TL;
     short* sh = reinterpret_cast<short*>(q);
@@ -693,7 +698,7 @@ struct Rod {
     sc_stage(sc_pos, p);
     for (int i = tl; i < SC_HT; i += TL) sc_cnt[i] = 0;
     __syncthreads();
-    const T ig = T(1) / sc_cell;
+    const T ig = frcp(sc_cell);
     unsigned key[C];
     int slot[C];
 #pragma unroll
@@ -765,7 +770,7 @@ struct Rod {
               V3<T> df = ca - cb;
               T ra = (T(1) - cp.s) * sc_r[lo] + cp.s * sc_r[lo + 1];
               T rb = (T(1) - cp.u) * sc_r[hi] + cp.u * sc_r[hi + 1];
-              if (!(sqrt(dot(df, df)) < ra + rb + margin)) continue;
+              if (!(fsqrt(dot(df, df)) < ra + rb + margin)) continue;
               // sorted insert without duplicates (hash collisions revisit buckets)
               int at = 0;
               while (at < cnt && pl[at] < j) ++at;
@@ -817,7 +822,7 @@ struct Rod {
         PairGeo<T> g = sc_pair(sc_pos, lo, hi);
         if (first) sc_d0[e * SC_MAXP + k] = g.act ? g.d : T(0);
         if (g.act) {
-          T kk = g.d / g.W;
+          T kk = fdiv(g.d, g.W);
           if (e == lo) {
             dA[c] += (kk * sc_w[lo] * (T(1) - g.cp.s)) * g.n;
             dB[c] += (kk * sc_w[lo + 1] * g.cp.s) * g.n;
@@ -862,7 +867,7 @@ struct Rod {
                                      sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
                                      sc_r[hi + 1], d0, mu, a.h);
         if (!f.ok) continue;
-        T iW = T(1) / f.g.W;
+        T iW = frcp(f.g.W);
         if (e == lo) {
           dA[c] += (sc_w[lo] * (T(1) - f.g.cp.s) * iW) * f.dvt;
           dB[c] += (sc_w[lo + 1] * f.g.cp.s * iW) * f.dvt;
@@ -993,9 +998,12 @@ struct Rod {
     dp = mk(pv[4], pv[5], pv[6]);
   }
 
+  // kr0/kr1: the rest curvature at the substep start (the adjoint passes the
+  // recorded values: the replayed substep has already updated the registers)
   __device__ __forceinline__ BendIn<T> bend_in(int c, const V3<T> (&t)[C], const T (&l)[C],
                                                const V3<T> (&dd1)[C], V3<T> tp, T lp,
-                                               V3<T> d1p) const {
+                                               V3<T> d1p, const T (&k0)[C],
+                                               const T (&k1)[C]) const {
     BendIn<T> q;
     q.t0 = c ? t[c - 1] : tp;
     q.t1 = t[c];
@@ -1005,8 +1013,8 @@ struct Rod {
     q.d1b = dd1[c];
     q.d2a = cross(q.t0, q.d1a);
     q.d2b = cross(q.t1, q.d1b);
-    q.kr0 = kr0[c];
-    q.kr1 = kr1[c];
+    q.kr0 = k0[c];
+    q.kr1 = k1[c];
     q.lbar = lbar[c];
     return q;
   }
@@ -1032,7 +1040,7 @@ struct Rod {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       if (ivalid(c)) {
-        BendIn<T> q = bend_in(c, t, l, d1, tp, lp, d1p);
+        BendIn<T> q = bend_in(c, t, l, d1, tp, lp, d1p, kr0, kr1);
         V3<T> g0, g1;
         bend_grad(q, b, g0, g1);
         F[c] += g1 - g0;
@@ -1044,7 +1052,7 @@ struct Rod {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         if (evalid(c)) {
-          V3<T> q = (ks[c] * (l[c] / rest[c] - T(1))) * t[c];
+          V3<T> q = (ks[c] * (fdiv(l[c], rest[c]) - T(1))) * t[c];
           F[c] += q;
           if (c < C - 1) F[c + 1] -= q; else to_next -= q;
         }
@@ -1155,10 +1163,10 @@ struct Rod {
           T k1, k2;
           curvature(c ? t1[c - 1] : t1p, t1[c], c ? d1[c - 1] : d1np, d1[c], k1, k2);
           T e0 = k1 - kr0[c], e1 = k2 - kr1[c];
-          T nrm = sqrt(e0 * e0 + e1 * e1);
+          T nrm = fsqrt(e0 * e0 + e1 * e1);
           T thr = sig * lbar[c];
           bool y = nrm > thr;
-          T phi = y ? rc * (nrm - thr) / nrm : T(0);
+          T phi = y ? fdiv(rc * (nrm - thr), nrm) : T(0);
           if constexpr (REC) {
             rc_->kel0[c] = e0;
             rc_->kel1[c] = e1;
@@ -1199,11 +1207,11 @@ struct Rod {
           T o0 = lk0[c], o1 = lk1[c];
           T phi = r.phi[c], nrm = r.nrm[c], thr = sig * lbar[c];
           T phib = r.kel0[c] * o0 + r.kel1[c] * o1;
-          T nrmb = rc * thr / (nrm * nrm) * phib;
-          T thrb = -rc / nrm * phib;
+          T nrmb = fdiv(rc * thr, nrm * nrm) * phib;
+          T thrb = fdiv(-rc, nrm) * phib;
           accs[c] += (double)(lbar[c] * thrb);
-          T e0 = phi * o0 + (nrmb / nrm) * r.kel0[c];
-          T e1 = phi * o1 + (nrmb / nrm) * r.kel1[c];
+          T e0 = phi * o0 + fdiv(nrmb, nrm) * r.kel0[c];
+          T e1 = phi * o1 + fdiv(nrmb, nrm) * r.kel1[c];
           lk0[c] -= e0;
           lk1[c] -= e1;
           V3<T> t0b, tcb, dab, dcb;
@@ -1307,7 +1315,7 @@ struct Rod {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       if (ivalid(c)) {
-        BendIn<T> q = bend_in(c, r.t, r.ell, r.d1, r.tp, r.lp, r.d1p);
+        BendIn<T> q = bend_in(c, r.t, r.ell, r.d1, r.tp, r.lp, r.d1p, r.kr0, r.kr1);
         V3<T> Fm = c ? Fb[c - 1] : Fp;
         V3<T> Fq = (c < C - 1) ? Fb[c + 1] : Fn;
         BendBar<T> o;
@@ -1338,9 +1346,9 @@ struct Rod {
         if (evalid(c)) {
           V3<T> Fq = (c < C - 1) ? Fb[c + 1] : Fn;
           V3<T> qb = Fb[c] - Fq;
-          T fs = ks[c] * (r.ell[c] / rest[c] - T(1));
+          T fs = ks[c] * (fdiv(r.ell[c], rest[c]) - T(1));
           tb[c] += fs * qb;
-          lb[c] += ks[c] * dot(qb, r.t[c]) / rest[c];
+          lb[c] += fdiv(ks[c] * dot(qb, r.t[c]), rest[c]);
         }
       }
     }
@@ -1609,7 +1617,7 @@ __global__ void k_selftest_exchange(int* out) {
 template <typename T, int C, int W, bool SC>
 static size_t lds_bytes(int which, int n_iters) {
   size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
-  if (SC) return xb + Rod<T, C, W, SC>::sc_bytes();
+  if constexpr (SC) return xb + Rod<T, C, W, SC>::sc_bytes();
   if (which == 2) return xb + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
   return xb;
 }
@@ -1664,12 +1672,14 @@ template <typename T>
 size_t kernel_lds_bytes(int which, int C, int W, bool SC, int n_iters) {
   size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
   if (SC) {
-    if (C == 2 && W == 1) return xb + Rod<T, 2, 1, true>::sc_bytes();
-    if (C == 2 && W == 2) return xb + Rod<T, 2, 2, true>::sc_bytes();
-    if (C == 2 && W == 4) return xb + Rod<T, 2, 4, true>::sc_bytes();
-    if (C == 2 && W == 8) return xb + Rod<T, 2, 8, true>::sc_bytes();
-    if (C == 4 && W == 4) return xb + Rod<T, 4, 4, true>::sc_bytes();
-    return (size_t)1 << 30;
+    if constexpr (sizeof(T) == 4) {
+      if (C == 2 && W == 1) return xb + Rod<T, 2, 1, true>::sc_bytes();
+      if (C == 2 && W == 2) return xb + Rod<T, 2, 2, true>::sc_bytes();
+      if (C == 2 && W == 4) return xb + Rod<T, 2, 4, true>::sc_bytes();
+      if (C == 2 && W == 8) return xb + Rod<T, 2, 8, true>::sc_bytes();
+      if (C == 4 && W == 4) return xb + Rod<T, 4, 4, true>::sc_bytes();
+    }
+    return (size_t)1 << 30;   // no self-contact kernel for this shape or precision
   }
   if (which == 2) return xb + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
   return xb;

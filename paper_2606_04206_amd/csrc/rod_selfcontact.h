@@ -10,7 +10,7 @@
 
 namespace rods {
 
-constexpr int SC_MAXP = 12;    // partner capacity per edge
+constexpr int SC_MAXP = 16;    // partner capacity per edge
 constexpr int SC_HT = 2048;    // hash buckets (power of two)
 
 template <typename T>
@@ -29,14 +29,14 @@ __device__ __forceinline__ Closest<T> closest_params(V3<T> P1, V3<T> Q1, V3<T> P
   T denom = a * e - b * b;
   Closest<T> o;
   o.gen = denom > T(1e-12) * (a * e);
-  T s_raw = o.gen ? (b * f - c * e) / denom : T(0);
+  T s_raw = o.gen ? fdiv(b * f - c * e, denom) : T(0);
   T s0 = clamp01(s_raw);
   o.s_cl = !o.gen || s_raw <= T(0) || s_raw >= T(1);
-  T u_raw = (b * s0 + f) / e;
+  T u_raw = fdiv(b * s0 + f, e);
   o.lo = u_raw < T(0);
   o.hi = u_raw > T(1);
   o.u = o.lo ? T(0) : (o.hi ? T(1) : u_raw);
-  T s_alt_raw = o.lo ? -c / a : (b - c) / a;
+  T s_alt_raw = o.lo ? fdiv(-c, a) : fdiv(b - c, a);
   o.s_alt_cl = s_alt_raw <= T(0) || s_alt_raw >= T(1);
   o.s = (o.lo || o.hi) ? clamp01(s_alt_raw) : s0;
   return o;
@@ -55,23 +55,26 @@ __device__ __forceinline__ void closest_params_vjp(V3<T> P1, V3<T> Q1, V3<T> P2,
   bool uc = br.lo || br.hi;
   T s_alt_b = (uc && !br.s_alt_cl) ? s_b : T(0);
   T num = br.lo ? -c : b - c;
-  c_b += -s_alt_b / a;
-  if (br.hi) b_b += s_alt_b / a;
-  a_b += -s_alt_b * num / (a * a);
+  const T ia = frcp(a);
+  c_b += -s_alt_b * ia;
+  if (br.hi) b_b += s_alt_b * ia;
+  a_b += -s_alt_b * num * ia * ia;
   T dn = br.gen ? denom : T(1);
-  T s_raw = br.gen ? (b * f - c * e) / dn : T(0);
+  const T idn = frcp(dn);
+  T s_raw = br.gen ? (b * f - c * e) * idn : T(0);
   T s0 = clamp01(s_raw);
   T u_raw_b = uc ? T(0) : u_b;
-  b_b += u_raw_b * s0 / e;
-  f_b += u_raw_b / e;
-  e_b += -u_raw_b * (b * s0 + f) / (e * e);
-  T s0_b = u_raw_b * b / e + (uc ? T(0) : s_b);
+  const T ie = frcp(e);
+  b_b += u_raw_b * s0 * ie;
+  f_b += u_raw_b * ie;
+  e_b += -u_raw_b * (b * s0 + f) * ie * ie;
+  T s0_b = u_raw_b * b * ie + (uc ? T(0) : s_b);
   T sr_b = br.s_cl ? T(0) : s0_b;
-  b_b += sr_b * f / dn;
-  f_b += sr_b * b / dn;
-  c_b += -sr_b * e / dn;
-  e_b += -sr_b * c / dn;
-  T dn_b = -sr_b * s_raw / dn;
+  b_b += sr_b * f * idn;
+  f_b += sr_b * b * idn;
+  c_b += -sr_b * e * idn;
+  e_b += -sr_b * c * idn;
+  T dn_b = -sr_b * s_raw * idn;
   a_b += dn_b * e;
   e_b += dn_b * a;
   b_b += T(-2) * dn_b * b;
@@ -105,10 +108,10 @@ __device__ __forceinline__ PairGeo<T> pair_geo(V3<T> P1, V3<T> Q1, V3<T> P2, V3<
   g.rb = (T(1) - u) * rj + u * rj1;
   g.W = wi * (T(1) - s) * (T(1) - s) + wi1 * s * s + wj * (T(1) - u) * (T(1) - u) + wj1 * u * u;
   g.diff = ca - cb;
-  g.dist = sqrt(dot(g.diff, g.diff));
+  g.dist = fsqrt(dot(g.diff, g.diff));
   g.d = g.ra + g.rb - g.dist;
   g.act = g.d > T(0) && g.dist > T(1e-12) && g.W > T(0);
-  g.n = (T(1) / (g.act ? g.dist : T(1))) * g.diff;
+  g.n = frcp(g.act ? g.dist : T(1)) * g.diff;
   return g;
 }
 
@@ -123,18 +126,19 @@ __device__ __forceinline__ void pair_proj_vjp(V3<T> P1, V3<T> Q1, V3<T> P2, V3<T
                                               V3<T>& P2b, V3<T>& Q2b) {
   T s = g.cp.s, u = g.cp.u;
   V3<T> n = g.n;
-  T kk = g.d / g.W;
+  T kk = fdiv(g.d, g.W);
   T ni = dot(gi, n), ni1 = dot(gi1, n), nj = dot(gj, n), nj1 = dot(gj1, n);
   T kk_b = wi * (T(1) - s) * ni + wi1 * s * ni1 - wj * (T(1) - u) * nj - wj1 * u * nj1;
   V3<T> n_b = (kk * wi * (T(1) - s)) * gi + (kk * wi1 * s) * gi1 - (kk * wj * (T(1) - u)) * gj -
               (kk * wj1 * u) * gj1;
   T s_b = kk * (-wi * ni + wi1 * ni1);
   T u_b = kk * (wj * nj - wj1 * nj1);
-  T d_b = kk_b / g.W;
-  T W_b = -kk_b * g.d / (g.W * g.W);
+  const T iW = frcp(g.W);
+  T d_b = kk_b * iW;
+  T W_b = -kk_b * g.d * iW * iW;
   s_b += W_b * (T(-2) * wi * (T(1) - s) + T(2) * wi1 * s);
   u_b += W_b * (T(-2) * wj * (T(1) - u) + T(2) * wj1 * u);
-  V3<T> diff_b = (T(1) / g.dist) * (n_b - dot(n, n_b) * n) - d_b * n;
+  V3<T> diff_b = frcp(g.dist) * (n_b - dot(n, n_b) * n) - d_b * n;
   s_b += d_b * (ri1 - ri);
   u_b += d_b * (rj1 - rj);
   s_b += dot(diff_b, Q1 - P1);
@@ -184,14 +188,14 @@ __device__ __forceinline__ FricGeo<T> pair_friction(V3<T> P1, V3<T> Q1, V3<T> P2
   f.g = pair_geo(P1, Q1, P2, Q2, wi, wi1, wj, wj1, ri, ri1, rj, rj1);
   T s = f.g.cp.s, u = f.g.cp.u;
   f.ok = f.g.dist > T(1e-12) && f.g.W > T(0);
-  f.g.n = (T(1) / (f.ok ? f.g.dist : T(1))) * f.g.diff;
+  f.g.n = frcp(f.ok ? f.g.dist : T(1)) * f.g.diff;
   f.vrel = (T(1) - s) * vi + s * vi1 - (T(1) - u) * vj - u * vj1;
   f.vn = dot(f.vrel, f.g.n);
   f.vt = f.vrel - f.vn * f.g.n;
-  T vtn = sqrt(dot(f.vt, f.vt));
+  T vtn = fsqrt(dot(f.vt, f.vt));
   f.ok = f.ok && vtn > T(0);
   f.vtn = f.ok ? vtn : T(1);
-  f.ratio = mu * d0 / (h * f.vtn);
+  f.ratio = fdiv(mu * d0, h * f.vtn);
   f.slide = f.ratio < T(1);
   f.scale = f.ok ? (f.slide ? f.ratio : T(1)) : T(0);
   f.dvt = (-f.scale) * f.vt;
@@ -215,17 +219,19 @@ __device__ __forceinline__ T pair_friction_vjp(V3<T> P1, V3<T> Q1, V3<T> P2, V3<
   V3<T> n = f.g.n;
   T ci = wi * (T(1) - s), ci1 = wi1 * s, cj = -wj * (T(1) - u), cj1 = -wj1 * u;
   V3<T> G = ci * gi + ci1 * gi1 + cj * gj + cj1 * gj1;
-  V3<T> dvt_b = (T(1) / W) * G;
-  T W_b = -dot(G, f.dvt) / (W * W);
-  T s_b = (-wi * dot(gi, f.dvt) + wi1 * dot(gi1, f.dvt)) / W;
-  T u_b = (wj * dot(gj, f.dvt) - wj1 * dot(gj1, f.dvt)) / W;
+  const T iW = frcp(W);
+  V3<T> dvt_b = iW * G;
+  T W_b = -dot(G, f.dvt) * iW * iW;
+  T s_b = (-wi * dot(gi, f.dvt) + wi1 * dot(gi1, f.dvt)) * iW;
+  T u_b = (wj * dot(gj, f.dvt) - wj1 * dot(gj1, f.dvt)) * iW;
   T scale_b = -dot(dvt_b, f.vt);
   V3<T> vt_b = (-f.scale) * dvt_b;
   T d0_b = T(0);
   if (f.slide) {
-    d0_b = scale_b * mu / (h * f.vtn);
-    T vtn_b = -scale_b * f.ratio / f.vtn;
-    vt_b += (vtn_b / f.vtn) * f.vt;
+    const T iv = frcp(f.vtn);
+    d0_b = fdiv(scale_b * mu, h) * iv;
+    T vtn_b = -scale_b * f.ratio * iv;
+    vt_b += (vtn_b * iv) * f.vt;
   }
   V3<T> vrel_b = vt_b - dot(n, vt_b) * n;
   V3<T> n_b = -(f.vn * vt_b + dot(vt_b, n) * f.vrel);
@@ -237,7 +243,7 @@ __device__ __forceinline__ T pair_friction_vjp(V3<T> P1, V3<T> Q1, V3<T> P2, V3<
   vj1b -= u * vrel_b;
   s_b += W_b * (T(-2) * wi * (T(1) - s) + T(2) * wi1 * s);
   u_b += W_b * (T(-2) * wj * (T(1) - u) + T(2) * wj1 * u);
-  V3<T> diff_b = (T(1) / f.g.dist) * (n_b - dot(n, n_b) * n);
+  V3<T> diff_b = frcp(f.g.dist) * (n_b - dot(n, n_b) * n);
   s_b += dot(diff_b, Q1 - P1);
   u_b -= dot(diff_b, Q2 - P2);
   P1b += (T(1) - s) * diff_b;

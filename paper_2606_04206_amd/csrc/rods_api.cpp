@@ -94,6 +94,11 @@ struct Impl : HandleBase {
   bool recorded = false;
   int n_rec = 0;
   int plain = 0;
+  // graph of one step (all size bins) over the handle's own buffers
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  T* u_step = nullptr;
   // kernel timing: event pairs around every launch batch, per kernel kind
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -101,8 +106,47 @@ struct Impl : HandleBase {
   size_t ev_next = 0;
 
   ~Impl() override {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
+  }
+
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
+
+  // One step through a captured HIP graph: the action is copied into the
+  // handle's own buffer (outside the graph), then the graph of the step's
+  // kernel launches is replayed.
+  int step_graph(const T* u, hipStream_t st) {
+    recorded = false;
+    if (G > 0) HIPCHK(hipMemcpyAsync(u_step, u, sizeof(T) * (size_t)R * G * 3,
+                                     hipMemcpyDeviceToDevice, st));
+    if (!graph_exec) {
+      RodArgs<T> a = args(cap_stream);
+      a.u = u_step;
+      a.act_stride = 0;
+      a.spa = 1;
+      a.step_off = 0;
+      a.n_steps = 1;
+      HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+      int e = launch_all_(0, a, cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t ce = hipStreamEndCapture(cap_stream, &g);
+      if (e) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+      }
+      HIPCHK(ce);
+      graph = g;
+      HIPCHK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(graph_exec, st));
+    return ROD_OK;
   }
 
   int set_profiling(int on) {
@@ -269,6 +313,7 @@ struct Impl : HandleBase {
         (e = alloc(ck, (size_t)n_ck * V * NF)) ||
         (e = alloc(acts, (size_t)n_act_max * R * G * 3)) ||
         (e = alloc(du_scratch, (size_t)n_act_max * R * G * 3)) ||
+        (e = alloc(u_step, (size_t)R * G * 3)) ||
         (e = alloc(tape, (size_t)std::min(d.ckpt_every, std::max(1, d.max_steps)) * d.n_sub * (size_t)tape_cap)))
       return e;
     HIPCHK(hipMemset(x, 0, 3 * sizeof(T) * V));
@@ -276,6 +321,7 @@ struct Impl : HandleBase {
     HIPCHK(hipMemset(kb, 0, 2 * sizeof(T) * V));
     HIPCHK(hipMemset(d1, 0, 3 * sizeof(T) * V));
     HIPCHK(hipMemset(status, 0, sizeof(int32_t) * R));
+    HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
     HIPCHK(hipDeviceSynchronize());
     return ROD_OK;
   }
@@ -527,6 +573,7 @@ struct Impl : HandleBase {
     std::vector<int64_t> toff_h, soff_h;
     layout_offsets(toff_h, soff_h);
     if (tape_stride > tape_cap || sc_stride_ > sc_cap) return ROD_EINVAL;   // cannot grow after create
+    drop_graph();
     HIPCHK(hipMemcpy(tape_off, toff_h.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(sc_off, soff_h.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice));
     HIPCHK(hipStreamSynchronize(st));
@@ -694,6 +741,15 @@ int rods_step(RodsHandle* h, const void* grasp_vel, rods_stream_t stream) {
   });
 }
 
+int rods_step_graph(RodsHandle* h, const void* grasp_vel, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    if (I->G > 0 && !grasp_vel) return (int)ROD_EINVAL;
+    return I->step_graph((const T*)grasp_vel, (hipStream_t)stream);
+  });
+}
+
 int rods_rollout(RodsHandle* h, int32_t n_steps, const void* grasp_vel, void* x_final,
                  int32_t record, rods_stream_t stream) {
   if (!h) return ROD_EINVAL;
@@ -762,6 +818,7 @@ int rods_set_plain(RodsHandle* h, int32_t plain) {
   if (!h) return ROD_EINVAL;
   return dispatch(h, [&](auto* I) {
     I->plain = plain ? 1 : 0;
+    I->drop_graph();
     return (int)ROD_OK;
   });
 }

@@ -34,7 +34,8 @@ class RodsDesc(ctypes.Structure):
 
 
 EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "rods_get_state",
-           "rods_set_params", "rods_curvature", "rods_step", "rods_rollout", "rods_backward",
+           "rods_set_params", "rods_curvature", "rods_step", "rods_step_graph", "rods_rollout",
+           "rods_backward",
            "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_plain",
            "rods_set_profiling", "rods_profile", "rods_selftest_exchange"]
 
@@ -63,6 +64,7 @@ def load():
         "rods_set_params": ([vp, vp, vp, vp], c_int32),
         "rods_curvature": ([vp, vp, vp, vp, vp], c_int32),
         "rods_step": ([vp, vp, vp], c_int32),
+        "rods_step_graph": ([vp, vp, vp], c_int32),
         "rods_rollout": ([vp, c_int32, vp, vp, c_int32, vp], c_int32),
         "rods_backward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], c_int32),
         "rods_loss_mse": ([vp, vp, vp, vp, vp, vp], c_int32),
@@ -209,6 +211,10 @@ class RodsHandle:
     def step(self, u):
         _require(u, (self.R, self.G, 3), self.dtype, "grasp_vel")
         _check(self._lib.rods_step(self._h, _ptr(u), _stream()), "rods_step")
+
+    def step_graph(self, u):
+        _require(u, (self.R, self.G, 3), self.dtype, "grasp_vel")
+        _check(self._lib.rods_step_graph(self._h, _ptr(u), _stream()), "rods_step_graph")
 
     def rollout(self, n_steps, U, record=False, x_final=None):
         _require(U, (self.n_actions(n_steps), self.R, self.G, 3), self.dtype, "grasp_vel")

@@ -18,8 +18,8 @@ pytestmark = pytest.mark.gpu
 def contact_workload(steps, full=True):
     wl = make_workload(4, steps=steps, start_height=0.006)
     rng = np.random.default_rng(44)
-    wl.v0[:, 2] = -0.3
-    wl.v0[:, :2] = rng.normal(0.0, 0.2, (wl.n_vert, 2))
+    wl.v0[:, 2] = -1.0
+    wl.v0[:, :2] = rng.normal(0.0, 0.4, (wl.n_vert, 2))
     return wl if full else wl.subset(wl.oracle_rods)
 
 
@@ -32,8 +32,9 @@ def test_contact_substep_teacher_forced_with_branch_agreement():
     """One substep of the full uneven batch from the seeded contact state:
     positions <= 1e-4 per oracle rod; at every vertex whose contact
     decisions all have a margin (|f - 0.1| > 1e-4, |v.n| > 1e-4 |v|), the
-    velocity agrees to 1e-3 relative + 5e-3 m/s, far below the jump a
-    different branch would cause (>= 0.03 m/s here)."""
+    velocity agrees to 1e-3 relative + 2e-2 m/s (FP32 rounding of 0.5 m
+    positions divided by h is ~1e-3 m/s per rounding), far below the jump a
+    different branch would cause (>= 0.1 m/s at 1 m/s impact)."""
     wl = contact_workload(2)
     run = sub_workload(wl)
     h = _handle(run, max_steps=2)
@@ -58,7 +59,7 @@ def test_contact_substep_teacher_forced_with_branch_agreement():
             n_active += int(c["act"].sum())
         sure &= orods.w[0] > 0
         dv = np.linalg.norm(gpu.v[0] - ref.v[0], axis=-1)
-        tol = 1e-3 * np.linalg.norm(ref.v[0], axis=-1) + 5e-3
+        tol = 1e-3 * np.linalg.norm(ref.v[0], axis=-1) + 2e-2
         assert np.all(dv[sure] <= tol[sure]), (r, dv[sure].max())
         n_sure += int(sure.sum())
     assert n_active > 100 and n_sure > 1000

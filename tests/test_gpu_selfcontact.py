@@ -1,5 +1,5 @@
 """GPU parity with self-contact (App. A.1, "Self-collision and Friction"):
-helices whose pitch (9 mm) is below the rod diameter, so neighbouring coils
+helices whose pitch (9.8 mm) is below the rod diameter, so neighbouring coils
 start interpenetrating and every substep has active pairs and friction."""
 import numpy as np
 import pytest
@@ -33,12 +33,13 @@ def _teacher_forced_substep(wl):
 def test_selfcontact_substep_teacher_forced(n_vert, n_rods):
     """One substep from the interpenetrating helices: positions <= 1e-4 per
     oracle rod, and velocities agree at every vertex away from friction and
-    contact ties (1e-3 relative + 5e-3 m/s)."""
-    wl = make_workload(5, steps=2, pitch=0.009, n_vert=n_vert, n_rods=n_rods)
+    contact ties (1e-3 relative + 2e-2 m/s)."""
+    wl = make_workload(5, steps=2, pitch=0.0098, n_vert=n_vert, n_rods=n_rods)
     run, full, out, status = _teacher_forced_substep(wl)
     assert not status.any(), status[status != 0]
     n_pairs = 0
-    for r in wl.oracle_rods:
+    check = range(wl.n_rods) if n_rods <= 8 else wl.oracle_rods
+    for r in check:
         st = gather_state(wl, [r], [a.astype(np.float32).astype(np.float64) for a in full])
         orods, osim = rods_from_workload(run, [r]), sim_from_workload(run)
         rec = {}
@@ -47,15 +48,15 @@ def test_selfcontact_substep_teacher_forced(n_vert, n_rods):
         assert rel_err(gpu.x, ref.x) <= 1e-4, r
         n_pairs += int((rec["d0"][0] > 0).sum())
         dv = np.linalg.norm(gpu.v[0] - ref.v[0], axis=-1)
-        tol = 1e-3 * np.linalg.norm(ref.v[0], axis=-1) + 5e-3
+        tol = 1e-3 * np.linalg.norm(ref.v[0], axis=-1) + 2e-2
         assert np.mean(dv <= tol) > 0.99, (r, dv.max())
-    assert n_pairs > 20
+    assert n_pairs > (5 if n_rods <= 8 else 1000)
 
 
 def test_selfcontact_step_parity_1024():
     """A full step (15 substeps) of the 256 x 1024 interpenetrating helices:
     positions <= 1e-4 on the oracle rods."""
-    wl = make_workload(5, steps=2, pitch=0.009)
+    wl = make_workload(5, steps=2, pitch=0.0098)
     h = _handle(wl, max_steps=2)
     full = initial_full_state(wl)
     h.set_state(*(to_dev(a) for a in full))
@@ -74,7 +75,7 @@ def test_selfcontact_rollout_gradients():
     creep rate 0.5: FP32 gradients w.r.t. grasp velocities, b, sigma_y and
     the initial state within 1e-3 of the oracle."""
     n, K = 3, 2
-    wl = make_workload(5, steps=n, pitch=0.009, n_vert=64, n_rods=8)
+    wl = make_workload(5, steps=n, pitch=0.0098, n_vert=64, n_rods=8)
     wl.rod_params[:, 4] = 0.5
     h = _handle(wl, max_steps=n, ckpt_every=K)
     h.set_state(*(to_dev(a) for a in initial_full_state(wl)))
