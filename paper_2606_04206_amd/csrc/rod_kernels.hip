@@ -450,17 +450,22 @@ struct Rod {
       for (int f = 0; f < NFIELD; ++f) base[(f * C + c) * TL + tl] = vals[f];
     }
   }
-  __device__ void load_tape(const T* base) {
+  // the adjoint reads a stored state one substep ahead into registers
+  // (prefetch), then installs it when that substep comes up
+  __device__ void fetch_tape(const T* base, T (&buf)[NFIELD * C]) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int f = 0; f < NFIELD; ++f) buf[f * C + c] = base[(f * C + c) * TL + tl];
+  }
+  __device__ void install_tape(const T (&buf)[NFIELD * C]) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      T vals[NFIELD];
-#pragma unroll
-      for (int f = 0; f < NFIELD; ++f) vals[f] = base[(f * C + c) * TL + tl];
-      x[c] = mk(vals[0], vals[1], vals[2]);
-      v[c] = mk(vals[3], vals[4], vals[5]);
-      kr0[c] = vals[6];
-      kr1[c] = vals[7];
-      d1[c] = mk(vals[8], vals[9], vals[10]);
+      x[c] = mk(buf[0 * C + c], buf[1 * C + c], buf[2 * C + c]);
+      v[c] = mk(buf[3 * C + c], buf[4 * C + c], buf[5 * C + c]);
+      kr0[c] = buf[6 * C + c];
+      kr1[c] = buf[7 * C + c];
+      d1[c] = mk(buf[8 * C + c], buf[9 * C + c], buf[10 * C + c]);
     }
   }
 
@@ -1461,12 +1466,16 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
   }
   const T* tape_rod = a.tape + a.tape_off[R.rod];
   Rec<T, C> rec;
+  T pf[NFIELD * C];
+  R.fetch_tape(tape_rod + (int64_t)(a.n_steps * a.n_sub - 1) * a.tape_stride, pf);
   for (int s = a.n_steps - 1; s >= 0; --s) {
     const int act = (a.step_off + s) / a.spa;
     V3<T> ug[C];
     R.load_actions(a, act, ug);
     for (int k = a.n_sub - 1; k >= 0; --k) {
-      R.load_tape(tape_rod + (int64_t)(s * a.n_sub + k) * a.tape_stride);
+      R.install_tape(pf);
+      const int nxt = s * a.n_sub + k - 1;   // the substep processed next
+      if (nxt >= 0) R.fetch_tape(tape_rod + (int64_t)nxt * a.tape_stride, pf);
       R.template substep<true>(a, X, ug, &rec, lds_tape);
       R.substep_vjp(a, X, rec, lds_tape, lx, lv, lk0, lk1, ld1, accb, accs, uacc);
     }
