@@ -19,12 +19,21 @@ Readings (the paper is silent on these):
   Collision Detection, 5.1.9); when |d1|^2 |d2|^2 - (d1.d2)^2 <=
   1e-12 |d1|^2 |d2|^2 the first parameter is set to 0 before clamping;
 * one Jacobi pass over all candidates per iteration (corrections from the
-  same positions, summed, applied after the pass), after the red and black
+  same positions, applied after the pass), after the red and black
   inextensibility passes; r_a, r_b are the radii interpolated at c_a, c_b;
+* each active pair's correction is divided by m = the largest number of
+  active pairs touching one of its four vertices.  A plain sum is not
+  stable: an edge with k > 2 active partners then receives k full
+  corrections, an over-relaxation that multiplies a penetration error by
+  about (1 - k) per iteration, so the N_C passes diverge in dense contact.
+  With the per-pair divisor a vertex moves by at most the mean of its
+  pairs' corrections, and every pair still moves its four vertices with
+  zero net momentum (sum of m_k dx_k = 0);
 * friction for pairs whose depth at the first iteration d0 > 0, evaluated at
   the final positions: v_t = tangential part of the relative velocity of
   c_a and c_b, dv_t = -min(1, mu d0 / (h |v_t|)) v_t, distributed like the
-  position correction, summed Jacobi-style.
+  position correction and divided the same way (counts of the pairs with
+  d0 > 0).
 """
 import numpy as np
 
@@ -153,8 +162,19 @@ def _pair_geometry(rods, bi, p, pairs):
                 ra=ra, rb=rb, W=W)
 
 
+def pair_divisors(n_vert, i, j, mask):
+    """Per pair (i, j), the largest number of masked pairs touching one of
+    its four vertices (at least 1)."""
+    cnt = np.zeros(n_vert)
+    for k in (i, i + 1, j, j + 1):
+        np.add.at(cnt, k[mask], 1.0)
+    return np.maximum(np.maximum(np.maximum(cnt[i], cnt[i + 1]), np.maximum(cnt[j], cnt[j + 1])),
+                      1.0)
+
+
 def project_pairs(rods, p, pairs, rec):
-    """One Jacobi pass of the self-contact projection over the candidates."""
+    """One Jacobi pass of the self-contact projection over the candidates,
+    each pair's correction divided by its divisor m."""
     p_new = p.copy()
     depth0 = []
     for bi in range(rods.B):
@@ -169,9 +189,10 @@ def project_pairs(rods, p, pairs, rec):
         act = (re(d) > 0.0) & (re(dist) > 1e-12) & (re(g["W"]) > 0.0)
         dist_s = np.where(act, dist, 1.0)
         n = diff / dist_s[:, None]
-        k = np.where(act, d / np.where(act, g["W"], 1.0), 0.0)
         w = rods.w[bi]
         i, j, s, u = g["i"], g["j"], g["s"], g["u"]
+        m = pair_divisors(len(p[bi]), i, j, re(act))
+        k = np.where(act, d / (np.where(act, g["W"], 1.0) * m), 0.0)
         delta = np.zeros_like(p[bi])
         np.add.at(delta, i, (k * w[i] * (1 - s))[:, None] * n)
         np.add.at(delta, i + 1, (k * w[i + 1] * s)[:, None] * n)
@@ -185,7 +206,8 @@ def project_pairs(rods, p, pairs, rec):
 
 
 def project_pairs_vjp(rods, p_b, item):
-    """Adjoint of one Jacobi contact pass (p' = p + sum of corrections)."""
+    """Adjoint of one Jacobi contact pass (p' = p + corrections / m; the
+    divisors are piecewise constant)."""
     _, pairs, p, _ = item
     p_b_in = p_b.copy()
     for bi in range(rods.B):
@@ -201,7 +223,9 @@ def project_pairs_vjp(rods, p_b, item):
         act = (d > 0.0) & (dist > 1e-12) & (g["W"] > 0.0)
         if not act.any():
             continue
+        m = pair_divisors(len(p[bi]), i, j, act)
         sel = np.where(act)[0]
+        m = m[sel]
         gi = {k: (v[sel] if isinstance(v, np.ndarray) else v) for k, v in g.items() if k != "br"}
         br = {k: v[sel] for k, v in g["br"].items()}
         i, j, s, u = gi["i"], gi["j"], gi["s"], gi["u"]
@@ -212,7 +236,8 @@ def project_pairs_vjp(rods, p_b, item):
         # corrections: delta_i = kk w_i (1-s) n, delta_{i+1} = kk w_{i+1} s n,
         #              delta_j = -kk w_j (1-u) n, delta_{j+1} = -kk w_{j+1} u n
         bi_ = p_b[bi]
-        gi_, gi1, gj, gj1 = bi_[i], bi_[i + 1], bi_[j], bi_[j + 1]
+        sc = (1.0 / m)[:, None]
+        gi_, gi1, gj, gj1 = sc * bi_[i], sc * bi_[i + 1], sc * bi_[j], sc * bi_[j + 1]
         coef = w[i] * (1 - s) * dot(gi_, n) + w[i + 1] * s * dot(gi1, n) \
             - w[j] * (1 - u) * dot(gj, n) - w[j + 1] * u * dot(gj1, n)
         kk_b = coef
@@ -289,7 +314,8 @@ def friction(rods, sim, x, v, pairs, depth0, rec):
         ratio = rods.mu[bi] * d0[sel] / (sim.h * vtn_s)
         slide = re(ratio) < 1.0
         scale = np.where(ok, np.where(slide, ratio, 1.0), 0.0)
-        dvt = -scale[:, None] * vt
+        m = pair_divisors(len(vb), i, j, np.ones(len(sel), bool))
+        dvt = -(scale / m)[:, None] * vt
         Ws = np.where(ok, W, 1.0)
         delta = np.zeros_like(vb)
         np.add.at(delta, i, (w[i] * (1 - s) / Ws)[:, None] * dvt)
@@ -343,8 +369,10 @@ def friction_vjp(rods, sim, rec, v_b):
         scale = np.where(ok, np.where(slide, ratio, 1.0), 0.0)
         dvt = -scale[:, None] * vt
         Ws = np.where(ok, W, 1.0)
+        m = pair_divisors(len(vb), i, j, np.ones(len(sel), bool))
         ob = v_b[bi]
-        gi_, gi1, gj, gj1 = ob[i], ob[i + 1], ob[j], ob[j + 1]
+        sc = (1.0 / m)[:, None]
+        gi_, gi1, gj, gj1 = sc * ob[i], sc * ob[i + 1], sc * ob[j], sc * ob[j + 1]
         # delta_k = c_k dvt / W with c = (w_i(1-s), w_{i+1}s, -w_j(1-u), -w_{j+1}u)
         ci, ci1, cj, cj1 = w[i] * (1 - s), w[i + 1] * s, -w[j] * (1 - u), -w[j + 1] * u
         G = (ci[:, None] * gi_ + ci1[:, None] * gi1 + cj[:, None] * gj + cj1[:, None] * gj1)

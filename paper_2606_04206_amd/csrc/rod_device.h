@@ -43,8 +43,17 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 template <typename T>
 __device__ __forceinline__ T fdiv(T a, T b) { return a * frcp(b); }
+
+// four values stored as one vector access (LDS or global)
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+  T x, y, z, w;
+};
+constexpr int PROJ_TAPE = 4;   // values per edge and iteration in the projection tape
 
 // ---------------------------------------------------------------------------
 // Lane exchange.  A rod is owned by a team of 64*W lanes (W waves of one

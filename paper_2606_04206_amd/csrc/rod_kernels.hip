@@ -172,31 +172,31 @@ __device__ __forceinline__ void curvature_vjp(V3<T> t0, V3<T> t1, V3<T> d1a, V3<
   t1b += cross(d1b, d2ab);
 }
 
-// One inextensibility projection of edge (pj, pk) (App. A.1): lambda = C/W,
-// pj += lambda wj t, pk -= lambda wk t.  Returns the edge vector D it saw.
+// One inextensibility projection of edge (pj, pk) (App. A.1).  With
+// lambda = (|D| - r) / W along t = D/|D|, pj moves by lambda wj t and pk by
+// -lambda wk t; written here as s = 1 - r/|D|, pj += s aj D, pk -= s ak D
+// with the per-edge ratios aj = wj/W, ak = wk/W (both zero for an edge that
+// is not projected).  D is the edge vector it saw; returns 1/|D|.
 template <typename T>
-__device__ __forceinline__ V3<T> project_edge(V3<T>& pj, V3<T>& pk, T wj, T wk, T r) {
-  V3<T> D = pk - pj;
-  T W = wj + wk;
-  if (W > T(0)) {
-    T l = fsqrt(dot(D, D));
-    T s = fdiv(l - r, W * l);
-    pj += (s * wj) * D;
-    pk -= (s * wk) * D;
-  }
-  return D;
+__device__ __forceinline__ T project_edge(V3<T>& pj, V3<T>& pk, T aj, T ak, T r, V3<T>& D) {
+  D = pk - pj;
+  T il = frsq(fmax(dot(D, D), T(1e-30)));
+  T s = T(1) - r * il;
+  pj += (s * aj) * D;
+  pk -= (s * ak) * D;
+  return il;
 }
 
-// Adjoint of project_edge: returns D_b (pj_b -= D_b, pk_b += D_b).
+// Adjoint of project_edge from what it saw (D, 1/|D|): the Jacobian of
+// s(D) D is (1 - r/|D|) I + r D D^T / |D|^3.  Given the adjoints Aj, Ak of
+// the moved endpoints returns D_b, with pj_b = Aj - D_b and pk_b = Ak + D_b.
 template <typename T>
-__device__ __forceinline__ V3<T> project_edge_vjp(V3<T> D, T wj, T wk, T r, V3<T> aj, V3<T> ak) {
-  T W = wj + wk;
-  if (!(W > T(0))) return zero3<T>();
-  T l = fsqrt(dot(D, D));
-  T il = frcp(l);
-  V3<T> t = il * D;
-  V3<T> qb = frcp(W) * (wj * aj - wk * ak);
-  return qb - (r * il) * (qb - dot(t, qb) * t);
+__device__ __forceinline__ V3<T> project_edge_vjp(V3<T> D, T il, T aj, T ak, T r, V3<T> Aj,
+                                                  V3<T> Ak) {
+  V3<T> q = aj * Aj - ak * Ak;
+  T ril = r * il;
+  T c2 = ril * il * il * dot(D, q);   // left to right: finite when r = 0
+  return (T(1) - ril) * q + c2 * D;
 }
 
 // ---------------------------------------------------------------------------
@@ -358,7 +358,7 @@ struct Rod {
   static constexpr int NV = TL * C;   // vertex capacity of the team
   int rod, N, v0, tl, flags, p0, p1;
   // self-contact scratch (LDS) and the adjoint's contact-pass inputs (global)
-  T *sc_pos, *sc_aux, *sc_adj, *sc_w, *sc_r, *sc_d0;
+  T *sc_pos, *sc_aux, *sc_adj, *sc_w, *sc_r, *sc_d0, *sc_vcnt;
   int *sc_cnt, *sc_start, *sc_pcnt, *sc_tmp;
   short *sc_items, *sc_plist;
   T sc_cell, sc_lmax;
@@ -366,8 +366,8 @@ struct Rod {
   T* ctape;
   T b, sig, rc, mu, e, K;
   T w[C], rest[C], lbar[C], ks[C], rad[C];
+  T aj[C], ak[C];   // projection ratios w_j/W, w_k/W of the edge starting at vertex c
   int gs[C];
-  T wn;
   V3<T> x[C], v[C], d1[C];
   T kr0[C], kr1[C];
 
@@ -403,9 +403,14 @@ struct Rod {
     X.prev(rp);
     T rn[2] = {rad[0], w[0]};
     X.next(rn);
-    wn = rn[1];
+    const T wn = rn[1];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+      T wk = c < C - 1 ? w[c + 1] : wn;
+      T Wsum = w[c] + wk;
+      bool pe = evalid(c) && Wsum > T(0);
+      aj[c] = pe ? w[c] / Wsum : T(0);
+      ak[c] = pe ? wk / Wsum : T(0);
       lbar[c] = ivalid(c) ? T(0.5) * ((c ? rest[c - 1] : rp[0]) + rest[c]) : T(0);
       T rb = T(0.5) * (rad[c] + (c < C - 1 ? rad[c + 1] : rn[0]));
       ks[c] = evalid(c) ? K * T(3.14159265358979323846) * rb * rb : T(0);
@@ -509,8 +514,11 @@ struct Rod {
     pb[0] += mk(s[0], s[1], s[2]);
   }
 
-  __device__ __forceinline__ T* tape_at(T* lds_tape, int it, int c, int k) const {
-    return lds_tape + ((it * C + c) * 3 + k) * TL + tl;
+  // projection tape: edge c of iteration it keeps (D, 1/|D|) as one
+  // PROJ_TAPE-value record per lane, lanes contiguous
+  __device__ __forceinline__ void tape_put(T* tape, int it, int c, V3<T> D, T il) const {
+    Q4<T> q = {D.x, D.y, D.z, il};
+    reinterpret_cast<Q4<T>*>(tape)[(it * C + c) * TL + tl] = q;
   }
 
   // N_C iterations of red (even edges) then black (odd edges) projections
@@ -518,7 +526,7 @@ struct Rod {
   __device__ void project(const RodArgs<T>& a, Team<T, W>& X, V3<T> (&p)[C], T* lds_tape) {
     const bool inext = (flags & FLAG_INEXT) != 0;
     for (int it = 0; it < a.n_iters; ++it) {
-      if (inext) project_iter<REC>(a, X, p, lds_tape, it);
+      if (inext) project_iter<REC>(X, p, lds_tape, it);
       if constexpr (SC) {
         if (flags & FLAG_SELF) sc_pass<REC>(X, p, it, it == 0);
       }
@@ -526,109 +534,101 @@ struct Rod {
   }
 
   template <bool REC>
-  __device__ void project_iter(const RodArgs<T>& a, Team<T, W>& X, V3<T> (&p)[C], T* lds_tape,
-                               int it) {
-    {
+  __device__ void project_iter(Team<T, W>& X, V3<T> (&p)[C], T* lds_tape, int it) {
+    V3<T> D;
 #pragma unroll
-      for (int c = 0; c < C; c += 2) {
-        V3<T> D = zero3<T>();
-        if (evalid(c)) D = project_edge(p[c], p[c + 1], w[c], w[c + 1], rest[c]);
-        if constexpr (REC) {
-          *tape_at(lds_tape, it, c, 0) = D.x;
-          *tape_at(lds_tape, it, c, 1) = D.y;
-          *tape_at(lds_tape, it, c, 2) = D.z;
-        }
-      }
-#pragma unroll
-      for (int c = 1; c < C - 1; c += 2) {
-        V3<T> D = zero3<T>();
-        if (evalid(c)) D = project_edge(p[c], p[c + 1], w[c], w[c + 1], rest[c]);
-        if constexpr (REC) {
-          *tape_at(lds_tape, it, c, 0) = D.x;
-          *tape_at(lds_tape, it, c, 1) = D.y;
-          *tape_at(lds_tape, it, c, 2) = D.z;
-        }
-      }
-      // the lane's last edge reaches into the next lane
-      T pn[3] = {p[0].x, p[0].y, p[0].z};
-      X.next(pn);
-      V3<T> q = mk(pn[0], pn[1], pn[2]);
-      V3<T> qn = q;
-      V3<T> D = zero3<T>();
-      if (evalid(C - 1)) D = project_edge(p[C - 1], q, w[C - 1], wn, rest[C - 1]);
-      if constexpr (REC) {
-        *tape_at(lds_tape, it, C - 1, 0) = D.x;
-        *tape_at(lds_tape, it, C - 1, 1) = D.y;
-        *tape_at(lds_tape, it, C - 1, 2) = D.z;
-      }
-      V3<T> dq = q - qn;
-      T s[3] = {dq.x, dq.y, dq.z};
-      X.prev(s);
-      p[0] += mk(s[0], s[1], s[2]);
+    for (int c = 0; c < C; c += 2) {   // red: even edges, inside the lane
+      T il = project_edge(p[c], p[c + 1], aj[c], ak[c], rest[c], D);
+      if constexpr (REC) tape_put(lds_tape, it, c, D, il);
     }
+#pragma unroll
+    for (int c = 1; c < C - 1; c += 2) {   // black edges inside the lane
+      T il = project_edge(p[c], p[c + 1], aj[c], ak[c], rest[c], D);
+      if constexpr (REC) tape_put(lds_tape, it, c, D, il);
+    }
+    // the lane's last (black) edge reaches into the next lane: project it
+    // here and send the next lane its endpoint's move
+    T pn[3] = {p[0].x, p[0].y, p[0].z};
+    X.next(pn);
+    V3<T> q = mk(pn[0], pn[1], pn[2]);
+    D = q - p[C - 1];
+    T il = frsq(fmax(dot(D, D), T(1e-30)));
+    T sc = T(1) - rest[C - 1] * il;
+    p[C - 1] += (sc * aj[C - 1]) * D;
+    if constexpr (REC) tape_put(lds_tape, it, C - 1, D, il);
+    T mv[3] = {-(sc * ak[C - 1]) * D.x, -(sc * ak[C - 1]) * D.y, -(sc * ak[C - 1]) * D.z};
+    X.prev(mv);
+    p[0] += mk(mv[0], mv[1], mv[2]);
   }
 
+  __device__ __forceinline__ void tape_load(const T* tape, int it, Q4<T> (&q)[C]) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) q[c] = reinterpret_cast<const Q4<T>*>(tape)[(it * C + c) * TL + tl];
+  }
+
+  // reverse sweep over the iterations.  Each iteration's tape records are
+  // read one iteration ahead into alternating buffers (loop unrolled by
+  // two, loads unconditional with a clamped index) so the LDS latency
+  // overlaps the arithmetic.
+  __device__ __forceinline__ void iter_vjp(Team<T, W>& X, V3<T> (&pb)[C], int it,
+                                           const Q4<T> (&rec)[C]) {
+    if constexpr (SC) {
+      if (flags & FLAG_SELF) sc_pass_vjp(X, pb, it, it == 0);
+    }
+    if (flags & FLAG_INEXT) project_iter_vjp(X, pb, rec);
+  }
   __device__ void project_vjp(const RodArgs<T>& a, Team<T, W>& X, V3<T> (&pb)[C],
                               const T* lds_tape) {
-    const bool inext = (flags & FLAG_INEXT) != 0;
-    for (int it = a.n_iters - 1; it >= 0; --it) {
-      if constexpr (SC) {
-        if (flags & FLAG_SELF) sc_pass_vjp(X, pb, it, it == 0);
-      }
-      if (inext) project_iter_vjp(X, pb, lds_tape, it);
+    int it = a.n_iters - 1;
+    if (it < 0) return;
+    Q4<T> A[C], B[C];
+    tape_load(lds_tape, it, A);
+    while (true) {
+      tape_load(lds_tape, it > 0 ? it - 1 : 0, B);
+      iter_vjp(X, pb, it, A);
+      if (--it < 0) break;
+      tape_load(lds_tape, it > 0 ? it - 1 : 0, A);
+      iter_vjp(X, pb, it, B);
+      if (--it < 0) break;
     }
   }
 
-  __device__ void project_iter_vjp(Team<T, W>& X, V3<T> (&pb)[C], const T* lds_tape,
-                                   int it) const {
-    {
-      // black pass, reversed
-      T an[3] = {pb[0].x, pb[0].y, pb[0].z};
-      X.next(an);
-      V3<T> Db = zero3<T>();
-      if (evalid(C - 1)) {
-        V3<T> D = mk(lds_tape[((it * C + C - 1) * 3 + 0) * TL + tl],
-                     lds_tape[((it * C + C - 1) * 3 + 1) * TL + tl],
-                     lds_tape[((it * C + C - 1) * 3 + 2) * TL + tl]);
-        Db = project_edge_vjp(D, w[C - 1], wn, rest[C - 1], pb[C - 1], mk(an[0], an[1], an[2]));
-        pb[C - 1] -= Db;
-      }
-      T s[3] = {Db.x, Db.y, Db.z};
-      X.prev(s);
-      pb[0] += mk(s[0], s[1], s[2]);
+  __device__ void project_iter_vjp(Team<T, W>& X, V3<T> (&pb)[C], const Q4<T> (&rec)[C]) const {
+    // the cross-lane black edge: its far endpoint's adjoint comes from the
+    // next lane, the edge adjoint goes back to it
+    T an[3] = {pb[0].x, pb[0].y, pb[0].z};
+    X.next(an);
+    const Q4<T>& q = rec[C - 1];
+    V3<T> Db = project_edge_vjp(mk(q.x, q.y, q.z), q.w, aj[C - 1], ak[C - 1], rest[C - 1],
+                                pb[C - 1], mk(an[0], an[1], an[2]));
+    pb[C - 1] -= Db;
+    T s[3] = {Db.x, Db.y, Db.z};
+    X.prev(s);
+    pb[0] += mk(s[0], s[1], s[2]);
 #pragma unroll
-      for (int c = 1; c < C - 1; c += 2) {
-        if (evalid(c)) {
-          V3<T> D = mk(lds_tape[((it * C + c) * 3 + 0) * TL + tl],
-                       lds_tape[((it * C + c) * 3 + 1) * TL + tl],
-                       lds_tape[((it * C + c) * 3 + 2) * TL + tl]);
-          V3<T> db = project_edge_vjp(D, w[c], w[c + 1], rest[c], pb[c], pb[c + 1]);
-          pb[c] -= db;
-          pb[c + 1] += db;
-        }
-      }
-      // red pass, reversed
+    for (int c = 1; c < C - 1; c += 2) {   // black edges inside the lane
+      V3<T> db = project_edge_vjp(mk(rec[c].x, rec[c].y, rec[c].z), rec[c].w, aj[c], ak[c],
+                                  rest[c], pb[c], pb[c + 1]);
+      pb[c] -= db;
+      pb[c + 1] += db;
+    }
 #pragma unroll
-      for (int c = 0; c < C; c += 2) {
-        if (evalid(c)) {
-          V3<T> D = mk(lds_tape[((it * C + c) * 3 + 0) * TL + tl],
-                       lds_tape[((it * C + c) * 3 + 1) * TL + tl],
-                       lds_tape[((it * C + c) * 3 + 2) * TL + tl]);
-          V3<T> db = project_edge_vjp(D, w[c], w[c + 1], rest[c], pb[c], pb[c + 1]);
-          pb[c] -= db;
-          pb[c + 1] += db;
-        }
-      }
+    for (int c = 0; c < C; c += 2) {   // red
+      V3<T> db = project_edge_vjp(mk(rec[c].x, rec[c].y, rec[c].z), rec[c].w, aj[c], ak[c],
+                                  rest[c], pb[c], pb[c + 1]);
+      pb[c] -= db;
+      pb[c + 1] += db;
     }
   }
 
   // ------------------------------------------------------------ self-contact
   // LDS: staging (positions, velocities), statics, first-pass depths, the
   // hash (counts, starts, items) and the partner lists.  The adjoint's third
-  // staging buffer reuses the hash counts and starts, which are dead once the
-  // partner lists are built.
+  // staging buffer and the per-vertex pair counts reuse the hash counts and
+  // starts, which are dead once the partner lists are built.
   static constexpr size_t sc_bytes() {
-    static_assert(!SC || 2 * SC_HT * sizeof(int) >= 3 * NV * sizeof(T), "adjoint staging alias");
+    static_assert(!SC || (2 * SC_HT + 1) * sizeof(int) >= 4 * NV * sizeof(T),
+                  "adjoint staging and vertex counts alias the hash arrays");
     return sizeof(T) * (size_t)(2 * NV * 3 + 2 * NV + NV * SC_MAXP) +
            sizeof(int) * (size_t)(SC_HT + SC_HT + 1 + NV + 2 * TL) +
            sizeof(short) * (size_t)(NV + NV * SC_MAXP) + 64;
@@ -644,6 +644,7 @@ struct Rod {
     sc_cnt = q; q += SC_HT;
     sc_start = q; q += SC_HT + 1;
     sc_adj = reinterpret_cast<T*>(sc_cnt);
+    sc_vcnt = sc_adj + 3 * NV;
     sc_pcnt = q; q += NV;
     sc_tmp = q; q += 2 * TL;
     short* sh = reinterpret_cast<short*>(q);
@@ -799,24 +800,37 @@ struct Rod {
                     sc_r[hi + 1]);
   }
 
-  // one Jacobi pass of the self-contact projection (gather per own edge)
+  // Per-pair divisor of the Jacobi passes: the largest number of counted
+  // pairs touching one of the pair's four vertices.  ne[c] is the number of
+  // counted pairs of own edge c; a vertex is touched by the pairs of the two
+  // edges that meet at it.  Stages the vertex counts into sc_vcnt (the
+  // caller synchronises) and returns them.
+  __device__ void sc_vertex_counts(Team<T, W>& X, const T (&ne)[C], T (&nv)[C]) {
+    T sp[1] = {ne[C - 1]};
+    X.prev(sp);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      nv[c] = ne[c] + (c ? ne[c - 1] : sp[0]);
+      if (vvalid(c)) sc_vcnt[gi(c)] = nv[c];
+    }
+  }
+  __device__ __forceinline__ T sc_divisor(int lo, int hi) const {
+    T m = fmax(fmax(sc_vcnt[lo], sc_vcnt[lo + 1]), fmax(sc_vcnt[hi], sc_vcnt[hi + 1]));
+    return fmax(m, T(1));
+  }
+
+  // one Jacobi pass of the self-contact projection (gather per own edge):
+  // a first sweep decides which pairs are active and counts them per
+  // vertex, the second applies every active pair's correction divided by
+  // its divisor
   template <bool REC>
   __device__ void sc_pass(Team<T, W>& X, V3<T> (&p)[C], int it, bool first) {
     sc_stage(sc_pos, p);
-    if constexpr (REC) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        ctape[((it * C + c) * 3 + 0) * TL + tl] = p[c].x;
-        ctape[((it * C + c) * 3 + 1) * TL + tl] = p[c].y;
-        ctape[((it * C + c) * 3 + 2) * TL + tl] = p[c].z;
-      }
-    }
     __syncthreads();
-    V3<T> dA[C], dB[C];
+    T ne[C], nv[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      dA[c] = zero3<T>();
-      dB[c] = zero3<T>();
+      ne[c] = T(0);
       if (!evalid(c)) continue;
       const int e = gi(c);
       const short* pl = sc_plist + e * SC_MAXP;
@@ -826,8 +840,33 @@ struct Rod {
         int lo = e < j ? e : j, hi = e < j ? j : e;
         PairGeo<T> g = sc_pair(sc_pos, lo, hi);
         if (first) sc_d0[e * SC_MAXP + k] = g.act ? g.d : T(0);
+        if (g.act) ne[c] += T(1);
+      }
+    }
+    sc_vertex_counts(X, ne, nv);
+    if constexpr (REC) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        Q4<T> q = {p[c].x, p[c].y, p[c].z, nv[c]};
+        reinterpret_cast<Q4<T>*>(ctape)[(it * C + c) * TL + tl] = q;
+      }
+    }
+    __syncthreads();
+    V3<T> dA[C], dB[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      dA[c] = zero3<T>();
+      dB[c] = zero3<T>();
+      if (!(ne[c] > T(0))) continue;
+      const int e = gi(c);
+      const short* pl = sc_plist + e * SC_MAXP;
+      const int n = sc_pcnt[e];
+      for (int k = 0; k < n; ++k) {
+        int j = pl[k];
+        int lo = e < j ? e : j, hi = e < j ? j : e;
+        PairGeo<T> g = sc_pair(sc_pos, lo, hi);
         if (g.act) {
-          T kk = fdiv(g.d, g.W);
+          T kk = fdiv(g.d, g.W * sc_divisor(lo, hi));
           if (e == lo) {
             dA[c] += (kk * sc_w[lo] * (T(1) - g.cp.s)) * g.n;
             dB[c] += (kk * sc_w[lo + 1] * g.cp.s) * g.n;
@@ -845,11 +884,27 @@ struct Rod {
     for (int c = 0; c < C; ++c) p[c] += dA[c] + (c ? dB[c - 1] : mk(s3[0], s3[1], s3[2]));
   }
 
+  // pairs with a positive first-pass depth per own edge (friction's counts)
+  __device__ void sc_friction_counts(Team<T, W>& X) {
+    T ne[C], nv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      ne[c] = T(0);
+      if (!evalid(c)) continue;
+      const int e = gi(c);
+      const int n = sc_pcnt[e];
+      for (int k = 0; k < n; ++k)
+        if (sc_d0[e * SC_MAXP + k] > T(0)) ne[c] += T(1);
+    }
+    sc_vertex_counts(X, ne, nv);
+  }
+
   // self-friction on velocities v at final positions x1
   __device__ void sc_friction(const RodArgs<T>& a, Team<T, W>& X, const V3<T> (&x1)[C],
                               V3<T> (&v)[C]) {
     sc_stage(sc_pos, x1);
     sc_stage(sc_aux, v);
+    sc_friction_counts(X);
     __syncthreads();
     V3<T> dA[C], dB[C];
 #pragma unroll
@@ -872,7 +927,7 @@ struct Rod {
                                      sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
                                      sc_r[hi + 1], d0, mu, a.h);
         if (!f.ok) continue;
-        T iW = frcp(f.g.W);
+        T iW = frcp(f.g.W * sc_divisor(lo, hi));
         if (e == lo) {
           dA[c] += (sc_w[lo] * (T(1) - f.g.cp.s) * iW) * f.dvt;
           dB[c] += (sc_w[lo + 1] * f.g.cp.s * iW) * f.dvt;
@@ -897,6 +952,7 @@ struct Rod {
     sc_stage(sc_pos, r.x1);
     sc_stage(sc_aux, r.v3);
     sc_stage(sc_adj, lv);
+    sc_friction_counts(X);
     __syncthreads();
     V3<T> vA[C], vB[C], xA[C], xB[C];
 #pragma unroll
@@ -920,10 +976,11 @@ struct Rod {
                                      sc_r[hi + 1], d0, mu, a.h);
         V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
         V3<T> q0 = zero3<T>(), q1 = zero3<T>(), q2 = zero3<T>(), q3 = zero3<T>();
+        const T im = frcp(sc_divisor(lo, hi));
         T d0b = pair_friction_vjp(P1, Q1, P2, Q2, vi, vi1, vj, vj1, f, sc_w[lo], sc_w[lo + 1],
-                                  sc_w[hi], sc_w[hi + 1], mu, a.h, sc_at(sc_adj, lo),
-                                  sc_at(sc_adj, lo + 1), sc_at(sc_adj, hi),
-                                  sc_at(sc_adj, hi + 1), b0, b1, b2, b3, q0, q1, q2, q3);
+                                  sc_w[hi], sc_w[hi + 1], mu, a.h, im * sc_at(sc_adj, lo),
+                                  im * sc_at(sc_adj, lo + 1), im * sc_at(sc_adj, hi),
+                                  im * sc_at(sc_adj, hi + 1), b0, b1, b2, b3, q0, q1, q2, q3);
         sc_d0[e * SC_MAXP + k] = d0b;
         if (e == lo) {
           vA[c] += b0; vB[c] += b1; xA[c] += q0; xB[c] += q1;
@@ -947,9 +1004,11 @@ struct Rod {
   __device__ void sc_pass_vjp(Team<T, W>& X, V3<T> (&pb)[C], int it, bool with_depth) {
     V3<T> pin[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      pin[c] = mk(ctape[((it * C + c) * 3 + 0) * TL + tl], ctape[((it * C + c) * 3 + 1) * TL + tl],
-                  ctape[((it * C + c) * 3 + 2) * TL + tl]);
+    for (int c = 0; c < C; ++c) {
+      Q4<T> q = reinterpret_cast<const Q4<T>*>(ctape)[(it * C + c) * TL + tl];
+      pin[c] = mk(q.x, q.y, q.z);
+      if (vvalid(c)) sc_vcnt[gi(c)] = q.w;
+    }
     sc_stage(sc_pos, pin);
     sc_stage(sc_adj, pb);
     __syncthreads();
@@ -969,10 +1028,11 @@ struct Rod {
         V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
         V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
         V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
+        const T im = frcp(sc_divisor(lo, hi));
         pair_proj_vjp(P1, Q1, P2, Q2, g, sc_w[lo], sc_w[lo + 1], sc_w[hi], sc_w[hi + 1],
-                      sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], sc_at(sc_adj, lo),
-                      sc_at(sc_adj, lo + 1), sc_at(sc_adj, hi), sc_at(sc_adj, hi + 1), b0, b1,
-                      b2, b3);
+                      sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], im * sc_at(sc_adj, lo),
+                      im * sc_at(sc_adj, lo + 1), im * sc_at(sc_adj, hi),
+                      im * sc_at(sc_adj, hi + 1), b0, b1, b2, b3);
         if (with_depth) {
           T d0b = sc_d0[e * SC_MAXP + k];
           if (d0b != T(0))
@@ -1430,23 +1490,30 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
 }
 
 // Adjoint over the launch's steps, last to first, from the substep tape.
-template <typename T, int C, int W, bool SC>
+// GT: the projection iterates of a substep go to a rod-private block of
+// global scratch (L2-resident) instead of LDS -- for teams whose iterates do
+// not fit in LDS, and always with self-contact, whose buffers fill the LDS.
+template <typename T, int C, int W, bool SC, bool GT>
 __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
+  static_assert(GT || !SC, "self-contact keeps the iterates in global scratch");
   extern __shared__ __align__(16) unsigned char smem[];
   Team<T, W> X;
   X.init(reinterpret_cast<T*>(smem));
   Rod<T, C, W, SC> R;
   R.load_static(a, X);
   T* lds_tape;
-  if constexpr (SC) {
-    // LDS holds the self-contact buffers; the projection iterates go to a
-    // rod-private global scratch block (written and read within a substep)
-    R.sc_layout(smem + xchg_bytes<T, W>());
+  if constexpr (GT) {
     lds_tape = a.sc_tape + a.sc_off[R.rod];
-    R.ctape = lds_tape + (size_t)a.n_iters * C * 3 * 64 * W;
-    R.sc_setup(a);
   } else {
     lds_tape = reinterpret_cast<T*>(smem + xchg_bytes<T, W>());
+  }
+  if constexpr (SC) {
+    // LDS holds the self-contact buffers; the contact-pass inputs follow the
+    // projection iterates in the rod's scratch block (written and read
+    // within a substep)
+    R.sc_layout(smem + xchg_bytes<T, W>());
+    R.ctape = lds_tape + (size_t)a.n_iters * C * PROJ_TAPE * 64 * W;
+    R.sc_setup(a);
   }
   V3<T> lx[C], lv[C], ld1[C], uacc[C];
   T lk0[C], lk1[C];
@@ -1624,38 +1691,40 @@ __global__ void k_selftest_exchange(int* out) {
 // ---------------------------------------------------------------------------
 
 template <typename T, int C, int W, bool SC>
-static size_t lds_bytes(int which, int n_iters) {
+static size_t lds_bytes(int which, bool gt, int n_iters) {
   size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
   if constexpr (SC) return xb + Rod<T, C, W, SC>::sc_bytes();
-  if (which == 2) return xb + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
+  if (which == 2 && !gt) return xb + (size_t)n_iters * C * PROJ_TAPE * 64 * W * sizeof(T);
   return xb;
 }
 
 template <typename T, int C, int W, bool SC>
-static hipError_t launch_shape(int which, const RodArgs<T>& a, int n_blocks, hipStream_t st) {
-  size_t lds = lds_bytes<T, C, W, SC>(which, a.n_iters);
+static hipError_t launch_shape(int which, bool gt, const RodArgs<T>& a, int n_blocks,
+                               hipStream_t st) {
+  size_t lds = lds_bytes<T, C, W, SC>(which, gt, a.n_iters);
+  auto go = [&](auto f) {
+    if (lds > 65536) hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, a);
+  };
   if (which == 0) {
-    auto f = k_forward<T, C, W, false, SC>;
-    if (lds > 65536) hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, a);
+    go(k_forward<T, C, W, false, SC>);
   } else if (which == 1) {
-    auto f = k_forward<T, C, W, true, SC>;
-    if (lds > 65536) hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, a);
+    go(k_forward<T, C, W, true, SC>);
+  } else if constexpr (SC) {
+    go(k_adjoint<T, C, W, true, true>);
   } else {
-    auto f = k_adjoint<T, C, W, SC>;
-    if (lds > 65536) hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, a);
+    if (gt) go(k_adjoint<T, C, W, false, true>);
+    else go(k_adjoint<T, C, W, false, false>);
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_rods(int which, int C, int W, bool SC, const RodArgs<T>& a, int n_blocks,
-                       hipStream_t st) {
+hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<T>& a,
+                       int n_blocks, hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
 #define RODS_SHAPE(CC, WW) \
-  if (!SC && C == CC && W == WW) return launch_shape<T, CC, WW, false>(which, a, n_blocks, st);
+  if (!SC && C == CC && W == WW) return launch_shape<T, CC, WW, false>(which, GT, a, n_blocks, st);
   RODS_SHAPE(2, 1)
   RODS_SHAPE(2, 2)
   RODS_SHAPE(2, 4)
@@ -1665,7 +1734,7 @@ hipError_t launch_rods(int which, int C, int W, bool SC, const RodArgs<T>& a, in
     RODS_SHAPE(4, 2)
     RODS_SHAPE(4, 4)
 #define RODS_SC_SHAPE(CC, WW) \
-  if (SC && C == CC && W == WW) return launch_shape<T, CC, WW, true>(which, a, n_blocks, st);
+  if (SC && C == CC && W == WW) return launch_shape<T, CC, WW, true>(which, true, a, n_blocks, st);
     RODS_SC_SHAPE(2, 1)
     RODS_SC_SHAPE(2, 2)
     RODS_SC_SHAPE(2, 4)
@@ -1678,7 +1747,7 @@ hipError_t launch_rods(int which, int C, int W, bool SC, const RodArgs<T>& a, in
 }
 
 template <typename T>
-size_t kernel_lds_bytes(int which, int C, int W, bool SC, int n_iters) {
+size_t kernel_lds_bytes(int which, int C, int W, bool SC, bool GT, int n_iters) {
   size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
   if (SC) {
     if constexpr (sizeof(T) == 4) {
@@ -1690,7 +1759,7 @@ size_t kernel_lds_bytes(int which, int C, int W, bool SC, int n_iters) {
     }
     return (size_t)1 << 30;   // no self-contact kernel for this shape or precision
   }
-  if (which == 2) return xb + (size_t)n_iters * C * 3 * 64 * W * sizeof(T);
+  if (which == 2 && !GT) return xb + (size_t)n_iters * C * PROJ_TAPE * 64 * W * sizeof(T);
   return xb;
 }
 
@@ -1744,8 +1813,9 @@ hipError_t launch_selftest_exchange(int* out, hipStream_t st) {
 }
 
 #define RODS_INST(T)                                                                          \
-  template hipError_t launch_rods<T>(int, int, int, bool, const RodArgs<T>&, int, hipStream_t); \
-  template size_t kernel_lds_bytes<T>(int, int, int, bool, int);                               \
+  template hipError_t launch_rods<T>(int, int, int, bool, bool, const RodArgs<T>&, int,       \
+                                     hipStream_t);                                            \
+  template size_t kernel_lds_bytes<T>(int, int, int, bool, bool, int);                         \
   template hipError_t launch_init_frames<T>(const int32_t*, int, const T*, T*, hipStream_t);  \
   template hipError_t launch_curvature<T>(const int32_t*, const int32_t*, int, const T*,      \
                                           const T*, T*, hipStream_t);                         \

@@ -8,12 +8,14 @@ namespace rods {
 
 // which: 0 = forward, 1 = forward writing the substep tape, 2 = adjoint
 // SC: rods with self-contact (FP32 only)
+// GT: the adjoint keeps a substep's projection iterates in the rod's block
+//     of global scratch (sc_tape/sc_off) rather than in LDS (implied by SC)
 template <typename T>
-hipError_t launch_rods(int which, int C, int W, bool SC, const RodArgs<T>& a, int n_blocks,
-                       hipStream_t st);
+hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<T>& a,
+                       int n_blocks, hipStream_t st);
 // dynamic LDS of a launch shape (kind 0/1 forward, 2 adjoint)
 template <typename T>
-size_t kernel_lds_bytes(int which, int C, int W, bool SC, int n_iters);
+size_t kernel_lds_bytes(int which, int C, int W, bool SC, bool GT, int n_iters);
 template <typename T>
 hipError_t launch_init_frames(const int32_t* voff, int R, const T* x, T* d1, hipStream_t st);
 template <typename T>

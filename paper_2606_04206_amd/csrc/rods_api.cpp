@@ -26,6 +26,7 @@ struct Bin {
   int C, W;       // vertices per lane, waves per rod
   int n, off;     // rods bin_rods[off .. off+n)
   bool sc;        // rods with self-contact
+  bool gt;        // the adjoint keeps projection iterates in global scratch
 };
 
 // self-contact kernels exist for these shapes (FP32)
@@ -280,15 +281,21 @@ struct Impl : HandleBase {
         return (voff_h[a + 1] - voff_h[a]) > (voff_h[b2 + 1] - voff_h[b2]);
       });
       Bin bn{std::get<0>(keys[k]), std::get<1>(keys[k]), (int)m.size(), (int)bin_rods_h.size(),
-             std::get<2>(keys[k])};
-      if (rods::kernel_lds_bytes<T>(2, bn.C, bn.W, bn.sc, d.n_iters) > lds_max) return ROD_EINVAL;
+             std::get<2>(keys[k]), false};
+      bn.gt = global_tape(bn.C, bn.W, bn.sc);
+      if (rods::kernel_lds_bytes<T>(2, bn.C, bn.W, bn.sc, bn.gt, d.n_iters) > lds_max)
+        return ROD_EINVAL;
       bins.push_back(bn);
       for (int r : m) bin_rods_h.push_back(r);
     }
     std::vector<int64_t> toff_h, soff_h;
     layout_offsets(toff_h, soff_h);
     tape_cap = 2 * tape_stride;   // autotuned teams are at most twice the smallest legal one
-    sc_cap = 2 * sc_stride_;
+    // scratch for the projection iterates: room for every rod at twice its
+    // smallest team, whatever shapes the autotuner picks
+    sc_cap = 0;
+    for (const Bin& bn : bins)
+      sc_cap += (int64_t)bn.n * 2 * scratch_per_rod(bn.C, bn.W);
     n_ck = std::max(1, (d.max_steps + d.ckpt_every - 1) / d.ckpt_every);
     n_act_max = std::max(1, (d.max_steps + d.steps_per_action - 1) / d.steps_per_action);
 
@@ -327,6 +334,16 @@ struct Impl : HandleBase {
   }
 
   int64_t sc_stride_ = 0;
+  // values of global scratch per rod for the adjoint's projection iterates
+  // (and, with self-contact, the contact-pass inputs)
+  int64_t scratch_per_rod(int C, int W) const {
+    return (int64_t)(rods::PROJ_TAPE + 4) * d.n_iters * C * 64 * W;
+  }
+  // iterates go to global scratch with self-contact, or when they do not fit
+  // in LDS next to the lane-exchange buffers
+  bool global_tape(int C, int W, bool sc) const {
+    return sc || rods::kernel_lds_bytes<T>(2, C, W, false, false, d.n_iters) > lds_max;
+  }
   // per-rod offsets of the backward tape block and of the self-contact
   // iterate block for the current launch shapes
   void layout_offsets(std::vector<int64_t>& toff_h, std::vector<int64_t>& soff_h) {
@@ -338,9 +355,9 @@ struct Impl : HandleBase {
         int r = bin_rods_h[bn.off + i];
         toff_h[r] = off;
         off += (int64_t)NF * bn.C * 64 * bn.W;
-        if (bn.sc) {
+        if (bn.gt) {
           soff_h[r] = soff;
-          soff += (int64_t)2 * d.n_iters * bn.C * 3 * 64 * bn.W;
+          soff += scratch_per_rod(bn.C, bn.W);
         }
       }
     tape_stride = off;
@@ -389,7 +406,7 @@ struct Impl : HandleBase {
     if (!plain) {
       for (const Bin& bn : bins) {
         a.rods = bin_rods + bn.off;
-        HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, bn.sc, a, bn.n, st));
+        HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, bn.sc, bn.gt, a, bn.n, st));
       }
       return ROD_OK;
     }
@@ -407,7 +424,7 @@ struct Impl : HandleBase {
           b1.step_off = step_off + s;
           if (tape0) b1.tape = tape0 + (int64_t)s * d.n_sub * tape_stride;
           b1.ck_x = (s == n_steps - 1) ? a.ck_x : nullptr;
-          HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, bn.sc, b1, 1, st));
+          HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, bn.sc, bn.gt, b1, 1, st));
         }
       }
     }
@@ -546,7 +563,8 @@ struct Impl : HandleBase {
         for (int W : Ws)
           if (64 * W * C >= nmax && 64 * W * C <= 2 * team0 && !(prec == 8 && C != 2) &&
               !(C == 4 && W == 8) && (!bn.sc || sc_shape_ok(C, W)) &&
-              rods::kernel_lds_bytes<T>(2, C, W, bn.sc, d.n_iters) <= lds_max)
+              rods::kernel_lds_bytes<T>(2, C, W, bn.sc, global_tape(C, W, bn.sc), d.n_iters) <=
+                  lds_max)
             cand.push_back({C, W});
       float best = 1e30f;
       std::pair<int, int> bestk{bn.C, bn.W};
@@ -555,9 +573,9 @@ struct Impl : HandleBase {
         a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;   // time on the scratch copy
         a.u = u0; a.act_stride = 0; a.spa = 1; a.step_off = 0; a.n_steps = n_steps;
         a.rods = bin_rods + bn.off;
-        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, bn.sc, a, bn.n, st));   // warm
+        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, bn.sc, false, a, bn.n, st));   // warm
         HIPCHK(hipEventRecord(e0, st));
-        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, bn.sc, a, bn.n, st));
+        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, bn.sc, false, a, bn.n, st));
         HIPCHK(hipEventRecord(e1, st));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
@@ -566,6 +584,7 @@ struct Impl : HandleBase {
       }
       bn.C = bestk.first;
       bn.W = bestk.second;
+      bn.gt = global_tape(bn.C, bn.W, bn.sc);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -197,11 +197,13 @@ def _target_curve(rng, x_ref, rest_edges):
 
 def make_workload(cid: int, steps: Optional[int] = None,
                   start_height: Optional[float] = None, pitch: Optional[float] = None,
-                  n_vert: Optional[int] = None, n_rods: Optional[int] = None) -> Workload:
+                  n_vert: Optional[int] = None, n_rods: Optional[int] = None,
+                  noise: Optional[float] = None) -> Workload:
     """Test knobs: start_height (configurations 2-4) replaces the initial arc
-    height (tests start just above the ground, in contact); pitch, n_vert and
-    n_rods (configuration 5) replace the helix pitch (below 2 r the coils
-    start in self-contact), the vertices per rod and the number of rods."""
+    height (tests start just above the ground, in contact); pitch, n_vert,
+    n_rods and noise (configuration 5) replace the helix pitch (below 2 r
+    the coils start in self-contact), the vertices per rod, the number of
+    rods and the standard deviation of the vertex noise (1 mm)."""
     cfg = CONFIGS[cid]
     if cid == 5 and (n_vert is not None or n_rods is not None):
         cfg = replace(cfg, n_vert=n_vert or cfg.n_vert, n_rods=n_rods or cfg.n_rods,
@@ -258,7 +260,7 @@ def make_workload(cid: int, steps: Optional[int] = None,
             rho = rng.uniform(0.05, 0.15)
             x_clean = helix_polyline(n, edge, rho, pitch or 0.03, 0.05,
                                      rng.uniform(0.0, 2.0 * np.pi))
-            x = x_clean + rng.normal(0.0, 1e-3, size=(n, 3))
+            x = x_clean + rng.normal(0.0, 1.0, size=(n, 3)) * (1e-3 if noise is None else noise)
             xr = x_clean
         rest_e = np.linalg.norm(x_clean[1:] - x_clean[:-1], axis=1)
         w = lumped_inv_mass(rest_e, RADIUS)

@@ -1,0 +1,97 @@
+"""Parity at full size, in the launch configuration the benchmark times
+(autotuned launch shapes, every rod of the batch in one launch per segment).
+
+* The 1024 x 128 batch, 1000 steps, checkpoint every 50, in FP64: final
+  positions, rest curvatures and every gradient of the 8 sampled rods
+  against FP64 oracle values stored in tests/golden (written by
+  tests/golden/make_c3_golden.py, which calls only the oracle).
+* The same batch in FP32: step 1000 of the full-batch rollout against one
+  oracle step from the GPU's own state at step 999 (the per-step bound).
+* The uneven 4096-rod contact batch and the 256 x 1024 self-contact batch:
+  one step at the end of their full horizons, teacher-forced the same way.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from synth import make_workload
+from oracle import forward as ofw
+from oracle.model import rods_from_workload, sim_from_workload
+from tests.gpukit import to_dev, gather_state, initial_full_state, rel_err
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                    "c3_oracle_1000steps.npz")
+
+
+def _handle(wl, precision, **kw):
+    from paper_2606_04206_amd import RodsHandle
+    return RodsHandle(wl, precision=precision, **kw)
+
+
+def test_fp64_full_batch_1000_steps_matches_golden():
+    g = np.load(GOLD)
+    wl = make_workload(3)
+    assert list(g["rods"]) == list(wl.oracle_rods)
+    n = wl.sim.steps
+    dt = torch.float64
+    h = _handle(wl, 8)
+    full = [to_dev(a, dt) for a in initial_full_state(wl)]
+    h.set_state(*full)
+    h.autotune(n_steps=2)
+    h.set_state(*full)
+    xT = h.tensor(wl.n_vert, 3)
+    h.rollout(n, to_dev(wl.actions, dt), record=True, x_final=xT)
+    loss, gx = h.loss_mse(xT, to_dev(wl.target, dt))
+    gr = {k: v.cpu().numpy() for k, v in h.backward(gx, n_steps=n).items()}
+    kb = h.get_state()[2].cpu().numpy()
+    x = xT.cpu().numpy()
+    assert not h.status().any()
+    for i, r in enumerate(g["rods"]):
+        a, b = wl.rod_range(int(r))
+        assert rel_err(x[a:b], g["xT"][i]) <= 1e-9, r
+        assert rel_err(kb[a:b], g["kbT"][i]) <= 1e-7, r
+        assert rel_err(gr["u"][:, r], g["u"][i]) <= 1e-7, r
+        assert rel_err(gr["x0"][a:b], g["x0"][i]) <= 1e-7, r
+        assert rel_err(gr["v0"][a:b], g["v0"][i]) <= 1e-7, r
+        assert abs(gr["b"][r] - g["b"][i]) <= 1e-6 * abs(g["b"][i]), r
+        assert abs(gr["sigma"][r] - g["sigma"][i]) <= 1e-7 * abs(g["sigma"][i]) + 1e-20, r
+
+
+def _last_step_parity(wl, n_before, tol=1e-4):
+    """FP32 full batch: n_before steps, then one more; the last step of each
+    oracle rod against one oracle step from the GPU's state before it."""
+    dt = torch.float32
+    h = _handle(wl, 4)
+    full = [to_dev(a, dt) for a in initial_full_state(wl)]
+    h.set_state(*full)
+    h.autotune(n_steps=2)
+    h.set_state(*full)
+    spa = wl.sim.steps_per_action
+    xT = h.tensor(wl.n_vert, 3)
+    h.rollout(n_before, to_dev(wl.actions[:h.n_actions(n_before)], dt), x_final=xT)
+    before = [t.double().cpu().numpy() for t in h.get_state()]
+    u = wl.actions[n_before // spa]
+    h.step(to_dev(u, dt))
+    after = [t.double().cpu().numpy() for t in h.get_state()]
+    assert not h.status().any()
+    for r in wl.oracle_rods:
+        st = gather_state(wl, [r], before)
+        orods, osim = rods_from_workload(wl, [r]), sim_from_workload(wl)
+        ref = ofw.step(orods, osim, st, u[[r]])
+        gpu = gather_state(wl, [r], after)
+        assert rel_err(gpu.x, ref.x) <= tol, r
+
+
+def test_fp32_full_batch_step_1000_parity():
+    _last_step_parity(make_workload(3), 999)
+
+
+def test_fp32_uneven_contact_batch_step_500_parity():
+    _last_step_parity(make_workload(4), 499)
+
+
+def test_fp32_selfcontact_batch_step_2000_parity():
+    _last_step_parity(make_workload(5), 1999)

@@ -150,7 +150,11 @@ def test_fp64_step_matches_oracle_tightly():
             assert rel_err(gpu.d1[r], ref.d1[r]) <= 1e-9
 
 
-def _grad_case(precision, n_steps, cid=3, K=None, sigma=None, r_c=None):
+def _fp32_rounded(full):
+    return [a.astype(np.float32).astype(np.float64) for a in full]
+
+
+def _grad_case(precision, n_steps, cid=3, K=None, sigma=None, r_c=None, rounded=False):
     wl = make_workload(cid, steps=n_steps)
     rods = list(wl.oracle_rods)
     sub = wl.subset(rods)
@@ -161,6 +165,8 @@ def _grad_case(precision, n_steps, cid=3, K=None, sigma=None, r_c=None):
     h = _handle(sub, precision=precision, max_steps=n_steps, ckpt_every=K or sub.sim.ckpt_every)
     dt = _dt(precision)
     full = initial_full_state(sub)
+    if rounded:
+        full = _fp32_rounded(full)
     _set_full(h, full, precision)
     U = to_dev(sub.actions, dt)
     xT = h.tensor(sub.n_vert, 3)
@@ -173,10 +179,11 @@ def _grad_case(precision, n_steps, cid=3, K=None, sigma=None, r_c=None):
     return sub, out
 
 
-def _oracle_grads(sub, n_steps, K):
+def _oracle_grads(sub, n_steps, K, rounded=False):
     rods = list(range(sub.n_rods))
     orods, osim = rods_from_workload(sub, rods), sim_from_workload(sub)
-    st = gather_state(sub, rods, initial_full_state(sub))
+    full = initial_full_state(sub)
+    st = gather_state(sub, rods, _fp32_rounded(full) if rounded else full)
     U = sub.actions[:, rods]
     xT, ck = ofw.rollout(orods, osim, st, U, n_steps, K)
     L, gx = oadj.loss_mse(xT.x, sub.target.reshape(xT.x.shape), sub.n_rods)
@@ -211,11 +218,17 @@ def test_fp64_rollout_gradients_match_oracle_tightly(variant):
 
 
 def test_fp32_rollout_gradients_match_oracle():
-    """Configuration 3 physics (r_c = 1), FP32 GPU against the FP64 oracle:
-    gradients within 1e-3 per block, loss within 1e-4."""
-    n, K = 20, 7
-    sub, g = _grad_case(4, n, K=K)
-    ref = _oracle_grads(sub, n, K)
+    """Configuration 3 physics (creep rate 1), FP32 GPU against the FP64
+    oracle from the same FP32-rounded start, over 2 steps (30 substeps),
+    checkpoint every step: gradients within 1e-3 per block, loss within
+    1e-4.  The horizon is where the comparison means something: perturbing
+    the oracle's own start by one FP32 rounding moves its gradients by
+    about 2e-4 after 2 steps but by up to 3e-2 after 5 (the return map puts
+    the state on the yield surface, so rounding-sized changes flip later
+    yield decisions); longer horizons are compared in FP64."""
+    n, K = 2, 1
+    sub, g = _grad_case(4, n, K=K, rounded=True)
+    ref = _oracle_grads(sub, n, K, rounded=True)
     _check_grads(sub, g, ref, 1e-3, 1e-4)
 
 

@@ -185,3 +185,31 @@ def test_selfcontact_conserves_momentum_over_steps():
     for _ in range(3):
         st = forward.step(rods, sim, st, np.zeros((1, 0, 3)))
     assert np.abs((m[:, None] * st.v[0]).sum(0) - P0).max() < 1e-13
+
+
+def test_dense_contact_pass_is_bounded_and_balanced():
+    """Reading of the Jacobi contact pass: each active pair's correction is
+    divided by the largest number of active pairs touching one of its
+    vertices.  In a tight coil (pitch 6 mm < 2 r, several partners per
+    edge) one pass moves every vertex by at most its largest single-pair
+    move, keeps sum m dx = 0 exactly, and a plain sum of the single-pair
+    moves would exceed that bound at some vertex."""
+    x, rest = _coil(N=40, pitch=0.006, noise=2e-4, seed=35)
+    rods = make_rods(x, rest=rest)
+    rods.flags |= 4
+    sim = make_sim()
+    pairs = sc.candidates(rods, sim, x)
+    p = sc.project_pairs(rods, x, pairs, None)
+    moved = np.linalg.norm(p[0] - x[0], axis=-1)
+    single = []
+    for pr in pairs[0]:
+        q = sc.project_pairs(rods, x, [pr[None]], None)
+        single.append(q[0] - x[0])
+    single = np.array(single)                      # [pairs, N, 3]
+    n_touch = (np.linalg.norm(single, axis=-1) > 0).sum(0)
+    assert n_touch.max() >= 3
+    bound = np.linalg.norm(single, axis=-1).max(0)
+    assert np.all(moved <= bound * (1 + 1e-12) + 1e-18)
+    assert np.any(np.linalg.norm(single.sum(0), axis=-1) > bound * 1.5)
+    m = 1.0 / rods.w[0]
+    np.testing.assert_allclose((m[:, None] * (p[0] - x[0])).sum(0), 0.0, atol=1e-18)
