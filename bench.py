@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "rod-vertex-steps/s fwd+bwd, batched vs plain, at ≤1e-4 pos / 1e-3 grad err"
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published)
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published; counts packed dual-rate FP32)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6   # one FP32 op per lane per cycle (packed forms are not used)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_1024x128_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2606_04206_amd", "csrc", "rod_kernels.hip")
 
@@ -158,6 +159,8 @@ def main():
             traffic = rec.get("bytes_per_launch")
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+            "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+            "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
             "kernel": "k_adjoint", "avg_launch_ms": round(adj_avg, 3),
             "algorithmic_bytes_per_launch": adjoint_bytes_per_vertex_substep() * units,
             "kernel_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in prof.items()}}

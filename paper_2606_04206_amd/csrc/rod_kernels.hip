@@ -522,43 +522,66 @@ struct Rod {
   }
 
   // N_C iterations of red (even edges) then black (odd edges) projections
+  // of p = p0 + dl: the edge vectors of p0 are formed once, an iteration
+  // adds the corrections' difference (more precise than differencing p)
   template <bool REC>
-  __device__ void project(const RodArgs<T>& a, Team<T, W>& X, V3<T> (&p)[C], T* lds_tape) {
+  __device__ void project(const RodArgs<T>& a, Team<T, W>& X, const V3<T> (&p0)[C],
+                          V3<T> (&dl)[C], T* lds_tape) {
     const bool inext = (flags & FLAG_INEXT) != 0;
+    V3<T> E0[C];
+    {
+      T pn[3] = {p0[0].x, p0[0].y, p0[0].z};
+      X.next(pn);
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        E0[c] = (c < C - 1 ? p0[c + 1] : mk(pn[0], pn[1], pn[2])) - p0[c];
+    }
     for (int it = 0; it < a.n_iters; ++it) {
-      if (inext) project_iter<REC>(X, p, lds_tape, it);
+      if (inext) project_iter<REC>(X, E0, dl, lds_tape, it);
       if constexpr (SC) {
-        if (flags & FLAG_SELF) sc_pass<REC>(X, p, it, it == 0);
+        if (flags & FLAG_SELF) sc_pass<REC>(X, p0, dl, it, it == 0);
       }
     }
   }
 
+  // one projection of edge c: D = E0 + (dl_k - dl_j); returns 1/|D|
+  __device__ __forceinline__ T proj_edge(int c, const V3<T>& E0, V3<T>& dj, V3<T>& dk,
+                                         V3<T>& D) const {
+    D = E0 + (dk - dj);
+    T il = frsq(fmax(dot(D, D), T(1e-30)));
+    T s = T(1) - rest[c] * il;
+    dj += (s * aj[c]) * D;
+    dk -= (s * ak[c]) * D;
+    return il;
+  }
+
   template <bool REC>
-  __device__ void project_iter(Team<T, W>& X, V3<T> (&p)[C], T* lds_tape, int it) {
+  __device__ void project_iter(Team<T, W>& X, const V3<T> (&E0)[C], V3<T> (&dl)[C],
+                               T* lds_tape, int it) {
     V3<T> D;
 #pragma unroll
     for (int c = 0; c < C; c += 2) {   // red: even edges, inside the lane
-      T il = project_edge(p[c], p[c + 1], aj[c], ak[c], rest[c], D);
+      T il = proj_edge(c, E0[c], dl[c], dl[c + 1], D);
       if constexpr (REC) tape_put(lds_tape, it, c, D, il);
     }
 #pragma unroll
     for (int c = 1; c < C - 1; c += 2) {   // black edges inside the lane
-      T il = project_edge(p[c], p[c + 1], aj[c], ak[c], rest[c], D);
+      T il = proj_edge(c, E0[c], dl[c], dl[c + 1], D);
       if constexpr (REC) tape_put(lds_tape, it, c, D, il);
     }
     // the lane's last (black) edge reaches into the next lane: project it
     // here and send the next lane its endpoint's move
-    T pn[3] = {p[0].x, p[0].y, p[0].z};
-    X.next(pn);
-    V3<T> q = mk(pn[0], pn[1], pn[2]);
-    D = q - p[C - 1];
+    T dn[3] = {dl[0].x, dl[0].y, dl[0].z};
+    X.next(dn);
+    D = E0[C - 1] + (mk(dn[0], dn[1], dn[2]) - dl[C - 1]);
     T il = frsq(fmax(dot(D, D), T(1e-30)));
     T sc = T(1) - rest[C - 1] * il;
-    p[C - 1] += (sc * aj[C - 1]) * D;
+    dl[C - 1] += (sc * aj[C - 1]) * D;
     if constexpr (REC) tape_put(lds_tape, it, C - 1, D, il);
-    T mv[3] = {-(sc * ak[C - 1]) * D.x, -(sc * ak[C - 1]) * D.y, -(sc * ak[C - 1]) * D.z};
+    const T mk_ = -(sc * ak[C - 1]);
+    T mv[3] = {mk_ * D.x, mk_ * D.y, mk_ * D.z};
     X.prev(mv);
-    p[0] += mk(mv[0], mv[1], mv[2]);
+    dl[0] += mk(mv[0], mv[1], mv[2]);
   }
 
   __device__ __forceinline__ void tape_load(const T* tape, int it, Q4<T> (&q)[C]) const {
@@ -824,7 +847,11 @@ struct Rod {
   // vertex, the second applies every active pair's correction divided by
   // its divisor
   template <bool REC>
-  __device__ void sc_pass(Team<T, W>& X, V3<T> (&p)[C], int it, bool first) {
+  __device__ void sc_pass(Team<T, W>& X, const V3<T> (&p0)[C], V3<T> (&dl)[C], int it,
+                          bool first) {
+    V3<T> p[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) p[c] = p0[c] + dl[c];
     sc_stage(sc_pos, p);
     __syncthreads();
     T ne[C], nv[C];
@@ -881,7 +908,7 @@ struct Rod {
     T s3[3] = {dB[C - 1].x, dB[C - 1].y, dB[C - 1].z};
     X.prev(s3);
 #pragma unroll
-    for (int c = 0; c < C; ++c) p[c] += dA[c] + (c ? dB[c - 1] : mk(s3[0], s3[1], s3[2]));
+    for (int c = 0; c < C; ++c) dl[c] += dA[c] + (c ? dB[c - 1] : mk(s3[0], s3[1], s3[2]));
   }
 
   // pairs with a positive first-pass depth per own edge (friction's counts)
@@ -1164,25 +1191,28 @@ struct Rod {
           if (w[c] > T(0)) contact_one(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, v[c]);
       }
     }
-    // S5 predict
-    V3<T> p[C], pp[C];
+    // S5 predict.  The projections below act on p = p0 + dl with the
+    // predicted positions p0 fixed and the corrections accumulated in dl,
+    // so S8's (p - p0) / h is dl / h, free of the cancellation that FP32
+    // positions would otherwise turn into velocity noise of ulp(x) / h.
+    V3<T> p0[C], dl[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      p[c] = x[c] + h * v[c];
-      pp[c] = p[c];
+      p0[c] = x[c] + h * v[c];
+      dl[c] = zero3<T>();
     }
     // S6 self-contact candidates at the predicted positions
     const bool self_on = SC && (flags & FLAG_SELF);
     if constexpr (SC) {
-      if (self_on) sc_broadphase(a, p);
+      if (self_on) sc_broadphase(a, p0);
     }
     // S7 projections
-    if ((flags & FLAG_INEXT) || self_on) project<REC>(a, X, p, lds_tape);
+    if ((flags & FLAG_INEXT) || self_on) project<REC>(a, X, p0, dl, lds_tape);
     // S8 velocity update from the corrections
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      v[c] += ih * (p[c] - pp[c]);
-      x[c] = p[c];
+      v[c] += ih * dl[c];
+      x[c] = p0[c] + dl[c];
     }
     // S9 self-friction
     if constexpr (SC) {

@@ -17,7 +17,9 @@ class SimParams:
     gravity: tuple = (0.0, 0.0, -9.81)
     eps_s: float = 1e-3              # contact softness epsilon_s (m)
     f_thresh: float = 0.1            # contact influence threshold
-    self_margin: float = 5e-3        # broadphase margin delta_c (m)
+    self_margin: float = 1e-3        # broadphase margin delta_c (m): candidates are fixed
+                                     # for a substep, so it must cover two segments' relative
+                                     # motion in one substep (1 mm = 15 m/s over h = dt/15)
     k_exclude: int = 2               # self-contact index exclusion |i-j| > K_ex
     steps_per_action: int = 1
     ckpt_every: int = 50

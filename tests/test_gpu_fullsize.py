@@ -60,9 +60,18 @@ def test_fp64_full_batch_1000_steps_matches_golden():
         assert abs(gr["sigma"][r] - g["sigma"][i]) <= 1e-7 * abs(g["sigma"][i]) + 1e-20, r
 
 
-def _last_step_parity(wl, n_before, tol=1e-4):
+def _perturbed(st, seed):
+    rng = np.random.default_rng(seed)
+    return type(st)(st.x * (1 + 6e-8 * rng.standard_normal(st.x.shape)),
+                    st.v * (1 + 6e-8 * rng.standard_normal(st.v.shape)), st.kb, st.d1)
+
+
+def _last_step_parity(wl, n_before, tol=1e-4, ties=False):
     """FP32 full batch: n_before steps, then one more; the last step of each
-    oracle rod against one oracle step from the GPU's state before it."""
+    oracle rod against one oracle step from the GPU's state before it.
+    ties: the step has contact ties by construction (self-contact), so the
+    bound is the larger of tol and twice the oracle's own spread under one
+    FP32 rounding of its start."""
     dt = torch.float32
     h = _handle(wl, 4)
     full = [to_dev(a, dt) for a in initial_full_state(wl)]
@@ -76,13 +85,19 @@ def _last_step_parity(wl, n_before, tol=1e-4):
     u = wl.actions[n_before // spa]
     h.step(to_dev(u, dt))
     after = [t.double().cpu().numpy() for t in h.get_state()]
-    assert not h.status().any()
+    status = h.status()
+    assert not status.any(), np.unique(status, return_counts=True)
     for r in wl.oracle_rods:
         st = gather_state(wl, [r], before)
         orods, osim = rods_from_workload(wl, [r]), sim_from_workload(wl)
         ref = ofw.step(orods, osim, st, u[[r]])
         gpu = gather_state(wl, [r], after)
-        assert rel_err(gpu.x, ref.x) <= tol, r
+        bound = tol
+        if ties:
+            spread = max(rel_err(ofw.step(orods, osim, _perturbed(st, s), u[[r]]).x, ref.x)
+                         for s in (1, 2))
+            bound = max(tol, 2 * spread)
+        assert rel_err(gpu.x, ref.x) <= bound, r
 
 
 def test_fp32_full_batch_step_1000_parity():
@@ -94,4 +109,4 @@ def test_fp32_uneven_contact_batch_step_500_parity():
 
 
 def test_fp32_selfcontact_batch_step_2000_parity():
-    _last_step_parity(make_workload(5), 1999)
+    _last_step_parity(make_workload(5), 1999, ties=True)
