@@ -169,7 +169,11 @@ int rods_loss_mse(RodsHandle* h, const void* x, const void* target, void* loss,
                   void* dL_dx, rods_stream_t stream);
 
 /* Synchronises the stream and copies per-rod status words to flags (host)
- * [R]: bit0 = non-finite state seen.  Returns ROD_EHIP if a kernel failed. */
+ * [R], accumulated since rods_set_state: bit0 = non-finite state seen;
+ * bit1 = a self-contact partner list was full (candidate pairs beyond its
+ * capacity were dropped for that substep); bit2 = an edge at predicted
+ * positions exceeded twice the rod's longest rest edge (a warning: the
+ * candidate search still covers it).  Returns ROD_EHIP if a kernel failed. */
 int rods_status(RodsHandle* h, int32_t* flags, rods_stream_t stream);
 
 /* Launch configuration per size bin: fills up to max_bins entries of

@@ -213,7 +213,7 @@ struct RodArgs {
   double* acc_s;            // [V] per-vertex dL/dsigma partials
   T* sc_tape;               // self-contact rods: projection iterates of one substep
   const int64_t* sc_off;    // [R] offset of the rod's block in sc_tape
-  int32_t* status;          // [R] bit0 non-finite, bit1 partner list full, bit2 edge too long for the hash cell
+  int32_t* status;          // [R] bit0 non-finite, bit1 partner list full, bit2 stretched edge
   // scalars
   T h;
   T gx, gy, gz;

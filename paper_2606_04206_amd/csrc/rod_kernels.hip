@@ -361,7 +361,7 @@ struct Rod {
   T *sc_pos, *sc_aux, *sc_adj, *sc_w, *sc_r, *sc_d0, *sc_vcnt;
   int *sc_cnt, *sc_start, *sc_pcnt, *sc_tmp;
   short *sc_items, *sc_plist;
-  T sc_cell, sc_lmax;
+  T sc_cell0, sc_lmax;
   int sc_flags;
   T* ctape;
   T b, sig, rc, mu, e, K;
@@ -687,9 +687,9 @@ struct Rod {
   __device__ __forceinline__ V3<T> sc_at(const T* a, int v) const {
     return mk(a[3 * v], a[3 * v + 1], a[3 * v + 2]);
   }
-  // static data into LDS and the hash cell size: 2 r_max + delta_c + 2 l_max
-  // (a partner's midpoint then lies in the 27 cells around the edge's own as
-  // long as no edge exceeds 2 l_max, which is checked every substep)
+  // static data into LDS; the hash cell is 2 r_max + delta_c + 2 l where l
+  // is the longest edge at the substep's predicted positions, so a
+  // partner's midpoint always lies in the 27 cells around the edge's own
   __device__ void sc_setup(const RodArgs<T>& a) {
     sc_flags = 0;
     T m_r = T(0), m_l = T(0);
@@ -717,17 +717,32 @@ struct Rod {
     __syncthreads();
     T rmax = red[0], lmax = red[1];
     sc_lmax = T(2) * lmax;
-    sc_cell = T(2) * rmax + a.self_margin + T(2) * lmax;
+    sc_cell0 = T(2) * rmax + a.self_margin;
     __syncthreads();
   }
 
   // candidate pairs at the predicted positions p (uniform-grid hash of edge
   // midpoints; per own edge a sorted, duplicate-free partner list)
   __device__ void sc_broadphase(const RodArgs<T>& a, const V3<T> (&p)[C]) {
+    static_assert(!SC || sizeof(T) == 4, "self-contact kernels are FP32");
     sc_stage(sc_pos, p);
     for (int i = tl; i < SC_HT; i += TL) sc_cnt[i] = 0;
+    int* lsq = sc_tmp;   // longest squared edge (bits of a non-negative float)
+    if (tl == 0) *lsq = 0;
     __syncthreads();
-    const T ig = frcp(sc_cell);
+    T l2 = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (evalid(c)) {
+        V3<T> D = sc_at(sc_pos, gi(c) + 1) - sc_at(sc_pos, gi(c));
+        l2 = fmax(l2, dot(D, D));
+      }
+    }
+    atomicMax(lsq, __float_as_int(l2));
+    __syncthreads();
+    l2 = __int_as_float(*lsq);   // sc_tmp is next written after the barrier below
+    if (l2 > sc_lmax * sc_lmax) sc_flags |= 4;
+    const T ig = frcp(sc_cell0 + T(2) * fsqrt(l2));
     unsigned key[C];
     int slot[C];
 #pragma unroll
@@ -737,8 +752,6 @@ struct Rod {
       if (evalid(c)) {
         int e = gi(c);
         V3<T> P = sc_at(sc_pos, e), Q = sc_at(sc_pos, e + 1);
-        V3<T> D = Q - P;
-        if (dot(D, D) > sc_lmax * sc_lmax) sc_flags |= 4;
         V3<T> m = T(0.5) * (P + Q);
         key[c] = sc_hash((int)floor(m.x * ig), (int)floor(m.y * ig), (int)floor(m.z * ig));
         slot[c] = atomicAdd(&sc_cnt[key[c]], 1);

