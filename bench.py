@@ -205,7 +205,7 @@ def main():
         out["speedup_vs_plain"] = round(value / pv, 1)
 
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(list(wl.oracle_rods), 150)
+        out["cpu_baseline"] = cpu_baseline(list(wl.oracle_rods), 300)
     print(json.dumps(out), flush=True)
 
 
