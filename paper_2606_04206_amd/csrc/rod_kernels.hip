@@ -56,23 +56,24 @@ __device__ __forceinline__ V3<T> transport_vjp(V3<T> v, V3<T> ta, V3<T> tb, V3<T
 template <typename T>
 struct BendIn {
   V3<T> t0, t1, d1a, d1b, d2a, d2b;
-  T l0, l1, kr0, kr1, lbar;
+  T il0, il1;      // inverse lengths of edges i-1 and i
+  T kr0, kr1;
+  T coef, ilbar;   // b / l_bar and 1 / l_bar (both 0 away from interior vertices)
 };
 
 template <typename T>
-__device__ __forceinline__ void bend_grad(const BendIn<T>& q, T b, V3<T>& g0, V3<T>& g1) {
+__device__ __forceinline__ void bend_grad(const BendIn<T>& q, V3<T>& g0, V3<T>& g1) {
   T ichi = frcp(T(1) + dot(q.t0, q.t1));
   V3<T> kbv = (T(2) * ichi) * cross(q.t0, q.t1);
   V3<T> a1 = T(0.5) * (q.d2a + q.d2b);
   V3<T> a2 = T(0.5) * (q.d1a + q.d1b);
   T k1 = dot(kbv, a1), k2 = dot(kbv, a2);
-  T coef = fdiv(b, q.lbar);
-  T c1 = coef * (k1 - q.kr0), c2 = coef * (k2 - q.kr1);
+  T c1 = q.coef * (k1 - q.kr0), c2 = q.coef * (k2 - q.kr1);
   T s = c1 * k1 + c2 * k2;
   V3<T> A = (T(2) * ichi) * (c1 * a1 + c2 * a2);
   V3<T> tt = ichi * (q.t0 + q.t1);
-  g0 = frcp(q.l0) * (cross(q.t1, A) - s * tt);
-  g1 = frcp(q.l1) * (-(s * tt) - cross(q.t0, A));
+  g0 = q.il0 * (cross(q.t1, A) - s * tt);
+  g1 = q.il1 * (-(s * tt) - cross(q.t0, A));
 }
 
 template <typename T>
@@ -83,7 +84,7 @@ struct BendBar {
 
 // Adjoint of bend_grad given g0_b, g1_b.
 template <typename T>
-__device__ __forceinline__ void bend_vjp(const BendIn<T>& q, T b, V3<T> g0b, V3<T> g1b,
+__device__ __forceinline__ void bend_vjp(const BendIn<T>& q, V3<T> g0b, V3<T> g1b,
                                          BendBar<T>& o) {
   T chi = T(1) + dot(q.t0, q.t1);
   T ichi = frcp(chi);
@@ -92,13 +93,13 @@ __device__ __forceinline__ void bend_vjp(const BendIn<T>& q, T b, V3<T> g0b, V3<
   V3<T> a1 = T(0.5) * (q.d2a + q.d2b);
   V3<T> a2 = T(0.5) * (q.d1a + q.d1b);
   T k1 = dot(kbv, a1), k2 = dot(kbv, a2);
-  T coef = fdiv(b, q.lbar);
+  const T coef = q.coef;
   T dk1 = k1 - q.kr0, dk2 = k2 - q.kr1;
   T c1 = coef * dk1, c2 = coef * dk2;
   T s = c1 * k1 + c2 * k2;
   V3<T> A = (T(2) * ichi) * (c1 * a1 + c2 * a2);
   V3<T> tt = ichi * (q.t0 + q.t1);
-  T il0 = frcp(q.l0), il1 = frcp(q.l1);
+  const T il0 = q.il0, il1 = q.il1;
   V3<T> g0 = il0 * (cross(q.t1, A) - s * tt);
   V3<T> g1 = il1 * (-(s * tt) - cross(q.t0, A));
   // g = G / l
@@ -120,7 +121,7 @@ __device__ __forceinline__ void bend_vjp(const BendIn<T>& q, T b, V3<T> g0b, V3<
   T k2b = c2 * sb + coef * c2b;
   o.kr0 = -coef * c1b;
   o.kr1 = -coef * c2b;
-  o.b = fdiv(c1b * dk1 + c2b * dk2, q.lbar);
+  o.b = (c1b * dk1 + c2b * dk2) * q.ilbar;
   V3<T> kbvb = k1b * a1 + k2b * a2;
   a1b += k1b * kbv;
   a2b += k2b * kbv;
@@ -340,12 +341,12 @@ __device__ __forceinline__ void contact_one_vjp(const Prim<T>& p, V3<T> x, T rad
 template <typename T, int C>
 struct Rec {   // what the adjoint needs from one substep's forward run
   V3<T> t[C], d1[C];
-  T ell[C], kr0[C], kr1[C];
+  T il[C], kr0[C], kr1[C];   // il: inverse edge lengths
   V3<T> tp, d1p;
-  T lp;
+  T ilp;
   V3<T> x[C], v1[C];
   V3<T> t1[C], d1n[C];
-  T ell1[C];
+  T il1[C];
   V3<T> t1p, d1np;
   T kel0[C], kel1[C], nrm[C], phi[C];
   bool yld[C];
@@ -367,6 +368,13 @@ struct Rod {
   T b, sig, rc, mu, e, K;
   T w[C], rest[C], lbar[C], ks[C], rad[C];
   T aj[C], ak[C];   // projection ratios w_j/W, w_k/W of the edge starting at vertex c
+  T coef[C], ilbar[C];   // b / l_bar and 1 / l_bar at interior vertices, else 0
+  // the forward (no recording) carries a substep's end geometry into the
+  // next substep: the same values edges() and prev_edge() would recompute
+  // from the same positions and frames
+  bool geo_ok, prev_ok;
+  V3<T> tc[C], tpc, d1pc;
+  T lc[C], ilc[C], ilpc;
   int gs[C];
   V3<T> x[C], v[C], d1[C];
   T kr0[C], kr1[C];
@@ -412,12 +420,15 @@ struct Rod {
       aj[c] = pe ? w[c] / Wsum : T(0);
       ak[c] = pe ? wk / Wsum : T(0);
       lbar[c] = ivalid(c) ? T(0.5) * ((c ? rest[c - 1] : rp[0]) + rest[c]) : T(0);
+      ilbar[c] = ivalid(c) ? T(1) / lbar[c] : T(0);
+      coef[c] = b * ilbar[c];
       T rb = T(0.5) * (rad[c] + (c < C - 1 ? rad[c + 1] : rn[0]));
       ks[c] = evalid(c) ? K * T(3.14159265358979323846) * rb * rb : T(0);
     }
   }
 
   __device__ void load_state(const T* X, const T* Vv, const T* KB, const T* D1) {
+    geo_ok = prev_ok = false;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       int g = gi(c), r = v0 + g;
@@ -483,28 +494,34 @@ struct Rod {
     }
   }
 
-  // edge vectors at positions p: tangents and lengths (invalid edges: t = 0, l = 1)
-  __device__ void edges(Team<T, W>& X, const V3<T> (&p)[C], V3<T> (&t)[C], T (&l)[C]) const {
+  // edge vectors at positions p: tangents, lengths and inverse lengths
+  // (invalid edges: t = 0, l = 1/l = 1)
+  __device__ void edges(Team<T, W>& X, const V3<T> (&p)[C], V3<T> (&t)[C], T (&l)[C],
+                        T (&il)[C]) const {
     T pn[3] = {p[0].x, p[0].y, p[0].z};
     X.next(pn);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       V3<T> q = (c < C - 1) ? p[c + 1] : mk(pn[0], pn[1], pn[2]);
       V3<T> D = q - p[c];
-      T ll = fsqrt(dot(D, D));
+      // explicit fused forms: every call site rounds identically, so the
+      // forward's carried geometry equals a recomputation bit for bit
+      T dd = fma(D.z, D.z, fma(D.y, D.y, D.x * D.x));
+      T ii = frsq(dd);
       bool ok = evalid(c);
-      l[c] = ok ? ll : T(1);
-      t[c] = ok ? frcp(ll) * D : zero3<T>();
+      l[c] = ok ? dd * ii : T(1);
+      il[c] = ok ? ii : T(1);
+      t[c] = ok ? ii * D : zero3<T>();
     }
   }
 
   // adjoint of edges(): adds the position adjoints to pb
-  __device__ void edges_vjp(Team<T, W>& X, const V3<T> (&t)[C], const T (&l)[C],
+  __device__ void edges_vjp(Team<T, W>& X, const V3<T> (&t)[C], const T (&il)[C],
                             const V3<T> (&tb)[C], const T (&lb)[C], V3<T> (&pb)[C]) const {
     V3<T> eb[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      eb[c] = evalid(c) ? frcp(l[c]) * (tb[c] - dot(t[c], tb[c]) * t[c]) + lb[c] * t[c]
+      eb[c] = evalid(c) ? il[c] * (tb[c] - dot(t[c], tb[c]) * t[c]) + lb[c] * t[c]
                         : zero3<T>();
       pb[c] -= eb[c];
       if (c < C - 1) pb[c + 1] += eb[c];
@@ -533,8 +550,9 @@ struct Rod {
       T pn[3] = {p0[0].x, p0[0].y, p0[0].z};
       X.next(pn);
 #pragma unroll
-      for (int c = 0; c < C; ++c)
-        E0[c] = (c < C - 1 ? p0[c + 1] : mk(pn[0], pn[1], pn[2])) - p0[c];
+      for (int c = 0; c < C; ++c)   // edges that are not projected get a unit dummy
+        E0[c] = evalid(c) ? (c < C - 1 ? p0[c + 1] : mk(pn[0], pn[1], pn[2])) - p0[c]
+                          : mk(T(1), T(0), T(0));
     }
     for (int it = 0; it < a.n_iters; ++it) {
       if (inext) project_iter<REC>(X, E0, dl, lds_tape, it);
@@ -548,7 +566,7 @@ struct Rod {
   __device__ __forceinline__ T proj_edge(int c, const V3<T>& E0, V3<T>& dj, V3<T>& dk,
                                          V3<T>& D) const {
     D = E0 + (dk - dj);
-    T il = frsq(fmax(dot(D, D), T(1e-30)));
+    T il = frsq(dot(D, D));
     T s = T(1) - rest[c] * il;
     dj += (s * aj[c]) * D;
     dk -= (s * ak[c]) * D;
@@ -574,7 +592,7 @@ struct Rod {
     T dn[3] = {dl[0].x, dl[0].y, dl[0].z};
     X.next(dn);
     D = E0[C - 1] + (mk(dn[0], dn[1], dn[2]) - dl[C - 1]);
-    T il = frsq(fmax(dot(D, D), T(1e-30)));
+    T il = frsq(dot(D, D));
     T sc = T(1) - rest[C - 1] * il;
     dl[C - 1] += (sc * aj[C - 1]) * D;
     if constexpr (REC) tape_put(lds_tape, it, C - 1, D, il);
@@ -1093,34 +1111,36 @@ struct Rod {
     for (int c = 0; c < C; ++c) pb[c] += cA[c] + (c ? cB[c - 1] : mk(s3[0], s3[1], s3[2]));
   }
 
-  // gather the previous lane's last edge: tangent, length, d1
-  __device__ void prev_edge(Team<T, W>& X, const V3<T> (&t)[C], const T (&l)[C],
-                            const V3<T> (&dd)[C], V3<T>& tp, T& lp, V3<T>& dp) const {
-    T pv[7] = {t[C - 1].x, t[C - 1].y, t[C - 1].z, l[C - 1], dd[C - 1].x, dd[C - 1].y, dd[C - 1].z};
+  // gather the previous lane's last edge: tangent, inverse length, d1
+  __device__ void prev_edge(Team<T, W>& X, const V3<T> (&t)[C], const T (&il)[C],
+                            const V3<T> (&dd)[C], V3<T>& tp, T& ilp, V3<T>& dp) const {
+    T pv[7] = {t[C - 1].x, t[C - 1].y, t[C - 1].z, il[C - 1], dd[C - 1].x, dd[C - 1].y,
+               dd[C - 1].z};
     X.prev(pv);
     tp = mk(pv[0], pv[1], pv[2]);
-    lp = pv[3];
+    ilp = pv[3];
     dp = mk(pv[4], pv[5], pv[6]);
   }
 
   // kr0/kr1: the rest curvature at the substep start (the adjoint passes the
   // recorded values: the replayed substep has already updated the registers)
-  __device__ __forceinline__ BendIn<T> bend_in(int c, const V3<T> (&t)[C], const T (&l)[C],
-                                               const V3<T> (&dd1)[C], V3<T> tp, T lp,
+  __device__ __forceinline__ BendIn<T> bend_in(int c, const V3<T> (&t)[C], const T (&il)[C],
+                                               const V3<T> (&dd1)[C], V3<T> tp, T ilp,
                                                V3<T> d1p, const T (&k0)[C],
                                                const T (&k1)[C]) const {
     BendIn<T> q;
     q.t0 = c ? t[c - 1] : tp;
     q.t1 = t[c];
-    q.l0 = c ? l[c - 1] : lp;
-    q.l1 = l[c];
+    q.il0 = c ? il[c - 1] : ilp;
+    q.il1 = il[c];
     q.d1a = c ? dd1[c - 1] : d1p;
     q.d1b = dd1[c];
     q.d2a = cross(q.t0, q.d1a);
     q.d2b = cross(q.t1, q.d1b);
     q.kr0 = k0[c];
     q.kr1 = k1[c];
-    q.lbar = lbar[c];
+    q.coef = coef[c];
+    q.ilbar = ilbar[c];
     return q;
   }
 
@@ -1133,25 +1153,40 @@ struct Rod {
     const V3<T> g = mk(a.gx, a.gy, a.gz);
     // S2 forces at x with frames fixed
     V3<T> t[C];
-    T l[C];
-    edges(X, x, t, l);
+    T l[C], il[C];
     V3<T> tp, d1p;
-    T lp;
-    prev_edge(X, t, l, d1, tp, lp, d1p);
+    T ilp;
+    if (!REC && geo_ok) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        t[c] = tc[c];
+        l[c] = lc[c];
+        il[c] = ilc[c];
+      }
+    } else {
+      edges(X, x, t, l, il);
+    }
+    if (!REC && prev_ok) {
+      tp = tpc;
+      ilp = ilpc;
+      d1p = d1pc;
+    } else {
+      prev_edge(X, t, il, d1, tp, ilp, d1p);
+    }
     V3<T> F[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) F[c] = zero3<T>();
     V3<T> to_prev = zero3<T>(), to_next = zero3<T>();
+    // every vertex runs the stencil: away from interior vertices coef = 0
+    // makes both gradients exactly zero (all inputs are finite there)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      if (ivalid(c)) {
-        BendIn<T> q = bend_in(c, t, l, d1, tp, lp, d1p, kr0, kr1);
-        V3<T> g0, g1;
-        bend_grad(q, b, g0, g1);
-        F[c] += g1 - g0;
-        if (c > 0) F[c - 1] += g0; else to_prev += g0;
-        if (c < C - 1) F[c + 1] -= g1; else to_next -= g1;
-      }
+      BendIn<T> q = bend_in(c, t, il, d1, tp, ilp, d1p, kr0, kr1);
+      V3<T> g0, g1;
+      bend_grad(q, g0, g1);
+      F[c] += g1 - g0;
+      if (c > 0) F[c - 1] += g0; else to_prev += g0;
+      if (c < C - 1) F[c + 1] -= g1; else to_next -= g1;
     }
     if (!(flags & FLAG_INEXT)) {
 #pragma unroll
@@ -1175,14 +1210,14 @@ struct Rod {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         rc_->t[c] = t[c];
-        rc_->ell[c] = l[c];
+        rc_->il[c] = il[c];
         rc_->d1[c] = d1[c];
         rc_->kr0[c] = kr0[c];
         rc_->kr1[c] = kr1[c];
         rc_->x[c] = x[c];
       }
       rc_->tp = tp;
-      rc_->lp = lp;
+      rc_->ilp = ilp;
       rc_->d1p = d1p;
     }
     // S3 velocity update and kinematic vertices
@@ -1242,8 +1277,8 @@ struct Rod {
     }
     // S10 frames by parallel transport in time
     V3<T> t1[C];
-    T l1[C];
-    edges(X, x, t1, l1);
+    T l1[C], il1[C];
+    edges(X, x, t1, l1, il1);
 #pragma unroll
     for (int c = 0; c < C; ++c)
       if (evalid(c)) d1[c] = transport(d1[c], t[c], t1[c]);
@@ -1251,42 +1286,55 @@ struct Rod {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         rc_->t1[c] = t1[c];
-        rc_->ell1[c] = l1[c];
+        rc_->il1[c] = il1[c];
         rc_->d1n[c] = d1[c];
         rc_->yld[c] = false;
       }
+    } else {
+      // the next substep starts from these positions and frames
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        tc[c] = t1[c];
+        lc[c] = l1[c];
+        ilc[c] = il1[c];
+      }
+      geo_ok = true;
+      prev_ok = false;
     }
-    // S11 plasticity
+    // S11 plasticity.  Every vertex runs the return map: away from interior
+    // vertices the curvature and kappa_bar are zero and so is the threshold,
+    // so the (strict) yield test fails there.
     if (flags & FLAG_PLASTIC) {
       V3<T> t1p, d1np;
-      T l1p;
-      prev_edge(X, t1, l1, d1, t1p, l1p, d1np);
+      T il1p;
+      prev_edge(X, t1, il1, d1, t1p, il1p, d1np);
       if constexpr (REC) {
         rc_->t1p = t1p;
         rc_->d1np = d1np;
+      } else {
+        tpc = t1p;
+        ilpc = il1p;
+        d1pc = d1np;
+        prev_ok = true;
       }
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        if (ivalid(c)) {
-          T k1, k2;
-          curvature(c ? t1[c - 1] : t1p, t1[c], c ? d1[c - 1] : d1np, d1[c], k1, k2);
-          T e0 = k1 - kr0[c], e1 = k2 - kr1[c];
-          T nrm = fsqrt(e0 * e0 + e1 * e1);
-          T thr = sig * lbar[c];
-          bool y = nrm > thr;
-          T phi = y ? fdiv(rc * (nrm - thr), nrm) : T(0);
-          if constexpr (REC) {
-            rc_->kel0[c] = e0;
-            rc_->kel1[c] = e1;
-            rc_->nrm[c] = y ? nrm : T(1);
-            rc_->phi[c] = phi;
-            rc_->yld[c] = y;
-          }
-          if (y) {
-            kr0[c] += phi * e0;
-            kr1[c] += phi * e1;
-          }
+        T k1, k2;
+        curvature(c ? t1[c - 1] : t1p, t1[c], c ? d1[c - 1] : d1np, d1[c], k1, k2);
+        T e0 = k1 - kr0[c], e1 = k2 - kr1[c];
+        T nrm = fsqrt(e0 * e0 + e1 * e1);
+        T thr = sig * lbar[c];
+        bool y = nrm > thr;
+        T phi = y ? fdiv(rc * (nrm - thr), nrm) : T(0);
+        if constexpr (REC) {
+          rc_->kel0[c] = e0;
+          rc_->kel1[c] = e1;
+          rc_->nrm[c] = y ? nrm : T(1);
+          rc_->phi[c] = phi;
+          rc_->yld[c] = y;
         }
+        kr0[c] += phi * e0;
+        kr1[c] += phi * e1;
       }
     }
   }
@@ -1311,7 +1359,7 @@ struct Rod {
       V3<T> tpb = zero3<T>(), dpb = zero3<T>();
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        if (ivalid(c) && r.yld[c]) {
+        if (r.yld[c]) {   // never set away from interior vertices
           T o0 = lk0[c], o1 = lk1[c];
           T phi = r.phi[c], nrm = r.nrm[c], thr = sig * lbar[c];
           T phib = r.kel0[c] * o0 + r.kel1[c] * o1;
@@ -1355,7 +1403,7 @@ struct Rod {
     V3<T> pb[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) pb[c] = lx[c];
-    edges_vjp(X, r.t1, r.ell1, t1b, l1b, pb);
+    edges_vjp(X, r.t1, r.il1, t1b, l1b, pb);
     // S9 self-friction
     if constexpr (SC) {
       if (flags & FLAG_SELF) sc_friction_vjp(a, X, r, lv, pb);
@@ -1420,33 +1468,33 @@ struct Rod {
     for (int c = 0; c < C; ++c) d2b[c] = zero3<T>();
     V3<T> tpb = zero3<T>(), d1pb = zero3<T>(), d2pb = zero3<T>();
     T lpb = T(0);
+    // every vertex runs the stencil's VJP: away from interior vertices
+    // coef = 1/l_bar = 0 makes every output exactly zero
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      if (ivalid(c)) {
-        BendIn<T> q = bend_in(c, r.t, r.ell, r.d1, r.tp, r.lp, r.d1p, r.kr0, r.kr1);
-        V3<T> Fm = c ? Fb[c - 1] : Fp;
-        V3<T> Fq = (c < C - 1) ? Fb[c + 1] : Fn;
-        BendBar<T> o;
-        bend_vjp(q, b, Fm - Fb[c], Fb[c] - Fq, o);
-        lk0[c] += o.kr0;
-        lk1[c] += o.kr1;
-        accb[c] += (double)o.b;
-        if (c > 0) {
-          tb[c - 1] += o.t0;
-          lb[c - 1] += o.l0;
-          d1b[c - 1] += o.d1a;
-          d2b[c - 1] += o.d2a;
-        } else {
-          tpb += o.t0;
-          lpb += o.l0;
-          d1pb += o.d1a;
-          d2pb += o.d2a;
-        }
-        tb[c] += o.t1;
-        lb[c] += o.l1;
-        d1b[c] += o.d1b;
-        d2b[c] += o.d2b;
+      BendIn<T> q = bend_in(c, r.t, r.il, r.d1, r.tp, r.ilp, r.d1p, r.kr0, r.kr1);
+      V3<T> Fm = c ? Fb[c - 1] : Fp;
+      V3<T> Fq = (c < C - 1) ? Fb[c + 1] : Fn;
+      BendBar<T> o;
+      bend_vjp(q, Fm - Fb[c], Fb[c] - Fq, o);
+      lk0[c] += o.kr0;
+      lk1[c] += o.kr1;
+      accb[c] += (double)o.b;
+      if (c > 0) {
+        tb[c - 1] += o.t0;
+        lb[c - 1] += o.l0;
+        d1b[c - 1] += o.d1a;
+        d2b[c - 1] += o.d2a;
+      } else {
+        tpb += o.t0;
+        lpb += o.l0;
+        d1pb += o.d1a;
+        d2pb += o.d2a;
       }
+      tb[c] += o.t1;
+      lb[c] += o.l1;
+      d1b[c] += o.d1b;
+      d2b[c] += o.d2b;
     }
     if (!(flags & FLAG_INEXT)) {
 #pragma unroll
@@ -1454,14 +1502,14 @@ struct Rod {
         if (evalid(c)) {
           V3<T> Fq = (c < C - 1) ? Fb[c + 1] : Fn;
           V3<T> qb = Fb[c] - Fq;
-          T fs = ks[c] * (fdiv(r.ell[c], rest[c]) - T(1));
+          T fs = ks[c] * (fdiv(frcp(r.il[c]), rest[c]) - T(1));
           tb[c] += fs * qb;
           lb[c] += fdiv(ks[c] * dot(qb, r.t[c]), rest[c]);
         }
       }
     }
     {
-      T s[12] = {tpb.x, tpb.y, tpb.z, lpb, d1pb.x, d1pb.y, d1pb.z, d2pb.x, d2pb.y, d2pb.z, T(0), T(0)};
+      T s[10] = {tpb.x, tpb.y, tpb.z, lpb, d1pb.x, d1pb.y, d1pb.z, d2pb.x, d2pb.y, d2pb.z};
       X.next(s);
       tb[C - 1] += mk(s[0], s[1], s[2]);
       lb[C - 1] += s[3];
@@ -1478,7 +1526,7 @@ struct Rod {
         d1b[c] = zero3<T>();
       }
     }
-    edges_vjp(X, r.t, r.ell, tb, lb, xb);
+    edges_vjp(X, r.t, r.il, tb, lb, xb);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       lx[c] = vvalid(c) ? xb[c] : zero3<T>();

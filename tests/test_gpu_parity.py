@@ -259,3 +259,47 @@ def test_repeatable_and_checkpoint_interval_invariant():
     for other in res[1:]:
         for k in ("u", "b", "sigma", "x0", "v0", "xT"):
             np.testing.assert_array_equal(res[0][k], other[k])
+
+
+def test_fp32_gradients_along_gpu_trajectory():
+    """Configuration 3 rods, creep rate 0.5, 5 steps, FP32: the oracle
+    differentiates along the GPU's own FP32 trajectory (its checkpoints are
+    the GPU's states after every step, its seed the GPU's loss gradient), so
+    only the FP32 arithmetic of the replays, the VJPs and their accumulation
+    over 75 substeps differs: every block within 1e-3.  (The adjoint
+    recursion amplifies that rounding like the forward amplifies a
+    perturbation: at 10-20 steps the sums dL/db, dL/dsigma reach 1e-2.)  (With creep rate 1
+    every yielded vertex sits exactly on the yield surface, so the next
+    yield decision is a tie that FP32 and FP64 arithmetic resolve
+    differently from the same input.)"""
+    n, K = 5, 1
+    wl = make_workload(3, steps=n)
+    sub = wl.subset(list(wl.oracle_rods))
+    sub.rod_params[:, 4] = 0.5
+    full = _fp32_rounded(initial_full_state(sub))
+    U = to_dev(sub.actions)
+    spa = sub.sim.steps_per_action
+    hs = _handle(sub, max_steps=n)
+    _set_full(hs, full, 4)
+    states = []
+    for s in range(n):
+        states.append([t.double().cpu().numpy() for t in hs.get_state()])
+        hs.step(U[s // spa])
+    h = _handle(sub, max_steps=n, ckpt_every=K)
+    _set_full(h, full, 4)
+    xT = h.tensor(sub.n_vert, 3)
+    h.rollout(n, U, record=True, x_final=xT)
+    np.testing.assert_array_equal(xT.cpu().numpy(), hs.get_state()[0].cpu().numpy())
+    _, gx = h.loss_mse(xT, to_dev(sub.target))
+    g = {k: v.double().cpu().numpy() for k, v in h.backward(gx, n_steps=n).items()}
+    rods = list(range(sub.n_rods))
+    orods, osim = rods_from_workload(sub, rods), sim_from_workload(sub)
+    ck = [gather_state(sub, rods, st) for st in states]
+    gxo = gx.double().cpu().numpy().reshape(sub.n_rods, -1, 3)
+    x0b, v0b, Ub, bb, sb = oadj.backward(orods, osim, ck, sub.actions, n, K, gxo)
+    for r in rods:
+        a, b = sub.rod_range(r)
+        assert rel_err(g["u"][:, r], Ub[:, r]) <= 1e-3, ("u", r)
+        assert rel_err(g["x0"][a:b], x0b[r]) <= 1e-3, ("x0", r)
+    assert rel_err(g["b"], bb) <= 1e-3
+    assert rel_err(g["sigma"], sb) <= 1e-3
