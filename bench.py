@@ -29,12 +29,18 @@ METRIC = "rod-vertex-steps/s fwd+bwd, batched vs plain, at ≤1e-4 pos / 1e-3 gr
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published; counts packed dual-rate FP32)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6   # one FP32 op per lane per cycle (packed forms are not used)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_1024x128_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2606_04206_amd", "csrc", "rod_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2606_04206_amd", "csrc", f)
+               for f in ("rod_kernels.hip", "rod_device.h", "rod_selfcontact.h")]
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] over the device sources: a stored traffic figure is used
+    only for the kernels it was measured on."""
+    h = hashlib.sha256()
+    for src in KERNEL_SRCS:
+        with open(src, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():

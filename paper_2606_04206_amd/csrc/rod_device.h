@@ -65,12 +65,12 @@ constexpr int PROJ_TAPE = 4;   // values per edge and iteration in the projectio
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int dpp_from_next_i(int v) {
-  // wave_shl:1 -- lane i receives lane i+1; lane 63 receives 0
-  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+  // wave_shl:1 -- lane i receives lane i+1; lane 63 receives 0 (bound_ctrl)
+  return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true);
 }
 __device__ __forceinline__ int dpp_from_prev_i(int v) {
-  // wave_shr:1 -- lane i receives lane i-1; lane 0 receives 0
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+  // wave_shr:1 -- lane i receives lane i-1; lane 0 receives 0 (bound_ctrl)
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
 }
 __device__ __forceinline__ float dpp_from_next(float v) {
   return __int_as_float(dpp_from_next_i(__float_as_int(v)));
