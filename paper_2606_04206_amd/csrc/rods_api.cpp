@@ -102,6 +102,11 @@ struct Impl : HandleBase {
   // segment s runs on the caller's stream (tape2 == nullptr: no room, the
   // segments run one after the other)
   T* tape2 = nullptr;
+  // the recorded rollout writes the tape of its last segment itself, so the
+  // backward starts with that segment's adjoint (valid until the backward
+  // reuses the buffer)
+  bool last_tape_ok = false;
+  T* tape_for(int seg) const { return (plain || !tape2) ? tape : ((seg & 1) ? tape2 : tape); }
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_start = nullptr, ev_tape[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
   hipGraph_t graph = nullptr;
@@ -490,16 +495,20 @@ struct Impl : HandleBase {
       for (int seg = 0; seg < nseg; ++seg) {
         a.step_off = seg * Kc;
         a.n_steps = std::min(Kc, n_steps - seg * Kc);
+        int which = 0;
         if (seg + 1 < nseg) {
           a.ck_x = ck_x(seg + 1); a.ck_v = ck_v(seg + 1); a.ck_kb = ck_kb(seg + 1);
           a.ck_d1 = ck_d1(seg + 1);
         } else {
           a.ck_x = a.ck_v = a.ck_kb = a.ck_d1 = nullptr;
+          which = 1;   // the last segment also writes its substep tape
+          a.tape = tape_for(seg);
         }
-        int e = launch_all(0, a, st);
+        int e = launch_all(which, a, st);
         if (e) return e;
       }
       recorded = true;
+      last_tape_ok = true;
       n_rec = n_steps;
     } else {
       a.u = u;
@@ -566,15 +575,23 @@ struct Impl : HandleBase {
       return launch_all(2, a, st);
     };
     int e;
+    const bool have_last = last_tape_ok;   // written by the recorded rollout
+    last_tape_ok = false;                  // the buffers are reused below
     if (plain || !tape2) {
-      for (int seg = nseg - 1; seg >= 0; --seg)
-        if ((e = replay(seg, tape, st)) || (e = adjoint(seg, tape))) return e;
+      for (int seg = nseg - 1; seg >= 0; --seg) {
+        if (!(have_last && seg == nseg - 1) && (e = replay(seg, tape, st))) return e;
+        if ((e = adjoint(seg, tape))) return e;
+      }
     } else {
       T* buf[2] = {tape, tape2};
       HIPCHK(hipEventRecord(ev_start, st));
       HIPCHK(hipStreamWaitEvent(side_stream, ev_start, 0));
-      if ((e = replay(nseg - 1, buf[(nseg - 1) & 1], side_stream))) return e;
-      HIPCHK(hipEventRecord(ev_tape[(nseg - 1) & 1], side_stream));
+      if (have_last) {
+        HIPCHK(hipEventRecord(ev_tape[(nseg - 1) & 1], st));
+      } else {
+        if ((e = replay(nseg - 1, buf[(nseg - 1) & 1], side_stream))) return e;
+        HIPCHK(hipEventRecord(ev_tape[(nseg - 1) & 1], side_stream));
+      }
       for (int seg = nseg - 1; seg >= 0; --seg) {
         if (seg >= 1) {
           // buffer (seg-1)&1 was last read by the adjoint of segment seg+1
