@@ -157,7 +157,11 @@ int rods_rollout(RodsHandle* h, int32_t n_steps, const void* grasp_vel, void* x_
  * [V][3] and dL_dvT [V][3] (NULL = 0) of the final state.  Writes (each
  * may be NULL): dL_du [A][R][G][3], dL_db [R], dL_dsigma [R], dL_dx0 [V][3],
  * dL_dv0 [V][3].  Outputs are overwritten.  ROD_ESTATE without a recorded
- * rollout.  The recorded rollout stays valid (backward may run again). */
+ * rollout.  The recorded rollout stays valid (backward may run again).
+ * The replay of the next segment runs on a stream of the handle while the
+ * current segment's adjoint runs on the given stream; events order them,
+ * and all of the call's work is complete when the given stream reaches the
+ * end of the call, as for any other call. */
 int rods_backward(RodsHandle* h, const void* dL_dxT, const void* dL_dvT, void* dL_du,
                   void* dL_db, void* dL_dsigma, void* dL_dx0, void* dL_dv0,
                   rods_stream_t stream);

@@ -348,7 +348,7 @@ struct Rec {   // what the adjoint needs from one substep's forward run
   V3<T> t1[C], d1n[C];
   T il1[C];
   V3<T> t1p, d1np;
-  T kel0[C], kel1[C], nrm[C], phi[C];
+  T kel0[C], kel1[C], inrm[C], phi[C];   // inrm = 1 / |kappa_el| on yield
   bool yld[C];
   V3<T> x1[C], v3[C];   // positions after projection, velocities before self-friction
 };
@@ -1322,14 +1322,15 @@ struct Rod {
         T k1, k2;
         curvature(c ? t1[c - 1] : t1p, t1[c], c ? d1[c - 1] : d1np, d1[c], k1, k2);
         T e0 = k1 - kr0[c], e1 = k2 - kr1[c];
-        T nrm = fsqrt(e0 * e0 + e1 * e1);
+        T ss = e0 * e0 + e1 * e1;
+        T in = frsq(ss);
         T thr = sig * lbar[c];
-        bool y = nrm > thr;
-        T phi = y ? fdiv(rc * (nrm - thr), nrm) : T(0);
+        bool y = ss > T(0) && ss * in > thr;   // |kappa_el| = ss / sqrt(ss)
+        T phi = y ? rc * (T(1) - thr * in) : T(0);
         if constexpr (REC) {
           rc_->kel0[c] = e0;
           rc_->kel1[c] = e1;
-          rc_->nrm[c] = y ? nrm : T(1);
+          rc_->inrm[c] = y ? in : T(1);
           rc_->phi[c] = phi;
           rc_->yld[c] = y;
         }
@@ -1361,13 +1362,13 @@ struct Rod {
       for (int c = 0; c < C; ++c) {
         if (r.yld[c]) {   // never set away from interior vertices
           T o0 = lk0[c], o1 = lk1[c];
-          T phi = r.phi[c], nrm = r.nrm[c], thr = sig * lbar[c];
+          T phi = r.phi[c], in = r.inrm[c], thr = sig * lbar[c];
           T phib = r.kel0[c] * o0 + r.kel1[c] * o1;
-          T nrmb = fdiv(rc * thr, nrm * nrm) * phib;
-          T thrb = fdiv(-rc, nrm) * phib;
+          T nrmb = rc * thr * in * in * phib;
+          T thrb = -rc * in * phib;
           accs[c] += (double)(lbar[c] * thrb);
-          T e0 = phi * o0 + fdiv(nrmb, nrm) * r.kel0[c];
-          T e1 = phi * o1 + fdiv(nrmb, nrm) * r.kel1[c];
+          T e0 = phi * o0 + (nrmb * in) * r.kel0[c];
+          T e1 = phi * o1 + (nrmb * in) * r.kel1[c];
           lk0[c] -= e0;
           lk1[c] -= e1;
           V3<T> t0b, tcb, dab, dcb;

@@ -86,11 +86,12 @@ def _last_step_parity(wl, n_before, tol=1e-4, ties=False):
     h.step(to_dev(u, dt))
     after = [t.double().cpu().numpy() for t in h.get_state()]
     status = h.status()
-    # bit0 non-finite anywhere, or any flag on a compared rod, fails; the
-    # stretched-edge warning (bit2) is tolerated on a few other rods
+    # a non-finite state anywhere, or any flag on a compared rod, fails; a
+    # full partner list (bit1: pairs dropped) is tolerated on a few other
+    # rods, the stretched-edge warning (bit2: search still exact) anywhere
     assert not (status & 1).any(), np.unique(status, return_counts=True)
     assert not status[list(wl.oracle_rods)].any(), status[list(wl.oracle_rods)]
-    assert (status != 0).mean() <= 0.02, np.unique(status, return_counts=True)
+    assert ((status & 2) != 0).mean() <= 0.02, np.unique(status, return_counts=True)
     for r in wl.oracle_rods:
         st = gather_state(wl, [r], before)
         orods, osim = rods_from_workload(wl, [r]), sim_from_workload(wl)
