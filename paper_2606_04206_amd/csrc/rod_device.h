@@ -33,8 +33,6 @@ template <typename T>
 __device__ __forceinline__ V3<T> cross(V3<T> a, V3<T> b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
-template <typename T>
-__device__ __forceinline__ V3<T> sel(bool c, V3<T> a, V3<T> b) { return c ? a : b; }
 
 // Reciprocal, quotient and square root.  FP32 uses the hardware
 // instructions (v_rcp_f32, v_sqrt_f32: about 1 ulp) instead of the correctly

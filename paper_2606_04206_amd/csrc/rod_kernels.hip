@@ -26,9 +26,6 @@ constexpr int FLAG_INEXT = 1, FLAG_PLASTIC = 2, FLAG_SELF = 4;
 constexpr int NFIELD = 11;   // x(3) v(3) kappa_bar(2) d1(3) per vertex slot
 
 template <typename T>
-__device__ __forceinline__ T rcp(T a) { return T(1) / a; }
-
-template <typename T>
 __device__ __forceinline__ V3<T> transport(V3<T> v, V3<T> ta, V3<T> tb) {
   V3<T> bb = cross(ta, tb);
   T c = dot(ta, tb);
@@ -1764,12 +1761,6 @@ __global__ void k_fill(T* p, int64_t n, T val) {
   if (i < n) p[i] = val;
 }
 
-template <typename T>
-__global__ void k_copy(T* dst, const T* src, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i];
-}
-
 __global__ void k_selftest_exchange(int* out) {
   int l = threadIdx.x;
   int nx = dpp_from_next_i(l + 1) - 1;
@@ -1892,13 +1883,6 @@ hipError_t launch_fill(T* p, int64_t n, T val, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);
-  return hipGetLastError();
-}
-
 hipError_t launch_selftest_exchange(int* out, hipStream_t st) {
   hipLaunchKernelGGL(k_selftest_exchange, dim3(1), dim3(64), 0, st, out);
   return hipGetLastError();
@@ -1916,7 +1900,7 @@ hipError_t launch_selftest_exchange(int* out, hipStream_t st) {
   template hipError_t launch_reduce_params<T>(const int32_t*, int, const double*,             \
                                               const double*, T*, T*, hipStream_t);            \
   template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                             \
-  template hipError_t launch_copy<T>(T*, const T*, int64_t, hipStream_t);
+
 RODS_INST(float)
 RODS_INST(double)
 template hipError_t launch_fill<int32_t>(int32_t*, int64_t, int32_t, hipStream_t);

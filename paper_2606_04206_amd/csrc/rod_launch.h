@@ -29,8 +29,6 @@ hipError_t launch_reduce_params(const int32_t* voff, int R, const double* ab, co
                                 T* db, T* ds, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(T* p, int64_t n, T val, hipStream_t st);
-template <typename T>
-hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t st);
 hipError_t launch_selftest_exchange(int* out, hipStream_t st);
 
 }  // namespace rods
