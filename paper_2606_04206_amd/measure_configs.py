@@ -1,0 +1,115 @@
+"""Throughput of the other workload configurations on one GPU, and what the
+launch-shape autotuner and the HIP-graph step path buy.  Prints one JSON
+line per measurement.
+
+    python -m paper_2606_04206_amd.measure_configs [--configs 2 4 5]
+
+Every figure is rod-vertex-steps/s over a timed loop bracketed by device
+synchronisations, after one untimed warm-up pass; inputs are resident on the
+GPU before timing starts.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def _dev(a, dtype):
+    import numpy as np
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _timed(fn, reps=1):
+    import torch
+    fn()                       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def _emit(**kw):
+    print(json.dumps(kw), flush=True)
+
+
+def main():
+    p = argparse.ArgumentParser()
+    p.add_argument("--configs", type=int, nargs="*", default=[2, 4, 5])
+    a = p.parse_args()
+    import torch
+    from synth import make_workload
+    from paper_2606_04206_amd import RodsHandle
+    f32 = torch.float32
+
+    for cid in a.configs:
+        wl = make_workload(cid)
+        n = {2: 500, 4: 100, 5: 100}.get(cid, 100)
+        K = wl.sim.ckpt_every
+        x0, v0 = _dev(wl.x0, f32), _dev(wl.v0, f32)
+        h = RodsHandle(wl, precision=4, max_steps=max(n, K), ckpt_every=K)
+        # rest curvature: that of the rest shape when the workload has one
+        # (configuration 5's noise-free helices), else zero
+        kb0 = None if wl.x_rest is None else h.curvature(_dev(wl.x_rest, f32))
+        U = _dev(wl.actions[:h.n_actions(n)], f32)
+        xT = h.tensor(wl.n_vert, 3)
+        shapes0 = [list(b) for b in h.bins()]
+
+        def fwd():
+            h.set_state(x0, v0, kb0)
+            h.rollout(n, U, x_final=xT)
+        h.set_state(x0, v0, kb0)
+        t_default = _timed(fwd)
+        h.set_state(x0, v0, kb0)
+        h.autotune(n_steps=3)
+        shapes1 = [list(b) for b in h.bins()]
+        t_tuned = _timed(fwd)
+        _emit(config=cid, measure="forward rollout", steps=n, rods=wl.n_rods,
+              vertices=wl.n_vert, value=wl.n_vert * n / t_tuned, unit="rod-vertex-steps/s",
+              ms=1e3 * t_tuned, default_shape_ms=1e3 * t_default,
+              autotune_speedup=t_default / t_tuned, shapes_default=shapes0, shapes_tuned=shapes1)
+
+        # one step per call: eager launches against the captured HIP graph
+        n_eager = 20
+        u0 = U[0].contiguous()
+
+        def eager():
+            for _ in range(n_eager):
+                h.step(u0)
+
+        def graph():
+            for _ in range(n_eager):
+                h.step_graph(u0)
+        h.set_state(x0, v0, kb0)
+        t_e = _timed(eager)
+        h.set_state(x0, v0, kb0)
+        t_g = _timed(graph)
+        _emit(config=cid, measure="single steps, eager vs HIP graph", steps=n_eager,
+              eager_ms_per_step=1e3 * t_e / n_eager, graph_ms_per_step=1e3 * t_g / n_eager,
+              graph_speedup=t_e / t_g, unit="ms/step")
+
+        if wl.cfg.backward:
+            tgt = _dev(wl.target, f32)
+
+            def fwd_bwd():
+                h.set_state(x0, v0, kb0)
+                h.rollout(n, U, record=True, x_final=xT)
+                _, g = h.loss_mse(xT, tgt)
+                h.backward(g, n_steps=n)
+            t_fb = _timed(fwd_bwd)
+            _emit(config=cid, measure="forward + checkpointed adjoint", steps=n,
+                  ckpt_every=K, value=wl.n_vert * n / t_fb, unit="rod-vertex-steps/s",
+                  ms=1e3 * t_fb, status_flagged=int((h.status() != 0).sum()))
+        del h
+        torch.cuda.empty_cache()
+
+
+if __name__ == "__main__":
+    main()

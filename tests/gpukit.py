@@ -7,7 +7,7 @@ import torch
 
 from synth import make_workload
 from oracle.model import rods_from_workload, sim_from_workload, State
-from oracle.geometry import init_frames
+from oracle.geometry import init_frames, curvature_of_shape
 from paper_2606_04206_amd import RodsHandle
 
 DEV = "cuda"
@@ -51,13 +51,17 @@ def gather_state(wl, rods, full):
 
 def initial_full_state(wl, dtype=np.float64):
     """Initial full-batch state with frames from the oracle's initial-frame
-    rule and zero rest curvature."""
+    rule; rest curvature zero, or that of the workload's rest shape (the
+    noise-free helix of configuration 5) when it has one."""
     V = wl.n_vert
     d1 = np.zeros((V, 3))
+    kb = np.zeros((V, 2))
     for r in range(wl.n_rods):
         a, b = wl.rod_range(r)
         d1[a:b - 1] = init_frames(wl.x0[a:b][None])[0]
-    return [wl.x0.astype(dtype), wl.v0.astype(dtype), np.zeros((V, 2), dtype), d1.astype(dtype)]
+        if wl.x_rest is not None:
+            kb[a:b] = curvature_of_shape(wl.x_rest[a:b][None])[0]
+    return [wl.x0.astype(dtype), wl.v0.astype(dtype), kb.astype(dtype), d1.astype(dtype)]
 
 
 def rel_err(a, b):
