@@ -1424,17 +1424,44 @@ struct Rod {
       xb[c] = p0b[c];
       v2b[c] += h * p0b[c];
     }
-    // S4 rigid contact, primitives in reverse (input velocities re-evaluated)
+    // S4 rigid contact, primitives in reverse.  One forward sweep re-runs the
+    // primitives in order and keeps the input velocity of each active one
+    // (up to three; inactive primitives leave v unchanged and have a zero
+    // VJP); more than three active contacts fall back to re-evaluating each
+    // primitive's input from the start.
     if (p1 > p0) {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         if (w[c] > T(0)) {
-          for (int k = p1 - 1; k >= p0; --k) {
-            V3<T> vin = r.v1[c];
-            for (int j = p0; j < k; ++j)
-              contact_one(load_prim(a, j), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vin);
-            contact_one_vjp(load_prim(a, k), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vin,
-                            v2b[c], xb[c]);
+          V3<T> vin = r.v1[c], vs0 = vin, vs1 = vin, vs2 = vin;
+          int k0 = -1, k1 = -1, k2 = -1, na = 0;
+          for (int j = p0; j < p1; ++j) {
+            V3<T> vb4 = vin;
+            if (contact_one(load_prim(a, j), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vin)) {
+              if (na == 0) { vs0 = vb4; k0 = j; }
+              else if (na == 1) { vs1 = vb4; k1 = j; }
+              else if (na == 2) { vs2 = vb4; k2 = j; }
+              ++na;
+            }
+          }
+          if (na <= 3) {
+            if (k2 >= 0)
+              contact_one_vjp(load_prim(a, k2), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vs2,
+                              v2b[c], xb[c]);
+            if (k1 >= 0)
+              contact_one_vjp(load_prim(a, k1), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vs1,
+                              v2b[c], xb[c]);
+            if (k0 >= 0)
+              contact_one_vjp(load_prim(a, k0), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vs0,
+                              v2b[c], xb[c]);
+          } else {
+            for (int k = p1 - 1; k >= p0; --k) {
+              V3<T> vk = r.v1[c];
+              for (int j = p0; j < k; ++j)
+                contact_one(load_prim(a, j), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vk);
+              contact_one_vjp(load_prim(a, k), r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vk,
+                              v2b[c], xb[c]);
+            }
           }
         }
       }
