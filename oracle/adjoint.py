@@ -18,6 +18,7 @@ from .geometry import dot, cross, curvature_binormal, edges
 from .forward import substep, step, PLANE, SPHERE, CAPSULE
 from .model import State
 from . import selfcontact
+from . import twist as tw
 
 
 # --------------------------------------------------------------------------
@@ -226,16 +227,18 @@ def rigid_contact_vjp(rods, sim, crec, v_b, x_b):
 # --------------------------------------------------------------------------
 
 def substep_vjp(rods, sim, rec, bar):
-    """Given adjoints `bar` = (x_b, v_b, kb_b, d1_b) of the substep's output
-    state and the forward record `rec`, return the adjoints of its input state
-    and (u_b [B,G,3], b_b [B], sigma_b [B])."""
-    xb1, vb3, kbb1, d1nb = bar
+    """Given adjoints `bar` = (x_b, v_b, kb_b, d1_b, theta_b, omega_b) of the
+    substep's output state and the forward record `rec`, return the adjoints
+    of its input state and (u_b [B,G,3], b_b [B], sigma_b [B])."""
+    xb1, vb3, kbb1, d1nb, thb1, omb1 = bar
     h = sim.h
     B = rods.B
     t, ell, t1, ell1 = rec["t"], rec["ell"], rec["t1"], rec["ell1"]
     d1, d1n, d2 = rec["d1"], rec["d1n"], rec["d2"]
+    m1 = rec["m1"]
     kb_b = np.array(kbb1, dtype=np.float64)
     d1n_b = np.array(d1nb, dtype=np.float64)
+    th1_b = np.array(thb1, dtype=np.float64)
     t1_b = np.zeros_like(t1)
     sig_b = np.zeros(B)
     # S11 plasticity: kb1 = kb + phi kel, phi = r_c (1 - thr/|kel|) on yield
@@ -254,9 +257,15 @@ def substep_vjp(rods, sim, rec, bar):
         kb_b[..., 1:-1, :] -= kel_b
         kappa_b = np.zeros_like(kbb1)
         kappa_b[..., 1:-1, :] = kel_b
-        tb, d1b = curvature_vjp(t1, d1n, kappa_b)
+        tb, m1b = curvature_vjp(t1, rec["m1n"], kappa_b)
         t1_b += tb
-        d1n_b += d1b
+        if rods.twist:
+            tb, d1b, thb = tw.material_frame_vjp(t1, d1n, rec["th1"], m1b)
+            t1_b += tb
+            d1n_b += d1b
+            th1_b += thb
+        else:
+            d1n_b += m1b
     # S10 transport
     d1_b, t_b, tb = transport_vjp(d1, t, t1, d1n_b)
     t1_b += tb
@@ -283,9 +292,12 @@ def substep_vjp(rods, sim, rec, bar):
                 p_in_b = p_in_b + selfcontact.depth0_vjp(rods, item, d0_b)
             p_b = p_in_b
     p0_b = p0_b + p_b
-    # S5 p0 = x + h v2
+    # S5 p0 = x + h v2, theta1 = theta + h omega1
     x_b = p0_b.copy()
     v2_b = v2_b + h * p0_b
+    om1_b = np.array(omb1, dtype=np.float64)
+    if rods.twist:
+        om1_b = om1_b + h * th1_b
     # S4 rigid contact
     if rec["crec"] is not None and rec["crec"].get("contact"):
         v1_b = rigid_contact_vjp(rods, sim, rec["crec"], v2_b, x_b)
@@ -300,19 +312,43 @@ def substep_vjp(rods, sim, rec, bar):
         for g, vi in enumerate(rods.gidx[bi]):
             if vi >= 0:
                 u_b[bi, g] += v1_b[bi, vi]
-    # S2 forces
-    tb, ellb, d1b, d2b, kbb, b_b = bending_force_vjp(rods, t, ell, d1, d2, rec["kb"], F_b)
+    if rods.twist:
+        Tq_b = np.where(rods.twist_free, h * rods.Jt * om1_b, 0.0)
+        om_b = np.where(rods.twist_free, om1_b, 0.0)
+    else:
+        om_b = om1_b
+    # S2 forces (material frames m1, m2 = t x m1 stand in for d1, d2)
+    tb, ellb, m1b, m2b, kbb, b_b = bending_force_vjp(rods, t, ell, m1, d2, rec["kb"], F_b)
     t_b = t_b + tb
-    d1_b = d1_b + d1b
     kb_b = kb_b + kbb
     if not rods.inextensible:
         tb, eb = stretch_force_vjp(rods, t, ell, F_b)
         t_b = t_b + tb
         ellb = ellb + eb
-    t_b = t_b + cross(d1, d2b)
-    d1_b = d1_b + cross(d2b, t)
+    th_b = th1_b
+    if rods.twist:
+        tb, eb, d1b, thb = tw.twist_force_torque_vjp(rods, t, ell, d1, rec["th"], F_b, Tq_b)
+        t_b = t_b + tb
+        ellb = ellb + eb
+        d1_b = d1_b + d1b
+        th_b = th_b + thb
+        tb, m1b2, m2b2, kbb, bb2 = tw.bending_torque_vjp(rods, t, m1, d2, rec["kb"], Tq_b)
+        t_b = t_b + tb
+        m1b = m1b + m1b2
+        m2b = m2b + m2b2
+        kb_b = kb_b + kbb
+        b_b = b_b + bb2
+    t_b = t_b + cross(m1, m2b)
+    m1b = m1b + cross(m2b, t)
+    if rods.twist:
+        tb, d1b, thb = tw.material_frame_vjp(t, d1, rec["th"], m1b)
+        t_b = t_b + tb
+        d1_b = d1_b + d1b
+        th_b = th_b + thb
+    else:
+        d1_b = d1_b + m1b
     x_b = x_b + edges_vjp(ell, t, t_b, ellb)
-    return State(x_b, v_b, kb_b, d1_b), u_b, b_b, sig_b
+    return State(x_b, v_b, kb_b, d1_b, th_b, om_b), u_b, b_b, sig_b
 
 
 # --------------------------------------------------------------------------
@@ -327,7 +363,8 @@ def backward(rods, sim, ckpts, U, n_steps, ckpt_every, xT_b, vT_b=None):
     B, N = rods.B, rods.N
     bar = State(np.array(xT_b, np.float64),
                 np.zeros((B, N, 3)) if vT_b is None else np.array(vT_b, np.float64),
-                np.zeros((B, N, 2)), np.zeros((B, N - 1, 3)))
+                np.zeros((B, N, 2)), np.zeros((B, N - 1, 3)), np.zeros((B, N - 1)),
+                np.zeros((B, N - 1)))
     u_b = np.zeros_like(U, dtype=np.float64)
     b_b = np.zeros(B)
     sig_b = np.zeros(B)

@@ -28,7 +28,7 @@ def bending_energy(rods, x, d1, d2, kb):
 def total_energy(rods, sim, st, gravity=True):
     """Kinetic + stretching + bending (+ gravitational) energy of free
     vertices (masses m_i = 1/w_i)."""
-    x, v, kb, d1 = st
+    x, v, kb, d1 = st[:4]
     _, _, t = edges(x)
     d2 = cross(t, d1)
     free = rods.w > 0.0

@@ -8,10 +8,11 @@ contact.  One substep (h = dt / n_sub, App. B.1 frames of 1e-3 s split in
 substeps):
 
   S2  forces f = m g - dU/dx at the substep-start x, frames held fixed
+      (twisting rods: material frames, plus the torques -dU/dtheta)
   S3  v += h w f on free vertices; grasped vertices take the action velocity,
-      pinned vertices stay at rest
+      pinned vertices stay at rest (twisting rods: the twist rates likewise)
   S4  rigid SDF contact on velocities (Section 3.2)
-  S5  predict p = x + h v
+  S5  predict p = x + h v (twisting rods: theta += h theta_dot)
   S6  self-contact candidate pairs at p (App. A.1, Self-collision)
   S7  N_C iterations of {inextensibility red pass (even edges), black pass
       (odd edges), self-contact Jacobi pass}
@@ -23,9 +24,10 @@ substeps):
 import numpy as np
 
 from .geometry import (re, dot, cross, norm, edges, transport, curvature_binormal,
-                       averaged_directors, material_curvature)
+                       averaged_directors, material_curvature, material_frame)
 from .model import State
 from . import selfcontact
+from . import twist as tw
 
 PLANE, SPHERE, CAPSULE = 0, 1, 2
 
@@ -228,14 +230,22 @@ def plasticity(rods, kappa, kb, rec=None):
 def substep(rods, sim, st, u, rec=None):
     """Advance state `st` by one substep under grasp velocities u [B,G,3].
     When `rec` is a dict the intermediates the adjoint needs are stored."""
-    x, v, kb, d1 = st
+    x, v, kb, d1, th, om = st
     h = sim.h
     # S2
     e, ell, t = edges(x)
-    d2 = cross(t, d1)
-    F = bending_force(rods, t, ell, d1, d2, kb)
+    if rods.twist:
+        m1, m2 = material_frame(t, d1, th)
+    else:
+        m1, m2 = d1, cross(t, d1)
+    F = bending_force(rods, t, ell, m1, m2, kb)
     if not rods.inextensible:
         F = F + stretch_force(rods, t, ell)
+    Tq = None
+    if rods.twist:
+        Ft, Tq = tw.twist_force_torque(rods, t, ell, d1, th)
+        F = F + Ft
+        Tq = Tq + tw.bending_torque(rods, t, m1, m2, kb)
     # S3
     w = rods.w[..., None]
     free = rods.w > 0.0
@@ -244,11 +254,13 @@ def substep(rods, sim, st, u, rec=None):
         for g, vi in enumerate(rods.gidx[bi]):
             if vi >= 0:
                 v1[bi, vi] = u[bi, g]
+    om1 = np.where(rods.twist_free, om + h * rods.Jt * Tq, 0.0 * om) if rods.twist else om
     # S4
     crec = {} if rec is not None else None
     v2 = rigid_contact(rods, sim, x, v1, crec) if any(len(p) for p in rods.prims) else v1
     # S5
     p0 = x + h * v2
+    th1 = th + h * om1 if rods.twist else th
     # S6
     pairs = selfcontact.candidates(rods, sim, p0) if rods.self_contact else None
     # S7
@@ -269,16 +281,19 @@ def substep(rods, sim, st, u, rec=None):
     d1n = transport(d1, t, t1)
     # S11
     prec = {} if rec is not None else None
+    m1n = None
     if rods.plastic:
-        kappa1 = material_curvature(t1, d1n)
+        m1n = material_frame(t1, d1n, th1)[0] if rods.twist else d1n
+        kappa1 = material_curvature(t1, m1n)
         kb1 = plasticity(rods, kappa1, kb, prec)
     else:
         kb1 = kb
     if rec is not None:
-        rec.update(x=x, v=v, kb=kb, d1=d1, u=u, ell=ell, t=t, d2=d2, F=F, v1=v1,
+        rec.update(x=x, v=v, kb=kb, d1=d1, u=u, ell=ell, t=t, d2=m2, m1=m1, th=th, om1=om1,
+                   th1=th1, m1n=m1n, F=F, v1=v1,
                    v2=v2, p0=p0, ptape=ptape, pairs=pairs, p=p, v3=v3, x1=x1, v3_pre=v3_pre, d0=d0,
                    ell1=ell1, t1=t1, d1n=d1n, prec=prec, crec=crec, frec=frec)
-    return State(x1, v3, kb1, d1n)
+    return State(x1, v3, kb1, d1n, th1, om1)
 
 
 def step(rods, sim, st, u):

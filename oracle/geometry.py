@@ -101,3 +101,36 @@ def curvature_of_shape(x):
     make a shape the rod's rest shape."""
     _, _, t = edges(x)
     return material_curvature(t, init_frames(x))
+
+
+def material_frame(t, d1, theta):
+    """Material directors of each edge: the reference pair (d1, d2 = t x d1)
+    turned by the twist angle theta^j about t^j (App. A.1, DLO
+    Representation).  m2 = t x m1, so a function of (t, d1) that builds
+    d2 = t x d1 gives its material version when handed m1."""
+    d2 = cross(t, d1)
+    c, s = np.cos(theta)[..., None], np.sin(theta)[..., None]
+    m1 = c * d1 + s * d2
+    return m1, cross(t, m1)
+
+
+def signed_angle(sn, cs):
+    """atan2(sn, cs) written with arctan only, so that it also takes
+    complex-step inputs (branches decided on the real parts)."""
+    rs, rc = re(sn), re(cs)
+    big = np.abs(rc) >= np.abs(rs)
+    cs_s = np.where(big, cs, 1.0)
+    sn_s = np.where(big, 1.0, sn)
+    a = np.arctan(sn / cs_s)
+    a = np.where(big & (rc < 0.0), a + np.where(rs >= 0.0, np.pi, -np.pi), a)
+    b = np.where(rs >= 0.0, 0.5 * np.pi, -0.5 * np.pi) - np.arctan(cs / sn_s)
+    return np.where(big, a, b)
+
+
+def reference_twist(t, d1):
+    """Reference twist m_ref_i at the interior vertices (App. A.1, Twisting):
+    the signed angle, about t^i, from the spatial parallel transport of
+    d1^{i-1} onto t^i to d1^i.  Returns [B,N-2]."""
+    u = transport(d1[..., :-1, :], t[..., :-1, :], t[..., 1:, :])
+    d1b = d1[..., 1:, :]
+    return signed_angle(dot(cross(u, d1b), t[..., 1:, :]), dot(u, d1b))

@@ -3,14 +3,17 @@
 Discrete elastic rod data (Appendix A.1, "DLO Representation"): N_v vertices
 with mass m_i and radius r_i, N_e = N_v - 1 edges with rest lengths |e_bar^j|.
 Inverse masses w_i = 1/m_i are inputs; a vertex with w_i = 0 is kinematic
-(pinned, or held by a grasp whose velocity is prescribed).
+(pinned, or held by a grasp whose velocity is prescribed).  With the twist
+flag each edge also carries its twist angle theta^j and angular velocity
+(App. A.1: 3 N_v + N_e degrees of freedom), with an inverse polar moment of
+inertia per edge as input.
 """
 from dataclasses import dataclass
-from typing import List, NamedTuple
+from typing import List, NamedTuple, Optional
 
 import numpy as np
 
-FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF = 1, 2, 4
+FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF, FLAG_TWIST = 1, 2, 4, 8
 
 
 class State(NamedTuple):
@@ -18,6 +21,8 @@ class State(NamedTuple):
     v: np.ndarray        # [B,N,3] vertex velocities
     kb: np.ndarray       # [B,N,2] rest curvature kappa_bar (ends unused, zero)
     d1: np.ndarray       # [B,E,3] first reference director per edge (d2 = t x d1)
+    theta: np.ndarray    # [B,E]   twist angle of the material frame about t^j
+    omega: np.ndarray    # [B,E]   twist angular velocity d theta / dt
 
 
 @dataclass
@@ -53,6 +58,9 @@ class Rods:
     restitution: np.ndarray  # [B]
     flags: int
     prims: List[list]    # per rod: list of (type, a[3], b[3], radius)
+    G: Optional[np.ndarray] = None    # [B]   twisting modulus (Pa), twist flag only
+    Jt: Optional[np.ndarray] = None   # [B,E] inverse polar moment of inertia of each
+                                      #       edge (1/(kg m^2)); 0 holds the twist
 
     @property
     def B(self):
@@ -73,6 +81,25 @@ class Rods:
     @property
     def self_contact(self):
         return bool(self.flags & FLAG_SELF)
+
+    @property
+    def twist(self):
+        return bool(self.flags & FLAG_TWIST)
+
+    @property
+    def twist_coef(self):
+        """beta_i / l_bar_i at the interior vertices, [B,N-2]: twisting
+        stiffness beta_i = G A_i r_i^2 / 2 with A_i = pi r_i^2 (App. A.1,
+        Twisting)."""
+        r = self.radius[:, 1:-1]
+        return self.G[:, None] * np.pi * r ** 4 / 2.0 / self.lbar
+
+    @property
+    def twist_free(self):
+        """[B,E] edges whose twist evolves: inverse inertia > 0 and not both
+        vertices kinematic (an edge held at both ends is clamped in twist)."""
+        both = (self.w[:, :-1] + self.w[:, 1:]) > 0.0
+        return both & (self.Jt > 0.0)
 
     @property
     def ks(self):
@@ -122,10 +149,13 @@ def rods_from_workload(wl, rods):
             lst.append((int(wl.prim_type[k]), wl.prim_a[k].copy(), wl.prim_b[k].copy(),
                         float(wl.prim_r[k])))
         prims.append(lst)
+    G = p[:, 7].copy() if p.shape[1] > 7 else np.zeros(len(rods))
+    Jt = np.stack([wl.twist_inv_inertia[s][:-1] for s in sl]) \
+        if getattr(wl, "twist_inv_inertia", None) is not None else np.zeros_like(rest)
     return Rods(N=N, rest=rest, w=w, radius=np.stack([wl.radius[s] for s in sl]),
                 gidx=gidx, K=p[:, 1].copy(), b=p[:, 2].copy(), sigma_y=p[:, 3].copy(),
                 r_c=p[:, 4].copy(), mu=p[:, 5].copy(), restitution=p[:, 6].copy(),
-                flags=flags.pop(), prims=prims)
+                flags=flags.pop(), prims=prims, G=G, Jt=Jt)
 
 
 def sim_from_workload(wl):
@@ -137,8 +167,8 @@ def sim_from_workload(wl):
 
 
 def state_from_workload(wl, rods, kb=None, d1=None):
-    """Initial state of the listed rods; frames by the initial-frame rule and
-    zero rest curvature unless given."""
+    """Initial state of the listed rods; frames by the initial-frame rule,
+    zero rest curvature unless given, zero twist angles and rates."""
     from .geometry import init_frames
     rods = [int(r) for r in rods]
     sl = [slice(*wl.rod_range(r)) for r in rods]
@@ -148,7 +178,8 @@ def state_from_workload(wl, rods, kb=None, d1=None):
         d1 = init_frames(x)
     if kb is None:
         kb = np.zeros(x.shape[:2] + (2,))
-    return State(x, v, kb, d1)
+    z = np.zeros(x.shape[:1] + (x.shape[1] - 1,))
+    return State(x, v, kb, d1, z, z.copy())
 
 
 def actions_for(wl, rods):

@@ -28,16 +28,17 @@ def rows(wl, rods):
     return np.concatenate([np.arange(*wl.rod_range(r)) for r in rods])
 
 
-def oracle_state_rows(wl, rods, st):
-    """Scatter an oracle State of `rods` (equal sizes) into full-batch rows."""
+def oracle_state_rows(wl, rods, st, n_fields=4):
+    """Scatter an oracle State of `rods` (equal sizes) into full-batch rows:
+    x, v, kappa_bar, d1 and, with n_fields = 6, theta and theta_dot."""
     out = []
-    for k, arr in enumerate(st):
+    for k, arr in enumerate(st[:n_fields]):
         B, n = arr.shape[:2]
-        if k == 3:   # d1 has N-1 rows per rod -> pad the last vertex row
-            pad = np.zeros((B, n + 1, 3))
+        if k >= 3:   # edge arrays have N-1 rows per rod -> pad the last vertex row
+            pad = np.zeros((B, n + 1) + arr.shape[2:])
             pad[:, :n] = arr
             arr = pad
-        out.append(arr.reshape(-1, arr.shape[-1]))
+        out.append(arr.reshape(-1, arr.shape[-1]) if arr.ndim == 3 else arr.reshape(-1))
     return out
 
 
@@ -45,8 +46,12 @@ def gather_state(wl, rods, full):
     """Full-batch arrays -> oracle State for `rods` (equal sizes)."""
     n = wl.rod_range(rods[0])[1] - wl.rod_range(rods[0])[0]
     idx = rows(wl, rods)
-    x, v, kb, d1 = (np.asarray(a, np.float64)[idx].reshape(len(rods), n, -1) for a in full)
-    return State(x, v, kb, d1[:, :-1])
+    x, v, kb, d1 = (np.asarray(a, np.float64)[idx].reshape(len(rods), n, -1) for a in full[:4])
+    if len(full) > 4:
+        th, om = (np.asarray(a, np.float64)[idx].reshape(len(rods), n)[:, :-1] for a in full[4:6])
+    else:
+        th = om = np.zeros((len(rods), n - 1))
+    return State(x, v, kb, d1[:, :-1], th, om)
 
 
 def initial_full_state(wl, dtype=np.float64):

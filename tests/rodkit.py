@@ -45,12 +45,15 @@ def make_sim(dt=1e-3, n_sub=15, n_iters=10, gravity=(0.0, 0.0, -9.81), spa=1):
                steps_per_action=spa)
 
 
-def state(x, v=None, kb=None, d1=None):
+def state(x, v=None, kb=None, d1=None, theta=None, omega=None):
     x = np.asarray(x, np.float64)
     B, N, _ = x.shape
+    z = np.zeros((B, N - 1))
     return State(x, np.zeros_like(x) if v is None else np.asarray(v, np.float64),
                  np.zeros((B, N, 2)) if kb is None else np.asarray(kb, np.float64),
-                 init_frames(x) if d1 is None else np.asarray(d1, np.float64))
+                 init_frames(x) if d1 is None else np.asarray(d1, np.float64),
+                 z.copy() if theta is None else np.asarray(theta, np.float64),
+                 z.copy() if omega is None else np.asarray(omega, np.float64))
 
 
 def arc(N, edge, turn, z=0.5):

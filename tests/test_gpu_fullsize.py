@@ -63,7 +63,8 @@ def test_fp64_full_batch_1000_steps_matches_golden():
 def _perturbed(st, seed):
     rng = np.random.default_rng(seed)
     return type(st)(st.x * (1 + 6e-8 * rng.standard_normal(st.x.shape)),
-                    st.v * (1 + 6e-8 * rng.standard_normal(st.v.shape)), st.kb, st.d1)
+                    st.v * (1 + 6e-8 * rng.standard_normal(st.v.shape)), st.kb, st.d1,
+                    st.theta, st.omega)
 
 
 def _last_step_parity(wl, n_before, tol=1e-4, ties=False):

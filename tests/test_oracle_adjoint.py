@@ -120,7 +120,8 @@ def test_rollout_dot_product_complex_step():
     U = rng.normal(0, 0.3, (4, rods.B, 2, 3))
     dx, dv = rng.normal(size=st.x.shape), rng.normal(size=st.v.shape)
     dU, db, ds = rng.normal(size=U.shape), rng.normal(size=rods.B), rng.normal(size=rods.B)
-    stc = State(st.x + 1j * H * dx, st.v + 1j * H * dv, st.kb.astype(complex), st.d1.astype(complex))
+    stc = State(st.x + 1j * H * dx, st.v + 1j * H * dv, st.kb.astype(complex),
+                st.d1.astype(complex), st.theta.astype(complex), st.omega.astype(complex))
     outc, _ = forward.rollout(_complexify(rods, db, ds), sim, stc, U + 1j * H * dU, n)
     yx, yv = rng.normal(size=st.x.shape), rng.normal(size=st.v.shape)
     lhs = np.sum(yx * outc.x.imag / H) + np.sum(yv * outc.v.imag / H)
