@@ -5,7 +5,7 @@
  * (arXiv 2606.04206): Section 3.1 (rod state, forces from the energy
  * derivatives, symplectic Euler, bending plasticity), Section 3.2 "Rigid
  * Body" (soft SDF contact), Section 3.3 (gradients through a checkpointed
- * rollout) and Appendix A.1 (stretching and bending energies,
+ * rollout) and Appendix A.1 (stretching, bending and twisting energies,
  * inextensibility projection, plastic creep update, self-collision and
  * friction).
  *
@@ -59,11 +59,20 @@ enum {
   ROD_P_RC = 4,      /* creep rate r_c */
   ROD_P_MU = 5,      /* Coulomb friction coefficient (rigid and self contact) */
   ROD_P_REST = 6,    /* restitution coefficient (rigid contact) */
-  ROD_NPARAM = 7
+  ROD_P_G = 7,       /* twisting modulus G (Pa): beta_i = G A_i r_i^2 / 2 (App. A.1, Twisting);
+                        read only for rods with ROD_FLAG_TWIST */
+  ROD_NPARAM = 8
 };
 #define ROD_FLAG_INEXT 1
 #define ROD_FLAG_PLASTIC 2
 #define ROD_FLAG_SELF 4
+/* bit3: the twist degree of freedom (App. A.1, DLO Representation): each
+ * edge carries a twist angle theta^j of its material frame against the
+ * reference frame and an angular rate, stepped by the same symplectic Euler
+ * as the vertices under -dU/dtheta (twisting energy U_t with zero rest
+ * twist, bending energy through the material frames).  Not combined with
+ * ROD_FLAG_SELF; rods of up to 1024 vertices. */
+#define ROD_FLAG_TWIST 8
 
 enum { ROD_PRIM_PLANE = 0, ROD_PRIM_SPHERE = 1, ROD_PRIM_CAPSULE = 2 };
 
@@ -100,6 +109,12 @@ typedef struct {
   int32_t steps_per_action;   /* steps that share one grasp velocity in rods_rollout */
   int32_t ckpt_every;         /* K: checkpoint interval of recorded rollouts (steps) */
   int32_t max_steps;          /* longest recorded rollout; sizes the checkpoints */
+  const double* twist_inv_inertia; /* (host) [V] 1/I^j (1/(kg m^2)) of edge row j, the
+                                 inverse polar moment of inertia that turns the torque
+                                 -dU/dtheta^j into angular acceleration; 0 holds the
+                                 edge's twist, as do edges whose two vertices are both
+                                 kinematic.  Required when a rod has ROD_FLAG_TWIST,
+                                 ignored (may be NULL) otherwise. */
 } RodsDesc;
 
 /* Validates the description, copies the static data to the device and
@@ -122,6 +137,16 @@ int rods_set_state(RodsHandle* h, const void* x, const void* v, const void* kapp
 /* Copies the current state out; any pointer may be NULL to skip it. */
 int rods_get_state(RodsHandle* h, void* x, void* v, void* kappa_bar, void* d1,
                    rods_stream_t stream);
+
+/* Twist state of rods with ROD_FLAG_TWIST (App. A.1, DLO Representation):
+ * theta [V] twist angle (rad) and theta_dot [V] its rate (rad/s) per edge
+ * row (edge rows as above).  rods_set_state sets both to zero; this call
+ * replaces them (NULL = zeros) and clears the recorded rollout.  Rows of
+ * rods without the flag are kept but never read. */
+int rods_set_twist(RodsHandle* h, const void* theta, const void* theta_dot,
+                   rods_stream_t stream);
+/* Copies the twist state out; either pointer may be NULL. */
+int rods_get_twist(RodsHandle* h, void* theta, void* theta_dot, rods_stream_t stream);
 
 /* Overrides the per-rod bending stiffness b and yield curvature sigma_y with
  * device arrays [R] (either may be NULL).  Clears the recorded rollout. */

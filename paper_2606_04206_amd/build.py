@@ -15,12 +15,17 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           # packed FP32 VALU forms stay off (hardware notes)
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-SOURCES = ["rod_kernels.hip", "rods_api.cpp"]
+# (source, extra flags, object): the kernel source is compiled a second time
+# for the kernels of twisting rods, in parallel with the first
+UNITS = [("rod_kernels.hip", [], "rod_kernels.o"),
+         ("rod_kernels.hip", ["-DRODS_TU=1"], "rod_kernels_twist.o"),
+         ("rods_api.cpp", [], "rods_api.o")]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit):
+    src, extra, name = unit
+    obj = os.path.join(BUILD, name)
+    cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -29,8 +34,8 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    with ThreadPoolExecutor(len(UNITS)) as ex:
+        objs = list(ex.map(_compile, UNITS))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

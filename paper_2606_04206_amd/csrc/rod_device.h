@@ -212,6 +212,15 @@ struct RodArgs {
   T* sc_tape;               // self-contact rods: projection iterates of one substep
   const int64_t* sc_off;    // [R] offset of the rod's block in sc_tape
   int32_t* status;          // [R] bit0 non-finite, bit1 partner list full, bit2 stretched edge
+  // twist degree of freedom (rods with the twist flag; edge rows)
+  const T* Gt;              // [R] twisting modulus
+  const T* jt;              // [V] inverse polar moment of inertia of edge row j
+  T* th;                    // [V] twist angle (state)
+  T* om;                    // [V] twist rate (state)
+  T* ck_th;
+  T* ck_om;
+  T* lth;                   // adjoints of theta and its rate
+  T* lom;
   // scalars
   T h;
   T gx, gy, gz;

@@ -8,6 +8,9 @@
 // iteration of the inextensibility projection needs exactly one neighbour
 // exchange pair (positions to the left, corrections to the right).
 //
+// The file is compiled twice: RODS_TU = 1 instantiates the kernels of rods
+// with the twist degree of freedom, the default everything else.
+//
 // Physics (DLO-Lab, Section 3.1 and Appendix A.1): bending forces of the
 // discrete elastic rod with frames held fixed, stretching forces for
 // extensible rods, symplectic Euler, soft SDF rigid contact (Section 3.2),
@@ -23,7 +26,10 @@
 namespace rods {
 
 constexpr int FLAG_INEXT = 1, FLAG_PLASTIC = 2, FLAG_SELF = 4;
-constexpr int NFIELD = 11;   // x(3) v(3) kappa_bar(2) d1(3) per vertex slot
+// values per vertex slot of a stored state: x(3) v(3) kappa_bar(2) d1(3),
+// and with the twist degree of freedom theta and its rate
+template <bool TW>
+constexpr int nfield() { return TW ? 13 : 11; }
 
 template <typename T>
 __device__ __forceinline__ V3<T> transport(V3<T> v, V3<T> ta, V3<T> tb) {
@@ -168,6 +174,122 @@ __device__ __forceinline__ void curvature_vjp(V3<T> t0, V3<T> t1, V3<T> d1a, V3<
   d1bb = T(0.5) * a2b + cross(d2ab, t1);
   t0b += cross(d1a, d2ab);
   t1b += cross(d1b, d2ab);
+}
+
+// ---------------------------------------------------------------------------
+// Twist degree of freedom (App. A.1, DLO Representation and Twisting).  The
+// material director m1 is the reference d1 turned by theta about t; the
+// twisting strain at an interior vertex is theta^i - theta^{i-1} + m_ref_i
+// (rest twist zero) with m_ref_i the signed angle, about t^i, from the
+// spatial parallel transport of d1^{i-1} to d1^i.  Theta is a dynamic
+// degree of freedom driven by -dU/dtheta; the twist energy acts on the
+// vertices through the holonomy gradient dm_ref_i/de = (kb)_i / (2 |e|) of
+// each adjacent edge.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ V3<T> material_m1(V3<T> t, V3<T> d1, T th) {
+  T s = sin(th), c = cos(th);
+  return c * d1 + s * cross(t, d1);
+}
+
+// Adjoint of material_m1: returns d1_b, adds to t_b and th_b.
+template <typename T>
+__device__ __forceinline__ V3<T> material_m1_vjp(V3<T> t, V3<T> d1, T th, V3<T> m1b, V3<T>& tb,
+                                                 T& thb) {
+  T s = sin(th), c = cos(th);
+  thb += dot(m1b, c * cross(t, d1) - s * d1);
+  tb += s * cross(d1, m1b);
+  return c * m1b + s * cross(m1b, t);
+}
+
+// Twist stencil of an interior vertex: edges i-1 (a) and i (b) with their
+// material (m1) and reference (d1) directors and angles; coef = b / l_bar,
+// tcoef = beta / l_bar (both 0 away from interior vertices).
+template <typename T>
+struct TwIn {
+  V3<T> t0, t1, m1a, m1b, d1a, d1b;
+  T il0, il1, tha, thb;
+  T kr0, kr1, coef, ilbar, tcoef;
+};
+
+// Adds the twist energy's edge gradients to g0 = dU/de^{i-1}, g1 = dU/de^i
+// and returns the torques -dU/dtheta (bending through the material frames,
+// and twisting) on edges i-1 (Ta) and i (Tb).
+template <typename T>
+__device__ __forceinline__ void twist_grad(const TwIn<T>& q, V3<T>& g0, V3<T>& g1, T& Ta,
+                                           T& Tb) {
+  T ichi = frcp(T(1) + dot(q.t0, q.t1));
+  V3<T> kbv = (T(2) * ichi) * cross(q.t0, q.t1);
+  V3<T> m2a = cross(q.t0, q.m1a), m2b = cross(q.t1, q.m1b);
+  V3<T> a1 = T(0.5) * (m2a + m2b), a2 = T(0.5) * (q.m1a + q.m1b);
+  T c1 = q.coef * (dot(kbv, a1) - q.kr0), c2 = q.coef * (dot(kbv, a2) - q.kr1);
+  V3<T> u = transport(q.d1a, q.t0, q.t1);
+  T g = q.tcoef * (q.thb - q.tha + atan2(dot(cross(u, q.d1b), q.t1), dot(u, q.d1b)));
+  Ta = T(0.5) * (c1 * dot(kbv, q.m1a) - c2 * dot(kbv, m2a)) + g;
+  Tb = T(0.5) * (c1 * dot(kbv, q.m1b) - c2 * dot(kbv, m2b)) - g;
+  T hg = T(0.5) * g;
+  g0 += (hg * q.il0) * kbv;
+  g1 += (hg * q.il1) * kbv;
+}
+
+template <typename T>
+struct TwBar {
+  V3<T> t0, t1, m1a, m1b, m2a, m2b, d1a, d1b;
+  T l0, l1, tha, thb, kr0, kr1, b;
+};
+
+// Adjoint of twist_grad given the adjoints of its g0, g1 contributions and
+// of the two torques.  m2 = t x m1 is left to the caller (m2a, m2b).
+template <typename T>
+__device__ __forceinline__ void twist_vjp(const TwIn<T>& q, V3<T> g0b, V3<T> g1b, T Tab, T Tbb,
+                                          TwBar<T>& o) {
+  T ichi = frcp(T(1) + dot(q.t0, q.t1));
+  V3<T> kbv = (T(2) * ichi) * cross(q.t0, q.t1);
+  V3<T> m2a = cross(q.t0, q.m1a), m2b = cross(q.t1, q.m1b);
+  V3<T> a1 = T(0.5) * (m2a + m2b), a2 = T(0.5) * (q.m1a + q.m1b);
+  T dk1 = dot(kbv, a1) - q.kr0, dk2 = dot(kbv, a2) - q.kr1;
+  T c1 = q.coef * dk1, c2 = q.coef * dk2;
+  V3<T> u = transport(q.d1a, q.t0, q.t1);
+  T sn = dot(cross(u, q.d1b), q.t1), cs = dot(u, q.d1b);
+  T g = q.tcoef * (q.thb - q.tha + atan2(sn, cs));
+  // g0 += (g/2) il0 kbv, g1 += (g/2) il1 kbv
+  T k0 = dot(kbv, g0b), k1 = dot(kbv, g1b);
+  T gb = T(0.5) * (q.il0 * k0 + q.il1 * k1) + Tab - Tbb;
+  V3<T> kbvb = (T(0.5) * g * q.il0) * g0b + (T(0.5) * g * q.il1) * g1b;
+  o.l0 = -T(0.5) * g * q.il0 * q.il0 * k0;
+  o.l1 = -T(0.5) * g * q.il1 * q.il1 * k1;
+  // bending torques
+  V3<T> P1 = T(0.5) * (Tab * q.m1a + Tbb * q.m1b);
+  V3<T> P2 = T(0.5) * (Tab * m2a + Tbb * m2b);
+  T c1b = dot(kbv, P1), c2b = -dot(kbv, P2);
+  kbvb += c1 * P1 - c2 * P2;
+  T ca = T(0.5) * Tab, cb = T(0.5) * Tbb;
+  V3<T> a1b = (q.coef * c1b) * kbv, a2b = (q.coef * c2b) * kbv;
+  o.m1a = (ca * c1) * kbv + T(0.5) * a2b;
+  o.m1b = (cb * c1) * kbv + T(0.5) * a2b;
+  o.m2a = (-(ca * c2)) * kbv + T(0.5) * a1b;
+  o.m2b = (-(cb * c2)) * kbv + T(0.5) * a1b;
+  kbvb += (q.coef * c1b) * a1 + (q.coef * c2b) * a2;
+  o.kr0 = -q.coef * c1b;
+  o.kr1 = -q.coef * c2b;
+  o.b = (c1b * dk1 + c2b * dk2) * q.ilbar;
+  // twisting strain and reference twist (sn = cs = 0 where tcoef = 0)
+  T taub = q.tcoef * gb;
+  o.thb = taub;
+  o.tha = -taub;
+  T r2 = sn * sn + cs * cs;
+  T mb = r2 > T(0) ? taub * frcp(r2) : T(0);
+  T snb = cs * mb, csb = -(sn * mb);
+  V3<T> ub = snb * cross(q.d1b, q.t1) + csb * q.d1b;
+  o.d1b = snb * cross(q.t1, u) + csb * u;
+  V3<T> t0b = zero3<T>();
+  V3<T> t1b = snb * cross(u, q.d1b);
+  o.d1a = transport_vjp(q.d1a, q.t0, q.t1, ub, t0b, t1b);
+  // kbv = 2 (t0 x t1) / (1 + t0.t1)
+  T chib = -dot(kbv, kbvb) * ichi;
+  V3<T> nb = (T(2) * ichi) * kbvb;
+  o.t0 = t0b + cross(q.t1, nb) + chib * q.t1;
+  o.t1 = t1b + cross(nb, q.t0) + chib * q.t0;
 }
 
 // One inextensibility projection of edge (pj, pk) (App. A.1).  With
@@ -348,12 +470,17 @@ struct Rec {   // what the adjoint needs from one substep's forward run
   T kel0[C], kel1[C], inrm[C], phi[C];   // inrm = 1 / |kappa_el| on yield
   bool yld[C];
   V3<T> x1[C], v3[C];   // positions after projection, velocities before self-friction
+  // twist: angles at the substep start and after the update, the previous
+  // lane's last edge (angle, material d1 at the start)
+  T th[C], th1[C], thp;
+  V3<T> m1p;
 };
 
-template <typename T, int C, int W, bool SC>
+template <typename T, int C, int W, bool SC, bool TW = false>
 struct Rod {
   static constexpr int TL = 64 * W;   // lanes per team
   static constexpr int NV = TL * C;   // vertex capacity of the team
+  static constexpr int NFIELD = nfield<TW>();
   int rod, N, v0, tl, flags, p0, p1;
   // self-contact scratch (LDS) and the adjoint's contact-pass inputs (global)
   T *sc_pos, *sc_aux, *sc_adj, *sc_w, *sc_r, *sc_d0, *sc_vcnt;
@@ -375,6 +502,8 @@ struct Rod {
   int gs[C];
   V3<T> x[C], v[C], d1[C];
   T kr0[C], kr1[C];
+  // twist: angle and rate per edge, inverse inertia (0: held), beta / l_bar
+  T th[C], om[C], jt[C], tcoef[C];
 
   __device__ __forceinline__ int gi(int c) const { return tl * C + c; }
   __device__ __forceinline__ bool vvalid(int c) const { return gi(c) < N; }
@@ -421,6 +550,13 @@ struct Rod {
       coef[c] = b * ilbar[c];
       T rb = T(0.5) * (rad[c] + (c < C - 1 ? rad[c + 1] : rn[0]));
       ks[c] = evalid(c) ? K * T(3.14159265358979323846) * rb * rb : T(0);
+      if constexpr (TW) {
+        // an edge with both vertices kinematic holds its twist
+        jt[c] = pe ? a.jt[v0 + gi(c)] : T(0);
+        T r2 = rad[c] * rad[c];
+        tcoef[c] = ivalid(c) ? a.Gt[rod] * T(3.14159265358979323846) * r2 * r2 / T(2) * ilbar[c]
+                             : T(0);
+      }
     }
   }
 
@@ -435,6 +571,24 @@ struct Rod {
       kr0[c] = ivalid(c) ? KB[2 * r] : T(0);
       kr1[c] = ivalid(c) ? KB[2 * r + 1] : T(0);
       d1[c] = evalid(c) ? get3(D1, 3 * r) : zero3<T>();
+    }
+  }
+  __device__ void load_twist(const T* TH, const T* OM) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int r = v0 + gi(c);
+      th[c] = evalid(c) ? TH[r] : T(0);
+      om[c] = evalid(c) ? OM[r] : T(0);
+    }
+  }
+  __device__ void store_twist(T* TH, T* OM) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int g = gi(c), r = v0 + g;
+      if (g < N) {
+        TH[r] = th[c];   // zero on the last vertex row
+        OM[r] = om[c];
+      }
     }
   }
 
@@ -457,8 +611,9 @@ struct Rod {
   __device__ void store_tape(T* base) const {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      T vals[NFIELD] = {x[c].x, x[c].y, x[c].z, v[c].x, v[c].y, v[c].z,
-                        kr0[c], kr1[c], d1[c].x, d1[c].y, d1[c].z};
+      T vals[13] = {x[c].x, x[c].y, x[c].z, v[c].x, v[c].y, v[c].z,
+                    kr0[c], kr1[c], d1[c].x, d1[c].y, d1[c].z, TW ? th[c] : T(0),
+                    TW ? om[c] : T(0)};
 #pragma unroll
       for (int f = 0; f < NFIELD; ++f) base[(f * C + c) * TL + tl] = vals[f];
     }
@@ -479,6 +634,10 @@ struct Rod {
       kr0[c] = buf[6 * C + c];
       kr1[c] = buf[7 * C + c];
       d1[c] = mk(buf[8 * C + c], buf[9 * C + c], buf[10 * C + c]);
+      if constexpr (TW) {
+        th[c] = buf[11 * C + c];
+        om[c] = buf[12 * C + c];
+      }
     }
   }
 
@@ -1119,6 +1278,21 @@ struct Rod {
     dp = mk(pv[4], pv[5], pv[6]);
   }
 
+  // twist: the previous lane's last edge with its material and reference
+  // d1 and its angle
+  __device__ void prev_edge_tw(Team<T, W>& X, const V3<T> (&t)[C], const T (&il)[C],
+                               const V3<T> (&m1)[C], const V3<T> (&dd)[C], const T (&ang)[C],
+                               V3<T>& tp, T& ilp, V3<T>& m1p, V3<T>& dp, T& angp) const {
+    T pv[11] = {t[C - 1].x,  t[C - 1].y,  t[C - 1].z,  il[C - 1], m1[C - 1].x, m1[C - 1].y,
+                m1[C - 1].z, dd[C - 1].x, dd[C - 1].y, dd[C - 1].z, ang[C - 1]};
+    X.prev(pv);
+    tp = mk(pv[0], pv[1], pv[2]);
+    ilp = pv[3];
+    m1p = mk(pv[4], pv[5], pv[6]);
+    dp = mk(pv[7], pv[8], pv[9]);
+    angp = pv[10];
+  }
+
   // kr0/kr1: the rest curvature at the substep start (the adjoint passes the
   // recorded values: the replayed substep has already updated the registers)
   __device__ __forceinline__ BendIn<T> bend_in(int c, const V3<T> (&t)[C], const T (&il)[C],
@@ -1163,7 +1337,17 @@ struct Rod {
     } else {
       edges(X, x, t, l, il);
     }
-    if (!REC && prev_ok) {
+    // twist: material directors m1 (bending sees them in place of d1)
+    V3<T> m1[C], m1p;
+    T thp = T(0), Tq[C], tq_prev = T(0);
+    if constexpr (TW) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        m1[c] = material_m1(t[c], d1[c], th[c]);
+        Tq[c] = T(0);
+      }
+      prev_edge_tw(X, t, il, m1, d1, th, tp, ilp, m1p, d1p, thp);
+    } else if (!REC && prev_ok) {
       tp = tpc;
       ilp = ilpc;
       d1p = d1pc;
@@ -1178,9 +1362,19 @@ struct Rod {
     // makes both gradients exactly zero (all inputs are finite there)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      BendIn<T> q = bend_in(c, t, il, d1, tp, ilp, d1p, kr0, kr1);
+      BendIn<T> q = TW ? bend_in(c, t, il, m1, tp, ilp, m1p, kr0, kr1)
+                       : bend_in(c, t, il, d1, tp, ilp, d1p, kr0, kr1);
       V3<T> g0, g1;
       bend_grad(q, g0, g1);
+      if constexpr (TW) {
+        TwIn<T> tq{q.t0,  q.t1,  q.d1a, q.d1b, c ? d1[c - 1] : d1p, d1[c], q.il0,
+                   q.il1, c ? th[c - 1] : thp, th[c], q.kr0, q.kr1, q.coef, q.ilbar,
+                   tcoef[c]};
+        T Ta, Tb;
+        twist_grad(tq, g0, g1, Ta, Tb);
+        Tq[c] += Tb;
+        if (c > 0) Tq[c - 1] += Ta; else tq_prev += Ta;
+      }
       F[c] += g1 - g0;
       if (c > 0) F[c - 1] += g0; else to_prev += g0;
       if (c < C - 1) F[c + 1] -= g1; else to_next -= g1;
@@ -1195,7 +1389,15 @@ struct Rod {
         }
       }
     }
-    {
+    if constexpr (TW) {
+      T s[4] = {to_prev.x, to_prev.y, to_prev.z, tq_prev};
+      X.next(s);
+      F[C - 1] += mk(s[0], s[1], s[2]);
+      Tq[C - 1] += s[3];
+      T s2[3] = {to_next.x, to_next.y, to_next.z};
+      X.prev(s2);
+      F[0] += mk(s2[0], s2[1], s2[2]);
+    } else {
       T s[3] = {to_prev.x, to_prev.y, to_prev.z};
       X.next(s);
       F[C - 1] += mk(s[0], s[1], s[2]);
@@ -1216,6 +1418,12 @@ struct Rod {
       rc_->tp = tp;
       rc_->ilp = ilp;
       rc_->d1p = d1p;
+      if constexpr (TW) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) rc_->th[c] = th[c];
+        rc_->thp = thp;
+        rc_->m1p = m1p;
+      }
     }
     // S3 velocity update and kinematic vertices
 #pragma unroll
@@ -1226,6 +1434,10 @@ struct Rod {
       else vn = zero3<T>();
       v[c] = vn;
       if constexpr (REC) rc_->v1[c] = vn;
+    }
+    if constexpr (TW) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) om[c] = jt[c] > T(0) ? om[c] + (h * jt[c]) * Tq[c] : T(0);
     }
     // S4 rigid contact, primitives in order
     if (p1 > p0) {
@@ -1245,6 +1457,13 @@ struct Rod {
     for (int c = 0; c < C; ++c) {
       p0[c] = x[c] + h * v[c];
       dl[c] = zero3<T>();
+    }
+    if constexpr (TW) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        th[c] += h * om[c];
+        if constexpr (REC) rc_->th1[c] = th[c];
+      }
     }
     // S6 self-contact candidates at the predicted positions
     const bool self_on = SC && (flags & FLAG_SELF);
@@ -1302,13 +1521,18 @@ struct Rod {
     // vertices the curvature and kappa_bar are zero and so is the threshold,
     // so the (strict) yield test fails there.
     if (flags & FLAG_PLASTIC) {
+      // material directors at the new positions and angles (d1 itself
+      // without twist)
+      V3<T> mn[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) mn[c] = TW ? material_m1(t1[c], d1[c], th[c]) : d1[c];
       V3<T> t1p, d1np;
       T il1p;
-      prev_edge(X, t1, il1, d1, t1p, il1p, d1np);
+      prev_edge(X, t1, il1, mn, t1p, il1p, d1np);
       if constexpr (REC) {
         rc_->t1p = t1p;
         rc_->d1np = d1np;
-      } else {
+      } else if constexpr (!TW) {
         tpc = t1p;
         ilpc = il1p;
         d1pc = d1np;
@@ -1317,7 +1541,7 @@ struct Rod {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         T k1, k2;
-        curvature(c ? t1[c - 1] : t1p, t1[c], c ? d1[c - 1] : d1np, d1[c], k1, k2);
+        curvature(c ? t1[c - 1] : t1p, t1[c], c ? mn[c - 1] : d1np, mn[c], k1, k2);
         T e0 = k1 - kr0[c], e1 = k2 - kr1[c];
         T ss = e0 * e0 + e1 * e1;
         T in = frsq(ss);
@@ -1343,7 +1567,7 @@ struct Rod {
   __device__ void substep_vjp(const RodArgs<T>& a, Team<T, W>& X, const Rec<T, C>& r,
                               const T* lds_tape, V3<T> (&lx)[C], V3<T> (&lv)[C], T (&lk0)[C],
                               T (&lk1)[C], V3<T> (&ld1)[C], double (&accb)[C],
-                              double (&accs)[C], V3<T> (&uacc)[C]) {
+                              double (&accs)[C], V3<T> (&uacc)[C], T (&lth)[C], T (&lom)[C]) {
     const T h = a.h;
     const T ih = T(1) / h;
     // S11 plasticity: kr' = kr + phi kel on yield
@@ -1355,6 +1579,15 @@ struct Rod {
     }
     if (flags & FLAG_PLASTIC) {
       V3<T> tpb = zero3<T>(), dpb = zero3<T>();
+      // twist: curvature of the material directors; their adjoints collect
+      // in mnb and go to d1n, t1 and theta afterwards
+      V3<T> mn[C], mnb[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        mn[c] = TW ? material_m1(r.t1[c], r.d1n[c], r.th1[c]) : r.d1n[c];
+        mnb[c] = zero3<T>();
+      }
+      V3<T> (&dnb)[C] = TW ? mnb : d1nb;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         if (r.yld[c]) {   // never set away from interior vertices
@@ -1369,23 +1602,28 @@ struct Rod {
           lk0[c] -= e0;
           lk1[c] -= e1;
           V3<T> t0b, tcb, dab, dcb;
-          curvature_vjp(c ? r.t1[c - 1] : r.t1p, r.t1[c], c ? r.d1n[c - 1] : r.d1np, r.d1n[c], e0,
-                        e1, t0b, tcb, dab, dcb);
+          curvature_vjp(c ? r.t1[c - 1] : r.t1p, r.t1[c], c ? mn[c - 1] : r.d1np, mn[c], e0, e1,
+                        t0b, tcb, dab, dcb);
           if (c > 0) {
             t1b[c - 1] += t0b;
-            d1nb[c - 1] += dab;
+            dnb[c - 1] += dab;
           } else {
             tpb += t0b;
             dpb += dab;
           }
           t1b[c] += tcb;
-          d1nb[c] += dcb;
+          dnb[c] += dcb;
         }
       }
       T s[6] = {tpb.x, tpb.y, tpb.z, dpb.x, dpb.y, dpb.z};
       X.next(s);
       t1b[C - 1] += mk(s[0], s[1], s[2]);
-      d1nb[C - 1] += mk(s[3], s[4], s[5]);
+      dnb[C - 1] += mk(s[3], s[4], s[5]);
+      if constexpr (TW) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          if (evalid(c)) d1nb[c] += material_m1_vjp(r.t1[c], r.d1n[c], r.th1[c], mnb[c], t1b[c], lth[c]);
+      }
     }
     // S10 transport
     V3<T> tb[C], d1b[C];
@@ -1416,13 +1654,14 @@ struct Rod {
     }
     // S7
     if ((flags & FLAG_INEXT) || (SC && (flags & FLAG_SELF))) project_vjp(a, X, pb, lds_tape);
-    // S5 p0 = x + h v2
+    // S5 p0 = x + h v2 (twist: theta' = theta + h omega')
     V3<T> xb[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       p0b[c] += pb[c];
       xb[c] = p0b[c];
       v2b[c] += h * p0b[c];
+      if constexpr (TW) lom[c] += h * lth[c];
     }
     // S4 rigid contact, primitives in reverse.  One forward sweep re-runs the
     // primitives in order and keeps the input velocity of each active one
@@ -1481,6 +1720,10 @@ struct Rod {
         lv[c] = zero3<T>();
         Fb[c] = zero3<T>();
       }
+    }
+    if constexpr (TW) {
+      s2_vjp_twist(a, X, r, Fb, tb, lb, d1b, xb, lx, lk0, lk1, ld1, accb, lth, lom);
+      return;
     }
     // S2 forces
     T fp[3] = {Fb[C - 1].x, Fb[C - 1].y, Fb[C - 1].z};
@@ -1558,6 +1801,120 @@ struct Rod {
       ld1[c] = d1b[c];
     }
   }
+
+  // Twist rates (S3) and forces and torques (S2) of the adjoint for rods
+  // with the twist degree of freedom: the bending stencil on the material
+  // directors, the twist stencil, then m2 = t x m1 and m1 = R(theta) d1.
+  __device__ void s2_vjp_twist(const RodArgs<T>& a, Team<T, W>& X, const Rec<T, C>& r,
+                               const V3<T> (&Fb)[C], V3<T> (&tb)[C], T (&lb)[C],
+                               V3<T> (&d1b)[C], V3<T> (&xb)[C], V3<T> (&lx)[C], T (&lk0)[C],
+                               T (&lk1)[C], V3<T> (&ld1)[C], double (&accb)[C], T (&lth)[C],
+                               T (&lom)[C]) {
+    const T h = a.h;
+    T Tqb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const bool fr = jt[c] > T(0);
+      Tqb[c] = fr ? (h * jt[c]) * lom[c] : T(0);
+      lom[c] = fr ? lom[c] : T(0);
+    }
+    T fp[4] = {Fb[C - 1].x, Fb[C - 1].y, Fb[C - 1].z, Tqb[C - 1]};
+    X.prev(fp);
+    T fn[3] = {Fb[0].x, Fb[0].y, Fb[0].z};
+    X.next(fn);
+    const V3<T> Fp = mk(fp[0], fp[1], fp[2]), Fn = mk(fn[0], fn[1], fn[2]);
+    const T Tqp = fp[3];
+    V3<T> m1[C], m1b[C], d2b[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      m1[c] = material_m1(r.t[c], r.d1[c], r.th[c]);
+      m1b[c] = zero3<T>();
+      d2b[c] = zero3<T>();
+    }
+    V3<T> tpb = zero3<T>(), m1pb = zero3<T>(), d2pb = zero3<T>(), rdpb = zero3<T>();
+    T lpb = T(0), thpb = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      BendIn<T> q = bend_in(c, r.t, r.il, m1, r.tp, r.ilp, r.m1p, r.kr0, r.kr1);
+      V3<T> Fm = c ? Fb[c - 1] : Fp;
+      V3<T> Fq = (c < C - 1) ? Fb[c + 1] : Fn;
+      V3<T> g0b = Fm - Fb[c], g1b = Fb[c] - Fq;
+      BendBar<T> o;
+      bend_vjp(q, g0b, g1b, o);
+      TwIn<T> tq{q.t0,  q.t1,  q.d1a, q.d1b, c ? r.d1[c - 1] : r.d1p, r.d1[c], q.il0,
+                 q.il1, c ? r.th[c - 1] : r.thp, r.th[c], q.kr0, q.kr1, q.coef, q.ilbar,
+                 tcoef[c]};
+      TwBar<T> ow;
+      twist_vjp(tq, g0b, g1b, c ? Tqb[c - 1] : Tqp, Tqb[c], ow);
+      lk0[c] += o.kr0 + ow.kr0;
+      lk1[c] += o.kr1 + ow.kr1;
+      accb[c] += (double)o.b + (double)ow.b;
+      if (c > 0) {
+        tb[c - 1] += o.t0 + ow.t0;
+        lb[c - 1] += o.l0 + ow.l0;
+        m1b[c - 1] += o.d1a + ow.m1a;
+        d2b[c - 1] += o.d2a + ow.m2a;
+        d1b[c - 1] += ow.d1a;
+        lth[c - 1] += ow.tha;
+      } else {
+        tpb += o.t0 + ow.t0;
+        lpb += o.l0 + ow.l0;
+        m1pb += o.d1a + ow.m1a;
+        d2pb += o.d2a + ow.m2a;
+        rdpb += ow.d1a;
+        thpb += ow.tha;
+      }
+      tb[c] += o.t1 + ow.t1;
+      lb[c] += o.l1 + ow.l1;
+      m1b[c] += o.d1b + ow.m1b;
+      d2b[c] += o.d2b + ow.m2b;
+      d1b[c] += ow.d1b;
+      lth[c] += ow.thb;
+    }
+    if (!(flags & FLAG_INEXT)) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (evalid(c)) {
+          V3<T> Fq = (c < C - 1) ? Fb[c + 1] : Fn;
+          V3<T> qb = Fb[c] - Fq;
+          T fs = ks[c] * (fdiv(frcp(r.il[c]), rest[c]) - T(1));
+          tb[c] += fs * qb;
+          lb[c] += fdiv(ks[c] * dot(qb, r.t[c]), rest[c]);
+        }
+      }
+    }
+    {
+      T s[10] = {tpb.x, tpb.y, tpb.z, lpb, m1pb.x, m1pb.y, m1pb.z, d2pb.x, d2pb.y, d2pb.z};
+      X.next(s);
+      tb[C - 1] += mk(s[0], s[1], s[2]);
+      lb[C - 1] += s[3];
+      m1b[C - 1] += mk(s[4], s[5], s[6]);
+      d2b[C - 1] += mk(s[7], s[8], s[9]);
+      T s2[4] = {rdpb.x, rdpb.y, rdpb.z, thpb};
+      X.next(s2);
+      d1b[C - 1] += mk(s2[0], s2[1], s2[2]);
+      lth[C - 1] += s2[3];
+    }
+    // m2 = t x m1, m1 = cos(theta) d1 + sin(theta) t x d1
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (evalid(c)) {
+        tb[c] += cross(m1[c], d2b[c]);
+        m1b[c] += cross(d2b[c], r.t[c]);
+        d1b[c] += material_m1_vjp(r.t[c], r.d1[c], r.th[c], m1b[c], tb[c], lth[c]);
+      } else {
+        d1b[c] = zero3<T>();
+        lth[c] = T(0);
+        lom[c] = T(0);
+      }
+    }
+    edges_vjp(X, r.t, r.il, tb, lb, xb);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      lx[c] = vvalid(c) ? xb[c] : zero3<T>();
+      ld1[c] = d1b[c];
+    }
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -1570,12 +1927,12 @@ __device__ __forceinline__ size_t xchg_bytes() { return W > 1 ? 2 * W * XK * siz
 // Forward: n_steps steps of every rod of the work list, the rod resident in
 // registers the whole time.  TAPE: store every substep-start state.  SC:
 // self-contact support (hash, partner lists and staging buffers in LDS).
-template <typename T, int C, int W, bool TAPE, bool SC>
+template <typename T, int C, int W, bool TAPE, bool SC, bool TW>
 __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Team<T, W> X;
   X.init(reinterpret_cast<T*>(smem));
-  Rod<T, C, W, SC> R;
+  Rod<T, C, W, SC, TW> R;
   R.load_static(a, X);
   if constexpr (SC) {
     R.sc_layout(smem + xchg_bytes<T, W>());
@@ -1583,6 +1940,7 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
     R.sc_setup(a);
   }
   R.load_state(a.x, a.v, a.kb, a.d1);
+  if constexpr (TW) R.load_twist(a.th, a.om);
   T* tape_rod = TAPE ? a.tape + a.tape_off[R.rod] : nullptr;
   for (int s = 0; s < a.n_steps; ++s) {
     V3<T> ug[C];
@@ -1594,6 +1952,10 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
   }
   R.store_state(a.x, a.v, a.kb, a.d1);
   if (a.ck_x) R.store_state(a.ck_x, a.ck_v, a.ck_kb, a.ck_d1);
+  if constexpr (TW) {
+    R.store_twist(a.th, a.om);
+    if (a.ck_x) R.store_twist(a.ck_th, a.ck_om);
+  }
   bool bad = false;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
@@ -1609,13 +1971,14 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
 // GT: the projection iterates of a substep go to a rod-private block of
 // global scratch (L2-resident) instead of LDS -- for teams whose iterates do
 // not fit in LDS, and always with self-contact, whose buffers fill the LDS.
-template <typename T, int C, int W, bool SC, bool GT>
+template <typename T, int C, int W, bool SC, bool GT, bool TW>
 __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
   static_assert(GT || !SC, "self-contact keeps the iterates in global scratch");
+  static_assert(!(SC && TW), "no kernels for twist with self-contact");
   extern __shared__ __align__(16) unsigned char smem[];
   Team<T, W> X;
   X.init(reinterpret_cast<T*>(smem));
-  Rod<T, C, W, SC> R;
+  Rod<T, C, W, SC, TW> R;
   R.load_static(a, X);
   T* lds_tape;
   if constexpr (GT) {
@@ -1632,7 +1995,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
     R.sc_setup(a);
   }
   V3<T> lx[C], lv[C], ld1[C], uacc[C];
-  T lk0[C], lk1[C];
+  T lk0[C], lk1[C], lth[C], lom[C];
   double accb[C], accs[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
@@ -1643,13 +2006,15 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
     lk0[c] = R.ivalid(c) ? a.lkb[2 * row] : T(0);
     lk1[c] = R.ivalid(c) ? a.lkb[2 * row + 1] : T(0);
     ld1[c] = R.evalid(c) ? get3(a.ld1, 3 * row) : zero3<T>();
+    lth[c] = (TW && R.evalid(c)) ? a.lth[row] : T(0);
+    lom[c] = (TW && R.evalid(c)) ? a.lom[row] : T(0);
     accb[c] = 0.0;
     accs[c] = 0.0;
     uacc[c] = zero3<T>();
   }
   const T* tape_rod = a.tape + a.tape_off[R.rod];
   Rec<T, C> rec;
-  T pf[NFIELD * C];
+  T pf[Rod<T, C, W, SC, TW>::NFIELD * C];
   R.fetch_tape(tape_rod + (int64_t)(a.n_steps * a.n_sub - 1) * a.tape_stride, pf);
   for (int s = a.n_steps - 1; s >= 0; --s) {
     const int act = (a.step_off + s) / a.spa;
@@ -1660,7 +2025,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
       const int nxt = s * a.n_sub + k - 1;   // the substep processed next
       if (nxt >= 0) R.fetch_tape(tape_rod + (int64_t)nxt * a.tape_stride, pf);
       R.template substep<true>(a, X, ug, &rec, lds_tape);
-      R.substep_vjp(a, X, rec, lds_tape, lx, lv, lk0, lk1, ld1, accb, accs, uacc);
+      R.substep_vjp(a, X, rec, lds_tape, lx, lv, lk0, lk1, ld1, accb, accs, uacc, lth, lom);
     }
     // grasp-velocity gradient of this step's action
 #pragma unroll
@@ -1683,6 +2048,10 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
       a.lkb[2 * row] = lk0[c];
       a.lkb[2 * row + 1] = lk1[c];
       put3(a.ld1, 3 * row, ld1[c]);
+      if constexpr (TW) {
+        a.lth[row] = lth[c];
+        a.lom[row] = lom[c];
+      }
       a.acc_b[row] += accb[c];
       a.acc_s[row] += accs[c];
     }
@@ -1788,6 +2157,7 @@ __global__ void k_fill(T* p, int64_t n, T val) {
   if (i < n) p[i] = val;
 }
 
+#if RODS_TU != 1
 __global__ void k_selftest_exchange(int* out) {
   int l = threadIdx.x;
   int nx = dpp_from_next_i(l + 1) - 1;
@@ -1795,6 +2165,7 @@ __global__ void k_selftest_exchange(int* out) {
   out[l] = nx;
   out[64 + l] = pv;
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // host-side launchers
@@ -1803,12 +2174,12 @@ __global__ void k_selftest_exchange(int* out) {
 template <typename T, int C, int W, bool SC>
 static size_t lds_bytes(int which, bool gt, int n_iters) {
   size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
-  if constexpr (SC) return xb + Rod<T, C, W, SC>::sc_bytes();
+  if constexpr (SC) return xb + Rod<T, C, W, SC, false>::sc_bytes();
   if (which == 2 && !gt) return xb + (size_t)n_iters * C * PROJ_TAPE * 64 * W * sizeof(T);
   return xb;
 }
 
-template <typename T, int C, int W, bool SC>
+template <typename T, int C, int W, bool SC, bool TW = false>
 static hipError_t launch_shape(int which, bool gt, const RodArgs<T>& a, int n_blocks,
                                hipStream_t st) {
   size_t lds = lds_bytes<T, C, W, SC>(which, gt, a.n_iters);
@@ -1817,18 +2188,37 @@ static hipError_t launch_shape(int which, bool gt, const RodArgs<T>& a, int n_bl
     hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, a);
   };
   if (which == 0) {
-    go(k_forward<T, C, W, false, SC>);
+    go(k_forward<T, C, W, false, SC, TW>);
   } else if (which == 1) {
-    go(k_forward<T, C, W, true, SC>);
+    go(k_forward<T, C, W, true, SC, TW>);
   } else if constexpr (SC) {
-    go(k_adjoint<T, C, W, true, true>);
+    go(k_adjoint<T, C, W, true, true, false>);
   } else {
-    if (gt) go(k_adjoint<T, C, W, false, true>);
-    else go(k_adjoint<T, C, W, false, false>);
+    if (gt) go(k_adjoint<T, C, W, false, true, TW>);
+    else go(k_adjoint<T, C, W, false, false, TW>);
   }
   return hipGetLastError();
 }
 
+#if RODS_TU == 1
+// Rods with the twist degree of freedom: two vertices per lane, no
+// self-contact (this translation unit instantiates only these kernels).
+template <typename T>
+hipError_t launch_rods_twist(int which, int C, int W, bool GT, const RodArgs<T>& a,
+                             int n_blocks, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  if (C != 2) return hipErrorInvalidValue;
+  if (W == 1) return launch_shape<T, 2, 1, false, true>(which, GT, a, n_blocks, st);
+  if (W == 2) return launch_shape<T, 2, 2, false, true>(which, GT, a, n_blocks, st);
+  if (W == 4) return launch_shape<T, 2, 4, false, true>(which, GT, a, n_blocks, st);
+  if (W == 8) return launch_shape<T, 2, 8, false, true>(which, GT, a, n_blocks, st);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_rods_twist<float>(int, int, int, bool, const RodArgs<float>&, int,
+                                             hipStream_t);
+template hipError_t launch_rods_twist<double>(int, int, int, bool, const RodArgs<double>&, int,
+                                              hipStream_t);
+#else
 template <typename T>
 hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<T>& a,
                        int n_blocks, hipStream_t st) {
@@ -1931,5 +2321,6 @@ hipError_t launch_selftest_exchange(int* out, hipStream_t st) {
 RODS_INST(float)
 RODS_INST(double)
 template hipError_t launch_fill<int32_t>(int32_t*, int64_t, int32_t, hipStream_t);
+#endif
 
 }  // namespace rods

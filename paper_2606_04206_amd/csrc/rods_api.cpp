@@ -20,13 +20,18 @@ using rods::RodArgs;
 
 namespace {
 
-constexpr int NF = 11;   // values per vertex of a full state (x 3, v 3, kappa_bar 2, d1 3)
+// values per vertex of a checkpointed state: x 3, v 3, kappa_bar 2, d1 3,
+// theta, theta_dot (the last two only used by twisting rods)
+constexpr int NF = 13;
+// values per vertex slot of the backward tape
+static int tape_fields(bool tw) { return tw ? 13 : 11; }
 
 struct Bin {
   int C, W;       // vertices per lane, waves per rod
   int n, off;     // rods bin_rods[off .. off+n)
   bool sc;        // rods with self-contact
   bool gt;        // the adjoint keeps projection iterates in global scratch
+  bool tw;        // rods with the twist degree of freedom
 };
 
 // self-contact kernels exist for these shapes (FP32)
@@ -35,12 +40,13 @@ static bool sc_shape_ok(int C, int W) {
 }
 
 // legal launch shapes for a rod of n vertices, smallest team first
-static std::vector<std::pair<int, int>> shapes_for(int n, int prec, bool sc = false) {
+static std::vector<std::pair<int, int>> shapes_for(int n, int prec, bool sc = false,
+                                                   bool tw = false) {
   std::vector<std::pair<int, int>> out;
   const int Cs[2] = {2, 4};
   const int Ws[4] = {1, 2, 4, 8};
   for (int C : Cs) {
-    if (prec == 8 && C != 2) continue;
+    if ((prec == 8 || tw) && C != 2) continue;
     for (int W : Ws) {
       if (sc && !sc_shape_ok(C, W)) continue;
       if (64 * W * C >= n) {
@@ -78,6 +84,10 @@ struct Impl : HandleBase {
     *prim_r = nullptr;
   T *x = nullptr, *v = nullptr, *kb = nullptr, *d1 = nullptr;
   T *sx = nullptr, *sv = nullptr, *skb = nullptr, *sd1 = nullptr;
+  // twist degree of freedom: modulus per rod, inverse edge inertia, angle
+  // and rate (state, scratch copy, adjoints)
+  T *Gt = nullptr, *jt = nullptr, *th = nullptr, *om = nullptr, *sth = nullptr, *som = nullptr,
+    *lth = nullptr, *lom = nullptr;
   T* ck = nullptr;          // [n_ck][V*NF]
   T* acts = nullptr;        // recorded actions [n_act_max][R][G][3]
   T* du_scratch = nullptr;  // dL/du when the caller does not want it
@@ -214,6 +224,8 @@ struct Impl : HandleBase {
   T* ck_v(int k) const { return ck_x(k) + (size_t)V * 3; }
   T* ck_kb(int k) const { return ck_x(k) + (size_t)V * 6; }
   T* ck_d1(int k) const { return ck_x(k) + (size_t)V * 8; }
+  T* ck_th(int k) const { return ck_x(k) + (size_t)V * 11; }
+  T* ck_om(int k) const { return ck_x(k) + (size_t)V * 12; }
 
   int create(const RodsDesc* dd) {
     d = *dd;
@@ -243,7 +255,7 @@ struct Impl : HandleBase {
       }
     }
     // ---- per-rod parameters
-    std::vector<T> b_h(R), s_h(R), rc_h(R), mu_h(R), e_h(R), K_h(R);
+    std::vector<T> b_h(R), s_h(R), rc_h(R), mu_h(R), e_h(R), K_h(R), G_h(R);
     std::vector<int32_t> fl_h(R);
     for (int r = 0; r < R; ++r) {
       const double* p = d.rod_params + (size_t)r * ROD_NPARAM;
@@ -254,7 +266,13 @@ struct Impl : HandleBase {
       rc_h[r] = (T)p[ROD_P_RC];
       mu_h[r] = (T)p[ROD_P_MU];
       e_h[r] = (T)p[ROD_P_REST];
+      G_h[r] = (T)p[ROD_P_G];
     }
+    // ---- inverse twist inertia per edge row (twisting rods only)
+    std::vector<T> jt_h(V, T(0));
+    for (int r = 0; r < R; ++r)
+      if (fl_h[r] & ROD_FLAG_TWIST)
+        for (int i = voff_h[r]; i < voff_h[r + 1] - 1; ++i) jt_h[i] = (T)d.twist_inv_inertia[i];
     // ---- primitives
     std::vector<int32_t> pt_h(P), po_h(R + 1, 0);
     std::vector<T> pa_h(3 * (size_t)P), pb_h(3 * (size_t)P), pr_h(P);
@@ -275,13 +293,14 @@ struct Impl : HandleBase {
         lds_max = (size_t)attr;
     }
     std::vector<std::vector<int>> members;
-    std::vector<std::tuple<int, int, bool>> keys;
+    std::vector<std::tuple<int, int, bool, bool>> keys;
     for (int r = 0; r < R; ++r) {
       const bool sc = (fl_h[r] & ROD_FLAG_SELF) != 0;
+      const bool tw = (fl_h[r] & ROD_FLAG_TWIST) != 0;
       if (sc && prec != 4) return ROD_EDTYPE;
-      auto sh = shapes_for(voff_h[r + 1] - voff_h[r], prec, sc);
+      auto sh = shapes_for(voff_h[r + 1] - voff_h[r], prec, sc, tw);
       if (sh.empty()) return ROD_EINVAL;
-      auto key = std::make_tuple(sh.front().first, sh.front().second, sc);
+      auto key = std::make_tuple(sh.front().first, sh.front().second, sc, tw);
       size_t k = 0;
       while (k < keys.size() && keys[k] != key) ++k;
       if (k == keys.size()) {
@@ -296,7 +315,7 @@ struct Impl : HandleBase {
         return (voff_h[a + 1] - voff_h[a]) > (voff_h[b2 + 1] - voff_h[b2]);
       });
       Bin bn{std::get<0>(keys[k]), std::get<1>(keys[k]), (int)m.size(), (int)bin_rods_h.size(),
-             std::get<2>(keys[k]), false};
+             std::get<2>(keys[k]), false, std::get<3>(keys[k])};
       bn.gt = global_tape(bn.C, bn.W, bn.sc);
       if (rods::kernel_lds_bytes<T>(2, bn.C, bn.W, bn.sc, bn.gt, d.n_iters) > lds_max)
         return ROD_EINVAL;
@@ -320,6 +339,7 @@ struct Impl : HandleBase {
         (e = upload(b, b_h)) || (e = upload(sigma, s_h)) || (e = upload(rc, rc_h)) ||
         (e = upload(mu, mu_h)) || (e = upload(restit, e_h)) || (e = upload(K, K_h)) ||
         (e = upload(w, w_h)) || (e = upload(rest, rest_h)) || (e = upload(radius, rad_h)) ||
+        (e = upload(Gt, G_h)) || (e = upload(jt, jt_h)) ||
         (e = upload(prim_a, pa_h)) || (e = upload(prim_b, pb_h)) || (e = upload(prim_r, pr_h)) ||
         (e = upload(bin_rods, bin_rods_h)) || (e = upload(tape_off, toff_h)) ||
         (e = upload(sc_off, soff_h)) || (e = alloc(sc_tape, (size_t)sc_cap)))
@@ -330,6 +350,9 @@ struct Impl : HandleBase {
         (e = alloc(skb, 2 * (size_t)V)) || (e = alloc(sd1, 3 * (size_t)V)) ||
         (e = alloc(lx, 3 * (size_t)V)) || (e = alloc(lv, 3 * (size_t)V)) ||
         (e = alloc(lkb, 2 * (size_t)V)) || (e = alloc(ld1, 3 * (size_t)V)) ||
+        (e = alloc(th, (size_t)V)) || (e = alloc(om, (size_t)V)) ||
+        (e = alloc(sth, (size_t)V)) || (e = alloc(som, (size_t)V)) ||
+        (e = alloc(lth, (size_t)V)) || (e = alloc(lom, (size_t)V)) ||
         (e = alloc(acc_b, (size_t)V)) || (e = alloc(acc_s, (size_t)V)) ||
         (e = alloc(loss_part, (size_t)R)) || (e = alloc(status, (size_t)R)) ||
         (e = alloc(ck, (size_t)n_ck * V * NF)) ||
@@ -342,6 +365,9 @@ struct Impl : HandleBase {
     HIPCHK(hipMemset(v, 0, 3 * sizeof(T) * V));
     HIPCHK(hipMemset(kb, 0, 2 * sizeof(T) * V));
     HIPCHK(hipMemset(d1, 0, 3 * sizeof(T) * V));
+    HIPCHK(hipMemset(th, 0, sizeof(T) * V));
+    HIPCHK(hipMemset(om, 0, sizeof(T) * V));
+    HIPCHK(hipMemset(ck, 0, sizeof(T) * (size_t)n_ck * V * NF));
     HIPCHK(hipMemset(status, 0, sizeof(int32_t) * R));
     HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking));
@@ -384,7 +410,7 @@ struct Impl : HandleBase {
       for (int i = 0; i < bn.n; ++i) {
         int r = bin_rods_h[bn.off + i];
         toff_h[r] = off;
-        off += (int64_t)NF * bn.C * 64 * bn.W;
+        off += (int64_t)tape_fields(bn.tw) * bn.C * 64 * bn.W;
         if (bn.gt) {
           soff_h[r] = soff;
           soff += scratch_per_rod(bn.C, bn.W);
@@ -412,6 +438,7 @@ struct Impl : HandleBase {
     a.acc_b = acc_b; a.acc_s = acc_s;
     a.sc_tape = sc_tape; a.sc_off = sc_off;
     a.status = status;
+    a.Gt = Gt; a.jt = jt; a.th = th; a.om = om; a.lth = lth; a.lom = lom;
     a.h = (T)(d.dt / d.n_sub);
     a.gx = (T)d.gravity[0]; a.gy = (T)d.gravity[1]; a.gz = (T)d.gravity[2];
     a.eps_s = (T)d.eps_s; a.f_thresh = (T)d.f_thresh; a.self_margin = (T)d.self_margin;
@@ -432,11 +459,17 @@ struct Impl : HandleBase {
     return e;
   }
 
+  static hipError_t launch_bin(int which, const Bin& bn, int C, int W, bool gt,
+                               const RodArgs<T>& a, int n, hipStream_t st) {
+    if (bn.tw) return rods::launch_rods_twist<T>(which, C, W, gt, a, n, st);
+    return rods::launch_rods<T>(which, C, W, bn.sc, gt, a, n, st);
+  }
+
   int launch_all_(int which, RodArgs<T> a, hipStream_t st) {
     if (!plain) {
       for (const Bin& bn : bins) {
         a.rods = bin_rods + bn.off;
-        HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, bn.sc, bn.gt, a, bn.n, st));
+        HIPCHK(launch_bin(which, bn, bn.C, bn.W, bn.gt, a, bn.n, st));
       }
       return ROD_OK;
     }
@@ -454,7 +487,7 @@ struct Impl : HandleBase {
           b1.step_off = step_off + s;
           if (tape0) b1.tape = tape0 + (int64_t)s * d.n_sub * tape_stride;
           b1.ck_x = (s == n_steps - 1) ? a.ck_x : nullptr;
-          HIPCHK(rods::launch_rods<T>(which, bn.C, bn.W, bn.sc, bn.gt, b1, 1, st));
+          HIPCHK(launch_bin(which, bn, bn.C, bn.W, bn.gt, b1, 1, st));
         }
       }
     }
@@ -468,7 +501,18 @@ struct Impl : HandleBase {
     else HIPCHK(rods::launch_fill<T>(kb, 2 * (int64_t)V, T(0), st));
     if (d1_) HIPCHK(hipMemcpyAsync(d1, d1_, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
     else HIPCHK(rods::launch_init_frames<T>(voff, R, x, d1, st));
+    HIPCHK(rods::launch_fill<T>(th, V, T(0), st));
+    HIPCHK(rods::launch_fill<T>(om, V, T(0), st));
     HIPCHK(rods::launch_fill<int32_t>(status, R, 0, st));
+    recorded = false;
+    return ROD_OK;
+  }
+
+  int set_twist(const T* th_, const T* om_, hipStream_t st) {
+    if (th_) HIPCHK(hipMemcpyAsync(th, th_, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(rods::launch_fill<T>(th, V, T(0), st));
+    if (om_) HIPCHK(hipMemcpyAsync(om, om_, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(rods::launch_fill<T>(om, V, T(0), st));
     recorded = false;
     return ROD_OK;
   }
@@ -492,13 +536,15 @@ struct Impl : HandleBase {
       HIPCHK(hipMemcpyAsync(ck_v(0), v, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(ck_kb(0), kb, sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(ck_d1(0), d1, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(ck_th(0), th, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(ck_om(0), om, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
       for (int seg = 0; seg < nseg; ++seg) {
         a.step_off = seg * Kc;
         a.n_steps = std::min(Kc, n_steps - seg * Kc);
         int which = 0;
         if (seg + 1 < nseg) {
           a.ck_x = ck_x(seg + 1); a.ck_v = ck_v(seg + 1); a.ck_kb = ck_kb(seg + 1);
-          a.ck_d1 = ck_d1(seg + 1);
+          a.ck_d1 = ck_d1(seg + 1); a.ck_th = ck_th(seg + 1); a.ck_om = ck_om(seg + 1);
         } else {
           a.ck_x = a.ck_v = a.ck_kb = a.ck_d1 = nullptr;
           which = 1;   // the last segment also writes its substep tape
@@ -544,6 +590,8 @@ struct Impl : HandleBase {
     else HIPCHK(rods::launch_fill<T>(lv, 3 * (int64_t)V, T(0), st));
     HIPCHK(rods::launch_fill<T>(lkb, 2 * (int64_t)V, T(0), st));
     HIPCHK(rods::launch_fill<T>(ld1, 3 * (int64_t)V, T(0), st));
+    HIPCHK(rods::launch_fill<T>(lth, V, T(0), st));
+    HIPCHK(rods::launch_fill<T>(lom, V, T(0), st));
     HIPCHK(rods::launch_fill<T>(dU, (int64_t)n_act * R * G * 3, T(0), st));
     HIPCHK(rods::launch_fill<double>(acc_b, V, 0.0, st));
     HIPCHK(rods::launch_fill<double>(acc_s, V, 0.0, st));
@@ -555,8 +603,10 @@ struct Impl : HandleBase {
       HIPCHK(hipMemcpyAsync(sv, ck_v(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, rs));
       HIPCHK(hipMemcpyAsync(skb, ck_kb(seg), sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, rs));
       HIPCHK(hipMemcpyAsync(sd1, ck_d1(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, rs));
+      HIPCHK(hipMemcpyAsync(sth, ck_th(seg), sizeof(T) * V, hipMemcpyDeviceToDevice, rs));
+      HIPCHK(hipMemcpyAsync(som, ck_om(seg), sizeof(T) * V, hipMemcpyDeviceToDevice, rs));
       RodArgs<T> a = args(rs);
-      a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;
+      a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1; a.th = sth; a.om = som;
       a.u = acts;
       a.step_off = s0;
       a.n_steps = ns;
@@ -566,7 +616,7 @@ struct Impl : HandleBase {
     auto adjoint = [&](int seg, T* buf) -> int {
       const int s0 = seg * Kc, ns = std::min(Kc, n - s0);
       RodArgs<T> a = args(st);
-      a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;
+      a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1; a.th = sth; a.om = som;
       a.u = acts;
       a.step_off = s0;
       a.n_steps = ns;
@@ -616,6 +666,8 @@ struct Impl : HandleBase {
     HIPCHK(hipMemcpyAsync(sv, v, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(skb, kb, sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(sd1, d1, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(sth, th, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(som, om, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
     std::vector<T> zeros((size_t)std::max(1, R * G * 3), T(0));
     T* u0 = du_scratch;
     HIPCHK(hipMemcpyAsync(u0, zeros.data(), sizeof(T) * zeros.size(), hipMemcpyHostToDevice, st));
@@ -634,7 +686,7 @@ struct Impl : HandleBase {
       const int team0 = 64 * bn.C * bn.W;   // smallest legal team of the bin
       for (int C : Cs)
         for (int W : Ws)
-          if (64 * W * C >= nmax && 64 * W * C <= 2 * team0 && !(prec == 8 && C != 2) &&
+          if (64 * W * C >= nmax && 64 * W * C <= 2 * team0 && !((prec == 8 || bn.tw) && C != 2) &&
               !(C == 4 && W == 8) && (!bn.sc || sc_shape_ok(C, W)) &&
               rods::kernel_lds_bytes<T>(2, C, W, bn.sc, global_tape(C, W, bn.sc), d.n_iters) <=
                   lds_max)
@@ -644,11 +696,12 @@ struct Impl : HandleBase {
       for (auto cw : cand) {
         RodArgs<T> a = args(st);
         a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;   // time on the scratch copy
+        a.th = sth; a.om = som;
         a.u = u0; a.act_stride = 0; a.spa = 1; a.step_off = 0; a.n_steps = n_steps;
         a.rods = bin_rods + bn.off;
-        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, bn.sc, false, a, bn.n, st));   // warm
+        HIPCHK(launch_bin(0, bn, cw.first, cw.second, false, a, bn.n, st));   // warm
         HIPCHK(hipEventRecord(e0, st));
-        HIPCHK(rods::launch_rods<T>(0, cw.first, cw.second, bn.sc, false, a, bn.n, st));
+        HIPCHK(launch_bin(0, bn, cw.first, cw.second, false, a, bn.n, st));
         HIPCHK(hipEventRecord(e1, st));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
@@ -701,8 +754,17 @@ static int validate(const RodsDesc* d) {
       int li = d->grasp_idx[r * d->n_grasp + g];
       if (li < -1 || li >= n) return ROD_EINVAL;
     }
-    int fl = (int)d->rod_params[(size_t)r * ROD_NPARAM + ROD_P_FLAGS];
-    if (fl < 0 || fl > 7) return ROD_EINVAL;
+    const double* p = d->rod_params + (size_t)r * ROD_NPARAM;
+    int fl = (int)p[ROD_P_FLAGS];
+    if (fl < 0 || fl > 15) return ROD_EINVAL;
+    if (fl & ROD_FLAG_TWIST) {
+      // twisting rods: no self-contact kernels, two vertices per lane
+      if ((fl & ROD_FLAG_SELF) || !d->twist_inv_inertia || !(p[ROD_P_G] >= 0) ||
+          shapes_for(n, d->precision, false, true).empty())
+        return ROD_EINVAL;
+      for (int i = d->vert_offsets[r]; i < d->vert_offsets[r + 1] - 1; ++i)
+        if (!(d->twist_inv_inertia[i] >= 0)) return ROD_EINVAL;
+    }
   }
   if (d->prim_offsets) {
     if (d->prim_offsets[0] != 0) return ROD_EINVAL;
@@ -792,6 +854,26 @@ int rods_get_state(RodsHandle* h, void* x, void* v, void* kappa_bar, void* d1,
     if (v) HIPCHK(hipMemcpyAsync(v, I->v, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
     if (kappa_bar) HIPCHK(hipMemcpyAsync(kappa_bar, I->kb, sizeof(T) * 2 * V, hipMemcpyDeviceToDevice, st));
     if (d1) HIPCHK(hipMemcpyAsync(d1, I->d1, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+    return (int)ROD_OK;
+  });
+}
+
+int rods_set_twist(RodsHandle* h, const void* theta, const void* theta_dot, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    return I->set_twist((const T*)theta, (const T*)theta_dot, (hipStream_t)stream);
+  });
+}
+
+int rods_get_twist(RodsHandle* h, void* theta, void* theta_dot, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    hipStream_t st = (hipStream_t)stream;
+    size_t V = I->V;
+    if (theta) HIPCHK(hipMemcpyAsync(theta, I->th, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
+    if (theta_dot) HIPCHK(hipMemcpyAsync(theta_dot, I->om, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
     return (int)ROD_OK;
   });
 }

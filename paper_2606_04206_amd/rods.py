@@ -11,8 +11,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librods.so")
 
-ROD_NPARAM = 7
-FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF = 1, 2, 4
+ROD_NPARAM = 8
+FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF, FLAG_TWIST = 1, 2, 4, 8
 ERRORS = {0: "ok", -1: "ROD_EINVAL", -2: "ROD_ENOMEM", -3: "ROD_EHIP", -4: "ROD_ESTATE",
           -5: "ROD_EDTYPE"}
 
@@ -30,11 +30,12 @@ class RodsDesc(ctypes.Structure):
                 ("dt", c_double), ("gravity", c_double * 3), ("eps_s", c_double),
                 ("f_thresh", c_double), ("self_margin", c_double),
                 ("n_sub", c_int32), ("n_iters", c_int32), ("k_exclude", c_int32),
-                ("steps_per_action", c_int32), ("ckpt_every", c_int32), ("max_steps", c_int32)]
+                ("steps_per_action", c_int32), ("ckpt_every", c_int32), ("max_steps", c_int32),
+                ("twist_inv_inertia", POINTER(c_double))]
 
 
 EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "rods_get_state",
-           "rods_set_params", "rods_curvature", "rods_step", "rods_step_graph", "rods_rollout",
+           "rods_set_twist", "rods_get_twist", "rods_set_params", "rods_curvature", "rods_step", "rods_step_graph", "rods_rollout",
            "rods_backward",
            "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_plain",
            "rods_set_profiling", "rods_profile", "rods_selftest_exchange"]
@@ -61,6 +62,8 @@ def load():
         "rods_strerror": ([c_int32], ctypes.c_char_p),
         "rods_set_state": ([vp, vp, vp, vp, vp, vp], c_int32),
         "rods_get_state": ([vp, vp, vp, vp, vp, vp], c_int32),
+        "rods_set_twist": ([vp, vp, vp, vp], c_int32),
+        "rods_get_twist": ([vp, vp, vp, vp], c_int32),
         "rods_set_params": ([vp, vp, vp, vp], c_int32),
         "rods_curvature": ([vp, vp, vp, vp, vp], c_int32),
         "rods_step": ([vp, vp, vp], c_int32),
@@ -154,6 +157,8 @@ class RodsHandle:
         d.steps_per_action = self.spa
         d.ckpt_every = self.ckpt_every
         d.max_steps = self.max_steps
+        jt = getattr(wl, "twist_inv_inertia", None)
+        d.twist_inv_inertia = arr(jt, c_double) if jt is not None else None
         h = c_void_p()
         _check(lib.rods_create(ctypes.byref(d), ctypes.byref(h)), "rods_create")
         self._h = h
@@ -193,6 +198,18 @@ class RodsHandle:
         _check(self._lib.rods_get_state(self._h, _ptr(x), _ptr(v), _ptr(kb), _ptr(d1),
                                         _stream()), "rods_get_state")
         return x, v, kb, d1
+
+    def set_twist(self, theta=None, theta_dot=None):
+        _require(theta, (self.V,), self.dtype, "theta")
+        _require(theta_dot, (self.V,), self.dtype, "theta_dot")
+        _check(self._lib.rods_set_twist(self._h, _ptr(theta), _ptr(theta_dot), _stream()),
+               "rods_set_twist")
+
+    def get_twist(self):
+        th, om = self.tensor(self.V), self.tensor(self.V)
+        _check(self._lib.rods_get_twist(self._h, _ptr(th), _ptr(om), _stream()),
+               "rods_get_twist")
+        return th, om
 
     def set_params(self, b=None, sigma_y=None):
         _require(b, (self.R,), self.dtype, "b")

@@ -70,6 +70,13 @@ CONFIGS = {
               oracle_rods=(0, 255),
               description="256 rods x 1024 vertices, FP32, helices, self-contact + rigid "
                           "contact + plasticity, 4 grasps, 2000 steps, fwd + adjoint"),
+    6: Config(6, "batch_1024x128_twist_fwd_adjoint_1000steps", 1024, 128,
+              sim=SimParams(n_sub=15, steps=1000, steps_per_action=2, ckpt_every=50),
+              backward=True,
+              oracle_rods=(0, 146, 292, 438, 585, 731, 877, 1023),
+              description="the 1024 x 128 forward + adjoint batch with the twist "
+                          "degree of freedom (twisting modulus 1e3 Pa) and clamped "
+                          "end edges, 1000 steps, checkpoint every 50, MSE loss"),
 }
 
 

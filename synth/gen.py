@@ -18,8 +18,9 @@ import numpy as np
 from .configs import CONFIGS, Config, SimParams
 
 PRIM_PLANE, PRIM_SPHERE, PRIM_CAPSULE = 0, 1, 2
-FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF = 1, 2, 4
-N_ROD_PARAMS = 7   # flags, K (Pa), b (N m^2), sigma_y (1/m), r_c, mu, restitution
+FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF, FLAG_TWIST = 1, 2, 4, 8
+N_ROD_PARAMS = 8   # flags, K (Pa), b (N m^2), sigma_y (1/m), r_c, mu, restitution, G (Pa)
+G_TWIST = 1e3      # twisting modulus of the paper's task table (Pa)
 
 RADIUS = 5e-3      # m
 DENSITY = 1000.0   # kg/m^3
@@ -48,6 +49,7 @@ class Workload:
     target: Optional[np.ndarray] = None   # [V,3] loss target
     x_rest: Optional[np.ndarray] = None   # [V,3] shape whose curvature is the rest curvature
     oracle_rods: tuple = ()
+    twist_inv_inertia: Optional[np.ndarray] = None   # [V] per edge (edge rows); twist rods
 
     @property
     def n_rods(self):
@@ -91,7 +93,9 @@ class Workload:
             prim_offsets=poffs, actions=self.actions[:n_act, rods].copy(),
             target=None if self.target is None else self.target[vidx].copy(),
             x_rest=None if self.x_rest is None else self.x_rest[vidx].copy(),
-            oracle_rods=tuple(range(len(rods))))
+            oracle_rods=tuple(range(len(rods))),
+            twist_inv_inertia=None if self.twist_inv_inertia is None
+            else self.twist_inv_inertia[vidx].copy())
 
 
 # ----------------------------------------------------------------------------
@@ -156,6 +160,17 @@ def lumped_inv_mass(rest_edges, radius):
     return 1.0 / (DENSITY * area * half)
 
 
+def edge_inv_inertia(rest_edges, radius):
+    """Inverse polar moment of inertia of each edge about its axis, taken as
+    a solid cylinder: I = m r^2 / 2, m = rho A |e_bar|, r the mean of the
+    edge's vertex radii.  Returns [n] with the last (vertex-only) row 0."""
+    rbar = 0.5 * (radius[:-1] + radius[1:])
+    m = DENSITY * np.pi * rbar ** 2 * rest_edges
+    out = np.zeros(len(rest_edges) + 1)
+    out[:-1] = 2.0 / (m * rbar ** 2)
+    return out
+
+
 def _unit(rng):
     v = rng.normal(size=3)
     return v / np.linalg.norm(v)
@@ -212,14 +227,16 @@ def make_workload(cid: int, steps: Optional[int] = None,
     spa = sim.steps_per_action
     n_act = -(-sim.steps // spa)
     action_dt = spa * sim.dt
-    # configuration 3 is configuration 2's batch with a target: same rod stream
-    rng = np.random.default_rng([SEED0, 2 if cid == 3 else cid])
-    rng_target = np.random.default_rng([SEED0, cid, 1])
+    # configurations 3 and 6 are configuration 2's batch with a target: same
+    # rod stream (6 adds twist and holds both vertices of each end edge)
+    rng = np.random.default_rng([SEED0, 2 if cid in (3, 6) else cid])
+    rng_target = np.random.default_rng([SEED0, 3 if cid == 6 else cid, 1])
 
     R = cfg.n_rods
     xs, rests, invm, rads, gidx, params, acts, tgts, xrests = [], [], [], [], [], [], [], [], []
     ptype, pa, pb, pr, pcount = [], [], [], [], []
-    G = {1: 0, 2: 2, 3: 2, 4: 2, 5: 4}[cid]
+    jts = []
+    G = {1: 0, 2: 2, 3: 2, 4: 2, 5: 4, 6: 4}[cid]
 
     for r in range(R):
         # ---------------- material
@@ -230,12 +247,13 @@ def make_workload(cid: int, steps: Optional[int] = None,
             b = E * np.pi * RADIUS ** 4 / 4.0     # paper's B_i = (E A/4) r^2, A = pi r^2
             sig, mu = 0.0, 0.0
         else:
-            flags = FLAG_INEXT | FLAG_PLASTIC | (FLAG_SELF if cid == 5 else 0)
+            flags = FLAG_INEXT | FLAG_PLASTIC | (FLAG_SELF if cid == 5 else 0) \
+                | (FLAG_TWIST if cid == 6 else 0)
             K = 0.0
             b = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
             sig = rng.uniform(2.0, 10.0)
             mu = rng.uniform(0.2, 0.8) if cid in (4, 5) else 0.0
-        params.append([flags, K, b, sig, 1.0, mu, 0.0])
+        params.append([flags, K, b, sig, 1.0, mu, 0.0, G_TWIST if cid == 6 else 0.0])
 
         # ---------------- geometry
         if cid == 1:
@@ -245,13 +263,13 @@ def make_workload(cid: int, steps: Optional[int] = None,
             x = x_clean.copy()
             x[1:] += rng.normal(0.0, 1e-3, size=(n - 1, 3))
             xr = None
-        elif cid in (2, 3, 4):
+        elif cid in (2, 3, 4, 6):
             n = cfg.n_vert if cfg.n_vert else int(rng.integers(cfg.n_min, cfg.n_max + 1))
             edge = EDGE_LEN
             x_clean = arc_polyline(n, edge, 0.6)
             x_clean = _rot_z(x_clean, rng.uniform(0.0, 2.0 * np.pi))
             x_clean[:, 2] += (start_height if start_height is not None
-                              else (0.5 if cid in (2, 3) else 0.3))
+                              else (0.5 if cid in (2, 3, 6) else 0.3))
             x = x_clean.copy()
             xr = None
         else:
@@ -273,6 +291,7 @@ def make_workload(cid: int, steps: Optional[int] = None,
         invm.append(w)
         rads.append(np.full(n, RADIUS))
         xrests.append(xr if xr is not None else x_clean)
+        jts.append(edge_inv_inertia(rest_e, rads[-1]) if cid == 6 else np.zeros(n))
 
         # ---------------- grasps
         if G:
@@ -281,8 +300,16 @@ def make_workload(cid: int, steps: Optional[int] = None,
             else:
                 gv = [0, n - 1]
             scale = 1.0 if cid != 4 else min(1.0, (n - 1) * edge / 1.27)
-            draws = [_grasp_draw(rng, scale) for _ in gv]
-            acts.append(_grasp_actions(draws, n_act, action_dt))
+            if cid == 6:
+                # both vertices of each end edge, moved together: the end
+                # edges translate and their twist is held
+                draws = [_grasp_draw(rng, scale) for _ in range(2)]
+                a2 = _grasp_actions(draws, n_act, action_dt)
+                acts.append(a2[:, [0, 0, 1, 1]])
+                gv = [0, 1, n - 2, n - 1]
+            else:
+                draws = [_grasp_draw(rng, scale) for _ in gv]
+                acts.append(_grasp_actions(draws, n_act, action_dt))
             gidx.append(gv)
         else:
             acts.append(np.zeros((n_act, 0, 3)))
@@ -342,4 +369,5 @@ def make_workload(cid: int, steps: Optional[int] = None,
         prim_offsets=poffs, actions=actions,
         target=np.concatenate(tgts) if tgts else None,
         x_rest=np.concatenate(xrests) if cid == 5 else None,
-        oracle_rods=oracle_rods)
+        oracle_rods=oracle_rods,
+        twist_inv_inertia=np.concatenate(jts) if cid == 6 else None)
