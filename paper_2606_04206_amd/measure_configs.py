@@ -2,11 +2,13 @@
 launch-shape autotuner and the HIP-graph step path buy.  Prints one JSON
 line per measurement.
 
-    python -m paper_2606_04206_amd.measure_configs [--configs 2 4 5]
+    python -m paper_2606_04206_amd.measure_configs [--configs 2 4 5 6]
 
 Every figure is rod-vertex-steps/s over a timed loop bracketed by device
 synchronisations, after one untimed warm-up pass; inputs are resident on the
-GPU before timing starts.
+GPU before timing starts.  For the forward + adjoint runs the adjoint
+kernel's average launch time (HIP events around each launch batch) gives
+its achieved FP32 rate from the algorithmic flop count of workmodel.
 """
 import argparse
 import json
@@ -42,16 +44,17 @@ def _emit(**kw):
 
 def main():
     p = argparse.ArgumentParser()
-    p.add_argument("--configs", type=int, nargs="*", default=[2, 4, 5])
+    p.add_argument("--configs", type=int, nargs="*", default=[2, 4, 5, 6])
     a = p.parse_args()
     import torch
     from synth import make_workload
     from paper_2606_04206_amd import RodsHandle
+    from paper_2606_04206_amd.workmodel import adjoint_flops_per_vertex_substep
     f32 = torch.float32
 
     for cid in a.configs:
         wl = make_workload(cid)
-        n = {2: 500, 4: 100, 5: 100}.get(cid, 100)
+        n = {2: 500, 4: 100, 5: 100, 6: 1000}.get(cid, 100)
         K = wl.sim.ckpt_every
         x0, v0 = _dev(wl.x0, f32), _dev(wl.v0, f32)
         h = RodsHandle(wl, precision=4, max_steps=max(n, K), ckpt_every=K)
@@ -103,10 +106,25 @@ def main():
                 h.rollout(n, U, record=True, x_final=xT)
                 _, g = h.loss_mse(xT, tgt)
                 h.backward(g, n_steps=n)
+            fwd_bwd()
+            torch.cuda.synchronize()
+            h.set_profiling(True)
+            h.profile()
             t_fb = _timed(fwd_bwd)
+            prof = h.profile()
+            h.set_profiling(False)
+            adj_ms, adj_n, _ = prof["adjoint"]
+            adj_avg = adj_ms / max(adj_n, 1)          # both passes of _timed
+            twist = wl.twist_inv_inertia is not None
+            units = wl.n_vert * K * wl.sim.n_sub
+            tflops = adjoint_flops_per_vertex_substep(wl.sim.n_iters, twist) * units \
+                / (adj_avg * 1e-3) / 1e12
             _emit(config=cid, measure="forward + checkpointed adjoint", steps=n,
                   ckpt_every=K, value=wl.n_vert * n / t_fb, unit="rod-vertex-steps/s",
-                  ms=1e3 * t_fb, status_flagged=int((h.status() != 0).sum()))
+                  ms=1e3 * t_fb, status_flagged=int((h.status() != 0).sum()),
+                  adjoint_avg_launch_ms=adj_avg, adjoint_tflops=tflops,
+                  adjoint_frac_of_157=tflops / 157.3, adjoint_frac_of_78=tflops / 78.6,
+                  kernel_ms={k: v[0] / 2 for k, v in prof.items()})
         del h
         torch.cuda.empty_cache()
 

@@ -36,6 +36,27 @@ Adjoint substep (kernel k_adjoint = the forward above, replayed, plus):
 The plastic return-map VJP (about 200 flops) runs only on yielding vertices
 and is left out, so the adjoint figure is a lower bound.
 
+Rods with the twist degree of freedom add (sine and cosine count 1 each,
+atan2 1):
+  forward:
+    material director m1 = cos(theta) d1 + sin(theta) t x d1     20
+    twist stencil (curvature binormal 20, m2 18, averaged
+      directors 12, c1 c2 14, reference twist: transport 43,
+      sine and cosine parts 19, atan2 1; strain 3; torques 30;
+      edge-gradient terms 15)                                   175
+    torque scatter 2, rate update 3, angle update 2               7
+    material director at x' for the return map                  20
+    total                                                       222
+  adjoint (beyond the replayed forward):
+    material director and its VJP in the return-map VJP         79
+    angle and rate updates                                        4
+    material director at x and its VJP                           79
+    twist stencil VJP (re-evaluation 130, reverse 357)          487
+    accumulation of the adjoints                                 25
+    total                                                       674
+  (twisting adjoint kernel: 916 + 222 + 674 + 59 N_C, 2402 at N_C = 10)
+and 8 B per vertex of state (theta and its rate).
+
 HBM bytes (FP32): a state is 44 B per vertex (x 12, v 12, kappa_bar 8,
 d1 12).  The adjoint kernel reads one stored substep-start state per vertex
 and substep (44 B); the tape-writing forward writes it (44 B).
@@ -43,16 +64,18 @@ and substep (44 B); the tape-writing forward writes it (44 B).
 
 FWD_BASE, FWD_PER_ITER = 303, 25
 VJP_BASE, VJP_PER_ITER = 613, 34
-STATE_BYTES = 44
+TWIST_FWD, TWIST_VJP = 222, 674
+STATE_BYTES, TWIST_STATE_BYTES = 44, 8
 
 
-def forward_flops_per_vertex_substep(n_iters):
-    return FWD_BASE + FWD_PER_ITER * n_iters
+def forward_flops_per_vertex_substep(n_iters, twist=False):
+    return FWD_BASE + FWD_PER_ITER * n_iters + (TWIST_FWD if twist else 0)
 
 
-def adjoint_flops_per_vertex_substep(n_iters):
-    return forward_flops_per_vertex_substep(n_iters) + VJP_BASE + VJP_PER_ITER * n_iters
+def adjoint_flops_per_vertex_substep(n_iters, twist=False):
+    return (forward_flops_per_vertex_substep(n_iters, twist) + VJP_BASE + VJP_PER_ITER * n_iters
+            + (TWIST_VJP if twist else 0))
 
 
-def adjoint_bytes_per_vertex_substep(precision=4):
-    return STATE_BYTES * precision // 4
+def adjoint_bytes_per_vertex_substep(precision=4, twist=False):
+    return (STATE_BYTES + (TWIST_STATE_BYTES if twist else 0)) * precision // 4

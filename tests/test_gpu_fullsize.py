@@ -7,8 +7,9 @@
   tests/golden/make_c3_golden.py, which calls only the oracle).
 * The same batch in FP32: step 1000 of the full-batch rollout against one
   oracle step from the GPU's own state at step 999 (the per-step bound).
-* The uneven 4096-rod contact batch and the 256 x 1024 self-contact batch:
-  one step at the end of their full horizons, teacher-forced the same way.
+* The uneven 4096-rod contact batch, the 256 x 1024 self-contact batch and
+  the 1024 x 128 batch with the twist degree of freedom: one step at the end
+  of their full horizons, teacher-forced the same way.
 """
 import os
 
@@ -82,10 +83,15 @@ def _last_step_parity(wl, n_before, tol=1e-4, ties=False):
     spa = wl.sim.steps_per_action
     xT = h.tensor(wl.n_vert, 3)
     h.rollout(n_before, to_dev(wl.actions[:h.n_actions(n_before)], dt), x_final=xT)
-    before = [t.double().cpu().numpy() for t in h.get_state()]
+    twist = wl.twist_inv_inertia is not None
+
+    def state():
+        out = [t.double().cpu().numpy() for t in h.get_state()]
+        return out + ([t.double().cpu().numpy() for t in h.get_twist()] if twist else [])
+    before = state()
     u = wl.actions[n_before // spa]
     h.step(to_dev(u, dt))
-    after = [t.double().cpu().numpy() for t in h.get_state()]
+    after = state()
     status = h.status()
     # a non-finite state anywhere, or any flag on a compared rod, fails; a
     # full partner list (bit1: pairs dropped) is tolerated on a few other
@@ -104,6 +110,9 @@ def _last_step_parity(wl, n_before, tol=1e-4, ties=False):
                          for s in (1, 2))
             bound = max(tol, 2 * spread)
         assert rel_err(gpu.x, ref.x) <= bound, r
+        if twist:
+            assert rel_err(gpu.theta, ref.theta) <= tol, r
+            assert np.abs(ref.theta).max() > 0.1, r   # the rod has twisted
 
 
 def test_fp32_full_batch_step_1000_parity():
@@ -116,3 +125,7 @@ def test_fp32_uneven_contact_batch_step_500_parity():
 
 def test_fp32_selfcontact_batch_step_2000_parity():
     _last_step_parity(make_workload(5), 1999, ties=True)
+
+
+def test_fp32_twist_batch_step_1000_parity():
+    _last_step_parity(make_workload(6), 999)
