@@ -191,6 +191,42 @@ int rods_backward(RodsHandle* h, const void* dL_dxT, const void* dL_dvT, void* d
                   void* dL_db, void* dL_dsigma, void* dL_dx0, void* dL_dv0,
                   rods_stream_t stream);
 
+/* Gradient-based trajectory optimisation and system identification
+ * (App. B, Trajectory Optimization Setup and System Identification).
+ * Adam (Kingma and Ba, 2014) whose learning rate falls from lr0 to lr_min on
+ * a cosine schedule over the iteration budget, lr_k = lr_min + (lr0 -
+ * lr_min)(1 + cos(pi k/(iters-1)))/2, with early stopping once `patience`
+ * iterations in a row have not gone below the lowest loss so far. */
+typedef struct {
+  int32_t iters;            /* iteration budget (>= 1) */
+  int32_t patience;         /* early stopping (>= 1) */
+  int32_t what;             /* bit0: the grasp velocities; bit1: log of the bending
+                               stiffness b of each rod (b spans decades; an update then
+                               scales b, with gradient b dL/db) */
+  double lr0, lr_min;       /* schedule of the grasp velocities (m/s per step) */
+  double lr0_b, lr_min_b;   /* schedule of log b */
+  double beta1, beta2, eps; /* Adam's moment decay rates and denominator offset */
+} RodsAdam;
+
+/* Runs the optimisation: each iteration sets the state to (x0, v0,
+ * kappa_bar0, frames by the initial-frame rule, zero twist), records a
+ * rollout of n_steps with grasp_vel, evaluates rods_loss_mse of the final
+ * positions against target [V][3], runs rods_backward, then takes one Adam
+ * step on the selected parameters.  grasp_vel [A][R][G][3] (A as in
+ * rods_rollout) is updated in place; with bit1 the handle's b is updated
+ * (read it with rods_get_params).  losses (host) [iters] receives the loss
+ * of every evaluated iteration and n_done (host) their number.  x0, v0
+ * [V][3] and kappa_bar0 [V][2] (NULL = zeros) are device arrays.
+ * Synchronises the stream once per iteration (the early-stopping test);
+ * allocates nothing.  Leaves the state of the last evaluated rollout. */
+int rods_optimize(RodsHandle* h, const RodsAdam* opt, int32_t n_steps, const void* x0,
+                  const void* v0, const void* kappa_bar0, const void* target, void* grasp_vel,
+                  double* losses, int32_t* n_done, rods_stream_t stream);
+
+/* Copies the per-rod bending stiffness b and yield curvature sigma_y [R]
+ * out (either may be NULL). */
+int rods_get_params(RodsHandle* h, void* b, void* sigma_y, rods_stream_t stream);
+
 /* Mean-squared-distance loss L = (1/R) sum_r (1/N_r) sum_i |x_i - target_i|^2
  * of the positions x [V][3]; writes loss [1] and dL_dx [V][3] (either may be
  * NULL). */

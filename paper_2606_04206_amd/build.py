@@ -19,6 +19,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 # for the kernels of twisting rods, in parallel with the first
 UNITS = [("rod_kernels.hip", [], "rod_kernels.o"),
          ("rod_kernels.hip", ["-DRODS_TU=1"], "rod_kernels_twist.o"),
+         ("rod_optim.hip", [], "rod_optim.o"),
          ("rods_api.cpp", [], "rods_api.o")]
 
 

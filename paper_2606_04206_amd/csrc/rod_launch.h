@@ -34,5 +34,14 @@ hipError_t launch_reduce_params(const int32_t* voff, int R, const double* ab, co
 template <typename T>
 hipError_t launch_fill(T* p, int64_t n, T val, hipStream_t st);
 hipError_t launch_selftest_exchange(int* out, hipStream_t st);
+// optimisation driver (rod_optim.hip): one Adam update of n parameters
+// (scale, nullable, multiplies the gradient), and elementwise log / exp
+template <typename T>
+hipError_t launch_adam(T* p, const T* g, const T* scale, T* m, T* v, int64_t n, double lr,
+                       double b1, double b2, double eps, int t, hipStream_t st);
+template <typename T>
+hipError_t launch_log(const T* a, T* out, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_exp(const T* a, T* out, int64_t n, hipStream_t st);
 
 }  // namespace rods

@@ -91,6 +91,11 @@ struct Impl : HandleBase {
   T* ck = nullptr;          // [n_ck][V*NF]
   T* acts = nullptr;        // recorded actions [n_act_max][R][G][3]
   T* du_scratch = nullptr;  // dL/du when the caller does not want it
+  // optimisation driver: Adam moments of the grasp velocities and of log b,
+  // log b itself, dL/db, the final positions, dL/dx_T and the loss
+  T *opt_mU = nullptr, *opt_vU = nullptr, *opt_mb = nullptr, *opt_vb = nullptr,
+    *opt_logb = nullptr, *opt_db = nullptr, *opt_xT = nullptr, *opt_g = nullptr,
+    *opt_loss = nullptr;
   T* tape = nullptr;
   int64_t tape_stride = 0, tape_cap = 0;
   int64_t* tape_off = nullptr;
@@ -358,6 +363,12 @@ struct Impl : HandleBase {
         (e = alloc(ck, (size_t)n_ck * V * NF)) ||
         (e = alloc(acts, (size_t)n_act_max * R * G * 3)) ||
         (e = alloc(du_scratch, (size_t)n_act_max * R * G * 3)) ||
+        (e = alloc(opt_mU, (size_t)n_act_max * R * G * 3)) ||
+        (e = alloc(opt_vU, (size_t)n_act_max * R * G * 3)) ||
+        (e = alloc(opt_mb, (size_t)R)) || (e = alloc(opt_vb, (size_t)R)) ||
+        (e = alloc(opt_logb, (size_t)R)) || (e = alloc(opt_db, (size_t)R)) ||
+        (e = alloc(opt_xT, 3 * (size_t)V)) || (e = alloc(opt_g, 3 * (size_t)V)) ||
+        (e = alloc(opt_loss, 1)) ||
         (e = alloc(u_step, (size_t)R * G * 3)) ||
         (e = alloc(tape, (size_t)std::min(d.ckpt_every, std::max(1, d.max_steps)) * d.n_sub * (size_t)tape_cap)))
       return e;
@@ -660,6 +671,64 @@ struct Impl : HandleBase {
     return ROD_OK;
   }
 
+  // Adam with a cosine schedule and early stopping over rollout + loss +
+  // adjoint (App. B); the iteration order is: set b = exp(log b), evaluate
+  // the loss and gradients, record the loss, stop on `patience` stalls,
+  // otherwise take the Adam step of iteration k (step count k + 1).
+  int optimize(const RodsAdam* o, int n_steps, const T* x0, const T* v0, const T* kb0,
+               const T* target, T* U, double* losses, int* n_done, hipStream_t st) {
+    if (!o || o->iters < 1 || o->patience < 1 || !(o->what & 3) || n_steps < 1 ||
+        n_steps > d.max_steps || !x0 || !v0 || !target || !U || !losses || !n_done)
+      return ROD_EINVAL;
+    const bool act = (o->what & 1) != 0, stiff = (o->what & 2) != 0;
+    const int spa = d.steps_per_action;
+    const int64_t nU = (int64_t)((n_steps + spa - 1) / spa) * R * G * 3;
+    auto cosine = [&](int k, double lr0, double lr_min) {
+      if (o->iters <= 1) return lr0;
+      return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + std::cos(M_PI * k / (o->iters - 1)));
+    };
+    HIPCHK(rods::launch_fill<T>(opt_mU, nU, T(0), st));
+    HIPCHK(rods::launch_fill<T>(opt_vU, nU, T(0), st));
+    HIPCHK(rods::launch_fill<T>(opt_mb, R, T(0), st));
+    HIPCHK(rods::launch_fill<T>(opt_vb, R, T(0), st));
+    if (stiff) HIPCHK(rods::launch_log<T>(b, opt_logb, R, st));
+    double best = HUGE_VAL;
+    int stall = 0, done = 0;
+    for (int k = 0; k < o->iters; ++k) {
+      if (stiff) HIPCHK(rods::launch_exp<T>(opt_logb, b, R, st));
+      int e = set_state(x0, v0, kb0, nullptr, st);
+      if (!e) e = rollout(n_steps, U, opt_xT, 1, st);
+      if (e) return e;
+      HIPCHK(rods::launch_loss<T>(voff, R, opt_xT, target, loss_part, opt_loss, opt_g, st));
+      e = backward(opt_g, nullptr, du_scratch, stiff ? opt_db : nullptr, nullptr, nullptr, nullptr,
+                   st);
+      if (e) return e;
+      T hl;
+      HIPCHK(hipMemcpyAsync(&hl, opt_loss, sizeof(T), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      losses[k] = (double)hl;
+      done = k + 1;
+      if ((double)hl < best) {
+        best = (double)hl;
+        stall = 0;
+      } else if (++stall >= o->patience) {
+        break;
+      }
+      if (act)
+        HIPCHK(rods::launch_adam<T>(U, du_scratch, nullptr, opt_mU, opt_vU, nU,
+                                    cosine(k, o->lr0, o->lr_min), o->beta1, o->beta2, o->eps,
+                                    k + 1, st));
+      if (stiff)
+        HIPCHK(rods::launch_adam<T>(opt_logb, opt_db, b, opt_mb, opt_vb, R,
+                                    cosine(k, o->lr0_b, o->lr_min_b), o->beta1, o->beta2,
+                                    o->eps, k + 1, st));
+    }
+    if (stiff) HIPCHK(rods::launch_exp<T>(opt_logb, b, R, st));
+    *n_done = done;
+    recorded = false;
+    return ROD_OK;
+  }
+
   int autotune(int n_steps, hipStream_t st) {
     // save state
     HIPCHK(hipMemcpyAsync(sx, x, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
@@ -874,6 +943,31 @@ int rods_get_twist(RodsHandle* h, void* theta, void* theta_dot, rods_stream_t st
     size_t V = I->V;
     if (theta) HIPCHK(hipMemcpyAsync(theta, I->th, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
     if (theta_dot) HIPCHK(hipMemcpyAsync(theta_dot, I->om, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
+    return (int)ROD_OK;
+  });
+}
+
+int rods_optimize(RodsHandle* h, const RodsAdam* opt, int32_t n_steps, const void* x0,
+                  const void* v0, const void* kappa_bar0, const void* target, void* grasp_vel,
+                  double* losses, int32_t* n_done, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    int nd = 0;
+    int e = I->optimize(opt, n_steps, (const T*)x0, (const T*)v0, (const T*)kappa_bar0,
+                        (const T*)target, (T*)grasp_vel, losses, &nd, (hipStream_t)stream);
+    if (n_done) *n_done = nd;
+    return e;
+  });
+}
+
+int rods_get_params(RodsHandle* h, void* b, void* sigma_y, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    hipStream_t st = (hipStream_t)stream;
+    if (b) HIPCHK(hipMemcpyAsync(b, I->b, sizeof(T) * I->R, hipMemcpyDeviceToDevice, st));
+    if (sigma_y) HIPCHK(hipMemcpyAsync(sigma_y, I->sigma, sizeof(T) * I->R, hipMemcpyDeviceToDevice, st));
     return (int)ROD_OK;
   });
 }

@@ -34,8 +34,16 @@ class RodsDesc(ctypes.Structure):
                 ("twist_inv_inertia", POINTER(c_double))]
 
 
+class RodsAdam(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("patience", c_int32), ("what", c_int32),
+                ("lr0", c_double), ("lr_min", c_double), ("lr0_b", c_double),
+                ("lr_min_b", c_double), ("beta1", c_double), ("beta2", c_double),
+                ("eps", c_double)]
+
+
 EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "rods_get_state",
-           "rods_set_twist", "rods_get_twist", "rods_set_params", "rods_curvature", "rods_step", "rods_step_graph", "rods_rollout",
+           "rods_set_twist", "rods_get_twist", "rods_set_params", "rods_get_params",
+           "rods_optimize", "rods_curvature", "rods_step", "rods_step_graph", "rods_rollout",
            "rods_backward",
            "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_plain",
            "rods_set_profiling", "rods_profile", "rods_selftest_exchange"]
@@ -63,6 +71,9 @@ def load():
         "rods_set_state": ([vp, vp, vp, vp, vp, vp], c_int32),
         "rods_get_state": ([vp, vp, vp, vp, vp, vp], c_int32),
         "rods_set_twist": ([vp, vp, vp, vp], c_int32),
+        "rods_get_params": ([vp, vp, vp, vp], c_int32),
+        "rods_optimize": ([vp, POINTER(RodsAdam), c_int32, vp, vp, vp, vp, vp,
+                           POINTER(c_double), POINTER(c_int32), vp], c_int32),
         "rods_get_twist": ([vp, vp, vp, vp], c_int32),
         "rods_set_params": ([vp, vp, vp, vp], c_int32),
         "rods_curvature": ([vp, vp, vp, vp, vp], c_int32),
@@ -216,6 +227,35 @@ class RodsHandle:
         _require(sigma_y, (self.R,), self.dtype, "sigma_y")
         _check(self._lib.rods_set_params(self._h, _ptr(b), _ptr(sigma_y), _stream()),
                "rods_set_params")
+
+    def get_params(self):
+        b, sig = self.tensor(self.R), self.tensor(self.R)
+        _check(self._lib.rods_get_params(self._h, _ptr(b), _ptr(sig), _stream()),
+               "rods_get_params")
+        return b, sig
+
+    def optimize(self, n_steps, x0, v0, target, U, iters, actions=True, stiffness=False,
+                 lr0=1e-3, lr_min=1e-6, lr0_b=1e-3, lr_min_b=1e-6, patience=10,
+                 beta1=0.9, beta2=0.999, eps=1e-8, kappa_bar0=None):
+        """Adam on the grasp velocities U (updated in place) and/or the log
+        bending stiffness (read back with get_params); returns the losses of
+        the evaluated iterations."""
+        V = self.V
+        _require(x0, (V, 3), self.dtype, "x0")
+        _require(v0, (V, 3), self.dtype, "v0")
+        _require(target, (V, 3), self.dtype, "target")
+        _require(kappa_bar0, (V, 2), self.dtype, "kappa_bar0")
+        _require(U, (self.n_actions(n_steps), self.R, self.G, 3), self.dtype, "grasp_vel")
+        o = RodsAdam(iters=iters, patience=patience,
+                     what=(1 if actions else 0) | (2 if stiffness else 0), lr0=lr0,
+                     lr_min=lr_min, lr0_b=lr0_b, lr_min_b=lr_min_b, beta1=beta1, beta2=beta2,
+                     eps=eps)
+        losses = (c_double * iters)()
+        nd = c_int32(0)
+        _check(self._lib.rods_optimize(self._h, ctypes.byref(o), int(n_steps), _ptr(x0), _ptr(v0),
+                                       _ptr(kappa_bar0), _ptr(target), _ptr(U), losses,
+                                       ctypes.byref(nd), _stream()), "rods_optimize")
+        return list(losses[:nd.value])
 
     def curvature(self, x, d1=None):
         _require(x, (self.V, 3), self.dtype, "x")

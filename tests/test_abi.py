@@ -33,16 +33,20 @@ def test_struct_layouts(tmp_path):
     """The ctypes mirrors have the C compiler's sizes and offsets."""
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "rods.h"\n'
-                    'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(RodsDesc), '
-                    'sizeof(RodsPrim), offsetof(RodsDesc, dt), offsetof(RodsDesc, n_sub), '
-                    'offsetof(RodsDesc, max_steps)); return 0;}\n')
+                    'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
+                    'sizeof(RodsDesc), sizeof(RodsPrim), offsetof(RodsDesc, dt), '
+                    'offsetof(RodsDesc, n_sub), offsetof(RodsDesc, max_steps), '
+                    'offsetof(RodsDesc, twist_inv_inertia), sizeof(RodsAdam), '
+                    'offsetof(RodsAdam, lr0), offsetof(RodsAdam, eps)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
                    check=True)
     c = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                         check=True).stdout.split()]
     py = [ctypes.sizeof(R.RodsDesc), ctypes.sizeof(R.RodsPrim), R.RodsDesc.dt.offset,
-          R.RodsDesc.n_sub.offset, R.RodsDesc.max_steps.offset]
+          R.RodsDesc.n_sub.offset, R.RodsDesc.max_steps.offset,
+          R.RodsDesc.twist_inv_inertia.offset, ctypes.sizeof(R.RodsAdam), R.RodsAdam.lr0.offset,
+          R.RodsAdam.eps.offset]
     assert c == py
 
 
