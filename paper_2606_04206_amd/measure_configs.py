@@ -2,7 +2,11 @@
 launch-shape autotuner and the HIP-graph step path buy.  Prints one JSON
 line per measurement.
 
-    python -m paper_2606_04206_amd.measure_configs [--configs 2 4 5 6]
+    python -m paper_2606_04206_amd.measure_configs [--configs 2 3 4 5 6]
+
+Configuration 3 (the benchmark's batch) is measured as the optimisation
+driver: iterations of Adam on the grasp velocities, and on the grasp
+velocities with the log bending stiffness (rods_optimize).
 
 Every figure is rod-vertex-steps/s over a timed loop bracketed by device
 synchronisations, after one untimed warm-up pass; inputs are resident on the
@@ -42,9 +46,41 @@ def _emit(**kw):
     print(json.dumps(kw), flush=True)
 
 
+def _measure_optimize(iters):
+    """rods_optimize on the full 1024 x 128 batch, 1000 steps per iteration."""
+    import torch
+    from synth import make_workload
+    from paper_2606_04206_amd import RodsHandle
+    f32 = torch.float32
+    wl = make_workload(3)
+    n = wl.sim.steps
+    h = RodsHandle(wl, precision=4)
+    x0, v0, tgt = _dev(wl.x0, f32), _dev(wl.v0, f32), _dev(wl.target, f32)
+    h.set_state(x0, v0)
+    h.autotune(n_steps=3)
+    b0 = h.get_params()[0].clone()
+    for what, kw in (("grasp velocities", dict()),
+                     ("grasp velocities + log bending stiffness",
+                      dict(stiffness=True, lr0_b=1e-2, lr_min_b=1e-4))):
+        U = _dev(wl.actions, f32)
+        h.optimize(n, x0, v0, tgt, U, 1, lr0=1e-3, **kw)      # warm-up
+        torch.cuda.synchronize()
+        U = _dev(wl.actions, f32)
+        h.set_params(b=b0)
+        t0 = time.perf_counter()
+        losses = h.optimize(n, x0, v0, tgt, U, iters, lr0=1e-3, lr_min=1e-6, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _emit(config=3, measure="optimisation driver, Adam on " + what, iterations=len(losses),
+              steps_per_iteration=n, ms_per_iteration=1e3 * dt / len(losses),
+              value=wl.n_vert * n * len(losses) / dt, unit="rod-vertex-steps/s",
+              loss_first=losses[0], loss_last=losses[-1])
+
+
 def main():
     p = argparse.ArgumentParser()
-    p.add_argument("--configs", type=int, nargs="*", default=[2, 4, 5, 6])
+    p.add_argument("--configs", type=int, nargs="*", default=[2, 3, 4, 5, 6])
+    p.add_argument("--opt-iters", type=int, default=5)
     a = p.parse_args()
     import torch
     from synth import make_workload
@@ -53,6 +89,9 @@ def main():
     f32 = torch.float32
 
     for cid in a.configs:
+        if cid == 3:
+            _measure_optimize(a.opt_iters)
+            continue
         wl = make_workload(cid)
         n = {2: 500, 4: 100, 5: 100, 6: 1000}.get(cid, 100)
         K = wl.sim.ckpt_every
