@@ -861,9 +861,10 @@ struct Rod {
   __device__ __forceinline__ V3<T> sc_at(const T* a, int v) const {
     return mk(a[3 * v], a[3 * v + 1], a[3 * v + 2]);
   }
-  // static data into LDS; the hash cell is 2 r_max + delta_c + 2 l where l
-  // is the longest edge at the substep's predicted positions, so a
-  // partner's midpoint always lies in the 27 cells around the edge's own
+  // static data into LDS; the hash cell is 2 r_max + delta_c + l where l is
+  // the longest edge at the substep's predicted positions: a partner's
+  // midpoint is within half of both edge lengths plus 2 r_max + delta_c of
+  // the edge's own, so it lies in the 27 cells around the edge's cell
   __device__ void sc_setup(const RodArgs<T>& a) {
     sc_flags = 0;
     T m_r = T(0), m_l = T(0);
@@ -916,7 +917,7 @@ struct Rod {
     __syncthreads();
     l2 = __int_as_float(*lsq);   // sc_tmp is next written after the barrier below
     if (l2 > sc_lmax * sc_lmax) sc_flags |= 4;
-    const T ig = frcp(sc_cell0 + T(2) * fsqrt(l2));
+    const T ig = frcp(sc_cell0 + fsqrt(l2));
     unsigned key[C];
     int slot[C];
 #pragma unroll
@@ -961,6 +962,10 @@ struct Rod {
       if (evalid(c)) sc_items[sc_start[key[c]] + slot[c]] = (short)gi(c);
     __syncthreads();
     const T margin = a.self_margin;
+    // a partner must have its midpoint within h_e + h_max + 2 r_max + margin
+    // of the edge's own (segment distance >= midpoint distance minus both
+    // half-lengths); the slack keeps every pair the exact test below accepts
+    const T h_max = T(0.5) * fsqrt(l2);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       if (!evalid(c)) continue;
@@ -969,6 +974,9 @@ struct Rod {
       int cnt = 0;
       V3<T> P = sc_at(sc_pos, e), Q = sc_at(sc_pos, e + 1);
       V3<T> m = T(0.5) * (P + Q);
+      V3<T> PQ = Q - P;
+      const T reach = (T(0.5) * fsqrt(dot(PQ, PQ)) + h_max + sc_cell0) * T(1.0001) + T(1e-6);
+      const T reach2 = reach * reach;
       int cx = (int)floor(m.x * ig), cy = (int)floor(m.y * ig), cz = (int)floor(m.z * ig);
       for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
@@ -977,6 +985,8 @@ struct Rod {
             for (int q = sc_start[kk]; q < sc_start[kk + 1]; ++q) {
               int j = sc_items[q];
               if (!(j - e > a.k_ex || e - j > a.k_ex)) continue;
+              V3<T> mm = T(0.5) * (sc_at(sc_pos, j) + sc_at(sc_pos, j + 1)) - m;
+              if (!(dot(mm, mm) < reach2)) continue;
               int lo = e < j ? e : j, hi = e < j ? j : e;
               V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
               V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
