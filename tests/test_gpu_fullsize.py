@@ -1,10 +1,11 @@
 """Parity at full size, in the launch configuration the benchmark times
 (autotuned launch shapes, every rod of the batch in one launch per segment).
 
-* The 1024 x 128 batch, 1000 steps, checkpoint every 50, in FP64: final
-  positions, rest curvatures and every gradient of the 8 sampled rods
-  against FP64 oracle values stored in tests/golden (written by
-  tests/golden/make_c3_golden.py, which calls only the oracle).
+* The 1024 x 128 batch, without and with the twist degree of freedom, 1000
+  steps, checkpoint every 50, in FP64: final positions (and twist angles),
+  rest curvatures and every gradient of the 8 sampled rods against FP64
+  oracle values stored in tests/golden (written by tests/golden/make_golden.py,
+  which calls only the oracle).
 * The same batch in FP32: step 1000 of the full-batch rollout against one
   oracle step from the GPU's own state at step 999 (the per-step bound).
 * The uneven 4096-rod contact batch, the 256 x 1024 self-contact batch and
@@ -23,8 +24,7 @@ from oracle.model import rods_from_workload, sim_from_workload
 from tests.gpukit import to_dev, gather_state, initial_full_state, rel_err
 
 pytestmark = pytest.mark.gpu
-GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                    "c3_oracle_1000steps.npz")
+GOLD_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _handle(wl, precision, **kw):
@@ -32,9 +32,19 @@ def _handle(wl, precision, **kw):
     return RodsHandle(wl, precision=precision, **kw)
 
 
-def test_fp64_full_batch_1000_steps_matches_golden():
-    g = np.load(GOLD)
-    wl = make_workload(3)
+def _golden(cid, tol_x=1e-9, tol_g=1e-7):
+    """FP64 full batch, 1000 steps, checkpoint every 50, autotuned shapes:
+    final positions (and twist angles), rest curvatures and every gradient of
+    the sampled rods against the stored oracle values, each within its
+    tolerance or three times the oracle's own spread when its start moves by
+    1e-15 (stored with the values), whichever is larger.  Rods whose final
+    positions move by more than 1e-6 under that change are chaotic over the
+    15000 substeps and not compared (the twist batch's kinks at held edges:
+    5 of its 8 rods, some decorrelated completely, one with gradients of
+    1e43; every rod of the batch without twist stays below 3e-12); the
+    per-step FP32 parity at the end of the horizon covers them."""
+    g = np.load(os.path.join(GOLD_DIR, f"c{cid}_oracle_1000steps.npz"))
+    wl = make_workload(cid)
     assert list(g["rods"]) == list(wl.oracle_rods)
     n = wl.sim.steps
     dt = torch.float64
@@ -48,17 +58,36 @@ def test_fp64_full_batch_1000_steps_matches_golden():
     loss, gx = h.loss_mse(xT, to_dev(wl.target, dt))
     gr = {k: v.cpu().numpy() for k, v in h.backward(gx, n_steps=n).items()}
     kb = h.get_state()[2].cpu().numpy()
+    th = h.get_twist()[0].cpu().numpy()
     x = xT.cpu().numpy()
     assert not h.status().any()
-    for i, r in enumerate(g["rods"]):
+    def bound(name, i, tol):
+        return max(tol, 3.0 * float(g["spread_" + name][i]))
+
+    compared = [i for i in range(len(g["rods"])) if g["spread_xT"][i] < 1e-6]
+    assert len(compared) >= 2
+    for i in compared:
+        r = g["rods"][i]
         a, b = wl.rod_range(int(r))
-        assert rel_err(x[a:b], g["xT"][i]) <= 1e-9, r
-        assert rel_err(kb[a:b], g["kbT"][i]) <= 1e-7, r
-        assert rel_err(gr["u"][:, r], g["u"][i]) <= 1e-7, r
-        assert rel_err(gr["x0"][a:b], g["x0"][i]) <= 1e-7, r
-        assert rel_err(gr["v0"][a:b], g["v0"][i]) <= 1e-7, r
-        assert abs(gr["b"][r] - g["b"][i]) <= 1e-6 * abs(g["b"][i]), r
-        assert abs(gr["sigma"][r] - g["sigma"][i]) <= 1e-7 * abs(g["sigma"][i]) + 1e-20, r
+        assert rel_err(x[a:b], g["xT"][i]) <= bound("xT", i, tol_x), r
+        assert rel_err(kb[a:b], g["kbT"][i]) <= bound("kbT", i, tol_g), r
+        if wl.twist_inv_inertia is not None:
+            assert rel_err(th[a:b - 1], g["thetaT"][i]) <= bound("thetaT", i, tol_g), r
+        assert rel_err(gr["u"][:, r], g["u"][i]) <= bound("u", i, tol_g), r
+        assert rel_err(gr["x0"][a:b], g["x0"][i]) <= bound("x0", i, tol_g), r
+        assert rel_err(gr["v0"][a:b], g["v0"][i]) <= bound("v0", i, tol_g), r
+        assert abs(gr["b"][r] - g["b"][i]) <= bound("b", i, 10 * tol_g) * abs(g["b"][i]), r
+        assert abs(gr["sigma"][r] - g["sigma"][i]) <= \
+            bound("sigma", i, tol_g) * abs(g["sigma"][i]) + 1e-20, r
+    return len(compared)
+
+
+def test_fp64_full_batch_1000_steps_matches_golden():
+    assert _golden(3) == 8
+
+
+def test_fp64_twist_batch_1000_steps_matches_golden():
+    assert _golden(6) >= 2
 
 
 def _perturbed(st, seed):
