@@ -75,8 +75,9 @@ CONFIGS = {
               backward=True,
               oracle_rods=(0, 146, 292, 438, 585, 731, 877, 1023),
               description="the 1024 x 128 forward + adjoint batch with the twist "
-                          "degree of freedom (twisting modulus 1e3 Pa) and clamped "
-                          "end edges, 1000 steps, checkpoint every 50, MSE loss"),
+                          "degree of freedom (twisting modulus 1e3 Pa), the grippers "
+                          "holding the end edges' twist, 1000 steps, checkpoint every "
+                          "50, MSE loss"),
 }
 
 

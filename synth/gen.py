@@ -228,7 +228,7 @@ def make_workload(cid: int, steps: Optional[int] = None,
     n_act = -(-sim.steps // spa)
     action_dt = spa * sim.dt
     # configurations 3 and 6 are configuration 2's batch with a target: same
-    # rod stream (6 adds twist and holds both vertices of each end edge)
+    # rod stream (6 adds twist, with the twist of both end edges held)
     rng = np.random.default_rng([SEED0, 2 if cid in (3, 6) else cid])
     rng_target = np.random.default_rng([SEED0, 3 if cid == 6 else cid, 1])
 
@@ -236,7 +236,7 @@ def make_workload(cid: int, steps: Optional[int] = None,
     xs, rests, invm, rads, gidx, params, acts, tgts, xrests = [], [], [], [], [], [], [], [], []
     ptype, pa, pb, pr, pcount = [], [], [], [], []
     jts = []
-    G = {1: 0, 2: 2, 3: 2, 4: 2, 5: 4, 6: 4}[cid]
+    G = {1: 0, 2: 2, 3: 2, 4: 2, 5: 4, 6: 2}[cid]
 
     for r in range(R):
         # ---------------- material
@@ -291,7 +291,12 @@ def make_workload(cid: int, steps: Optional[int] = None,
         invm.append(w)
         rads.append(np.full(n, RADIUS))
         xrests.append(xr if xr is not None else x_clean)
-        jts.append(edge_inv_inertia(rest_e, rads[-1]) if cid == 6 else np.zeros(n))
+        if cid == 6:
+            jt = edge_inv_inertia(rest_e, rads[-1])
+            jt[[0, n - 2]] = 0.0          # the grippers hold the end edges' twist
+            jts.append(jt)
+        else:
+            jts.append(np.zeros(n))
 
         # ---------------- grasps
         if G:
@@ -300,16 +305,8 @@ def make_workload(cid: int, steps: Optional[int] = None,
             else:
                 gv = [0, n - 1]
             scale = 1.0 if cid != 4 else min(1.0, (n - 1) * edge / 1.27)
-            if cid == 6:
-                # both vertices of each end edge, moved together: the end
-                # edges translate and their twist is held
-                draws = [_grasp_draw(rng, scale) for _ in range(2)]
-                a2 = _grasp_actions(draws, n_act, action_dt)
-                acts.append(a2[:, [0, 0, 1, 1]])
-                gv = [0, 1, n - 2, n - 1]
-            else:
-                draws = [_grasp_draw(rng, scale) for _ in gv]
-                acts.append(_grasp_actions(draws, n_act, action_dt))
+            draws = [_grasp_draw(rng, scale) for _ in gv]
+            acts.append(_grasp_actions(draws, n_act, action_dt))
             gidx.append(gv)
         else:
             acts.append(np.zeros((n_act, 0, 3)))

@@ -39,10 +39,10 @@ def _golden(cid, tol_x=1e-9, tol_g=1e-7):
     tolerance or three times the oracle's own spread when its start moves by
     1e-15 (stored with the values), whichever is larger.  Rods whose final
     positions move by more than 1e-6 under that change are chaotic over the
-    15000 substeps and not compared (the twist batch's kinks at held edges:
-    5 of its 8 rods, some decorrelated completely, one with gradients of
-    1e43; every rod of the batch without twist stays below 3e-12); the
-    per-step FP32 parity at the end of the horizon covers them."""
+    15000 substeps and not compared (5 of the twist batch's 8 rods: a 1e-15
+    change moves their final positions by 6e-5 to 5e-2 and one rod's grasp
+    gradients to 5e21; every rod of the batch without twist stays below
+    3e-12); the per-step FP32 parity at the end of the horizon covers them."""
     g = np.load(os.path.join(GOLD_DIR, f"c{cid}_oracle_1000steps.npz"))
     wl = make_workload(cid)
     assert list(g["rods"]) == list(wl.oracle_rods)

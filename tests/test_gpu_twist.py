@@ -1,16 +1,14 @@
 """GPU parity of the twist degree of freedom (App. A.1, DLO Representation and
 Twisting) against the FP64 oracle, through the C ABI: the 1024 x 128 batch
-with twisting modulus 1e3 Pa and both vertices of each end edge held
+with twisting modulus 1e3 Pa and the twist of both end edges held
 (configuration 6), its 8 oracle rods, starting from non-zero twist angles
 and rates so that the twist terms act from the first substep.
 
 Tolerances as for rods without twist: FP64 GPU path 1e-9 relative (same
 algorithm, other rounding order); FP32 teacher-forced step 1e-4 relative on
 positions and twist angles; FP32 gradients 1e-3 per block over a two-step
-horizon.  Twist rates in FP32: 1e-3, or three times the oracle's own spread
-when one FP32 rounding of its start moves them by more (next to a held end
-edge the rod kinks, and the bending torque there is a small difference of
-large terms: measured spread up to 9e-4).
+horizon; twist rates in FP32 within 1e-3 (one FP32 rounding of the start
+moves the oracle's own rates by at most 4e-5 on these rods).
 """
 import copy
 
@@ -50,7 +48,7 @@ def _twist_rows(sub, seed):
         rate = sum(rng.normal(0, 4.0) * np.sin(k * np.pi * s) for k in (1, 2))
         th[a:b - 1] = prof
         om[a:b - 1] = rate
-        th[[a, b - 2]] = 0.0     # end edges: both vertices grasped
+        th[[a, b - 2]] = 0.0     # end edges: twist held
         om[[a, b - 2]] = 0.0
     return th, om
 
@@ -94,24 +92,13 @@ def _teacher_forced(precision, at_steps=(0, 3, 8)):
         h.step(to_dev(sub.actions[s // spa], _dt(precision)))
         gpu = gather_state(sub, rods, _get(h))
         ref = ofw.step(orods, osim, start, sub.actions[s // spa])
-        spread = np.zeros(len(rods))
-        if precision == 4:
-            for seed in (1, 2):
-                q = ofw.step(orods, osim, _perturbed(start, seed), sub.actions[s // spa])
-                spread = np.maximum(spread, [rel_err(q.omega[r], ref.omega[r]) for r in rods])
-        out.append((start, ref, gpu, spread))
+        out.append((start, ref, gpu))
     assert not h.status().any()
     return out
 
 
-def _perturbed(st, seed, eps=6e-8):
-    rng = np.random.default_rng(seed)
-    f = lambda a: a * (1 + eps * rng.standard_normal(a.shape))
-    return State(f(st.x), f(st.v), st.kb, st.d1, f(st.theta), f(st.omega))
-
-
 def test_fp64_twist_step_matches_oracle_tightly():
-    for start, ref, gpu, _ in _teacher_forced(8):
+    for start, ref, gpu in _teacher_forced(8):
         for r in range(ref.x.shape[0]):
             assert rel_err(gpu.x[r], ref.x[r]) <= 1e-9
             assert rel_err(gpu.v[r], ref.v[r]) <= 1e-7
@@ -125,11 +112,11 @@ def test_fp64_twist_step_matches_oracle_tightly():
 
 
 def test_fp32_twist_step_teacher_forced_parity():
-    for start, ref, gpu, spread in _teacher_forced(4):
+    for start, ref, gpu in _teacher_forced(4):
         for r in range(ref.x.shape[0]):
-            assert rel_err(gpu.x[r], ref.x[r]) <= 1e-4
-            assert rel_err(gpu.theta[r], ref.theta[r]) <= 1e-4
-            assert rel_err(gpu.omega[r], ref.omega[r]) <= max(1e-3, 3 * spread[r]), r
+            assert rel_err(gpu.x[r], ref.x[r]) <= 1e-4, r
+            assert rel_err(gpu.theta[r], ref.theta[r]) <= 1e-4, r
+            assert rel_err(gpu.omega[r], ref.omega[r]) <= 1e-3, r
 
 
 def _gpu_grads(sub, full, tw, precision, n, K, rounded=False):
