@@ -188,21 +188,34 @@ def sdf_vjp(c, sdf_b, n_b):
     return xb
 
 
-def rigid_contact_vjp(rods, sim, crec, v_b, x_b):
-    """Adjoint of rigid_contact, primitives in reverse order."""
+def rigid_contact_vjp(rods, sim, crec, v_b, x_b, P_b=None, L_b=None, body_b=None):
+    """Adjoint of rigid_contact, primitives in reverse order.  P_b, L_b: the
+    adjoints of the summed momentum changes and moments [B,P,3] (moving
+    bodies only); the adjoints of the bodies' substep-start centre, velocity
+    and angular velocity are added to body_b [B,P,9]."""
     v_b = v_b.copy()
     for c in reversed(crec["contact"]):
         bi = c["bi"]
         act = c["act"]
         e, mu = c["e"], c["mu"]
         vo_b = v_b[bi]
-        f, vin, n = c["f"], c["vin"], c["n"]
+        f, vrel, n = c["f"], c["vrel"], c["n"]
         vn, vt, vtn, s, vres = c["vn"], c["vt"], c["vtn"], c["s"], c["vres"]
-        vi_b = (1.0 - f)[:, None] * vo_b
+        n_b = np.zeros_like(n)
+        vin_extra = 0.0
+        if c["dyn"]:
+            j, R, m = c["j"], c["prim"][3], c["mass"]
+            # dp = m (v_out - v_in) summed into P and, through (R n) x dp, into L
+            dp_b = P_b[bi, j][None, :] + R * cross(L_b[bi, j][None, :], n)
+            n_b = n_b + R * cross(c["dp"], L_b[bi, j][None, :])
+            vo_b = vo_b + m[:, None] * dp_b
+            vin_extra = -m[:, None] * dp_b
+        # v_out = vb + (1 - f) v_rel + f v_res(v_rel, n)
+        vr_b = (1.0 - f)[:, None] * vo_b
         vres_b = f[:, None] * vo_b
-        f_b = dot(vres - vin, vo_b)
+        f_b = dot(vres - vrel, vo_b)
         vn_b = -e * dot(n, vres_b)
-        n_b = (-e * vn)[:, None] * vres_b
+        n_b = n_b + (-e * vn)[:, None] * vres_b
         s_b = dot(vt, vres_b)
         vt_b = s[:, None] * vres_b
         slide = c["slide"]
@@ -210,16 +223,39 @@ def rigid_contact_vjp(rods, sim, crec, v_b, x_b):
         vtn_b = np.where(slide, mu * c["dvn"] * s_b / vtn ** 2, 0.0)
         vn_b = vn_b - (1.0 + e) * dvn_b
         vt_b = vt_b + (vtn_b / vtn)[:, None] * vt
-        vi_b = vi_b + vt_b
+        vr_b = vr_b + vt_b
         vn_b = vn_b - dot(n, vt_b)
         n_b = n_b - vn[:, None] * vt_b
-        vi_b = vi_b + vn_b[:, None] * n
-        n_b = n_b + vn_b[:, None] * vin
+        vr_b = vr_b + vn_b[:, None] * n
+        n_b = n_b + vn_b[:, None] * vrel
+        vi_b = vr_b + vin_extra
+        if c["dyn"]:
+            # v_rel = v_in - vb, vb = V + Omega x (R n)
+            vb_b = np.where(act[:, None], vo_b - vr_b, 0.0)
+            Om = c["Om"]
+            n_b = n_b + R * cross(vb_b, Om[None, :])
+            body_b[bi, j, 3:6] += vb_b.sum(0)
+            body_b[bi, j, 6:9] += (R * cross(n, vb_b)).sum(0)
         d_b = np.where(c["d"] < 0.0, f_b * f / sim.eps_s, 0.0)
         xb = sdf_vjp(c, -d_b, n_b)
-        v_b[bi] = np.where(act[:, None], vi_b, vo_b)
+        v_b[bi] = np.where(act[:, None], vi_b, v_b[bi])
         x_b[bi] += np.where(act[:, None], xb, 0.0)
+        if c["dyn"]:
+            # the sphere's distance and normal depend on x - c
+            body_b[bi, j, :3] -= np.where(act[:, None], xb, 0.0).sum(0)
     return v_b
+
+
+def body_update_vjp(rods, body1_b, h):
+    """Adjoint of body_update: returns (body0_b without the contact terms,
+    P_b, L_b)."""
+    W = rods.body_w[..., None]
+    Ii = rods.body_iinv[..., None]
+    c_b = body1_b[..., :3]
+    V1_b = body1_b[..., 3:6] + h * c_b
+    Om1_b = body1_b[..., 6:9]
+    body0_b = np.concatenate([c_b, V1_b, Om1_b], axis=-1)
+    return body0_b, -W * V1_b, -Ii * Om1_b
 
 
 # --------------------------------------------------------------------------
@@ -227,10 +263,10 @@ def rigid_contact_vjp(rods, sim, crec, v_b, x_b):
 # --------------------------------------------------------------------------
 
 def substep_vjp(rods, sim, rec, bar):
-    """Given adjoints `bar` = (x_b, v_b, kb_b, d1_b, theta_b, omega_b) of the
-    substep's output state and the forward record `rec`, return the adjoints
-    of its input state and (u_b [B,G,3], b_b [B], sigma_b [B])."""
-    xb1, vb3, kbb1, d1nb, thb1, omb1 = bar
+    """Given adjoints `bar` = (x_b, v_b, kb_b, d1_b, theta_b, omega_b, body_b)
+    of the substep's output state and the forward record `rec`, return the
+    adjoints of its input state and (u_b [B,G,3], b_b [B], sigma_b [B])."""
+    xb1, vb3, kbb1, d1nb, thb1, omb1, bodyb1 = bar
     h = sim.h
     B = rods.B
     t, ell, t1, ell1 = rec["t"], rec["ell"], rec["t1"], rec["ell1"]
@@ -299,8 +335,12 @@ def substep_vjp(rods, sim, rec, bar):
     if rods.twist:
         om1_b = om1_b + h * th1_b
     # S4 rigid contact
+    body_b = bodyb1
     if rec["crec"] is not None and rec["crec"].get("contact"):
-        v1_b = rigid_contact_vjp(rods, sim, rec["crec"], v2_b, x_b)
+        P_b = L_b = None
+        if rods.has_bodies:
+            body_b, P_b, L_b = body_update_vjp(rods, np.array(bodyb1, np.float64), h)
+        v1_b = rigid_contact_vjp(rods, sim, rec["crec"], v2_b, x_b, P_b, L_b, body_b)
     else:
         v1_b = v2_b
     # S3 velocity update / kinematic vertices
@@ -348,23 +388,28 @@ def substep_vjp(rods, sim, rec, bar):
     else:
         d1_b = d1_b + m1b
     x_b = x_b + edges_vjp(ell, t, t_b, ellb)
-    return State(x_b, v_b, kb_b, d1_b, th_b, om_b), u_b, b_b, sig_b
+    return State(x_b, v_b, kb_b, d1_b, th_b, om_b, body_b), u_b, b_b, sig_b
 
 
 # --------------------------------------------------------------------------
 # checkpointed rollout backward and the loss
 # --------------------------------------------------------------------------
 
-def backward(rods, sim, ckpts, U, n_steps, ckpt_every, xT_b, vT_b=None):
+def backward(rods, sim, ckpts, U, n_steps, ckpt_every, xT_b, vT_b=None, bodyT_b=None,
+             with_body=False):
     """Reverse pass through a rollout that kept a state every ckpt_every
     steps.  Each segment is re-run forward from its checkpoint (keeping the
     substep-start states), then its substeps are reversed.  Returns
-    (x0_b, v0_b, u_b [A,B,G,3], b_b [B], sigma_b [B])."""
+    (x0_b, v0_b, u_b [A,B,G,3], b_b [B], sigma_b [B]), and with_body the
+    adjoint of the bodies' initial state [B,P,9] as a sixth value; bodyT_b
+    seeds the adjoint of their final state."""
     B, N = rods.B, rods.N
+    body_shape = ckpts[0].body.shape
     bar = State(np.array(xT_b, np.float64),
                 np.zeros((B, N, 3)) if vT_b is None else np.array(vT_b, np.float64),
                 np.zeros((B, N, 2)), np.zeros((B, N - 1, 3)), np.zeros((B, N - 1)),
-                np.zeros((B, N - 1)))
+                np.zeros((B, N - 1)),
+                np.zeros(body_shape) if bodyT_b is None else np.array(bodyT_b, np.float64))
     u_b = np.zeros_like(U, dtype=np.float64)
     b_b = np.zeros(B)
     sig_b = np.zeros(B)
@@ -387,6 +432,8 @@ def backward(rods, sim, ckpts, U, n_steps, ckpt_every, xT_b, vT_b=None):
             u_b[a] += ub
             b_b += bb
             sig_b += sb
+    if with_body:
+        return bar.x, bar.v, u_b, b_b, sig_b, bar.body
     return bar.x, bar.v, u_b, b_b, sig_b
 
 

@@ -11,7 +11,8 @@ substeps):
       (twisting rods: material frames, plus the torques -dU/dtheta)
   S3  v += h w f on free vertices; grasped vertices take the action velocity,
       pinned vertices stay at rest (twisting rods: the twist rates likewise)
-  S4  rigid SDF contact on velocities (Section 3.2)
+  S4  rigid SDF contact on velocities (Section 3.2); moving bodies take the
+      opposite momentum change and advance their centres
   S5  predict p = x + h v (twisting rods: theta += h theta_dot)
   S6  self-contact candidate pairs at p (App. A.1, Self-collision)
   S7  N_C iterations of {inextensibility red pass (even edges), black pass
@@ -116,34 +117,51 @@ def sdf_normal(prim, p):
     return nq - rad, q / nq[..., None], interior
 
 
-def rigid_contact(rods, sim, x, v, rec=None):
+def rigid_contact(rods, sim, x, v, body=None, rec=None):
     """Soft SDF contact on free vertices, primitives in index order.
 
     Paper (Section 3.2): depth d = r - SDF(p), influence f = min(exp(d/eps_s),
     1), resolve when f exceeds 0.1 with an impulse; normal from grad SDF;
-    restitution on the normal and friction on the tangential velocity.
-    Readings: p = vertex positions at the substep start; static bodies;
-    active iff f > 0.1 and v.n < 0; v_n' = -e v_n; Coulomb
-    v_t' = max(0, 1 - mu dv_n/|v_t|) v_t with dv_n = -(1+e) v_n; the soft
-    response is the blend v <- (1-f) v + f v_res.
+    restitution on the normal and friction on the tangential component of
+    the velocity relative to the body's contact point; the vertex's momentum
+    change goes back to the body with the opposite sign.
+    Readings: p = vertex positions at the substep start; active iff f > 0.1
+    and v_rel.n < 0; v_n' = -e v_n; Coulomb v_t' = max(0, 1 - mu dv_n/|v_t|)
+    v_t with dv_n = -(1+e) v_n; the soft response is the blend v_rel <- (1-f)
+    v_rel + f v_res.  A moving body is a sphere of centre c, velocity V and
+    angular velocity Omega; its contact point is c + R n, moving at
+    V + Omega x (R n); every vertex sees the body's substep-start state.
+    Returns (v, P, L): P [B,P,3] the summed vertex momentum changes per
+    primitive, L [B,P,3] their moments sum (R n) x m dv about the centre.
     """
     B = x.shape[0]
     v = v.copy()
+    dyn_on = body is not None and rods.has_bodies
+    Pm = body.shape[1] if dyn_on else 0
+    Pimp = np.zeros((B, Pm, 3), dtype=v.dtype)
+    Limp = np.zeros((B, Pm, 3), dtype=v.dtype)
     if rec is not None:
         rec["contact"] = []
     for bi in range(B):
         free = rods.w[bi] > 0.0
+        mass = np.where(free, 1.0 / np.where(free, rods.w[bi], 1.0), 0.0)
         e = rods.restitution[bi]
         mu = rods.mu[bi]
-        for prim in rods.prims[bi]:
+        for j, prim in enumerate(rods.prims[bi]):
+            dyn = dyn_on and rods.body_w[bi, j] > 0.0
+            if dyn:
+                cen, Vb, Om = body[bi, j, :3], body[bi, j, 3:6], body[bi, j, 6:9]
+                prim = (SPHERE, cen, prim[2], prim[3])
             sdf, n, interior = sdf_normal(prim, x[bi])
             d = rods.radius[bi] - sdf
             f = np.where(re(d) >= 0.0, 1.0 + 0.0 * d, np.exp(np.where(re(d) >= 0.0, 0.0, d) / sim.eps_s))
             vin = v[bi].copy()
-            vn = dot(vin, n)
+            vb = (Vb + cross(Om, prim[3] * n)) if dyn else 0.0 * vin
+            vrel = vin - vb
+            vn = dot(vrel, n)
             act = free & (re(f) > sim.f_thresh) & (re(vn) < 0.0)
             dvn = -(1.0 + e) * vn
-            vt = vin - vn[:, None] * n
+            vt = vrel - vn[:, None] * n
             vtn = norm(vt)
             pos = re(vtn) > 0.0
             vtn_safe = np.where(pos, vtn, 1.0)
@@ -151,13 +169,34 @@ def rigid_contact(rods, sim, x, v, rec=None):
             slide = pos & (re(s_raw) > 0.0)
             s = np.where(slide, s_raw, 0.0)
             vres = (-e * vn)[:, None] * n + s[:, None] * vt
-            vout = (1.0 - f)[:, None] * vin + f[:, None] * vres
+            vout = vb + (1.0 - f)[:, None] * vrel + f[:, None] * vres
             v[bi] = np.where(act[:, None], vout, vin)
+            dp = None
+            if dyn:
+                dp = mass[:, None] * (v[bi] - vin)
+                Pimp[bi, j] = dp.sum(0)
+                Limp[bi, j] = cross(prim[3] * n, dp).sum(0)
             if rec is not None:
-                rec["contact"].append(dict(bi=bi, prim=prim, vin=vin, n=n, sdf=sdf, d=d, f=f,
-                                           vn=vn, dvn=dvn, vt=vt, vtn=vtn_safe, s=s, vres=vres,
-                                           act=act, slide=slide, interior=interior, e=e, mu=mu))
-    return v
+                rec["contact"].append(dict(bi=bi, j=j, prim=prim, vin=vin, n=n, sdf=sdf, d=d,
+                                           f=f, vn=vn, dvn=dvn, vt=vt, vtn=vtn_safe, s=s,
+                                           vres=vres, vrel=vrel, act=act, slide=slide,
+                                           interior=interior, e=e, mu=mu, dyn=dyn, mass=mass,
+                                           dp=dp, Om=Om if dyn else None))
+    return v, Pimp, Limp
+
+
+def body_update(rods, body, Pimp, Limp, h):
+    """Equal and opposite reactions on the bodies, then symplectic Euler of
+    their centres: V -= W P, Omega -= I^-1 L, c += h V (Section 3.2, Rigid
+    Body).  Reading: the rigid solver's other forces (gravity, support,
+    rigid-rigid contact) are not part of the rod solver, so a moving body
+    feels only the rods' reactions."""
+    W = rods.body_w[..., None]
+    Ii = rods.body_iinv[..., None]
+    V1 = body[..., 3:6] - W * Pimp
+    Om1 = body[..., 6:9] - Ii * Limp
+    c1 = body[..., :3] + h * V1
+    return np.concatenate([c1, V1, Om1], axis=-1)
 
 
 # --------------------------------------------------------------------------
@@ -230,7 +269,7 @@ def plasticity(rods, kappa, kb, rec=None):
 def substep(rods, sim, st, u, rec=None):
     """Advance state `st` by one substep under grasp velocities u [B,G,3].
     When `rec` is a dict the intermediates the adjoint needs are stored."""
-    x, v, kb, d1, th, om = st
+    x, v, kb, d1, th, om, body = st
     h = sim.h
     # S2
     e, ell, t = edges(x)
@@ -257,7 +296,14 @@ def substep(rods, sim, st, u, rec=None):
     om1 = np.where(rods.twist_free, om + h * rods.Jt * Tq, 0.0 * om) if rods.twist else om
     # S4
     crec = {} if rec is not None else None
-    v2 = rigid_contact(rods, sim, x, v1, crec) if any(len(p) for p in rods.prims) else v1
+    body1 = body
+    if any(len(p) for p in rods.prims):
+        v2, Pimp, Limp = rigid_contact(rods, sim, x, v1, body, crec)
+        # reactions on the moving bodies and their motion
+        if rods.has_bodies:
+            body1 = body_update(rods, body, Pimp, Limp, h)
+    else:
+        v2 = v1
     # S5
     p0 = x + h * v2
     th1 = th + h * om1 if rods.twist else th
@@ -292,8 +338,8 @@ def substep(rods, sim, st, u, rec=None):
         rec.update(x=x, v=v, kb=kb, d1=d1, u=u, ell=ell, t=t, d2=m2, m1=m1, th=th, om1=om1,
                    th1=th1, m1n=m1n, F=F, v1=v1,
                    v2=v2, p0=p0, ptape=ptape, pairs=pairs, p=p, v3=v3, x1=x1, v3_pre=v3_pre, d0=d0,
-                   ell1=ell1, t1=t1, d1n=d1n, prec=prec, crec=crec, frec=frec)
-    return State(x1, v3, kb1, d1n, th1, om1)
+                   ell1=ell1, t1=t1, d1n=d1n, prec=prec, crec=crec, frec=frec, body=body)
+    return State(x1, v3, kb1, d1n, th1, om1, body1)
 
 
 def step(rods, sim, st, u):

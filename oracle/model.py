@@ -7,6 +7,12 @@ Inverse masses w_i = 1/m_i are inputs; a vertex with w_i = 0 is kinematic
 flag each edge also carries its twist angle theta^j and angular velocity
 (App. A.1: 3 N_v + N_e degrees of freedom), with an inverse polar moment of
 inertia per edge as input.
+
+Rigid bodies coupled both ways (Section 3.2, Rigid Body): a sphere primitive
+given an inverse mass W > 0 moves.  Its state (centre c, velocity V, angular
+velocity Omega) is the `body` field of the state, [B,P,9] per rod and
+primitive slot; the primitive's inverse mass and inverse moment of inertia
+are inputs.  Primitives with W = 0 are static and keep their body row.
 """
 from dataclasses import dataclass
 from typing import List, NamedTuple, Optional
@@ -14,6 +20,7 @@ from typing import List, NamedTuple, Optional
 import numpy as np
 
 FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF, FLAG_TWIST = 1, 2, 4, 8
+NO_BODY = np.zeros((0, 0, 9))
 
 
 class State(NamedTuple):
@@ -23,6 +30,7 @@ class State(NamedTuple):
     d1: np.ndarray       # [B,E,3] first reference director per edge (d2 = t x d1)
     theta: np.ndarray    # [B,E]   twist angle of the material frame about t^j
     omega: np.ndarray    # [B,E]   twist angular velocity d theta / dt
+    body: np.ndarray = NO_BODY   # [B,P,9] rigid bodies: centre, velocity, angular velocity
 
 
 @dataclass
@@ -61,6 +69,8 @@ class Rods:
     G: Optional[np.ndarray] = None    # [B]   twisting modulus (Pa), twist flag only
     Jt: Optional[np.ndarray] = None   # [B,E] inverse polar moment of inertia of each
                                       #       edge (1/(kg m^2)); 0 holds the twist
+    body_w: Optional[np.ndarray] = None     # [B,P] inverse mass of each primitive (0: static)
+    body_iinv: Optional[np.ndarray] = None  # [B,P] inverse moment of inertia (isotropic)
 
     @property
     def B(self):
@@ -85,6 +95,10 @@ class Rods:
     @property
     def twist(self):
         return bool(self.flags & FLAG_TWIST)
+
+    @property
+    def has_bodies(self):
+        return self.body_w is not None and bool(np.any(self.body_w > 0.0))
 
     @property
     def twist_coef(self):
@@ -149,13 +163,21 @@ def rods_from_workload(wl, rods):
             lst.append((int(wl.prim_type[k]), wl.prim_a[k].copy(), wl.prim_b[k].copy(),
                         float(wl.prim_r[k])))
         prims.append(lst)
+    body_w = body_iinv = None
+    if getattr(wl, "prim_inv_mass", None) is not None:
+        P = max(len(l) for l in prims)
+        body_w, body_iinv = np.zeros((len(rods), P)), np.zeros((len(rods), P))
+        for bi, r in enumerate(rods):
+            k0, k1 = wl.prim_offsets[r], wl.prim_offsets[r + 1]
+            body_w[bi, :k1 - k0] = wl.prim_inv_mass[k0:k1]
+            body_iinv[bi, :k1 - k0] = wl.prim_inv_inertia[k0:k1]
     G = p[:, 7].copy() if p.shape[1] > 7 else np.zeros(len(rods))
     Jt = np.stack([wl.twist_inv_inertia[s][:-1] for s in sl]) \
         if getattr(wl, "twist_inv_inertia", None) is not None else np.zeros_like(rest)
     return Rods(N=N, rest=rest, w=w, radius=np.stack([wl.radius[s] for s in sl]),
                 gidx=gidx, K=p[:, 1].copy(), b=p[:, 2].copy(), sigma_y=p[:, 3].copy(),
                 r_c=p[:, 4].copy(), mu=p[:, 5].copy(), restitution=p[:, 6].copy(),
-                flags=flags.pop(), prims=prims, G=G, Jt=Jt)
+                flags=flags.pop(), prims=prims, G=G, Jt=Jt, body_w=body_w, body_iinv=body_iinv)
 
 
 def sim_from_workload(wl):
@@ -168,7 +190,9 @@ def sim_from_workload(wl):
 
 def state_from_workload(wl, rods, kb=None, d1=None):
     """Initial state of the listed rods; frames by the initial-frame rule,
-    zero rest curvature unless given, zero twist angles and rates."""
+    zero rest curvature unless given, zero twist angles and rates; rigid
+    bodies (workloads with primitive masses) at their primitives' centres,
+    at rest."""
     from .geometry import init_frames
     rods = [int(r) for r in rods]
     sl = [slice(*wl.rod_range(r)) for r in rods]
@@ -179,7 +203,14 @@ def state_from_workload(wl, rods, kb=None, d1=None):
     if kb is None:
         kb = np.zeros(x.shape[:2] + (2,))
     z = np.zeros(x.shape[:1] + (x.shape[1] - 1,))
-    return State(x, v, kb, d1, z, z.copy())
+    body = NO_BODY
+    if getattr(wl, "prim_inv_mass", None) is not None:
+        P = max(wl.prim_offsets[r + 1] - wl.prim_offsets[r] for r in rods)
+        body = np.zeros((len(rods), P, 9))
+        for bi, r in enumerate(rods):
+            k0, k1 = wl.prim_offsets[r], wl.prim_offsets[r + 1]
+            body[bi, :k1 - k0, :3] = wl.prim_a[k0:k1]
+    return State(x, v, kb, d1, z, z.copy(), body)
 
 
 def actions_for(wl, rods):
