@@ -76,9 +76,11 @@ enum {
 
 enum { ROD_PRIM_PLANE = 0, ROD_PRIM_SPHERE = 1, ROD_PRIM_CAPSULE = 2 };
 
-/* A static rigid primitive seen as a signed distance field (Section 3.2).
+/* A rigid primitive seen as a signed distance field (Section 3.2).
  * plane: a = point on the plane, b = unit normal.  sphere: a = centre,
- * radius.  capsule: segment a-b, radius. */
+ * radius.  capsule: segment a-b, radius.  Static unless given an inverse
+ * mass in RodsDesc.prim_inv_mass (spheres only): then a is its initial
+ * centre and the sphere moves under the rods' contact reactions. */
 typedef struct {
   int32_t type;
   double a[3], b[3], radius;
@@ -115,6 +117,15 @@ typedef struct {
                                  edge's twist, as do edges whose two vertices are both
                                  kinematic.  Required when a rod has ROD_FLAG_TWIST,
                                  ignored (may be NULL) otherwise. */
+  const double* prim_inv_mass;    /* (host) [P] 1/M of each primitive; > 0 makes a
+                                 sphere a moving rigid body (two-way coupling, Section
+                                 3.2, Rigid Body), 0 keeps it static; NULL: every
+                                 primitive is static.  A rod with a moving body has
+                                 at most 16 primitives and neither ROD_FLAG_SELF nor
+                                 ROD_FLAG_TWIST. */
+  const double* prim_inv_inertia; /* (host) [P] inverse moment of inertia (isotropic,
+                                 e.g. 5/(2 M R^2) for a solid sphere); read where
+                                 prim_inv_mass > 0, may be NULL when prim_inv_mass is */
 } RodsDesc;
 
 /* Validates the description, copies the static data to the device and
@@ -147,6 +158,29 @@ int rods_set_twist(RodsHandle* h, const void* theta, const void* theta_dot,
                    rods_stream_t stream);
 /* Copies the twist state out; either pointer may be NULL. */
 int rods_get_twist(RodsHandle* h, void* theta, void* theta_dot, rods_stream_t stream);
+
+/* Moving rigid bodies (Section 3.2, Rigid Body).  A moving sphere's state is
+ * its centre c, velocity V and angular velocity Omega, stored as [P][9] =
+ * (c, V, Omega) per primitive (rows of static primitives are kept but never
+ * read).  In each substep every free vertex within the soft-contact band
+ * responds to its velocity relative to the sphere's contact point c + R n,
+ * which moves at V + Omega x (R n), all vertices seeing the substep-start
+ * state; the sphere then takes the opposite of the summed momentum change,
+ * V -= (1/M) sum dp, and of its moment, Omega -= I^-1 sum (R n) x dp, and
+ * moves its centre by h V.  Nothing else acts on a moving body (gravity,
+ * support and rigid-rigid contact are the rigid solver's).  rods_create
+ * starts every body at its primitive's centre, at rest; rods_set_state
+ * leaves the bodies as they are.  set replaces the state (device [P][9];
+ * NULL = centres of the primitives, at rest) and clears the recorded
+ * rollout; get copies it out. */
+int rods_set_bodies(RodsHandle* h, const void* body, rods_stream_t stream);
+int rods_get_bodies(RodsHandle* h, void* body, rods_stream_t stream);
+/* Adjoints of the body state through rods_backward: set gives the cotangent
+ * [P][9] of the bodies' state at the end of the recorded rollout (NULL =
+ * zero; kept for every later backward), get the adjoint [P][9] of their
+ * state at its start, as left by the last rods_backward. */
+int rods_set_body_adjoint(RodsHandle* h, const void* dL_dbodyT, rods_stream_t stream);
+int rods_get_body_adjoint(RodsHandle* h, void* dL_dbody0, rods_stream_t stream);
 
 /* Overrides the per-rod bending stiffness b and yield curvature sigma_y with
  * device arrays [R] (either may be NULL).  Clears the recorded rollout. */
@@ -209,7 +243,8 @@ typedef struct {
 } RodsAdam;
 
 /* Runs the optimisation: each iteration sets the state to (x0, v0,
- * kappa_bar0, frames by the initial-frame rule, zero twist), records a
+ * kappa_bar0, frames by the initial-frame rule, zero twist, the moving
+ * bodies as they were when the call began), records a
  * rollout of n_steps with grasp_vel, evaluates rods_loss_mse of the final
  * positions against target [V][3], runs rods_backward, then takes one Adam
  * step on the selected parameters.  grasp_vel [A][R][G][3] (A as in

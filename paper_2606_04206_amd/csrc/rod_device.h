@@ -90,6 +90,12 @@ __device__ __forceinline__ double dpp_from_prev(double v) {
 }
 
 constexpr int XK = 12;   // largest exchange group (values)
+// moving rigid bodies: at most NB_MAX primitives on a rod with moving bodies;
+// per primitive 9 values (centre, velocity, angular velocity)
+constexpr int NB_MAX = 16;
+constexpr int NB_VALS = 9;
+template <typename T>
+constexpr size_t body_lds_bytes() { return 2 * (size_t)NB_MAX * NB_VALS * sizeof(T); }
 
 template <typename T, int W>
 struct Team {
@@ -146,6 +152,33 @@ struct Team {
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = r[k];
+  }
+  // v[k] <- sum of v[k] over the team, in every lane (K <= XK).  Butterfly
+  // within each wave, then the W wave sums through LDS in wave order, so
+  // every lane forms the same sum in the same order.
+  template <int K>
+  __device__ __forceinline__ void sum(T (&v)[K]) {
+    static_assert(K <= XK, "exchange group too large");
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    if constexpr (W > 1) {
+      T* b = buf + pp * (W * XK);
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) b[wave * XK + k] = v[k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        T s = b[k];
+        for (int q = 1; q < W; ++q) s += b[q * XK + k];
+        v[k] = s;
+      }
+      pp ^= 1;
+    }
   }
 };
 
@@ -221,6 +254,16 @@ struct RodArgs {
   T* ck_om;
   T* lth;                   // adjoints of theta and its rate
   T* lom;
+  // moving rigid bodies (sphere primitives with inverse mass > 0); bw null:
+  // every primitive is static
+  const T* bw;              // [P] inverse mass, 0 for static primitives
+  const T* bii;             // [P] inverse moment of inertia (isotropic)
+  T* body;                  // [P][9] centre, velocity, angular velocity (state)
+  T* ck_body;               // optional copy of the final body state (checkpoint)
+  T* btape;                 // substep-start body states, [substep][P][9]
+  T* lbody;                 // [P][9] adjoint of the body state
+  int64_t bstride;          // values per body-tape slice (P * 9)
+  int32_t body_lds;         // byte offset of the team's body block in dynamic LDS
   // scalars
   T h;
   T gx, gy, gz;

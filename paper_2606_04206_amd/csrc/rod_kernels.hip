@@ -454,6 +454,107 @@ __device__ __forceinline__ void contact_one_vjp(const Prim<T>& p, V3<T> x, T rad
   vb = vib;
 }
 
+// Contact with a moving sphere (centre p.a, radius p.r; Section 3.2, Rigid
+// Body): the response of contact_one acts on the velocity relative to the
+// body's contact point c + R n, which moves at vb = Vb + Om x (R n).  Every
+// vertex sees the body's substep-start state.  Returns true when active,
+// with the unit normal in n.
+template <typename T>
+__device__ __forceinline__ bool contact_moving(const Prim<T>& p, V3<T> x, T rad, T mu, T e,
+                                               T eps_s, T f_thresh, V3<T> Vb, V3<T> Om,
+                                               V3<T>& v, V3<T>& n) {
+  const V3<T> q = x - p.a;
+  const T nq = fsqrt(dot(q, q));
+  n = frcp(nq) * q;
+  const T d = rad - (nq - p.r);
+  const T f = d >= T(0) ? T(1) : exp_t(fdiv(d, eps_s));
+  const V3<T> vb = Vb + cross(Om, p.r * n);
+  const V3<T> vrel = v - vb;
+  const T vn = dot(vrel, n);
+  if (!(f > f_thresh && vn < T(0))) return false;
+  const T dvn = -(T(1) + e) * vn;
+  const V3<T> vt = vrel - vn * n;
+  const T vtn = fsqrt(dot(vt, vt));
+  T s = T(0);
+  if (vtn > T(0)) {
+    T sr = T(1) - fdiv(mu * dvn, vtn);
+    s = sr > T(0) ? sr : T(0);
+  }
+  const V3<T> vres = (-e * vn) * n + s * vt;
+  v = vb + ((T(1) - f) * vrel + f * vres);
+  return true;
+}
+
+// Adjoint of contact_moving at input velocity vin, together with the
+// reaction it feeds: the vertex's momentum change dp = m (v_out - vin) is
+// summed into P and (R n) x dp into L, whose adjoints Pb, Lb are given.
+// vb: adjoint of the output velocity, replaced by that of the input; xb +=
+// the position adjoint; acc[0..8] += the adjoints of the body's centre,
+// velocity and angular velocity.
+template <typename T>
+__device__ __forceinline__ void contact_moving_vjp(const Prim<T>& p, V3<T> x, T rad, T mu, T e,
+                                                   T eps_s, T f_thresh, V3<T> Vb, V3<T> Om,
+                                                   T m, V3<T> vin, V3<T> Pb, V3<T> Lb,
+                                                   V3<T>& vb_adj, V3<T>& xb, T (&acc)[9]) {
+  const V3<T> q = x - p.a;
+  const T nq = fsqrt(dot(q, q));
+  const V3<T> n = frcp(nq) * q;
+  const T d = rad - (nq - p.r);
+  const T f = d >= T(0) ? T(1) : exp_t(fdiv(d, eps_s));
+  const V3<T> vbody = Vb + cross(Om, p.r * n);
+  const V3<T> vrel = vin - vbody;
+  const T vn = dot(vrel, n);
+  if (!(f > f_thresh && vn < T(0))) return;
+  const T dvn = -(T(1) + e) * vn;
+  const V3<T> vt = vrel - vn * n;
+  const T vtn = fsqrt(dot(vt, vt));
+  T s = T(0);
+  bool slide = false;
+  if (vtn > T(0)) {
+    T sr = T(1) - fdiv(mu * dvn, vtn);
+    slide = sr > T(0);
+    s = slide ? sr : T(0);
+  }
+  const V3<T> vres = (-e * vn) * n + s * vt;
+  const V3<T> vout = vbody + ((T(1) - f) * vrel + f * vres);
+  const V3<T> dp = m * (vout - vin);
+  // reaction: P += dp, L += (R n) x dp
+  const V3<T> dpb = Pb + p.r * cross(Lb, n);
+  V3<T> nb = p.r * cross(dp, Lb);
+  const V3<T> vob = vb_adj + m * dpb;
+  // v_out = vb + (1 - f) v_rel + f v_res(v_rel, n)
+  V3<T> vrb = (T(1) - f) * vob;
+  const V3<T> vresb = f * vob;
+  const T fb = dot(vres - vrel, vob);
+  T vnb = -e * dot(n, vresb);
+  nb += (-e * vn) * vresb;
+  const T sb = dot(vt, vresb);
+  V3<T> vtb = s * vresb;
+  if (slide) {
+    T dvnb = fdiv(-mu * sb, vtn);
+    T vtnb = fdiv(mu * dvn * sb, vtn * vtn);
+    vnb += -(T(1) + e) * dvnb;
+    vtb += fdiv(vtnb, vtn) * vt;
+  }
+  vrb += vtb;
+  vnb -= dot(n, vtb);
+  nb -= vn * vtb;
+  vrb += vnb * n;
+  nb += vnb * vrel;
+  // v_rel = vin - vb, vb = Vb + Om x (R n)
+  const V3<T> vbb = vob - vrb;
+  nb += p.r * cross(vbb, Om);
+  const V3<T> omb = p.r * cross(n, vbb);
+  // depth and normal through q = x - c
+  const T db = d < T(0) ? fdiv(fb * f, eps_s) : T(0);
+  const V3<T> g = (-db) * n + frcp(nq) * (nb - dot(n, nb) * n);
+  xb += g;
+  acc[0] -= g.x; acc[1] -= g.y; acc[2] -= g.z;
+  acc[3] += vbb.x; acc[4] += vbb.y; acc[5] += vbb.z;
+  acc[6] += omb.x; acc[7] += omb.y; acc[8] += omb.z;
+  vb_adj = vrb - m * dpb;
+}
+
 // ---------------------------------------------------------------------------
 // Per-lane rod state
 // ---------------------------------------------------------------------------
@@ -476,7 +577,8 @@ struct Rec {   // what the adjoint needs from one substep's forward run
   V3<T> m1p;
 };
 
-template <typename T, int C, int W, bool SC, bool TW = false>
+// BD: the rod may have moving rigid bodies (instantiated for those rods only)
+template <typename T, int C, int W, bool SC, bool TW = false, bool BD = false>
 struct Rod {
   static constexpr int TL = 64 * W;   // lanes per team
   static constexpr int NV = TL * C;   // vertex capacity of the team
@@ -504,6 +606,27 @@ struct Rod {
   T kr0[C], kr1[C];
   // twist: angle and rate per edge, inverse inertia (0: held), beta / l_bar
   T th[C], om[C], jt[C], tcoef[C];
+  // moving rigid bodies of the rod (dyn: at least one): their state and, in
+  // the adjoint, its adjoint, NB_VALS values per primitive slot k - p0 in LDS
+  bool dyn;
+  T *bs, *lbs;
+
+  // every lane of the team calls these (they end with a team barrier)
+  __device__ void body_setup(const RodArgs<T>& a, unsigned char* smem) {
+    dyn = false;
+    bs = lbs = nullptr;
+    if (!BD || !a.bw) return;
+    for (int k = p0; k < p1; ++k) dyn |= a.bw[k] > T(0);
+    bs = reinterpret_cast<T*>(smem + a.body_lds);
+    lbs = bs + NB_MAX * NB_VALS;
+  }
+  __device__ void load_bodies(T* dst, const T* src) const {
+    for (int i = tl; i < (p1 - p0) * NB_VALS; i += TL) dst[i] = src[(int64_t)p0 * NB_VALS + i];
+    __syncthreads();
+  }
+  __device__ void store_bodies(T* dst, const T* src) const {
+    for (int i = tl; i < (p1 - p0) * NB_VALS; i += TL) dst[(int64_t)p0 * NB_VALS + i] = src[i];
+  }
 
   __device__ __forceinline__ int gi(int c) const { return tl * C + c; }
   __device__ __forceinline__ bool vvalid(int c) const { return gi(c) < N; }
@@ -1449,13 +1572,47 @@ struct Rod {
 #pragma unroll
       for (int c = 0; c < C; ++c) om[c] = jt[c] > T(0) ? om[c] + (h * jt[c]) * Tq[c] : T(0);
     }
-    // S4 rigid contact, primitives in order
+    // S4 rigid contact, primitives in order.  A moving body takes the
+    // opposite of the summed momentum change and its moment, then its
+    // centre moves (symplectic Euler); its block in LDS is rewritten once
+    // every lane has read it (the team sum orders that).
     if (p1 > p0) {
       for (int k = p0; k < p1; ++k) {
         Prim<T> pr = load_prim(a, k);
+        if (!(BD && dyn && a.bw[k] > T(0))) {
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-          if (w[c] > T(0)) contact_one(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, v[c]);
+          for (int c = 0; c < C; ++c)
+            if (w[c] > T(0)) contact_one(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, v[c]);
+        } else {
+          T* bk = bs + (k - p0) * NB_VALS;
+          pr.a = V3<T>{bk[0], bk[1], bk[2]};
+          const V3<T> Vb{bk[3], bk[4], bk[5]}, Om{bk[6], bk[7], bk[8]};
+          T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            if (w[c] > T(0)) {
+              const V3<T> vin = v[c];
+              V3<T> n;
+              if (contact_moving(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, Vb, Om, v[c], n)) {
+                const V3<T> dp = (T(1) / w[c]) * (v[c] - vin);
+                const V3<T> lm = cross(pr.r * n, dp);
+                acc[0] += dp.x; acc[1] += dp.y; acc[2] += dp.z;
+                acc[3] += lm.x; acc[4] += lm.y; acc[5] += lm.z;
+              }
+            }
+          }
+          X.sum(acc);
+          if (tl == 0) {
+            const T bwk = a.bw[k], bik = a.bii[k];
+            const V3<T> V1 = Vb - bwk * V3<T>{acc[0], acc[1], acc[2]};
+            const V3<T> Om1 = Om - bik * V3<T>{acc[3], acc[4], acc[5]};
+            const V3<T> c1 = pr.a + h * V1;
+            bk[0] = c1.x; bk[1] = c1.y; bk[2] = c1.z;
+            bk[3] = V1.x; bk[4] = V1.y; bk[5] = V1.z;
+            bk[6] = Om1.x; bk[7] = Om1.y; bk[8] = Om1.z;
+          }
+          __syncthreads();
+        }
       }
     }
     // S5 predict.  The projections below act on p = p0 + dl with the
@@ -1673,12 +1830,75 @@ struct Rod {
       v2b[c] += h * p0b[c];
       if constexpr (TW) lom[c] += h * lth[c];
     }
-    // S4 rigid contact, primitives in reverse.  One forward sweep re-runs the
-    // primitives in order and keeps the input velocity of each active one
-    // (up to three; inactive primitives leave v unchanged and have a zero
-    // VJP); more than three active contacts fall back to re-evaluating each
-    // primitive's input from the start.
-    if (p1 > p0) {
+    // S4 rigid contact, primitives in reverse.
+    if (BD && p1 > p0 && dyn) {
+      // With moving bodies every lane walks the primitives in the same
+      // (reverse) order, so that each body's adjoint can be summed over the
+      // team: the input velocity of primitive k is re-evaluated from the
+      // substep's post-S3 velocity; bs holds the substep-start body states.
+      for (int k = p1 - 1; k >= p0; --k) {
+        Prim<T> pk = load_prim(a, k);
+        const bool mk = a.bw[k] > T(0);
+        V3<T> Vk = zero3<T>(), Omk = zero3<T>(), Pb = zero3<T>(), Lb = zero3<T>();
+        T lnew[9];
+        T acc[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) acc[i] = T(0);
+        if (mk) {
+          const T* bk = bs + (k - p0) * NB_VALS;
+          const T* lk = lbs + (k - p0) * NB_VALS;
+          pk.a = V3<T>{bk[0], bk[1], bk[2]};
+          Vk = V3<T>{bk[3], bk[4], bk[5]};
+          Omk = V3<T>{bk[6], bk[7], bk[8]};
+          // c1 = c0 + h V1, V1 = V0 - W P, Om1 = Om0 - I^-1 L
+          const V3<T> cb{lk[0], lk[1], lk[2]};
+          const V3<T> V1b = V3<T>{lk[3], lk[4], lk[5]} + h * cb;
+          const V3<T> Om1b{lk[6], lk[7], lk[8]};
+          Pb = (-a.bw[k]) * V1b;
+          Lb = (-a.bii[k]) * Om1b;
+          lnew[0] = cb.x; lnew[1] = cb.y; lnew[2] = cb.z;
+          lnew[3] = V1b.x; lnew[4] = V1b.y; lnew[5] = V1b.z;
+          lnew[6] = Om1b.x; lnew[7] = Om1b.y; lnew[8] = Om1b.z;
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          if (w[c] > T(0)) {
+            V3<T> vk = r.v1[c];
+            for (int j = p0; j < k; ++j) {
+              Prim<T> pj = load_prim(a, j);
+              if (a.bw[j] > T(0)) {
+                const T* bj = bs + (j - p0) * NB_VALS;
+                pj.a = V3<T>{bj[0], bj[1], bj[2]};
+                V3<T> nn;
+                contact_moving(pj, r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh,
+                               V3<T>{bj[3], bj[4], bj[5]}, V3<T>{bj[6], bj[7], bj[8]}, vk, nn);
+              } else {
+                contact_one(pj, r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vk);
+              }
+            }
+            if (mk)
+              contact_moving_vjp(pk, r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, Vk, Omk,
+                                 T(1) / w[c], vk, Pb, Lb, v2b[c], xb[c], acc);
+            else
+              contact_one_vjp(pk, r.x[c], rad[c], mu, e, a.eps_s, a.f_thresh, vk, v2b[c], xb[c]);
+          }
+        }
+        if (mk) {
+          X.sum(acc);
+          if (tl == 0) {
+            T* lk = lbs + (k - p0) * NB_VALS;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) lk[i] = lnew[i] + acc[i];
+          }
+          __syncthreads();
+        }
+      }
+    } else if (p1 > p0) {
+      // One forward sweep re-runs the primitives in order and keeps the
+      // input velocity of each active one (up to three; inactive primitives
+      // leave v unchanged and have a zero VJP); more than three active
+      // contacts fall back to re-evaluating each primitive's input from the
+      // start.
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         if (w[c] > T(0)) {
@@ -1937,31 +2157,40 @@ __device__ __forceinline__ size_t xchg_bytes() { return W > 1 ? 2 * W * XK * siz
 // Forward: n_steps steps of every rod of the work list, the rod resident in
 // registers the whole time.  TAPE: store every substep-start state.  SC:
 // self-contact support (hash, partner lists and staging buffers in LDS).
-template <typename T, int C, int W, bool TAPE, bool SC, bool TW>
+template <typename T, int C, int W, bool TAPE, bool SC, bool TW, bool BD>
 __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Team<T, W> X;
   X.init(reinterpret_cast<T*>(smem));
-  Rod<T, C, W, SC, TW> R;
+  Rod<T, C, W, SC, TW, BD> R;
   R.load_static(a, X);
   if constexpr (SC) {
     R.sc_layout(smem + xchg_bytes<T, W>());
     R.ctape = nullptr;
     R.sc_setup(a);
   }
+  R.body_setup(a, smem);
   R.load_state(a.x, a.v, a.kb, a.d1);
   if constexpr (TW) R.load_twist(a.th, a.om);
+  if (BD && R.dyn) R.load_bodies(R.bs, a.body);
   T* tape_rod = TAPE ? a.tape + a.tape_off[R.rod] : nullptr;
   for (int s = 0; s < a.n_steps; ++s) {
     V3<T> ug[C];
     R.load_actions(a, (a.step_off + s) / a.spa, ug);
     for (int k = 0; k < a.n_sub; ++k) {
-      if constexpr (TAPE) R.store_tape(tape_rod + (int64_t)(s * a.n_sub + k) * a.tape_stride);
+      if constexpr (TAPE) {
+        R.store_tape(tape_rod + (int64_t)(s * a.n_sub + k) * a.tape_stride);
+        if (BD && R.dyn) R.store_bodies(a.btape + (int64_t)(s * a.n_sub + k) * a.bstride, R.bs);
+      }
       R.template substep<false>(a, X, ug, nullptr, nullptr);
     }
   }
   R.store_state(a.x, a.v, a.kb, a.d1);
   if (a.ck_x) R.store_state(a.ck_x, a.ck_v, a.ck_kb, a.ck_d1);
+  if (BD && R.dyn) {
+    R.store_bodies(a.body, R.bs);
+    if (a.ck_body) R.store_bodies(a.ck_body, R.bs);
+  }
   if constexpr (TW) {
     R.store_twist(a.th, a.om);
     if (a.ck_x) R.store_twist(a.ck_th, a.ck_om);
@@ -1981,14 +2210,14 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
 // GT: the projection iterates of a substep go to a rod-private block of
 // global scratch (L2-resident) instead of LDS -- for teams whose iterates do
 // not fit in LDS, and always with self-contact, whose buffers fill the LDS.
-template <typename T, int C, int W, bool SC, bool GT, bool TW>
+template <typename T, int C, int W, bool SC, bool GT, bool TW, bool BD>
 __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
   static_assert(GT || !SC, "self-contact keeps the iterates in global scratch");
   static_assert(!(SC && TW), "no kernels for twist with self-contact");
   extern __shared__ __align__(16) unsigned char smem[];
   Team<T, W> X;
   X.init(reinterpret_cast<T*>(smem));
-  Rod<T, C, W, SC, TW> R;
+  Rod<T, C, W, SC, TW, BD> R;
   R.load_static(a, X);
   T* lds_tape;
   if constexpr (GT) {
@@ -2004,6 +2233,8 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
     R.ctape = lds_tape + (size_t)a.n_iters * C * PROJ_TAPE * 64 * W;
     R.sc_setup(a);
   }
+  R.body_setup(a, smem);
+  if (BD && R.dyn) R.load_bodies(R.lbs, a.lbody);
   V3<T> lx[C], lv[C], ld1[C], uacc[C];
   T lk0[C], lk1[C], lth[C], lom[C];
   double accb[C], accs[C];
@@ -2024,7 +2255,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
   }
   const T* tape_rod = a.tape + a.tape_off[R.rod];
   Rec<T, C> rec;
-  T pf[Rod<T, C, W, SC, TW>::NFIELD * C];
+  T pf[Rod<T, C, W, SC, TW, BD>::NFIELD * C];
   R.fetch_tape(tape_rod + (int64_t)(a.n_steps * a.n_sub - 1) * a.tape_stride, pf);
   for (int s = a.n_steps - 1; s >= 0; --s) {
     const int act = (a.step_off + s) / a.spa;
@@ -2034,7 +2265,11 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
       R.install_tape(pf);
       const int nxt = s * a.n_sub + k - 1;   // the substep processed next
       if (nxt >= 0) R.fetch_tape(tape_rod + (int64_t)nxt * a.tape_stride, pf);
+      // the replay advances the bodies; the adjoint needs their start state
+      const T* btape_k = (BD && R.dyn) ? a.btape + (int64_t)(s * a.n_sub + k) * a.bstride : nullptr;
+      if (BD && R.dyn) R.load_bodies(R.bs, btape_k);
       R.template substep<true>(a, X, ug, &rec, lds_tape);
+      if (BD && R.dyn) R.load_bodies(R.bs, btape_k);
       R.substep_vjp(a, X, rec, lds_tape, lx, lv, lk0, lk1, ld1, accb, accs, uacc, lth, lom);
     }
     // grasp-velocity gradient of this step's action
@@ -2066,6 +2301,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
       a.acc_s[row] += accs[c];
     }
   }
+  if (BD && R.dyn) R.store_bodies(a.lbody, R.lbs);
 }
 
 // ---------------------------------------------------------------------------
@@ -2189,23 +2425,29 @@ static size_t lds_bytes(int which, bool gt, int n_iters) {
   return xb;
 }
 
-template <typename T, int C, int W, bool SC, bool TW = false>
+template <typename T, int C, int W, bool SC, bool TW = false, bool BD = false>
 static hipError_t launch_shape(int which, bool gt, const RodArgs<T>& a, int n_blocks,
                                hipStream_t st) {
   size_t lds = lds_bytes<T, C, W, SC>(which, gt, a.n_iters);
+  RodArgs<T> b = a;
+  if constexpr (BD) {
+    // moving bodies: state and adjoint blocks after everything else
+    b.body_lds = (int32_t)((lds + 15) / 16 * 16);
+    lds = (size_t)b.body_lds + body_lds_bytes<T>();
+  }
   auto go = [&](auto f) {
     if (lds > 65536) hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, a);
+    hipLaunchKernelGGL(f, dim3(n_blocks), dim3(64 * W), lds, st, b);
   };
   if (which == 0) {
-    go(k_forward<T, C, W, false, SC, TW>);
+    go(k_forward<T, C, W, false, SC, TW, BD>);
   } else if (which == 1) {
-    go(k_forward<T, C, W, true, SC, TW>);
+    go(k_forward<T, C, W, true, SC, TW, BD>);
   } else if constexpr (SC) {
-    go(k_adjoint<T, C, W, true, true, false>);
+    go(k_adjoint<T, C, W, true, true, false, false>);
   } else {
-    if (gt) go(k_adjoint<T, C, W, false, true, TW>);
-    else go(k_adjoint<T, C, W, false, false, TW>);
+    if (gt) go(k_adjoint<T, C, W, false, true, TW, BD>);
+    else go(k_adjoint<T, C, W, false, false, TW, BD>);
   }
   return hipGetLastError();
 }
@@ -2253,6 +2495,20 @@ hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<
 #undef RODS_SC_SHAPE
   }
 #undef RODS_SHAPE
+  return hipErrorInvalidValue;
+}
+
+// Rods with moving rigid bodies: two vertices per lane, no self-contact or
+// twist.
+template <typename T>
+hipError_t launch_rods_bodies(int which, int C, int W, bool GT, const RodArgs<T>& a,
+                              int n_blocks, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  if (C != 2 || !a.bw) return hipErrorInvalidValue;
+  if (W == 1) return launch_shape<T, 2, 1, false, false, true>(which, GT, a, n_blocks, st);
+  if (W == 2) return launch_shape<T, 2, 2, false, false, true>(which, GT, a, n_blocks, st);
+  if (W == 4) return launch_shape<T, 2, 4, false, false, true>(which, GT, a, n_blocks, st);
+  if (W == 8) return launch_shape<T, 2, 8, false, false, true>(which, GT, a, n_blocks, st);
   return hipErrorInvalidValue;
 }
 
@@ -2318,6 +2574,8 @@ hipError_t launch_selftest_exchange(int* out, hipStream_t st) {
 #define RODS_INST(T)                                                                          \
   template hipError_t launch_rods<T>(int, int, int, bool, bool, const RodArgs<T>&, int,       \
                                      hipStream_t);                                            \
+  template hipError_t launch_rods_bodies<T>(int, int, int, bool, const RodArgs<T>&, int,      \
+                                            hipStream_t);                                     \
   template size_t kernel_lds_bytes<T>(int, int, int, bool, bool, int);                         \
   template hipError_t launch_init_frames<T>(const int32_t*, int, const T*, T*, hipStream_t);  \
   template hipError_t launch_curvature<T>(const int32_t*, const int32_t*, int, const T*,      \

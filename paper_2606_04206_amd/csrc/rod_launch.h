@@ -17,6 +17,10 @@ hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<
 template <typename T>
 hipError_t launch_rods_twist(int which, int C, int W, bool GT, const RodArgs<T>& a,
                              int n_blocks, hipStream_t st);
+// rods with moving rigid bodies (C = 2, no self-contact or twist; a.bw set)
+template <typename T>
+hipError_t launch_rods_bodies(int which, int C, int W, bool GT, const RodArgs<T>& a,
+                              int n_blocks, hipStream_t st);
 // dynamic LDS of a launch shape (kind 0/1 forward, 2 adjoint)
 template <typename T>
 size_t kernel_lds_bytes(int which, int C, int W, bool SC, bool GT, int n_iters);

@@ -32,6 +32,7 @@ struct Bin {
   bool sc;        // rods with self-contact
   bool gt;        // the adjoint keeps projection iterates in global scratch
   bool tw;        // rods with the twist degree of freedom
+  bool bd;        // rods with moving rigid bodies
 };
 
 // self-contact kernels exist for these shapes (FP32)
@@ -89,6 +90,16 @@ struct Impl : HandleBase {
   T *Gt = nullptr, *jt = nullptr, *th = nullptr, *om = nullptr, *sth = nullptr, *som = nullptr,
     *lth = nullptr, *lom = nullptr;
   T* ck = nullptr;          // [n_ck][V*NF]
+  // moving rigid bodies (has_bodies): inverse mass and inertia per
+  // primitive, state [P][9] with a scratch copy for replays, checkpoints
+  // [n_ck][P][9], the substep tape (two buffers, as the vertex tape), the
+  // adjoint, its seed, and the optimiser's start state
+  bool has_bodies = false;
+  T *bwv = nullptr, *biiv = nullptr, *body = nullptr, *sbody = nullptr, *ck_body = nullptr,
+    *btape = nullptr, *btape2 = nullptr, *lbody = nullptr, *bseed = nullptr, *body_opt0 = nullptr;
+  std::vector<T> body_init_h;   // centres of the primitives, at rest
+  T* ckb(int k) const { return ck_body + (size_t)k * P * rods::NB_VALS; }
+  T* btape_for(T* vtape) const { return vtape == tape2 ? btape2 : btape; }
   T* acts = nullptr;        // recorded actions [n_act_max][R][G][3]
   T* du_scratch = nullptr;  // dL/du when the caller does not want it
   // optimisation driver: Adam moments of the grasp velocities and of log b,
@@ -290,6 +301,16 @@ struct Impl : HandleBase {
       }
       pr_h[k] = (T)d.prims[k].radius;
     }
+    std::vector<T> bw_h(P, T(0)), bii_h(P, T(0));
+    body_init_h.assign((size_t)P * rods::NB_VALS, T(0));
+    for (int k = 0; k < P; ++k) {
+      for (int c = 0; c < 3; ++c) body_init_h[(size_t)k * rods::NB_VALS + c] = pa_h[3 * k + c];
+      if (d.prim_inv_mass && d.prim_inv_mass[k] > 0) {
+        has_bodies = true;
+        bw_h[k] = (T)d.prim_inv_mass[k];
+        bii_h[k] = (T)d.prim_inv_inertia[k];
+      }
+    }
     // ---- size bins: smallest legal team per rod, largest rods first
     {
       int attr = 0;
@@ -298,14 +319,16 @@ struct Impl : HandleBase {
         lds_max = (size_t)attr;
     }
     std::vector<std::vector<int>> members;
-    std::vector<std::tuple<int, int, bool, bool>> keys;
+    std::vector<std::tuple<int, int, bool, bool, bool>> keys;
     for (int r = 0; r < R; ++r) {
       const bool sc = (fl_h[r] & ROD_FLAG_SELF) != 0;
       const bool tw = (fl_h[r] & ROD_FLAG_TWIST) != 0;
+      bool bd = false;
+      for (int k = po_h[r]; k < po_h[r + 1]; ++k) bd |= bw_h[k] > T(0);
       if (sc && prec != 4) return ROD_EDTYPE;
-      auto sh = shapes_for(voff_h[r + 1] - voff_h[r], prec, sc, tw);
+      auto sh = shapes_for(voff_h[r + 1] - voff_h[r], prec, sc, tw || bd);
       if (sh.empty()) return ROD_EINVAL;
-      auto key = std::make_tuple(sh.front().first, sh.front().second, sc, tw);
+      auto key = std::make_tuple(sh.front().first, sh.front().second, sc, tw, bd);
       size_t k = 0;
       while (k < keys.size() && keys[k] != key) ++k;
       if (k == keys.size()) {
@@ -320,9 +343,9 @@ struct Impl : HandleBase {
         return (voff_h[a + 1] - voff_h[a]) > (voff_h[b2 + 1] - voff_h[b2]);
       });
       Bin bn{std::get<0>(keys[k]), std::get<1>(keys[k]), (int)m.size(), (int)bin_rods_h.size(),
-             std::get<2>(keys[k]), false, std::get<3>(keys[k])};
+             std::get<2>(keys[k]), false, std::get<3>(keys[k]), std::get<4>(keys[k])};
       bn.gt = global_tape(bn.C, bn.W, bn.sc);
-      if (rods::kernel_lds_bytes<T>(2, bn.C, bn.W, bn.sc, bn.gt, d.n_iters) > lds_max)
+      if (rods::kernel_lds_bytes<T>(2, bn.C, bn.W, bn.sc, bn.gt, d.n_iters) + body_lds() > lds_max)
         return ROD_EINVAL;
       bins.push_back(bn);
       for (int r : m) bin_rods_h.push_back(r);
@@ -372,6 +395,17 @@ struct Impl : HandleBase {
         (e = alloc(u_step, (size_t)R * G * 3)) ||
         (e = alloc(tape, (size_t)std::min(d.ckpt_every, std::max(1, d.max_steps)) * d.n_sub * (size_t)tape_cap)))
       return e;
+    if (has_bodies) {
+      const size_t nb = (size_t)P * rods::NB_VALS;
+      const size_t nbt = (size_t)std::min(d.ckpt_every, std::max(1, d.max_steps)) * d.n_sub * nb;
+      if ((e = upload(bwv, bw_h)) || (e = upload(biiv, bii_h)) || (e = upload(body, body_init_h)) ||
+          (e = alloc(sbody, nb)) || (e = alloc(ck_body, (size_t)n_ck * nb)) ||
+          (e = alloc(btape, nbt)) || (e = alloc(btape2, nbt)) || (e = alloc(lbody, nb)) ||
+          (e = alloc(bseed, nb)) || (e = alloc(body_opt0, nb)))
+        return e;
+      HIPCHK(hipMemset(bseed, 0, sizeof(T) * nb));
+      HIPCHK(hipMemset(lbody, 0, sizeof(T) * nb));
+    }
     HIPCHK(hipMemset(x, 0, 3 * sizeof(T) * V));
     HIPCHK(hipMemset(v, 0, 3 * sizeof(T) * V));
     HIPCHK(hipMemset(kb, 0, 2 * sizeof(T) * V));
@@ -401,6 +435,7 @@ struct Impl : HandleBase {
   }
 
   int64_t sc_stride_ = 0;
+  size_t body_lds() const { return has_bodies ? rods::body_lds_bytes<T>() + 16 : 0; }
   // values of global scratch per rod for the adjoint's projection iterates
   // (and, with self-contact, the contact-pass inputs)
   int64_t scratch_per_rod(int C, int W) const {
@@ -409,7 +444,7 @@ struct Impl : HandleBase {
   // iterates go to global scratch with self-contact, or when they do not fit
   // in LDS next to the lane-exchange buffers
   bool global_tape(int C, int W, bool sc) const {
-    return sc || rods::kernel_lds_bytes<T>(2, C, W, false, false, d.n_iters) > lds_max;
+    return sc || rods::kernel_lds_bytes<T>(2, C, W, false, false, d.n_iters) + body_lds() > lds_max;
   }
   // per-rod offsets of the backward tape block and of the self-contact
   // iterate block for the current launch shapes
@@ -450,6 +485,10 @@ struct Impl : HandleBase {
     a.sc_tape = sc_tape; a.sc_off = sc_off;
     a.status = status;
     a.Gt = Gt; a.jt = jt; a.th = th; a.om = om; a.lth = lth; a.lom = lom;
+    if (has_bodies) {
+      a.bw = bwv; a.bii = biiv; a.body = body; a.lbody = lbody; a.btape = btape;
+      a.bstride = (int64_t)P * rods::NB_VALS;
+    }
     a.h = (T)(d.dt / d.n_sub);
     a.gx = (T)d.gravity[0]; a.gy = (T)d.gravity[1]; a.gz = (T)d.gravity[2];
     a.eps_s = (T)d.eps_s; a.f_thresh = (T)d.f_thresh; a.self_margin = (T)d.self_margin;
@@ -473,6 +512,7 @@ struct Impl : HandleBase {
   static hipError_t launch_bin(int which, const Bin& bn, int C, int W, bool gt,
                                const RodArgs<T>& a, int n, hipStream_t st) {
     if (bn.tw) return rods::launch_rods_twist<T>(which, C, W, gt, a, n, st);
+    if (bn.bd) return rods::launch_rods_bodies<T>(which, C, W, gt, a, n, st);
     return rods::launch_rods<T>(which, C, W, bn.sc, gt, a, n, st);
   }
 
@@ -488,6 +528,7 @@ struct Impl : HandleBase {
     const int n_steps = a.n_steps;
     const int step_off = a.step_off;
     T* tape0 = a.tape;
+    T* btape0 = a.btape;
     for (const Bin& bn : bins) {
       for (int i = 0; i < bn.n; ++i) {
         RodArgs<T> b1 = a;
@@ -497,7 +538,9 @@ struct Impl : HandleBase {
           int s = (which == 2) ? (n_steps - 1 - s0) : s0;
           b1.step_off = step_off + s;
           if (tape0) b1.tape = tape0 + (int64_t)s * d.n_sub * tape_stride;
+          if (btape0) b1.btape = btape0 + (int64_t)s * d.n_sub * a.bstride;
           b1.ck_x = (s == n_steps - 1) ? a.ck_x : nullptr;
+          b1.ck_body = (s == n_steps - 1) ? a.ck_body : nullptr;
           HIPCHK(launch_bin(which, bn, bn.C, bn.W, bn.gt, b1, 1, st));
         }
       }
@@ -528,6 +571,15 @@ struct Impl : HandleBase {
     return ROD_OK;
   }
 
+  int set_bodies(const T* b_, hipStream_t st) {
+    if (!has_bodies) return ROD_OK;
+    const size_t nb = (size_t)P * rods::NB_VALS;
+    if (b_) HIPCHK(hipMemcpyAsync(body, b_, sizeof(T) * nb, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(hipMemcpyAsync(body, body_init_h.data(), sizeof(T) * nb, hipMemcpyHostToDevice, st));
+    recorded = false;
+    return ROD_OK;
+  }
+
   int rollout(int n_steps, const T* u, T* x_final, int record, hipStream_t st) {
     if (n_steps < 0) return ROD_EINVAL;
     if (record && n_steps > d.max_steps) return ROD_ESTATE;
@@ -549,6 +601,8 @@ struct Impl : HandleBase {
       HIPCHK(hipMemcpyAsync(ck_d1(0), d1, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(ck_th(0), th, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(ck_om(0), om, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
+      if (has_bodies)
+        HIPCHK(hipMemcpyAsync(ckb(0), body, sizeof(T) * P * rods::NB_VALS, hipMemcpyDeviceToDevice, st));
       for (int seg = 0; seg < nseg; ++seg) {
         a.step_off = seg * Kc;
         a.n_steps = std::min(Kc, n_steps - seg * Kc);
@@ -556,10 +610,13 @@ struct Impl : HandleBase {
         if (seg + 1 < nseg) {
           a.ck_x = ck_x(seg + 1); a.ck_v = ck_v(seg + 1); a.ck_kb = ck_kb(seg + 1);
           a.ck_d1 = ck_d1(seg + 1); a.ck_th = ck_th(seg + 1); a.ck_om = ck_om(seg + 1);
+          a.ck_body = has_bodies ? ckb(seg + 1) : nullptr;
         } else {
           a.ck_x = a.ck_v = a.ck_kb = a.ck_d1 = nullptr;
+          a.ck_body = nullptr;
           which = 1;   // the last segment also writes its substep tape
           a.tape = tape_for(seg);
+          a.btape = btape_for(a.tape);
         }
         int e = launch_all(which, a, st);
         if (e) return e;
@@ -606,6 +663,8 @@ struct Impl : HandleBase {
     HIPCHK(rods::launch_fill<T>(dU, (int64_t)n_act * R * G * 3, T(0), st));
     HIPCHK(rods::launch_fill<double>(acc_b, V, 0.0, st));
     HIPCHK(rods::launch_fill<double>(acc_s, V, 0.0, st));
+    if (has_bodies)
+      HIPCHK(hipMemcpyAsync(lbody, bseed, sizeof(T) * P * rods::NB_VALS, hipMemcpyDeviceToDevice, st));
     // replay segment seg from its checkpoint on stream rs, writing its
     // substep-start states into buf
     auto replay = [&](int seg, T* buf, hipStream_t rs) -> int {
@@ -616,12 +675,17 @@ struct Impl : HandleBase {
       HIPCHK(hipMemcpyAsync(sd1, ck_d1(seg), sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, rs));
       HIPCHK(hipMemcpyAsync(sth, ck_th(seg), sizeof(T) * V, hipMemcpyDeviceToDevice, rs));
       HIPCHK(hipMemcpyAsync(som, ck_om(seg), sizeof(T) * V, hipMemcpyDeviceToDevice, rs));
+      if (has_bodies)
+        HIPCHK(hipMemcpyAsync(sbody, ckb(seg), sizeof(T) * P * rods::NB_VALS,
+                              hipMemcpyDeviceToDevice, rs));
       RodArgs<T> a = args(rs);
       a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1; a.th = sth; a.om = som;
+      a.body = sbody;
       a.u = acts;
       a.step_off = s0;
       a.n_steps = ns;
       a.tape = buf;
+      a.btape = btape_for(buf);
       return launch_all(1, a, rs);
     };
     auto adjoint = [&](int seg, T* buf) -> int {
@@ -631,7 +695,9 @@ struct Impl : HandleBase {
       a.u = acts;
       a.step_off = s0;
       a.n_steps = ns;
+      a.body = sbody;
       a.tape = buf;
+      a.btape = btape_for(buf);
       a.dL_du = dU;
       return launch_all(2, a, st);
     };
@@ -692,11 +758,14 @@ struct Impl : HandleBase {
     HIPCHK(rods::launch_fill<T>(opt_mb, R, T(0), st));
     HIPCHK(rods::launch_fill<T>(opt_vb, R, T(0), st));
     if (stiff) HIPCHK(rods::launch_log<T>(b, opt_logb, R, st));
+    if (has_bodies)
+      HIPCHK(hipMemcpyAsync(body_opt0, body, sizeof(T) * P * rods::NB_VALS, hipMemcpyDeviceToDevice, st));
     double best = HUGE_VAL;
     int stall = 0, done = 0;
     for (int k = 0; k < o->iters; ++k) {
       if (stiff) HIPCHK(rods::launch_exp<T>(opt_logb, b, R, st));
       int e = set_state(x0, v0, kb0, nullptr, st);
+      if (!e && has_bodies) e = set_bodies(body_opt0, st);
       if (!e) e = rollout(n_steps, U, opt_xT, 1, st);
       if (e) return e;
       HIPCHK(rods::launch_loss<T>(voff, R, opt_xT, target, loss_part, opt_loss, opt_g, st));
@@ -737,6 +806,8 @@ struct Impl : HandleBase {
     HIPCHK(hipMemcpyAsync(sd1, d1, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(sth, th, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(som, om, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
+    if (has_bodies)
+      HIPCHK(hipMemcpyAsync(sbody, body, sizeof(T) * P * rods::NB_VALS, hipMemcpyDeviceToDevice, st));
     std::vector<T> zeros((size_t)std::max(1, R * G * 3), T(0));
     T* u0 = du_scratch;
     HIPCHK(hipMemcpyAsync(u0, zeros.data(), sizeof(T) * zeros.size(), hipMemcpyHostToDevice, st));
@@ -755,10 +826,10 @@ struct Impl : HandleBase {
       const int team0 = 64 * bn.C * bn.W;   // smallest legal team of the bin
       for (int C : Cs)
         for (int W : Ws)
-          if (64 * W * C >= nmax && 64 * W * C <= 2 * team0 && !((prec == 8 || bn.tw) && C != 2) &&
+          if (64 * W * C >= nmax && 64 * W * C <= 2 * team0 && !((prec == 8 || bn.tw || bn.bd) && C != 2) &&
               !(C == 4 && W == 8) && (!bn.sc || sc_shape_ok(C, W)) &&
-              rods::kernel_lds_bytes<T>(2, C, W, bn.sc, global_tape(C, W, bn.sc), d.n_iters) <=
-                  lds_max)
+              rods::kernel_lds_bytes<T>(2, C, W, bn.sc, global_tape(C, W, bn.sc), d.n_iters) +
+                      body_lds() <= lds_max)
             cand.push_back({C, W});
       float best = 1e30f;
       std::pair<int, int> bestk{bn.C, bn.W};
@@ -766,6 +837,7 @@ struct Impl : HandleBase {
         RodArgs<T> a = args(st);
         a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;   // time on the scratch copy
         a.th = sth; a.om = som;
+        a.body = sbody;
         a.u = u0; a.act_stride = 0; a.spa = 1; a.step_off = 0; a.n_steps = n_steps;
         a.rods = bin_rods + bn.off;
         HIPCHK(launch_bin(0, bn, cw.first, cw.second, false, a, bn.n, st));   // warm
@@ -843,6 +915,27 @@ static int validate(const RodsDesc* d) {
     if (P > 0 && !d->prims) return ROD_EINVAL;
     for (int k = 0; k < P; ++k)
       if (d->prims[k].type < 0 || d->prims[k].type > 2) return ROD_EINVAL;
+    if (d->prim_inv_mass) {
+      // moving bodies: spheres, on rods of at most NB_MAX primitives without
+      // self-contact or twist
+      for (int r = 0; r < d->n_rods; ++r) {
+        bool moving = false;
+        for (int k = d->prim_offsets[r]; k < d->prim_offsets[r + 1]; ++k) {
+          const double wk = d->prim_inv_mass[k];
+          if (!(wk >= 0)) return ROD_EINVAL;
+          if (wk > 0) {
+            if (d->prims[k].type != ROD_PRIM_SPHERE || !d->prim_inv_inertia ||
+                !(d->prim_inv_inertia[k] >= 0))
+              return ROD_EINVAL;
+            moving = true;
+          }
+        }
+        const int fl = (int)d->rod_params[(size_t)r * ROD_NPARAM + ROD_P_FLAGS];
+        if (moving && (d->prim_offsets[r + 1] - d->prim_offsets[r] > rods::NB_MAX ||
+                       (fl & (ROD_FLAG_SELF | ROD_FLAG_TWIST))))
+          return ROD_EINVAL;
+      }
+    }
   }
   if (!(d->dt > 0) || d->n_sub < 1 || d->n_iters < 0 || d->n_iters > 32 ||
       d->steps_per_action < 1 || d->ckpt_every < 1 || d->max_steps < 0 || !(d->eps_s > 0))
@@ -943,6 +1036,53 @@ int rods_get_twist(RodsHandle* h, void* theta, void* theta_dot, rods_stream_t st
     size_t V = I->V;
     if (theta) HIPCHK(hipMemcpyAsync(theta, I->th, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
     if (theta_dot) HIPCHK(hipMemcpyAsync(theta_dot, I->om, sizeof(T) * V, hipMemcpyDeviceToDevice, st));
+    return (int)ROD_OK;
+  });
+}
+
+int rods_set_bodies(RodsHandle* h, const void* body, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    return I->set_bodies((const T*)body, (hipStream_t)stream);
+  });
+}
+
+int rods_get_bodies(RodsHandle* h, void* body, rods_stream_t stream) {
+  if (!h || !body) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t nb = (size_t)I->P * rods::NB_VALS;
+    if (nb == 0) return (int)ROD_OK;
+    if (I->has_bodies) HIPCHK(hipMemcpyAsync(body, I->body, sizeof(T) * nb, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(hipMemcpyAsync(body, I->body_init_h.data(), sizeof(T) * nb, hipMemcpyHostToDevice, st));
+    return (int)ROD_OK;
+  });
+}
+
+int rods_set_body_adjoint(RodsHandle* h, const void* dL_dbodyT, rods_stream_t stream) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    hipStream_t st = (hipStream_t)stream;
+    if (!I->has_bodies) return (int)ROD_OK;
+    const int64_t nb = (int64_t)I->P * rods::NB_VALS;
+    if (dL_dbodyT) HIPCHK(hipMemcpyAsync(I->bseed, dL_dbodyT, sizeof(T) * nb, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(rods::launch_fill<T>(I->bseed, nb, T(0), st));
+    return (int)ROD_OK;
+  });
+}
+
+int rods_get_body_adjoint(RodsHandle* h, void* dL_dbody0, rods_stream_t stream) {
+  if (!h || !dL_dbody0) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nb = (int64_t)I->P * rods::NB_VALS;
+    if (nb == 0) return (int)ROD_OK;
+    if (I->has_bodies) HIPCHK(hipMemcpyAsync(dL_dbody0, I->lbody, sizeof(T) * nb, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(rods::launch_fill<T>((T*)dL_dbody0, nb, T(0), st));
     return (int)ROD_OK;
   });
 }

@@ -2,7 +2,7 @@
 launch-shape autotuner and the HIP-graph step path buy.  Prints one JSON
 line per measurement.
 
-    python -m paper_2606_04206_amd.measure_configs [--configs 2 3 4 5 6]
+    python -m paper_2606_04206_amd.measure_configs [--configs 2 3 4 5 6 7]
 
 Configuration 3 (the benchmark's batch) is measured as the optimisation
 driver: iterations of Adam on the grasp velocities, and on the grasp
@@ -79,7 +79,7 @@ def _measure_optimize(iters):
 
 def main():
     p = argparse.ArgumentParser()
-    p.add_argument("--configs", type=int, nargs="*", default=[2, 3, 4, 5, 6])
+    p.add_argument("--configs", type=int, nargs="*", default=[2, 3, 4, 5, 6, 7])
     p.add_argument("--opt-iters", type=int, default=5)
     a = p.parse_args()
     import torch
@@ -93,7 +93,7 @@ def main():
             _measure_optimize(a.opt_iters)
             continue
         wl = make_workload(cid)
-        n = {2: 500, 4: 100, 5: 100, 6: 1000}.get(cid, 100)
+        n = {2: 500, 4: 100, 5: 100, 6: 1000, 7: 1000}.get(cid, 100)
         K = wl.sim.ckpt_every
         x0, v0 = _dev(wl.x0, f32), _dev(wl.v0, f32)
         h = RodsHandle(wl, precision=4, max_steps=max(n, K), ckpt_every=K)
@@ -103,13 +103,20 @@ def main():
         U = _dev(wl.actions[:h.n_actions(n)], f32)
         xT = h.tensor(wl.n_vert, 3)
         shapes0 = [list(b) for b in h.bins()]
+        bodies = wl.prim_inv_mass is not None
+
+        def reset():
+            # rods and (configuration 7) the moving spheres back to their start
+            h.set_state(x0, v0, kb0)
+            if bodies:
+                h.set_bodies()
 
         def fwd():
-            h.set_state(x0, v0, kb0)
+            reset()
             h.rollout(n, U, x_final=xT)
-        h.set_state(x0, v0, kb0)
+        reset()
         t_default = _timed(fwd)
-        h.set_state(x0, v0, kb0)
+        reset()
         h.autotune(n_steps=3)
         shapes1 = [list(b) for b in h.bins()]
         t_tuned = _timed(fwd)
@@ -129,9 +136,9 @@ def main():
         def graph():
             for _ in range(n_eager):
                 h.step_graph(u0)
-        h.set_state(x0, v0, kb0)
+        reset()
         t_e = _timed(eager)
-        h.set_state(x0, v0, kb0)
+        reset()
         t_g = _timed(graph)
         _emit(config=cid, measure="single steps, eager vs HIP graph", steps=n_eager,
               eager_ms_per_step=1e3 * t_e / n_eager, graph_ms_per_step=1e3 * t_g / n_eager,
@@ -141,7 +148,7 @@ def main():
             tgt = _dev(wl.target, f32)
 
             def fwd_bwd():
-                h.set_state(x0, v0, kb0)
+                reset()
                 h.rollout(n, U, record=True, x_final=xT)
                 _, g = h.loss_mse(xT, tgt)
                 h.backward(g, n_steps=n)

@@ -31,7 +31,8 @@ class RodsDesc(ctypes.Structure):
                 ("f_thresh", c_double), ("self_margin", c_double),
                 ("n_sub", c_int32), ("n_iters", c_int32), ("k_exclude", c_int32),
                 ("steps_per_action", c_int32), ("ckpt_every", c_int32), ("max_steps", c_int32),
-                ("twist_inv_inertia", POINTER(c_double))]
+                ("twist_inv_inertia", POINTER(c_double)),
+                ("prim_inv_mass", POINTER(c_double)), ("prim_inv_inertia", POINTER(c_double))]
 
 
 class RodsAdam(ctypes.Structure):
@@ -42,7 +43,8 @@ class RodsAdam(ctypes.Structure):
 
 
 EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "rods_get_state",
-           "rods_set_twist", "rods_get_twist", "rods_set_params", "rods_get_params",
+           "rods_set_twist", "rods_get_twist", "rods_set_bodies", "rods_get_bodies",
+           "rods_set_body_adjoint", "rods_get_body_adjoint", "rods_set_params", "rods_get_params",
            "rods_optimize", "rods_curvature", "rods_step", "rods_step_graph", "rods_rollout",
            "rods_backward",
            "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_plain",
@@ -75,6 +77,10 @@ def load():
         "rods_optimize": ([vp, POINTER(RodsAdam), c_int32, vp, vp, vp, vp, vp,
                            POINTER(c_double), POINTER(c_int32), vp], c_int32),
         "rods_get_twist": ([vp, vp, vp, vp], c_int32),
+        "rods_set_bodies": ([vp, vp, vp], c_int32),
+        "rods_get_bodies": ([vp, vp, vp], c_int32),
+        "rods_set_body_adjoint": ([vp, vp, vp], c_int32),
+        "rods_get_body_adjoint": ([vp, vp, vp], c_int32),
         "rods_set_params": ([vp, vp, vp, vp], c_int32),
         "rods_curvature": ([vp, vp, vp, vp, vp], c_int32),
         "rods_step": ([vp, vp, vp], c_int32),
@@ -170,6 +176,10 @@ class RodsHandle:
         d.max_steps = self.max_steps
         jt = getattr(wl, "twist_inv_inertia", None)
         d.twist_inv_inertia = arr(jt, c_double) if jt is not None else None
+        pw = getattr(wl, "prim_inv_mass", None)
+        d.prim_inv_mass = arr(pw, c_double) if pw is not None and P else None
+        d.prim_inv_inertia = arr(wl.prim_inv_inertia, c_double) if pw is not None and P else None
+        self.P = P
         h = c_void_p()
         _check(lib.rods_create(ctypes.byref(d), ctypes.byref(h)), "rods_create")
         self._h = h
@@ -221,6 +231,30 @@ class RodsHandle:
         _check(self._lib.rods_get_twist(self._h, _ptr(th), _ptr(om), _stream()),
                "rods_get_twist")
         return th, om
+
+    def set_bodies(self, body=None):
+        """Moving rigid bodies, [P, 9] = (centre, velocity, angular velocity)
+        per primitive; None = the primitives' centres, at rest."""
+        _require(body, (self.P, 9), self.dtype, "body")
+        _check(self._lib.rods_set_bodies(self._h, _ptr(body), _stream()), "rods_set_bodies")
+
+    def get_bodies(self):
+        out = self.tensor(max(self.P, 1), 9)[:self.P]
+        if self.P:
+            _check(self._lib.rods_get_bodies(self._h, _ptr(out), _stream()), "rods_get_bodies")
+        return out
+
+    def set_body_adjoint(self, dL_dbodyT=None):
+        _require(dL_dbodyT, (self.P, 9), self.dtype, "dL_dbodyT")
+        _check(self._lib.rods_set_body_adjoint(self._h, _ptr(dL_dbodyT), _stream()),
+               "rods_set_body_adjoint")
+
+    def get_body_adjoint(self):
+        out = self.tensor(max(self.P, 1), 9)[:self.P]
+        if self.P:
+            _check(self._lib.rods_get_body_adjoint(self._h, _ptr(out), _stream()),
+                   "rods_get_body_adjoint")
+        return out
 
     def set_params(self, b=None, sigma_y=None):
         _require(b, (self.R,), self.dtype, "b")

@@ -78,6 +78,13 @@ CONFIGS = {
                           "degree of freedom (twisting modulus 1e3 Pa), the grippers "
                           "holding the end edges' twist, 1000 steps, checkpoint every "
                           "50, MSE loss"),
+    7: Config(7, "batch_1024x128_moving_spheres_fwd_adjoint_1000steps", 1024, 128,
+              sim=SimParams(n_sub=15, steps=1000, steps_per_action=2, ckpt_every=50),
+              backward=True,
+              oracle_rods=(0, 146, 292, 438, 585, 731, 877, 1023),
+              description="the 1024 x 128 forward + adjoint batch with two moving "
+                          "spheres under each rod (two-way rigid coupling), 1000 "
+                          "steps, checkpoint every 50, MSE loss"),
 }
 
 

@@ -20,7 +20,8 @@ from .configs import CONFIGS, Config, SimParams
 PRIM_PLANE, PRIM_SPHERE, PRIM_CAPSULE = 0, 1, 2
 FLAG_INEXT, FLAG_PLASTIC, FLAG_SELF, FLAG_TWIST = 1, 2, 4, 8
 N_ROD_PARAMS = 8   # flags, K (Pa), b (N m^2), sigma_y (1/m), r_c, mu, restitution, G (Pa)
-G_TWIST = 1e3      # twisting modulus of the paper's task table (Pa)
+G_TWIST = 1e3   # twisting modulus of the paper's task table (Pa)
+BODY_DENSITY = 300.0   # moving spheres of configuration 7 (kg/m^3, a foam ball)
 
 RADIUS = 5e-3      # m
 DENSITY = 1000.0   # kg/m^3
@@ -50,6 +51,8 @@ class Workload:
     x_rest: Optional[np.ndarray] = None   # [V,3] shape whose curvature is the rest curvature
     oracle_rods: tuple = ()
     twist_inv_inertia: Optional[np.ndarray] = None   # [V] per edge (edge rows); twist rods
+    prim_inv_mass: Optional[np.ndarray] = None       # [P] 1/M, > 0 for moving spheres
+    prim_inv_inertia: Optional[np.ndarray] = None    # [P] inverse moment of inertia
 
     @property
     def n_rods(self):
@@ -95,7 +98,10 @@ class Workload:
             x_rest=None if self.x_rest is None else self.x_rest[vidx].copy(),
             oracle_rods=tuple(range(len(rods))),
             twist_inv_inertia=None if self.twist_inv_inertia is None
-            else self.twist_inv_inertia[vidx].copy())
+            else self.twist_inv_inertia[vidx].copy(),
+            prim_inv_mass=None if self.prim_inv_mass is None else self.prim_inv_mass[pidx].copy(),
+            prim_inv_inertia=None if self.prim_inv_inertia is None
+            else self.prim_inv_inertia[pidx].copy())
 
 
 # ----------------------------------------------------------------------------
@@ -227,16 +233,19 @@ def make_workload(cid: int, steps: Optional[int] = None,
     spa = sim.steps_per_action
     n_act = -(-sim.steps // spa)
     action_dt = spa * sim.dt
-    # configurations 3 and 6 are configuration 2's batch with a target: same
-    # rod stream (6 adds twist, with the twist of both end edges held)
-    rng = np.random.default_rng([SEED0, 2 if cid in (3, 6) else cid])
-    rng_target = np.random.default_rng([SEED0, 3 if cid == 6 else cid, 1])
+    # configurations 3, 6 and 7 are configuration 2's batch with a target:
+    # same rod stream (6 adds twist, with the twist of both end edges held;
+    # 7 adds two moving spheres per rod, drawn from a stream of their own)
+    rng = np.random.default_rng([SEED0, 2 if cid in (3, 6, 7) else cid])
+    rng_target = np.random.default_rng([SEED0, 3 if cid in (6, 7) else cid, 1])
+    rng_body = np.random.default_rng([SEED0, cid, 2])
+    pw, pii = [], []
 
     R = cfg.n_rods
     xs, rests, invm, rads, gidx, params, acts, tgts, xrests = [], [], [], [], [], [], [], [], []
     ptype, pa, pb, pr, pcount = [], [], [], [], []
     jts = []
-    G = {1: 0, 2: 2, 3: 2, 4: 2, 5: 4, 6: 2}[cid]
+    G = {1: 0, 2: 2, 3: 2, 4: 2, 5: 4, 6: 2, 7: 2}[cid]
 
     for r in range(R):
         # ---------------- material
@@ -263,13 +272,13 @@ def make_workload(cid: int, steps: Optional[int] = None,
             x = x_clean.copy()
             x[1:] += rng.normal(0.0, 1e-3, size=(n - 1, 3))
             xr = None
-        elif cid in (2, 3, 4, 6):
+        elif cid in (2, 3, 4, 6, 7):
             n = cfg.n_vert if cfg.n_vert else int(rng.integers(cfg.n_min, cfg.n_max + 1))
             edge = EDGE_LEN
             x_clean = arc_polyline(n, edge, 0.6)
             x_clean = _rot_z(x_clean, rng.uniform(0.0, 2.0 * np.pi))
             x_clean[:, 2] += (start_height if start_height is not None
-                              else (0.5 if cid in (2, 3, 6) else 0.3))
+                              else (0.5 if cid in (2, 3, 6, 7) else 0.3))
             x = x_clean.copy()
             xr = None
         else:
@@ -329,6 +338,23 @@ def make_workload(cid: int, steps: Optional[int] = None,
                     ptype.append(PRIM_CAPSULE); pa.append(c - hl * ax); pb.append(c + hl * ax)
                     pr.append(rad)
             pcount.append(k + 1)
+            pw.extend([0.0] * (k + 1))
+            pii.extend([0.0] * (k + 1))
+        elif cid == 7:
+            # two free spheres just under the rod at a third and two thirds
+            # of its length, inside the soft-contact band: the sagging rod
+            # presses on them and they roll away
+            params[-1][5] = rng_body.uniform(0.2, 0.8)          # friction with them
+            for i in (n // 3, (2 * n) // 3):
+                rad = rng_body.uniform(0.03, 0.06)
+                gap = rng_body.uniform(0.0, 2e-3)
+                side = rng_body.normal(0.0, 3e-3, 2)
+                c = x_clean[i] + np.array([side[0], side[1], -(rad + RADIUS + gap)])
+                M = BODY_DENSITY * 4.0 / 3.0 * np.pi * rad ** 3
+                ptype.append(PRIM_SPHERE); pa.append(c); pb.append(c); pr.append(rad)
+                pw.append(1.0 / M)
+                pii.append(2.5 / (M * rad * rad))               # solid sphere, I = 2/5 M R^2
+            pcount.append(2)
         else:
             pcount.append(0)
 
@@ -367,4 +393,6 @@ def make_workload(cid: int, steps: Optional[int] = None,
         target=np.concatenate(tgts) if tgts else None,
         x_rest=np.concatenate(xrests) if cid == 5 else None,
         oracle_rods=oracle_rods,
-        twist_inv_inertia=np.concatenate(jts) if cid == 6 else None)
+        twist_inv_inertia=np.concatenate(jts) if cid == 6 else None,
+        prim_inv_mass=np.array(pw, np.float64) if cid == 7 else None,
+        prim_inv_inertia=np.array(pii, np.float64) if cid == 7 else None)

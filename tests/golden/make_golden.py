@@ -2,14 +2,16 @@
 curvatures (and twist angles for twisting rods), loss terms and gradients
 (grasp velocities, bending stiffness, yield curvature, initial positions and
 velocities) for the 8 sampled rods of a 1024 x 128, 1000-step workload with
-checkpoints every 50 steps: configuration 3 (rods without twist) or 6 (with
-the twist degree of freedom).  Also stores, per rod and quantity, how far
+checkpoints every 50 steps: configuration 3 (rods without twist), 6 (with
+the twist degree of freedom) or 7 (with moving spheres: also their final
+state and the adjoint of their initial state).  Also stores, per rod and quantity, how far
 the same run moves when the initial positions change by 1e-15 relative
 (`spread_<name>`): the trajectory's own sensitivity to FP64 rounding, which
 a comparison over 15000 substeps cannot beat.  Calls only the oracle and the
 input generators; run from the repository root:
     python tests/golden/make_golden.py 3
     python tests/golden/make_golden.py 6
+    python tests/golden/make_golden.py 7
 """
 import os
 import sys
@@ -42,10 +44,14 @@ def one_rod(cid, rod, eps=0.0):
     t0 = time.time()
     xT, ck = ofw.rollout(orods, osim, st, sub.actions, n, K)
     L, gx = oadj.loss_mse(xT.x, sub.target.reshape(xT.x.shape), wl.n_rods)
-    x0b, v0b, Ub, bb, sb = oadj.backward(orods, osim, ck, sub.actions, n, K, gx)
+    x0b, v0b, Ub, bb, sb, b0b = oadj.backward(orods, osim, ck, sub.actions, n, K, gx,
+                                              with_body=True)
     print(f"rod {rod} (start moved by {eps:g}): {time.time() - t0:.1f} s", flush=True)
-    return dict(xT=xT.x[0], loss=L, u=Ub[:, 0], b=bb[0], sigma=sb[0], x0=x0b[0], v0=v0b[0],
-                kbT=xT.kb[0], thetaT=xT.theta[0])
+    out = dict(xT=xT.x[0], loss=L, u=Ub[:, 0], b=bb[0], sigma=sb[0], x0=x0b[0], v0=v0b[0],
+               kbT=xT.kb[0], thetaT=xT.theta[0])
+    if orods.has_bodies:
+        out.update(bodyT=xT.body[0], body0=b0b[0])
+    return out
 
 
 def main():
@@ -56,9 +62,10 @@ def main():
     with get_context("spawn").Pool(len(rods)) as pool:
         res = pool.starmap(partial(one_rod, cid), [(r, 0.0) for r in rods] + [(r, 1e-15) for r in rods])
     base, moved = res[:len(rods)], res[len(rods):]
+    names = NAMES + (("bodyT", "body0") if "bodyT" in base[0] else ())
     spread = {"spread_" + k: np.array([np.linalg.norm(np.ravel(m[k]) - np.ravel(b[k]))
                                        / max(np.linalg.norm(np.ravel(b[k])), 1e-300)
-                                       for b, m in zip(base, moved)]) for k in NAMES}
+                                       for b, m in zip(base, moved)]) for k in names}
     np.savez_compressed(out, rods=np.array(rods),
                         **{k: np.stack([r[k] for r in base]) for k in base[0]}, **spread)
     print("wrote", out)

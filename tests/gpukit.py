@@ -42,8 +42,9 @@ def oracle_state_rows(wl, rods, st, n_fields=4):
     return out
 
 
-def gather_state(wl, rods, full):
-    """Full-batch arrays -> oracle State for `rods` (equal sizes)."""
+def gather_state(wl, rods, full, body=None):
+    """Full-batch arrays -> oracle State for `rods` (equal sizes); body: the
+    full [P, 9] body rows (moving rigid bodies), gathered per rod."""
     n = wl.rod_range(rods[0])[1] - wl.rod_range(rods[0])[0]
     idx = rows(wl, rods)
     x, v, kb, d1 = (np.asarray(a, np.float64)[idx].reshape(len(rods), n, -1) for a in full[:4])
@@ -51,7 +52,36 @@ def gather_state(wl, rods, full):
         th, om = (np.asarray(a, np.float64)[idx].reshape(len(rods), n)[:, :-1] for a in full[4:6])
     else:
         th = om = np.zeros((len(rods), n - 1))
-    return State(x, v, kb, d1[:, :-1], th, om)
+    if body is None:
+        return State(x, v, kb, d1[:, :-1], th, om)
+    return State(x, v, kb, d1[:, :-1], th, om, gather_bodies(wl, rods, body))
+
+
+def gather_bodies(wl, rods, body):
+    """[P, 9] rows of the workload's primitives -> [B, P_max, 9] per rod."""
+    counts = [wl.prim_offsets[r + 1] - wl.prim_offsets[r] for r in rods]
+    out = np.zeros((len(rods), max(counts), 9))
+    for bi, r in enumerate(rods):
+        k0 = wl.prim_offsets[r]
+        out[bi, :counts[bi]] = np.asarray(body, np.float64)[k0:k0 + counts[bi]]
+    return out
+
+
+def scatter_bodies(wl, rods, ob, full=None):
+    """Oracle bodies [B, P_max, 9] of `rods` -> [P, 9] rows (into a copy of
+    `full`, else into the initial rows)."""
+    out = initial_bodies(wl) if full is None else np.array(full, np.float64)
+    for bi, r in enumerate(rods):
+        k0, k1 = wl.prim_offsets[r], wl.prim_offsets[r + 1]
+        out[k0:k1] = ob[bi, :k1 - k0]
+    return out
+
+
+def initial_bodies(wl):
+    """[P, 9]: every primitive at its centre, at rest."""
+    out = np.zeros((len(wl.prim_type), 9))
+    out[:, :3] = wl.prim_a
+    return out
 
 
 def initial_full_state(wl, dtype=np.float64):

@@ -33,11 +33,13 @@ def test_struct_layouts(tmp_path):
     """The ctypes mirrors have the C compiler's sizes and offsets."""
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "rods.h"\n'
-                    'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
+                    'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
                     'sizeof(RodsDesc), sizeof(RodsPrim), offsetof(RodsDesc, dt), '
                     'offsetof(RodsDesc, n_sub), offsetof(RodsDesc, max_steps), '
                     'offsetof(RodsDesc, twist_inv_inertia), sizeof(RodsAdam), '
-                    'offsetof(RodsAdam, lr0), offsetof(RodsAdam, eps)); return 0;}\n')
+                    'offsetof(RodsAdam, lr0), offsetof(RodsAdam, eps), '
+                    'offsetof(RodsDesc, prim_inv_mass), offsetof(RodsDesc, prim_inv_inertia));'
+                    ' return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
                    check=True)
@@ -46,7 +48,8 @@ def test_struct_layouts(tmp_path):
     py = [ctypes.sizeof(R.RodsDesc), ctypes.sizeof(R.RodsPrim), R.RodsDesc.dt.offset,
           R.RodsDesc.n_sub.offset, R.RodsDesc.max_steps.offset,
           R.RodsDesc.twist_inv_inertia.offset, ctypes.sizeof(R.RodsAdam), R.RodsAdam.lr0.offset,
-          R.RodsAdam.eps.offset]
+          R.RodsAdam.eps.offset, R.RodsDesc.prim_inv_mass.offset,
+          R.RodsDesc.prim_inv_inertia.offset]
     assert c == py
 
 
@@ -72,3 +75,51 @@ def test_strerror_and_invalid_descriptions():
     assert lib.rods_create(ctypes.byref(d), ctypes.byref(h)) == -5
     assert lib.rods_backward(None, None, None, None, None, None, None, None, None) == -1
     assert lib.rods_status(None, None, None) == -1
+
+
+def test_moving_body_descriptions_are_validated():
+    """Moving bodies are spheres with a non-negative inverse inertia, on rods
+    of at most 16 primitives without self-contact or twist; the checks run
+    before any device call."""
+    lib = R.load()
+    h = ctypes.c_void_p()
+    keep = []
+
+    def ptr(a, ct=ctypes.c_double):
+        a = np.ascontiguousarray(a)
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(ct))
+
+    def desc(types, w, ii, flags=1, n_prims=None):
+        P = len(types)
+        prims = (R.RodsPrim * P)()
+        for k, ty in enumerate(types):
+            prims[k].type = ty
+            prims[k].b[:] = [0.0, 0.0, 1.0]
+            prims[k].radius = 0.05
+        keep.append(prims)
+        d = R.RodsDesc()
+        d.n_rods, d.precision = 1, 4
+        d.vert_offsets = ptr(np.array([0, 8], np.int32), ctypes.c_int32)
+        params = np.zeros(R.ROD_NPARAM)
+        params[0] = flags
+        d.rod_params = ptr(params)
+        for f in ("radius", "inv_mass", "rest_len"):
+            setattr(d, f, ptr(np.full(8, 0.01)))
+        d.twist_inv_inertia = ptr(np.ones(8))
+        d.prims = prims
+        d.prim_offsets = ptr(np.array([0, P], np.int32), ctypes.c_int32)
+        d.prim_inv_mass = ptr(np.asarray(w, np.float64))
+        d.prim_inv_inertia = ptr(np.asarray(ii, np.float64)) if ii is not None else None
+        d.dt, d.n_sub, d.n_iters, d.steps_per_action, d.ckpt_every, d.eps_s = \
+            1e-3, 1, 1, 1, 1, 1e-3
+        return d
+    bad = [desc([2], [1.0], [1.0]),                      # a moving capsule
+           desc([1], [1.0], None),                        # no inverse inertia
+           desc([1], [1.0], [-1.0]),                      # negative inverse inertia
+           desc([1], [-1.0], [1.0]),                      # negative inverse mass
+           desc([1] * 17, [1.0] * 17, [1.0] * 17),        # too many primitives
+           desc([1], [1.0], [1.0], flags=1 | 4),          # with self-contact
+           desc([1], [1.0], [1.0], flags=1 | 8)]          # with twist
+    for d in bad:
+        assert lib.rods_create(ctypes.byref(d), ctypes.byref(h)) == -1
