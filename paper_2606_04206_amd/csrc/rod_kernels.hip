@@ -624,6 +624,24 @@ struct Rod {
     for (int i = tl; i < (p1 - p0) * NB_VALS; i += TL) dst[i] = src[(int64_t)p0 * NB_VALS + i];
     __syncthreads();
   }
+  // the adjoint's body tape, one substep ahead: each lane holds up to BPF
+  // values of the rod's block in registers until install_bodies
+  static constexpr int BPF = (NB_MAX * NB_VALS + TL - 1) / TL;
+  __device__ void fetch_bodies(const T* src, T (&pf)[BPF]) const {
+#pragma unroll
+    for (int q = 0; q < BPF; ++q) {
+      const int i = tl + q * TL;
+      pf[q] = i < (p1 - p0) * NB_VALS ? src[(int64_t)p0 * NB_VALS + i] : T(0);
+    }
+  }
+  __device__ void install_bodies(const T (&pf)[BPF]) const {
+#pragma unroll
+    for (int q = 0; q < BPF; ++q) {
+      const int i = tl + q * TL;
+      if (i < (p1 - p0) * NB_VALS) bs[i] = pf[q];
+    }
+    __syncthreads();
+  }
   __device__ void store_bodies(T* dst, const T* src) const {
     for (int i = tl; i < (p1 - p0) * NB_VALS; i += TL) dst[(int64_t)p0 * NB_VALS + i] = src[i];
   }
@@ -1575,7 +1593,9 @@ struct Rod {
     // S4 rigid contact, primitives in order.  A moving body takes the
     // opposite of the summed momentum change and its moment, then its
     // centre moves (symplectic Euler); its block in LDS is rewritten once
-    // every lane has read it (the team sum orders that).
+    // every lane has read it (the team sum orders that).  The adjoint's
+    // replay (REC) leaves the bodies at their substep-start state, which
+    // is all its VJP reads.
     if (p1 > p0) {
       for (int k = p0; k < p1; ++k) {
         Prim<T> pr = load_prim(a, k);
@@ -1593,7 +1613,8 @@ struct Rod {
             if (w[c] > T(0)) {
               const V3<T> vin = v[c];
               V3<T> n;
-              if (contact_moving(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, Vb, Om, v[c], n)) {
+              if (contact_moving(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, Vb, Om, v[c], n) &&
+                  !REC) {
                 const V3<T> dp = (T(1) / w[c]) * (v[c] - vin);
                 const V3<T> lm = cross(pr.r * n, dp);
                 acc[0] += dp.x; acc[1] += dp.y; acc[2] += dp.z;
@@ -1601,6 +1622,7 @@ struct Rod {
               }
             }
           }
+          if constexpr (REC) continue;
           X.sum(acc);
           if (tl == 0) {
             const T bwk = a.bw[k], bik = a.bii[k];
@@ -2257,6 +2279,8 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
   Rec<T, C> rec;
   T pf[Rod<T, C, W, SC, TW, BD>::NFIELD * C];
   R.fetch_tape(tape_rod + (int64_t)(a.n_steps * a.n_sub - 1) * a.tape_stride, pf);
+  T bpf[Rod<T, C, W, SC, TW, BD>::BPF];
+  if (BD && R.dyn) R.fetch_bodies(a.btape + (int64_t)(a.n_steps * a.n_sub - 1) * a.bstride, bpf);
   for (int s = a.n_steps - 1; s >= 0; --s) {
     const int act = (a.step_off + s) / a.spa;
     V3<T> ug[C];
@@ -2265,11 +2289,12 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
       R.install_tape(pf);
       const int nxt = s * a.n_sub + k - 1;   // the substep processed next
       if (nxt >= 0) R.fetch_tape(tape_rod + (int64_t)nxt * a.tape_stride, pf);
-      // the replay advances the bodies; the adjoint needs their start state
-      const T* btape_k = (BD && R.dyn) ? a.btape + (int64_t)(s * a.n_sub + k) * a.bstride : nullptr;
-      if (BD && R.dyn) R.load_bodies(R.bs, btape_k);
+      // the substep-start body states (the replay leaves them unchanged)
+      if (BD && R.dyn) {
+        R.install_bodies(bpf);
+        if (nxt >= 0) R.fetch_bodies(a.btape + (int64_t)nxt * a.bstride, bpf);
+      }
       R.template substep<true>(a, X, ug, &rec, lds_tape);
-      if (BD && R.dyn) R.load_bodies(R.bs, btape_k);
       R.substep_vjp(a, X, rec, lds_tape, lx, lv, lk0, lk1, ld1, accb, accs, uacc, lth, lom);
     }
     // grasp-velocity gradient of this step's action
