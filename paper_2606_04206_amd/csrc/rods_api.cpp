@@ -584,7 +584,10 @@ struct Impl : HandleBase {
     if (n_steps < 0) return ROD_EINVAL;
     if (record && n_steps > d.max_steps) return ROD_ESTATE;
     recorded = false;
-    if (n_steps == 0) return ROD_OK;
+    if (n_steps == 0) {
+      if (x_final) HIPCHK(hipMemcpyAsync(x_final, x, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
+      return ROD_OK;
+    }
     const int spa = d.steps_per_action;
     const int n_act = (n_steps + spa - 1) / spa;
     RodArgs<T> a = args(st);

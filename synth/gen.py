@@ -219,13 +219,19 @@ def _target_curve(rng, x_ref, rest_edges):
 def make_workload(cid: int, steps: Optional[int] = None,
                   start_height: Optional[float] = None, pitch: Optional[float] = None,
                   n_vert: Optional[int] = None, n_rods: Optional[int] = None,
-                  noise: Optional[float] = None) -> Workload:
+                  noise: Optional[float] = None, sizes=None) -> Workload:
     """Test knobs: start_height (configurations 2-4) replaces the initial arc
     height (tests start just above the ground, in contact); pitch, n_vert,
     n_rods and noise (configuration 5) replace the helix pitch (below 2 r
     the coils start in self-contact), the vertices per rod, the number of
-    rods and the standard deviation of the vertex noise (1 mm)."""
+    rods and the standard deviation of the vertex noise (1 mm); sizes
+    (configurations 2 and 3) gives one rod per entry with that many
+    vertices, grasp amplitudes scaled by L / 1.27 m as in configuration 4."""
     cfg = CONFIGS[cid]
+    if sizes is not None:
+        assert cid in (2, 3)
+        cfg = replace(cfg, n_rods=len(sizes), n_vert=None,
+                      oracle_rods=tuple(range(len(sizes))))
     if cid == 5 and (n_vert is not None or n_rods is not None):
         cfg = replace(cfg, n_vert=n_vert or cfg.n_vert, n_rods=n_rods or cfg.n_rods,
                       oracle_rods=(0, (n_rods or cfg.n_rods) - 1))
@@ -273,7 +279,10 @@ def make_workload(cid: int, steps: Optional[int] = None,
             x[1:] += rng.normal(0.0, 1e-3, size=(n - 1, 3))
             xr = None
         elif cid in (2, 3, 4, 6, 7):
-            n = cfg.n_vert if cfg.n_vert else int(rng.integers(cfg.n_min, cfg.n_max + 1))
+            if sizes is not None:
+                n = int(sizes[r])
+            else:
+                n = cfg.n_vert if cfg.n_vert else int(rng.integers(cfg.n_min, cfg.n_max + 1))
             edge = EDGE_LEN
             x_clean = arc_polyline(n, edge, 0.6)
             x_clean = _rot_z(x_clean, rng.uniform(0.0, 2.0 * np.pi))
@@ -313,7 +322,7 @@ def make_workload(cid: int, steps: Optional[int] = None,
                 gv = [int(round(k * (n - 1) / 3.0)) for k in range(4)]
             else:
                 gv = [0, n - 1]
-            scale = 1.0 if cid != 4 else min(1.0, (n - 1) * edge / 1.27)
+            scale = 1.0 if (cid != 4 and sizes is None) else min(1.0, (n - 1) * edge / 1.27)
             draws = [_grasp_draw(rng, scale) for _ in gv]
             acts.append(_grasp_actions(draws, n_act, action_dt))
             gidx.append(gv)

@@ -1,0 +1,135 @@
+"""GPU parity at the sizes where the kernels' lane and team boundaries fall,
+all in one ragged batch (several size bins), against the FP64 oracle one rod
+at a time.  Rods of configuration 3's kind with N = 2 (one edge, both
+vertices grasped: nothing free), 3 (one interior vertex), 4, 5, odd and even
+N on both sides of a full team of 64 lanes x 2 vertices x W waves, up to the
+largest rod a team holds (1024).
+
+* FP64 teacher-forced step from a seeded moving state: 1e-9 relative.
+* FP32 teacher-forced step: 1e-4 relative.
+* FP64 gradients of a 3-step rollout (checkpoint every 2, creep rate 0.5):
+  every block to 1e-9.
+* Bitwise: the one-rod-per-launch path equals the batched one, gradients do
+  not depend on the checkpoint interval.
+* Rollouts of zero steps leave the state as it was; a backward without a
+  recorded rollout is refused.
+"""
+import numpy as np
+import pytest
+import torch
+
+from synth import make_workload
+from oracle import forward as ofw, adjoint as oadj
+from oracle.model import rods_from_workload, sim_from_workload
+from tests.gpukit import to_dev, gather_state, initial_full_state, rel_err
+
+pytestmark = pytest.mark.gpu
+SIZES = [2, 3, 4, 5, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024]
+
+
+def _handle(wl, precision, **kw):
+    from paper_2606_04206_amd import RodsHandle
+    return RodsHandle(wl, precision=precision, **kw)
+
+
+def _dt(precision):
+    return torch.float32 if precision == 4 else torch.float64
+
+
+def _case(n_steps):
+    wl = make_workload(3, steps=n_steps, sizes=SIZES)
+    wl.rod_params[:, 4] = 0.5
+    full = initial_full_state(wl)
+    full[1] = np.random.default_rng(3).normal(0.0, 0.05, full[1].shape)
+    return wl, full
+
+
+def _oracle_step(wl, full, r):
+    orods, osim = rods_from_workload(wl, [r]), sim_from_workload(wl)
+    return ofw.step(orods, osim, gather_state(wl, [r], full), wl.actions[0, [r]])
+
+
+@pytest.mark.parametrize("precision,tol", [(8, 1e-9), (4, 1e-4)])
+def test_ragged_sizes_step_parity(precision, tol):
+    wl, full = _case(1)
+    if precision == 4:
+        full = [a.astype(np.float32).astype(np.float64) for a in full]
+    dt = _dt(precision)
+    h = _handle(wl, precision, max_steps=1)
+    assert sorted(b[:2] for b in h.bins()) == [(2, 1), (2, 2), (2, 4), (2, 8)]
+    h.set_state(*(to_dev(a, dt) for a in full))
+    h.step(to_dev(wl.actions[0], dt))
+    after = [t.double().cpu().numpy() for t in h.get_state()]
+    assert not h.status().any()
+    for r, n in enumerate(SIZES):
+        ref = _oracle_step(wl, full, r)
+        gpu = gather_state(wl, [r], after)
+        assert rel_err(gpu.x, ref.x) <= tol, n
+        assert rel_err(gpu.d1, ref.d1) <= tol, n
+        if precision == 8:
+            assert rel_err(gpu.v, ref.v) <= 1e-6, n
+            if n > 2:
+                assert rel_err(gpu.kb, ref.kb) <= 1e-7, n
+
+
+def _gpu_grads(wl, full, n, K, plain=False, precision=8):
+    dt = _dt(precision)
+    h = _handle(wl, precision, max_steps=n, ckpt_every=K)
+    h.set_plain(plain)
+    h.set_state(*(to_dev(a, dt) for a in full))
+    xT = h.tensor(wl.n_vert, 3)
+    h.rollout(n, to_dev(wl.actions, dt), record=True, x_final=xT)
+    _, g = h.loss_mse(xT, to_dev(wl.target, dt))
+    out = {k: v.double().cpu().numpy() for k, v in h.backward(g, n_steps=n).items()}
+    out["xT"] = xT.double().cpu().numpy()
+    assert not h.status().any()
+    return out
+
+
+def test_ragged_sizes_gradients_fp64():
+    n, K = 3, 2
+    wl, full = _case(n)
+    g = _gpu_grads(wl, full, n, K)
+    for r, size in enumerate(SIZES):
+        orods, osim = rods_from_workload(wl, [r]), sim_from_workload(wl)
+        st = gather_state(wl, [r], full)
+        U = wl.actions[:, [r]]
+        xT, ck = ofw.rollout(orods, osim, st, U, n, K)
+        a, b = wl.rod_range(r)
+        _, gx = oadj.loss_mse(xT.x, wl.target[a:b][None], wl.n_rods)
+        x0b, v0b, Ub, bb, sb = oadj.backward(orods, osim, ck, U, n, K, gx)
+        assert rel_err(g["xT"][a:b], xT.x[0]) <= 1e-9, size
+        assert rel_err(g["u"][:, r], Ub[:, 0]) <= 1e-9, size
+        assert rel_err(g["x0"][a:b], x0b[0]) <= 1e-9, size
+        assert rel_err(g["v0"][a:b], v0b[0]) <= 1e-9, size
+        if size > 2:
+            assert abs(g["b"][r] - bb[0]) <= 1e-9 * abs(bb[0]) + 1e-30, size
+            assert abs(g["sigma"][r] - sb[0]) <= 1e-9 * abs(sb[0]) + 1e-30, size
+        else:
+            # no interior vertex: no bending, no plasticity
+            assert g["b"][r] == 0.0 and g["sigma"][r] == 0.0
+
+
+def test_ragged_sizes_plain_equals_batched_and_checkpoint_invariance():
+    n = 4
+    wl, full = _case(n)
+    full = [a.astype(np.float32).astype(np.float64) for a in full]
+    outs = [_gpu_grads(wl, full, n, K, plain=plain, precision=4)
+            for plain, K in ((False, 2), (True, 2), (False, 1), (False, 4))]
+    for other in outs[1:]:
+        for k in ("xT", "u", "b", "sigma", "x0", "v0"):
+            np.testing.assert_array_equal(outs[0][k], other[k])
+
+
+def test_zero_step_rollout_and_backward_without_recording():
+    from paper_2606_04206_amd.rods import RodsError
+    wl, full = _case(1)
+    h = _handle(wl, 4, max_steps=1)
+    h.set_state(*(to_dev(a, torch.float32) for a in full))
+    x0 = h.get_state()[0].clone()
+    xT = torch.full_like(x0, float("nan"))
+    h.rollout(0, to_dev(wl.actions[:0], torch.float32), x_final=xT)
+    assert torch.equal(h.get_state()[0], x0)
+    assert torch.equal(xT, x0)
+    with pytest.raises(RodsError):
+        h.backward(torch.zeros_like(x0), n_steps=1)
