@@ -100,8 +100,10 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}): the rods of a batch are "
-              f"independent and this build measures one GPU's share; see DESIGN.md for how the "
-              f"path would shard.", file=sys.stderr)
+              f"independent, so the path shards by splitting the rod list into per-GPU parts "
+              f"balanced by vertex count, with no data exchanged during steps and one "
+              f"all-reduce of the scalar loss per backward; this benchmark measures one GPU's "
+              f"share.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

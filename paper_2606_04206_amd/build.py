@@ -12,7 +12,8 @@ BUILD = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-          # packed FP32 VALU forms stay off (hardware notes)
+          # packed FP32 VALU forms stay off: the kernels target the
+          # non-packed FP32 rate, with no v_pk_* FP32 arithmetic
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 # (source, extra flags, object): the kernel source is compiled a second time

@@ -1,6 +1,6 @@
 """GPU parity of the HIP path against the FP64 oracle (run through the C ABI).
 
-Tolerances (written here, derived in the design doc):
+Tolerances:
 * FP32 teacher-forced step: relative position error <= 1e-4 per rod (the
   stated bound), and yield decisions whose oracle margin exceeds 1e-5 agree
   exactly.
