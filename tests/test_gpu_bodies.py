@@ -237,3 +237,101 @@ def test_body_plain_equals_batched_and_checkpoint_invariance():
     for other in outs[1:]:
         for a, b in zip(outs[0], other):
             np.testing.assert_array_equal(a, b)
+
+
+# rods with moving spheres in every size bin: teams of 1, 2, 4 and 8 waves
+# (the team sums of the reactions cross waves through LDS)
+BIN_SIZES = [3, 65, 129, 200, 300, 513, 700, 1024]
+
+
+def _bins_case(n_steps, seed=4):
+    sub = make_workload(CID, steps=n_steps, sizes=BIN_SIZES)
+    sub.rod_params[:, 4] = 0.5
+    rng = np.random.default_rng(seed)
+    body = initial_bodies(sub)
+    body[:, 3:6] = rng.normal(0, 0.05, (len(body), 3))
+    body[:, 5] = 0.1 + np.abs(body[:, 5])       # rising into the rod above
+    body[:, 6:9] = rng.normal(0, 3.0, (len(body), 3))
+    return sub, initial_full_state(sub), body
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_moving_spheres_every_team_size_step(precision):
+    sub, full, body = _bins_case(1)
+    if precision == 4:
+        full = [a.astype(np.float32).astype(np.float64) for a in full]
+        body = body.astype(np.float32).astype(np.float64)
+    h = _handle(sub, precision=precision, max_steps=1)
+    assert sorted(b[:2] for b in h.bins()) == [(2, 1), (2, 2), (2, 4), (2, 8)]
+    _set(h, full, body, precision)
+    h.step(to_dev(sub.actions[0], _dt(precision)))
+    fr, b = _get(h)
+    assert not h.status().any()
+    moved = 0.0
+    for r, n in enumerate(BIN_SIZES):
+        orods, osim = rods_from_workload(sub, [r]), sim_from_workload(sub)
+        st = gather_state(sub, [r], full, body)
+        ref = ofw.step(orods, osim, st, sub.actions[0, [r]])
+        gpu = gather_state(sub, [r], fr, b)
+        tol = 1e-9 if precision == 8 else 1e-4
+        assert rel_err(gpu.x, ref.x) <= tol, n
+        assert rel_err(gpu.body[..., :3], ref.body[..., :3]) <= tol, n
+        assert rel_err(gpu.body[..., 3:], ref.body[..., 3:]) <= (1e-9 if precision == 8 else 1e-3), n
+        moved = max(moved, np.abs(ref.body[..., 3:] - st.body[..., 3:]).max())
+    assert moved > 1e-3
+
+
+def test_moving_spheres_every_team_size_gradients_and_invariance():
+    """FP64 gradients of a 3-step rollout (checkpoint every 2) against the
+    oracle one rod at a time (loss normalised by the batch's rod count, the
+    same cotangent on the spheres' final state): every block to 1e-9, the
+    spheres' start-state adjoint included; dL/db and dL/dsigma to 1e-9 or
+    three times the oracle's own FP64 sensitivity.  FP32: plain == batched
+    and checkpoint invariance, bitwise."""
+    from tests.gpukit import gather_bodies
+    n, K = 3, 2
+    sub, full, body = _bins_case(n)
+    sb = _seed(sub)
+    g = _gpu_grads(sub, full, body, 8, n, K, sb)
+    for r, size in enumerate(BIN_SIZES):
+        orods, osim = rods_from_workload(sub, [r]), sim_from_workload(sub)
+        st = gather_state(sub, [r], full, body)
+        U = sub.actions[:, [r]]
+        xT, ck = ofw.rollout(orods, osim, st, U, n, K)
+        a, b = sub.rod_range(r)
+        k0, k1 = sub.prim_offsets[r], sub.prim_offsets[r + 1]
+        _, gx = oadj.loss_mse(xT.x, sub.target[a:b][None], sub.n_rods)
+        x0b, v0b, Ub, bb, sbb, b0b = oadj.backward(
+            orods, osim, ck, U, n, K, gx, bodyT_b=gather_bodies(sub, [r], sb), with_body=True)
+        assert rel_err(g["xT"][a:b], xT.x[0]) <= 1e-9, size
+        assert rel_err(g["bodyT"][k0:k1], xT.body[0, :k1 - k0]) <= 1e-9, size
+        assert rel_err(g["u"][:, r], Ub[:, 0]) <= 1e-9, size
+        assert rel_err(g["x0"][a:b], x0b[0]) <= 1e-9, size
+        assert rel_err(g["v0"][a:b], v0b[0]) <= 1e-9, size
+        assert rel_err(g["body0"][k0:k1], b0b[0, :k1 - k0]) <= 1e-9, size
+        # dL/db and dL/dsigma are sums with heavy cancellation on some rods
+        # (-1e-3 on the 1024-vertex rod against 1.7 on the 700-vertex one):
+        # bounded by 1e-9 or three times the oracle's own largest change
+        # over three draws of a 1e-15 change of its start positions,
+        # whichever is larger (5e-8 relative on that rod, below 3.1e-10 on
+        # the others)
+        spread = np.zeros(2)
+        for seed in (1, 2, 3):
+            stp = st._replace(x=st.x * (1 + 1e-15 * np.random.default_rng(seed).standard_normal(
+                st.x.shape)))
+            xp, ckp = ofw.rollout(orods, osim, stp, U, n, K)
+            _, gxp = oadj.loss_mse(xp.x, sub.target[a:b][None], sub.n_rods)
+            outp = oadj.backward(orods, osim, ckp, U, n, K, gxp,
+                                 bodyT_b=gather_bodies(sub, [r], sb), with_body=True)
+            spread = np.maximum(spread, [abs(outp[3][0] - bb[0]), abs(outp[4][0] - sbb[0])])
+        for got, ref, sp in ((g["b"][r], bb[0], spread[0]), (g["sigma"][r], sbb[0], spread[1])):
+            assert abs(got - ref) <= max(1e-9 * abs(ref), 3 * sp) + 1e-30, size
+    outs = []
+    full32 = [f.astype(np.float32).astype(np.float64) for f in full]
+    body32 = body.astype(np.float32).astype(np.float64)
+    for plain, KK in ((False, 2), (True, 2), (False, 1), (False, 3)):
+        o = _gpu_grads(sub, full32, body32, 4, n, KK, sb, plain=plain)
+        outs.append([o[k] for k in ("xT", "bodyT", "u", "b", "sigma", "x0", "v0", "body0")])
+    for other in outs[1:]:
+        for x, y in zip(outs[0], other):
+            np.testing.assert_array_equal(x, y)
