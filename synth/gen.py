@@ -225,11 +225,11 @@ def make_workload(cid: int, steps: Optional[int] = None,
     n_rods and noise (configuration 5) replace the helix pitch (below 2 r
     the coils start in self-contact), the vertices per rod, the number of
     rods and the standard deviation of the vertex noise (1 mm); sizes
-    (configurations 2, 3 and 7) gives one rod per entry with that many
+    (configurations 2, 3, 6 and 7) gives one rod per entry with that many
     vertices, grasp amplitudes scaled by L / 1.27 m as in configuration 4."""
     cfg = CONFIGS[cid]
     if sizes is not None:
-        assert cid in (2, 3, 7)
+        assert cid in (2, 3, 6, 7)
         cfg = replace(cfg, n_rods=len(sizes), n_vert=None,
                       oracle_rods=tuple(range(len(sizes))))
     if cid == 5 and (n_vert is not None or n_rods is not None):

@@ -205,3 +205,96 @@ def test_twist_plain_equals_batched_and_checkpoint_invariance():
     for other in outs[1:]:
         for a, b in zip(outs[0], other):
             assert torch.equal(a, b)
+
+
+# twisting rods in every size bin: teams of 1, 2, 4 and 8 waves (the twist
+# angles, rates and material frames cross waves through LDS)
+BIN_SIZES = [3, 65, 129, 200, 300, 513, 700, 1024]
+
+
+def _bins_case(n_steps, seed=5):
+    sub = make_workload(CID, steps=n_steps, sizes=BIN_SIZES)
+    sub.rod_params[:, 4] = 0.5
+    return sub, initial_full_state(sub), _twist_rows(sub, seed)
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_twist_every_team_size_step(precision):
+    sub, full, tw = _bins_case(1)
+    if precision == 4:
+        full = [a.astype(np.float32).astype(np.float64) for a in full]
+        tw = [a.astype(np.float32).astype(np.float64) for a in tw]
+    h = _handle(sub, precision=precision, max_steps=1)
+    assert sorted(b[:2] for b in h.bins()) == [(2, 1), (2, 2), (2, 4), (2, 8)]
+    _set(h, full, tw, precision)
+    h.step(to_dev(sub.actions[0], _dt(precision)))
+    out = _get(h)
+    assert not h.status().any()
+    for r, n in enumerate(BIN_SIZES):
+        orods, osim = rods_from_workload(sub, [r]), sim_from_workload(sub)
+        st = gather_state(sub, [r], full + list(tw))
+        ref = ofw.step(orods, osim, st, sub.actions[0, [r]])
+        gpu = gather_state(sub, [r], out)
+        tol = 1e-9 if precision == 8 else 1e-4
+        assert rel_err(gpu.x, ref.x) <= tol, n
+        assert rel_err(gpu.theta, ref.theta) <= tol, n
+        assert rel_err(gpu.omega, ref.omega) <= (1e-8 if precision == 8 else 1e-3), n
+        if n > 3:
+            assert np.abs(ref.theta - st.theta).max() > 1e-4, n
+
+
+def test_twist_every_team_size_gradients_and_invariance():
+    """FP64 gradients of a 3-step rollout (checkpoint every 2) against the
+    oracle one rod at a time (loss normalised by the batch's rod count):
+    every block to 1e-9, dL/db and dL/dsigma to 1e-9 or three times the
+    oracle's own FP64 sensitivity (the largest change over three draws of a
+    1e-15 change of its start positions).  FP32: plain == batched and
+    checkpoint invariance, bitwise."""
+    n, K = 3, 2
+    sub, full, tw = _bins_case(n)
+    h = _handle(sub, precision=8, max_steps=n, ckpt_every=K)
+    _set(h, full, tw, 8)
+    xT = h.tensor(sub.n_vert, 3)
+    h.rollout(n, to_dev(sub.actions, torch.float64), record=True, x_final=xT)
+    _, gxd = h.loss_mse(xT, to_dev(sub.target, torch.float64))
+    g = {k: v.cpu().numpy() for k, v in h.backward(gxd, n_steps=n).items()}
+    xg = xT.cpu().numpy()
+    assert not h.status().any()
+    for r, size in enumerate(BIN_SIZES):
+        orods, osim = rods_from_workload(sub, [r]), sim_from_workload(sub)
+        st = gather_state(sub, [r], full + list(tw))
+        U = sub.actions[:, [r]]
+        a, b = sub.rod_range(r)
+
+        def grads(s):
+            xr, ck = ofw.rollout(orods, osim, s, U, n, K)
+            _, gx = oadj.loss_mse(xr.x, sub.target[a:b][None], sub.n_rods)
+            return xr, oadj.backward(orods, osim, ck, U, n, K, gx)
+        xr, (x0b, v0b, Ub, bb, sbb) = grads(st)
+        assert rel_err(xg[a:b], xr.x[0]) <= 1e-9, size
+        assert rel_err(g["u"][:, r], Ub[:, 0]) <= 1e-9, size
+        assert rel_err(g["x0"][a:b], x0b[0]) <= 1e-9, size
+        assert rel_err(g["v0"][a:b], v0b[0]) <= 1e-9, size
+        spread = np.zeros(2)
+        for seed in (1, 2, 3):
+            sp = st._replace(x=st.x * (1 + 1e-15 * np.random.default_rng(seed).standard_normal(
+                st.x.shape)))
+            _, o = grads(sp)
+            spread = np.maximum(spread, [abs(o[3][0] - bb[0]), abs(o[4][0] - sbb[0])])
+        for got, ref, s in ((g["b"][r], bb[0], spread[0]), (g["sigma"][r], sbb[0], spread[1])):
+            assert abs(got - ref) <= max(1e-9 * abs(ref), 3 * s) + 1e-30, size
+    outs = []
+    full32 = [f.astype(np.float32).astype(np.float64) for f in full]
+    tw32 = [a.astype(np.float32).astype(np.float64) for a in tw]
+    for plain, KK in ((False, 2), (True, 2), (False, 1), (False, 3)):
+        h = _handle(sub, max_steps=n, ckpt_every=KK)
+        h.set_plain(plain)
+        _set(h, full32, tw32, 4)
+        xT = h.tensor(sub.n_vert, 3)
+        h.rollout(n, to_dev(sub.actions, torch.float32), record=True, x_final=xT)
+        gg = h.backward(torch.ones_like(xT) * 1e-3, n_steps=n)
+        outs.append([xT.cpu()] + [t.cpu() for t in h.get_twist()] +
+                    [gg[k].cpu() for k in ("u", "b", "sigma", "x0", "v0")])
+    for other in outs[1:]:
+        for x, y in zip(outs[0], other):
+            assert torch.equal(x, y)
