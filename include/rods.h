@@ -282,9 +282,24 @@ int rods_status(RodsHandle* h, int32_t* flags, rods_stream_t stream);
 int rods_bins(RodsHandle* h, int32_t* out, int32_t max_bins);
 
 /* Times every legal launch shape of every size bin on a short forward run
- * and keeps the fastest (the results do not depend on the choice).  Saves
+ * and keeps the fastest.  For a given shape results are bitwise repeatable;
+ * across shapes they agree to rounding (each shape is its own kernel
+ * instantiation, whose multiply-adds the compiler may fuse differently).  Saves
  * and restores the state; synchronises the stream. */
 int rods_autotune(RodsHandle* h, int32_t n_steps, rods_stream_t stream);
+
+/* Pins size bin `bin` (the order of rods_bins) to a launch shape of
+ * vertices_per_lane (C) and waves (W) per rod, overriding the default or
+ * the autotuner's choice.  Legal shapes: C = 2 or 4 and W = 1, 2, 4 or 8
+ * with a team (64 W C vertices) that holds the bin's largest rod and is at
+ * most twice the bin's smallest legal team (the tape and scratch are sized
+ * for that); C = 2 for FP64, twisting rods and rods with moving bodies; no
+ * C = 4 with W = 8; self-contact only on the shapes it is built for; the
+ * kernel's LDS within the device limit.  ROD_EINVAL otherwise (the bin
+ * keeps its shape).  Results agree with those of other shapes to rounding,
+ * as for rods_autotune.  Clears the
+ * recorded rollout; allocates nothing. */
+int rods_set_launch_shape(RodsHandle* h, int32_t bin, int32_t vertices_per_lane, int32_t waves);
 
 /* Plain path switch: with plain != 0, rods_rollout and rods_backward launch
  * the same kernels once per rod and per step (a one-rod work list, no

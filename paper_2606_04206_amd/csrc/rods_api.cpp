@@ -801,6 +801,50 @@ struct Impl : HandleBase {
     return ROD_OK;
   }
 
+  int bin_nmax(const Bin& bn) const {
+    int nmax = 0;
+    for (int i = 0; i < bn.n; ++i) {
+      int r = bin_rods_h[bn.off + i];
+      nmax = std::max(nmax, voff_h[r + 1] - voff_h[r]);
+    }
+    return nmax;
+  }
+  // a launch shape the bin may use: a kernel exists for it, the team holds
+  // the bin's largest rod and is at most twice its smallest legal team (the
+  // tape and scratch are sized for that), and its LDS fits
+  bool shape_legal(const Bin& bn, int C, int W) const {
+    if (!(C == 2 || C == 4) || !(W == 1 || W == 2 || W == 4 || W == 8)) return false;
+    const int nmax = bin_nmax(bn);
+    auto sh = shapes_for(nmax, prec, bn.sc, bn.tw || bn.bd);
+    if (sh.empty()) return false;
+    const int team0 = 64 * sh.front().first * sh.front().second;
+    return 64 * W * C >= nmax && 64 * W * C <= 2 * team0 &&
+           !((prec == 8 || bn.tw || bn.bd) && C != 2) && !(C == 4 && W == 8) &&
+           (!bn.sc || sc_shape_ok(C, W)) &&
+           rods::kernel_lds_bytes<T>(2, C, W, bn.sc, global_tape(C, W, bn.sc), d.n_iters) +
+                   body_lds() <= lds_max;
+  }
+  // pins bin b to shape (C, W); the tape layout follows
+  int set_shape(int b, int C, int W) {
+    if (b < 0 || b >= (int)bins.size() || !shape_legal(bins[b], C, W)) return ROD_EINVAL;
+    const Bin old = bins[b];
+    bins[b].C = C;
+    bins[b].W = W;
+    bins[b].gt = global_tape(C, W, bins[b].sc);
+    std::vector<int64_t> toff_h, soff_h;
+    layout_offsets(toff_h, soff_h);
+    if (tape_stride > tape_cap || sc_stride_ > sc_cap) {
+      bins[b] = old;
+      layout_offsets(toff_h, soff_h);
+      return ROD_EINVAL;
+    }
+    drop_graph();
+    HIPCHK(hipMemcpy(tape_off, toff_h.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(sc_off, soff_h.data(), sizeof(int64_t) * R, hipMemcpyHostToDevice));
+    recorded = false;
+    return ROD_OK;
+  }
+
   int autotune(int n_steps, hipStream_t st) {
     // save state
     HIPCHK(hipMemcpyAsync(sx, x, sizeof(T) * 3 * V, hipMemcpyDeviceToDevice, st));
@@ -818,22 +862,12 @@ struct Impl : HandleBase {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     for (Bin& bn : bins) {
-      int nmax = 0;
-      for (int i = 0; i < bn.n; ++i) {
-        int r = bin_rods_h[bn.off + i];
-        nmax = std::max(nmax, voff_h[r + 1] - voff_h[r]);
-      }
       std::vector<std::pair<int, int>> cand;
       const int Cs[2] = {2, 4};
       const int Ws[4] = {1, 2, 4, 8};
-      const int team0 = 64 * bn.C * bn.W;   // smallest legal team of the bin
       for (int C : Cs)
         for (int W : Ws)
-          if (64 * W * C >= nmax && 64 * W * C <= 2 * team0 && !((prec == 8 || bn.tw || bn.bd) && C != 2) &&
-              !(C == 4 && W == 8) && (!bn.sc || sc_shape_ok(C, W)) &&
-              rods::kernel_lds_bytes<T>(2, C, W, bn.sc, global_tape(C, W, bn.sc), d.n_iters) +
-                      body_lds() <= lds_max)
-            cand.push_back({C, W});
+          if (shape_legal(bn, C, W)) cand.push_back({C, W});
       float best = 1e30f;
       std::pair<int, int> bestk{bn.C, bn.W};
       for (auto cw : cand) {
@@ -1223,6 +1257,11 @@ int rods_bins(RodsHandle* h, int32_t* out, int32_t max_bins) {
 int rods_autotune(RodsHandle* h, int32_t n_steps, rods_stream_t stream) {
   if (!h || n_steps < 1) return ROD_EINVAL;
   return dispatch(h, [&](auto* I) { return I->autotune(n_steps, (hipStream_t)stream); });
+}
+
+int rods_set_launch_shape(RodsHandle* h, int32_t bin, int32_t vertices_per_lane, int32_t waves) {
+  if (!h) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) { return I->set_shape(bin, vertices_per_lane, waves); });
 }
 
 int rods_set_plain(RodsHandle* h, int32_t plain) {

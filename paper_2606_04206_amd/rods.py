@@ -47,7 +47,8 @@ EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "ro
            "rods_set_body_adjoint", "rods_get_body_adjoint", "rods_set_params", "rods_get_params",
            "rods_optimize", "rods_curvature", "rods_step", "rods_step_graph", "rods_rollout",
            "rods_backward",
-           "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_plain",
+           "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_launch_shape",
+           "rods_set_plain",
            "rods_set_profiling", "rods_profile", "rods_selftest_exchange"]
 
 _lib = None
@@ -91,6 +92,7 @@ def load():
         "rods_status": ([vp, POINTER(c_int32), vp], c_int32),
         "rods_bins": ([vp, POINTER(c_int32), c_int32], c_int32),
         "rods_autotune": ([vp, c_int32, vp], c_int32),
+        "rods_set_launch_shape": ([vp, c_int32, c_int32, c_int32], c_int32),
         "rods_set_plain": ([vp, c_int32], c_int32),
         "rods_set_profiling": ([vp, c_int32], c_int32),
         "rods_profile": ([vp, POINTER(c_double), vp], c_int32),
@@ -352,6 +354,10 @@ class RodsHandle:
 
     def autotune(self, n_steps=2):
         _check(self._lib.rods_autotune(self._h, int(n_steps), _stream()), "rods_autotune")
+
+    def set_launch_shape(self, bin_index, vertices_per_lane, waves):
+        _check(self._lib.rods_set_launch_shape(self._h, int(bin_index), int(vertices_per_lane),
+                                               int(waves)), "rods_set_launch_shape")
 
     def set_profiling(self, on=True):
         _check(self._lib.rods_set_profiling(self._h, 1 if on else 0), "rods_set_profiling")

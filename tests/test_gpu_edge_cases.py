@@ -133,3 +133,65 @@ def test_zero_step_rollout_and_backward_without_recording():
     assert torch.equal(xT, x0)
     with pytest.raises(RodsError):
         h.backward(torch.zeros_like(x0), n_steps=1)
+
+
+SHAPE_SIZES = [60, 100, 128, 129, 200, 256, 300, 500]
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+def test_every_launch_shape_agrees_to_rounding(precision):
+    """Every legal launch shape of every size bin (vertices per lane and
+    waves per rod) gives the same rollout and gradients up to rounding: each
+    shape is its own kernel instantiation, whose multiply-adds the compiler
+    may fuse differently.  FP64: positions within 1e-14, gradients within
+    1e-11 per rod and block (measured 5e-16 and 5e-13).  FP32: positions
+    within 1e-6 per rod (measured 3e-7); FP32 gradients over 4 steps move
+    by more than that under one FP32 rounding and are compared in FP64.
+    Illegal shapes are refused and leave the bin as it was."""
+    from paper_2606_04206_amd.rods import RodsError
+    n, K = 4, 2
+    wl = make_workload(3, steps=n, sizes=SHAPE_SIZES)
+    full = initial_full_state(wl)
+    full[1] = np.random.default_rng(6).normal(0.0, 0.05, full[1].shape)
+    if precision == 4:
+        full = [a.astype(np.float32).astype(np.float64) for a in full]
+    dt = _dt(precision)
+
+    def run(shapes):
+        h = _handle(wl, precision, max_steps=n, ckpt_every=K)
+        for b, (C, W) in enumerate(shapes):
+            h.set_launch_shape(b, C, W)
+        assert [x[:2] for x in h.bins()] == list(shapes)
+        h.set_state(*(to_dev(a, dt) for a in full))
+        xT = h.tensor(wl.n_vert, 3)
+        h.rollout(n, to_dev(wl.actions, dt), record=True, x_final=xT)
+        _, g = h.loss_mse(xT, to_dev(wl.target, dt))
+        out = {k: v.double().cpu().numpy() for k, v in h.backward(g, n_steps=n).items()}
+        out["xT"] = xT.double().cpu().numpy()
+        return out
+    default = [(2, 1), (2, 2), (2, 4)]
+    if precision == 4:
+        variants = [[(4, 1), (4, 1), (4, 2)], [(2, 2), (2, 4), (2, 8)], [(2, 1), (4, 2), (4, 4)]]
+    else:
+        variants = [[(2, 2), (2, 4), (2, 8)]]
+    ref = run(default)
+    for shapes in variants:
+        got = run(shapes)
+        for r in range(wl.n_rods):
+            a, b = wl.rod_range(r)
+            assert rel_err(got["xT"][a:b], ref["xT"][a:b]) <= (1e-14 if precision == 8 else 1e-6)
+            if precision == 8:
+                for k, blk in (("u", np.s_[:, r]), ("x0", np.s_[a:b]), ("v0", np.s_[a:b])):
+                    assert rel_err(got[k][blk], ref[k][blk]) <= 1e-11, (shapes, k, r)
+        if precision == 8:
+            assert rel_err(got["b"], ref["b"]) <= 1e-11
+            assert rel_err(got["sigma"], ref["sigma"]) <= 1e-11
+    # the same shape twice: bitwise
+    again = run(default)
+    for k in ref:
+        np.testing.assert_array_equal(again[k], ref[k])
+    h = _handle(wl, precision, max_steps=n, ckpt_every=K)
+    for b, C, W in ((0, 2, 4), (1, 2, 1), (2, 4, 8), (3, 2, 1), (0, 3, 1)):
+        with pytest.raises(RodsError):
+            h.set_launch_shape(b, C, W)     # too big, too small, not built, no bin, no C
+    assert [x[:2] for x in h.bins()] == default
