@@ -335,3 +335,29 @@ def test_moving_spheres_every_team_size_gradients_and_invariance():
     for other in outs[1:]:
         for x, y in zip(outs[0], other):
             np.testing.assert_array_equal(x, y)
+
+
+def test_fp64_optimisation_with_moving_spheres_matches_oracle():
+    """rods_optimize with moving spheres: every iteration restarts the
+    spheres from their state when the call began, as the oracle's driver
+    restarts from its fixed start state.  FP64: every iteration's loss and
+    the updated grasp velocities to 1e-9; the loss falls."""
+    from oracle import optimize as oopt
+    n, K = 4, 2
+    sub, full, body = _case(n, rods=[0, 877])
+    h = _handle(sub, precision=8, max_steps=n, ckpt_every=K)
+    h.set_bodies(to_dev(body, torch.float64))
+    U = to_dev(sub.actions, torch.float64).contiguous()
+    losses = h.optimize(n, to_dev(full[0], torch.float64), to_dev(full[1], torch.float64),
+                        to_dev(sub.target, torch.float64), U, iters=4, lr0=5e-2, lr_min=1e-3)
+    assert not h.status().any()
+    rods = list(range(sub.n_rods))
+    orods, osim = rods_from_workload(sub, rods), sim_from_workload(sub)
+    st = gather_state(sub, rods, full, body)
+    cfg = oopt.AdamConfig(iters=4, lr0=5e-2, lr_min=1e-3)
+    Uo, _, lo = oopt.optimize(orods, osim, st, sub.actions, n, K, sub.target.reshape(st.x.shape),
+                              sub.n_rods, cfg)
+    assert len(losses) == len(lo) == 4
+    np.testing.assert_allclose(losses, lo, rtol=1e-9)
+    assert rel_err(U.cpu().numpy(), Uo) <= 1e-9
+    assert lo[-1] < lo[0]
