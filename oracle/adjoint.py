@@ -14,8 +14,8 @@ positions and velocities.
 """
 import numpy as np
 
-from .geometry import dot, cross, curvature_binormal, edges
-from .forward import substep, step, PLANE, SPHERE, CAPSULE
+from .geometry import dot, cross, curvature_binormal
+from .forward import substep, PLANE, CAPSULE
 from .model import State
 from . import selfcontact
 from . import twist as tw

@@ -25,7 +25,7 @@ substeps):
 import numpy as np
 
 from .geometry import (re, dot, cross, norm, edges, transport, curvature_binormal,
-                       averaged_directors, material_curvature, material_frame)
+                       material_curvature, material_frame)
 from .model import State
 from . import selfcontact
 from . import twist as tw

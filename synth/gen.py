@@ -10,7 +10,7 @@ path casts them to its own precision.
 Draw order per rod is fixed: material -> geometry -> grasps -> obstacles ->
 target, from ``numpy.random.default_rng([20604206, seed_key])``.
 """
-from dataclasses import dataclass, field, replace
+from dataclasses import dataclass, replace
 from typing import Optional
 
 import numpy as np

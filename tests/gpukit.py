@@ -5,10 +5,8 @@ from dataclasses import replace
 import numpy as np
 import torch
 
-from synth import make_workload
-from oracle.model import rods_from_workload, sim_from_workload, State
+from oracle.model import State
 from oracle.geometry import init_frames, curvature_of_shape
-from paper_2606_04206_amd import RodsHandle
 
 DEV = "cuda"
 

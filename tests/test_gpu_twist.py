@@ -19,7 +19,7 @@ import torch
 from synth import make_workload
 from oracle import forward as ofw, adjoint as oadj
 from oracle.model import rods_from_workload, sim_from_workload, State
-from tests.gpukit import to_dev, rows, oracle_state_rows, gather_state, initial_full_state, rel_err
+from tests.gpukit import to_dev, oracle_state_rows, gather_state, initial_full_state, rel_err
 
 pytestmark = pytest.mark.gpu
 CID = 6
