@@ -382,21 +382,30 @@ def selftest_exchange():
 
 class RodsRollout(torch.autograd.Function):
     """x_T = rollout(x0, v0, U; b, sigma_y) through librods; backward runs the
-    library's checkpointed adjoint.  kappa_bar0 is a fixed input."""
+    library's checkpointed adjoint.  kappa_bar0 is a fixed input.  body0
+    ([P, 9], optional) is the moving bodies' start state, set before the
+    rollout and differentiated through them; without it the bodies start
+    from the handle's current state and get no gradient."""
 
     @staticmethod
-    def forward(ctx, handle, n_steps, x0, v0, U, b, sigma_y, kappa_bar0=None):
+    def forward(ctx, handle, n_steps, x0, v0, U, b, sigma_y, kappa_bar0=None, body0=None):
         handle.set_params(b.detach().contiguous(), sigma_y.detach().contiguous())
         handle.set_state(x0.detach().contiguous(), v0.detach().contiguous(),
                          None if kappa_bar0 is None else kappa_bar0.detach().contiguous())
+        if body0 is not None:
+            handle.set_bodies(body0.detach().contiguous())
         xT = handle.tensor(handle.V, 3)
         handle.rollout(n_steps, U.detach().contiguous(), record=True, x_final=xT)
         ctx.handle = handle
         ctx.n_steps = n_steps
+        ctx.with_body = body0 is not None
         return xT
 
     @staticmethod
     def backward(ctx, gx):
         h = ctx.handle
+        if ctx.with_body:
+            h.set_body_adjoint(None)      # the bodies' final state is not an output
         g = h.backward(gx.contiguous(), n_steps=ctx.n_steps)
-        return None, None, g["x0"], g["v0"], g["u"], g["b"], g["sigma"], None
+        gb0 = h.get_body_adjoint() if ctx.with_body else None
+        return None, None, g["x0"], g["v0"], g["u"], g["b"], g["sigma"], None, gb0
