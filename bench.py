@@ -187,7 +187,7 @@ def main():
     torch.cuda.empty_cache()
 
     if not a.no_plain:
-        n_plain, steps_plain = 16, 10
+        n_plain, steps_plain = 64, 10
         sub = wl.subset(list(range(n_plain)), steps=steps_plain)
         hp = RodsHandle(sub, precision=4, max_steps=steps_plain)
         hp.set_plain(True)
