@@ -89,6 +89,46 @@ __device__ __forceinline__ double dpp_from_prev(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Sum over the 64 lanes of a wave, the same value in every lane: within
+// each row of 16 lanes a DPP shift-and-add chain (row_shr 1, 2, 4, 8; lanes
+// shifted in from outside the row read 0) leaves the row's sum in its last
+// lane, and the four row sums, read out with readlane, are added in row
+// order.  No LDS, no cross-lane permute through the LDS crossbar.
+__device__ __forceinline__ float dpp_row_shr(float v, int n) {
+  int i = __float_as_int(v);
+  switch (n) {
+    case 1: i = __builtin_amdgcn_mov_dpp(i, 0x111, 0xf, 0xf, true); break;
+    case 2: i = __builtin_amdgcn_mov_dpp(i, 0x112, 0xf, 0xf, true); break;
+    case 4: i = __builtin_amdgcn_mov_dpp(i, 0x114, 0xf, 0xf, true); break;
+    default: i = __builtin_amdgcn_mov_dpp(i, 0x118, 0xf, 0xf, true); break;
+  }
+  return __int_as_float(i);
+}
+__device__ __forceinline__ double dpp_row_shr(double v, int n) {
+  long long b = __double_as_longlong(v);
+  float lo = dpp_row_shr(__int_as_float((int)(b & 0xffffffffLL)), n);
+  float hi = dpp_row_shr(__int_as_float((int)(b >> 32)), n);
+  return __longlong_as_double(((long long)__float_as_int(hi) << 32) |
+                              (unsigned int)__float_as_int(lo));
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v += dpp_row_shr(v, 1);
+  v += dpp_row_shr(v, 2);
+  v += dpp_row_shr(v, 4);
+  v += dpp_row_shr(v, 8);
+  return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
+}
+
 constexpr int XK = 12;   // largest exchange group (values)
 // moving rigid bodies: at most NB_MAX primitives on a rod with moving bodies;
 // per primitive 9 values (centre, velocity, angular velocity)
@@ -153,17 +193,14 @@ struct Team {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = r[k];
   }
-  // v[k] <- sum of v[k] over the team, in every lane (K <= XK).  Butterfly
-  // within each wave, then the W wave sums through LDS in wave order, so
-  // every lane forms the same sum in the same order.
+  // v[k] <- sum of v[k] over the team, in every lane (K <= XK): wave_sum in
+  // each wave, then the W wave sums through LDS in wave order, so every
+  // lane holds the same sum.
   template <int K>
   __device__ __forceinline__ void sum(T (&v)[K]) {
     static_assert(K <= XK, "exchange group too large");
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], off, 64);
-    }
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
     if constexpr (W > 1) {
       T* b = buf + pp * (W * XK);
       if (lane == 0) {
