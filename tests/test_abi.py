@@ -123,3 +123,17 @@ def test_moving_body_descriptions_are_validated():
            desc([1], [1.0], [1.0], flags=1 | 8)]          # with twist
     for d in bad:
         assert lib.rods_create(ctypes.byref(d), ctypes.byref(h)) == -1
+
+
+def test_new_entry_points_refuse_a_null_handle():
+    """The moving-body, launch-shape and twist calls return ROD_EINVAL for a
+    null handle before touching any device."""
+    lib = R.load()
+    assert lib.rods_set_bodies(None, None, None) == -1
+    assert lib.rods_get_bodies(None, None, None) == -1
+    assert lib.rods_set_body_adjoint(None, None, None) == -1
+    assert lib.rods_get_body_adjoint(None, None, None) == -1
+    assert lib.rods_set_launch_shape(None, 0, 2, 1) == -1
+    assert lib.rods_set_twist(None, None, None, None) == -1
+    assert lib.rods_get_twist(None, None, None, None) == -1
+    assert lib.rods_optimize(None, None, 1, None, None, None, None, None, None, None, None) == -1
