@@ -268,6 +268,24 @@ int rods_get_params(RodsHandle* h, void* b, void* sigma_y, rods_stream_t stream)
 int rods_loss_mse(RodsHandle* h, const void* x, const void* target, void* loss,
                   void* dL_dx, rods_stream_t stream);
 
+/* The same loss without a handle, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It allocates nothing: the per-rod partial sums go to a
+ * static device array of ROD_LOSS_STATIC_MAX_RODS doubles (512 KiB), which
+ * each GPU the library runs on holds until the process ends.  vert_offsets
+ * is the device array [n_rods + 1] of the CSR layout above; x and target are
+ * [V][3] of `precision` (4 float, 8 double); loss [1] and dL_dx [V][3] may be
+ * NULL.  Results equal those of rods_loss_mse bit for bit.  ROD_EINVAL for
+ * n_rods outside 1..ROD_LOSS_STATIC_MAX_RODS or a NULL input, ROD_EDTYPE for
+ * another precision, ROD_EHIP if the array cannot be located on the current
+ * device.  Every call on one GPU uses that GPU's one array (each call writes
+ * every part it reads, so nothing needs clearing): calls that overlap on one
+ * GPU, on different streams or host threads, race. */
+#define ROD_LOSS_STATIC_MAX_RODS 65536
+int rods_loss_mse_static(const int32_t* vert_offsets, int32_t n_rods, int32_t precision,
+                         const void* x, const void* target, void* loss, void* dL_dx,
+                         rods_stream_t stream);
+
 /* Synchronises the stream and copies per-rod status words to flags (host)
  * [R], accumulated since rods_set_state: bit0 = non-finite state seen;
  * bit1 = a self-contact partner list was full (candidate pairs beyond its

@@ -2376,37 +2376,6 @@ __global__ void k_curvature(const int32_t* voff, const int32_t* rod_of, int V, c
   kappa[2 * i + 1] = k2;
 }
 
-// per-rod part of the MSE loss and dL/dx
-template <typename T>
-__global__ void k_loss(const int32_t* voff, int R, const T* x, const T* tgt, double* part,
-                       T* dldx) {
-  int r = blockIdx.x;
-  int v0 = voff[r], N = voff[r + 1] - v0;
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    V3<T> d = get3(x, 3 * (v0 + j)) - get3(tgt, 3 * (v0 + j));
-    s += (double)dot(d, d);
-    if (dldx) put3(dldx, 3 * (v0 + j), (T(2) / (T(R) * T(N))) * d);
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[r] = red[0] / ((double)R * N);
-}
-
-// fixed-order sum of the per-rod loss parts (one thread)
-template <typename T>
-__global__ void k_loss_sum(const double* part, int R, T* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int r = 0; r < R; ++r) s += part[r];
-  out[0] = (T)s;
-}
-
 // per-rod fixed-order sum of per-vertex parameter partials
 template <typename T>
 __global__ void k_reduce_params(const int32_t* voff, int R, const double* acc_b,
@@ -2569,14 +2538,6 @@ hipError_t launch_curvature(const int32_t* voff, const int32_t* rod_of, int V, c
 }
 
 template <typename T>
-hipError_t launch_loss(const int32_t* voff, int R, const T* x, const T* tgt, double* part,
-                       T* loss, T* dldx, hipStream_t st) {
-  hipLaunchKernelGGL(k_loss<T>, dim3(R), dim3(256), 0, st, voff, R, x, tgt, part, dldx);
-  if (loss) hipLaunchKernelGGL(k_loss_sum<T>, dim3(1), dim3(64), 0, st, part, R, loss);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_reduce_params(const int32_t* voff, int R, const double* ab, const double* as,
                                 T* db, T* ds, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_params<T>, dim3((R + 63) / 64), dim3(64), 0, st, voff, R, ab, as,
@@ -2605,8 +2566,6 @@ hipError_t launch_selftest_exchange(int* out, hipStream_t st) {
   template hipError_t launch_init_frames<T>(const int32_t*, int, const T*, T*, hipStream_t);  \
   template hipError_t launch_curvature<T>(const int32_t*, const int32_t*, int, const T*,      \
                                           const T*, T*, hipStream_t);                         \
-  template hipError_t launch_loss<T>(const int32_t*, int, const T*, const T*, double*, T*, T*, \
-                                     hipStream_t);                                            \
   template hipError_t launch_reduce_params<T>(const int32_t*, int, const double*,             \
                                               const double*, T*, T*, hipStream_t);            \
   template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                             \

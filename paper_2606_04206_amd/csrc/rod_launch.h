@@ -38,6 +38,9 @@ hipError_t launch_reduce_params(const int32_t* voff, int R, const double* ab, co
 template <typename T>
 hipError_t launch_fill(T* p, int64_t n, T val, hipStream_t st);
 hipError_t launch_selftest_exchange(int* out, hipStream_t st);
+// device address of the static loss scratch on the current device, looked
+// up once per device (rod_loss.hip); out may be NULL
+int loss_scratch_setup(double** out);
 // optimisation driver (rod_optim.hip): one Adam update of n parameters
 // (scale, nullable, multiplies the gradient), and elementwise log / exp
 template <typename T>

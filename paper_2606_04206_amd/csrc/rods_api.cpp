@@ -993,6 +993,8 @@ int rods_create(const RodsDesc* desc, RodsHandle** out) {
   *out = nullptr;
   int e = validate(desc);
   if (e) return e;
+  // the handle-free loss's static scratch: locate it on this device now
+  if ((e = rods::loss_scratch_setup(nullptr))) return e;
   RodsHandle* H = new (std::nothrow) RodsHandle;
   if (!H) return ROD_ENOMEM;
   H->h.prec = desc->precision;

@@ -49,7 +49,8 @@ EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "ro
            "rods_backward",
            "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_launch_shape",
            "rods_set_plain",
-           "rods_set_profiling", "rods_profile", "rods_selftest_exchange"]
+           "rods_set_profiling", "rods_profile", "rods_selftest_exchange",
+           "rods_loss_mse_static"]
 
 _lib = None
 
@@ -97,6 +98,7 @@ def load():
         "rods_set_profiling": ([vp, c_int32], c_int32),
         "rods_profile": ([vp, POINTER(c_double), vp], c_int32),
         "rods_selftest_exchange": ([vp, vp], c_int32),
+        "rods_loss_mse_static": ([vp, c_int32, c_int32, vp, vp, vp, vp, vp], c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -378,6 +380,27 @@ def selftest_exchange():
     out = torch.zeros(2, 64, dtype=torch.int32, device="cuda")
     _check(load().rods_selftest_exchange(_ptr(out), _stream()), "rods_selftest_exchange")
     return out.cpu().numpy()
+
+
+LOSS_STATIC_MAX_RODS = 65536
+
+
+def loss_mse_static(vert_offsets, x, target, want_grad=True):
+    """rods_loss_mse without a handle (no device allocation inside the
+    library): vert_offsets is a device int32 tensor [R+1], x and target
+    [V][3] float32 or float64 device tensors.  Returns (loss [1], dL/dx)."""
+    R = vert_offsets.numel() - 1
+    V = x.shape[0]
+    _require(vert_offsets, (R + 1,), torch.int32, "vert_offsets")
+    _require(x, (V, 3), x.dtype, "x")
+    _require(target, (V, 3), x.dtype, "target")
+    prec = {torch.float32: 4, torch.float64: 8}.get(x.dtype, 0)
+    loss = torch.empty(1, dtype=x.dtype, device=x.device)
+    g = torch.empty(V, 3, dtype=x.dtype, device=x.device) if want_grad else None
+    _check(load().rods_loss_mse_static(_ptr(vert_offsets), int(R), int(prec), _ptr(x),
+                                       _ptr(target), _ptr(loss), _ptr(g), _stream()),
+           "rods_loss_mse_static")
+    return loss, g
 
 
 class RodsRollout(torch.autograd.Function):
