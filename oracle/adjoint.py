@@ -396,13 +396,16 @@ def substep_vjp(rods, sim, rec, bar):
 # --------------------------------------------------------------------------
 
 def backward(rods, sim, ckpts, U, n_steps, ckpt_every, xT_b, vT_b=None, bodyT_b=None,
-             with_body=False):
+             with_body=False, with_frames=False):
     """Reverse pass through a rollout that kept a state every ckpt_every
     steps.  Each segment is re-run forward from its checkpoint (keeping the
     substep-start states), then its substeps are reversed.  Returns
     (x0_b, v0_b, u_b [A,B,G,3], b_b [B], sigma_b [B]), and with_body the
-    adjoint of the bodies' initial state [B,P,9] as a sixth value; bodyT_b
-    seeds the adjoint of their final state."""
+    adjoint of the bodies' initial state [B,P,9] as a further value; bodyT_b
+    seeds the adjoint of their final state.  x0_b holds the initial frames
+    fixed; with_frames appends the adjoint of the initial frames d1 [B,E,3]
+    (geometry.init_frames_vjp maps it onto x0 when the frames come from the
+    initial-frame rule)."""
     B, N = rods.B, rods.N
     body_shape = ckpts[0].body.shape
     bar = State(np.array(xT_b, np.float64),
@@ -432,9 +435,12 @@ def backward(rods, sim, ckpts, U, n_steps, ckpt_every, xT_b, vT_b=None, bodyT_b=
             u_b[a] += ub
             b_b += bb
             sig_b += sb
+    out = (bar.x, bar.v, u_b, b_b, sig_b)
     if with_body:
-        return bar.x, bar.v, u_b, b_b, sig_b, bar.body
-    return bar.x, bar.v, u_b, b_b, sig_b
+        out = out + (bar.body,)
+    if with_frames:
+        out = out + (bar.d1,)
+    return out
 
 
 def loss_mse(x, target, n_rods_total, sizes=None):

@@ -64,6 +64,44 @@ def init_frames(x):
     return d1
 
 
+def init_frames_vjp(x, d1_b):
+    """Adjoint of init_frames: the position adjoint [B,N,3] that the frame
+    adjoint d1_b [B,E,3] induces through the initial-frame rule.  The choice
+    between a = z and a = x is piecewise constant (zero derivative).
+
+    Reverse of the rule, edge E-1 down to 1: the transport that made d1^j
+    from d1^{j-1} passes its adjoint on to d1^{j-1}, t^{j-1} and t^j; at edge
+    0, d1^0 = d/|d| with d = a - (a.t^0) t^0 passes it to t^0; every t^j then
+    reaches x through t^j = e^j/|e^j|."""
+    from .adjoint import transport_vjp   # adjoint imports this module
+    _, ell, t = edges(x)
+    d1 = init_frames(x)
+    B, E, _ = t.shape
+    t_b = np.zeros_like(t)
+    carry = np.zeros((B, 3), dtype=t.dtype)
+    for j in range(E - 1, 0, -1):
+        g = d1_b[:, j] + carry
+        carry, ta_b, tb_b = transport_vjp(d1[:, j - 1], t[:, j - 1], t[:, j], g)
+        t_b[:, j - 1] += ta_b
+        t_b[:, j] += tb_b
+    g = d1_b[:, 0] + carry
+    for bi in range(B):
+        t0 = t[bi, 0]
+        a = np.array([0.0, 0.0, 1.0], dtype=t.dtype)
+        if re(norm(cross(t0, a))) < 1e-6:
+            a = np.array([1.0, 0.0, 0.0], dtype=t.dtype)
+        d = a - dot(a, t0) * t0
+        nd = norm(d)
+        u = d / nd
+        d_b = (g[bi] - u * dot(u, g[bi])) / nd
+        t_b[bi, 0] += -dot(a, t0) * d_b - dot(d_b, t0) * a
+    e_b = (t_b - t * dot(t, t_b)[..., None]) / ell[..., None]
+    x_b = np.zeros_like(x, dtype=np.result_type(x, d1_b))
+    x_b[..., 1:, :] += e_b
+    x_b[..., :-1, :] -= e_b
+    return x_b
+
+
 def curvature_binormal(t):
     """(kappa b)_i = 2 t^{i-1} x t^i / (1 + t^{i-1}.t^i) at interior vertices
     (App. A.1, Bending).  Returns (kb [B,N-2,3], chi = 1 + t^{i-1}.t^i)."""

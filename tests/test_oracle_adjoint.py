@@ -228,3 +228,47 @@ def test_sigma_gradient_is_zero_without_yield():
     _, _, _, bb, sb = adjoint.backward(rods, sim, ck, U, 5, 2, gx)
     np.testing.assert_array_equal(sb, 0.0)
     assert np.all(bb != 0.0)
+
+
+def test_init_frames_vjp_matches_complex_step():
+    """<init_frames_vjp(x, y), dx> equals the complex-step derivative of
+    <y, init_frames(x + i h dx)>, for bent noisy rods and for a rod whose
+    first edge is within 1e-6 of z (the rule's x branch)."""
+    from oracle.geometry import init_frames_vjp
+    rng = np.random.default_rng(31)
+    xs = np.stack([arc(9, 0.01, 0.3, z=0.4) + rng.normal(0, 2e-3, (9, 3)) for _ in range(3)])
+    xs[2, 1] = xs[2, 0] + np.array([1e-9, 0.0, 0.01])      # first edge along z
+    for trial in range(3):
+        y = rng.normal(size=(3, 8, 3))
+        dx = rng.normal(size=xs.shape)
+        lhs = np.sum(y * init_frames(xs + 1j * H * dx).imag / H, axis=(1, 2))
+        xb = init_frames_vjp(xs, y)
+        rhs = np.sum(xb * dx, axis=(1, 2))
+        np.testing.assert_allclose(rhs, lhs, rtol=1e-12, atol=1e-12)
+
+
+def test_rollout_gradient_through_derived_frames_complex_step():
+    """With the frames derived from x0 by the initial-frame rule, the total
+    derivative of a 5-step rollout w.r.t. x0 is x0_b + init_frames_vjp(x0,
+    d1_b): complex step through the rule and the rollout.  The frame part is
+    not small (it is compared on its own too), so dropping it fails."""
+    from oracle.geometry import init_frames_vjp
+    rng = np.random.default_rng(32)
+    rods, st = _bent_rods(rng, r_c=0.5)
+    sim = make_sim(n_iters=4, n_sub=6, spa=1)
+    n, K = 5, 2
+    U = rng.normal(0, 0.3, (n, rods.B, 2, 3))
+    dx = rng.normal(size=st.x.shape)
+    xc = st.x + 1j * H * dx
+    stc = State(xc, st.v.astype(complex), st.kb.astype(complex), init_frames(xc),
+                st.theta.astype(complex), st.omega.astype(complex))
+    outc, _ = forward.rollout(rods, sim, stc, U, n)
+    yx = rng.normal(size=st.x.shape)
+    lhs = np.sum(yx * outc.x.imag / H)
+    st0 = State(st.x, st.v, st.kb, init_frames(st.x), st.theta, st.omega)
+    _, ck = forward.rollout(rods, sim, st0, U, n, K)
+    x0b, v0b, Ub, bb, sb, d1b = adjoint.backward(rods, sim, ck, U, n, K, yx, with_frames=True)
+    frame_part = np.sum(init_frames_vjp(st.x, d1b) * dx)
+    rhs = np.sum(x0b * dx) + frame_part
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+    assert abs(frame_part) > 1e-3 * abs(lhs)
