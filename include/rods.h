@@ -130,10 +130,23 @@ typedef struct {
 
 /* Validates the description, copies the static data to the device and
  * allocates every buffer the handle will ever use (state, checkpoints,
- * backward tape, work lists): no call below allocates device memory.
- * The state starts as x = 0 and must be set with rods_set_state. */
+ * backward tape, work lists, self-contact pair scratch): no call below
+ * allocates device memory.  The description holds the discretised rods of
+ * Section 3.1 (vertices, edges, per-vertex radius and mass, App. A.1 DLO
+ * Representation), the material rows of App. A.1 (stretching, bending,
+ * twisting, plasticity, friction), the rigid scene of Section 3.2 and the
+ * substepped time integration of App. B.1 (frame time dt, n_sub substeps,
+ * N_C constraint iterations).  Rods with self-contact get two blocks of pair
+ * scratch each (forward, adjoint) with room for every admissible edge pair:
+ * for a rod of N vertices M (M + 1) / 2 pairs, M = N - 2 - k_exclude, of 56
+ * bytes (FP32) or 88 bytes (FP64) in the forward block and 128 or 232 in
+ * the adjoint's.  On error *out is NULL and nothing is left allocated.  The
+ * state starts as x = 0 and must be set with rods_set_state. */
 int rods_create(const RodsDesc* desc, RodsHandle** out);
+/* Frees every buffer of the handle (NULL is ignored).  The caller makes sure
+ * no work on the handle is still running. */
 void rods_destroy(RodsHandle* h);
+/* Static text of an ROD_E* code. */
 const char* rods_strerror(int code);
 
 /* Current state S = (x, x_dot, r) of Section 4.1 plus the reference frames.
@@ -194,6 +207,13 @@ int rods_curvature(RodsHandle* h, const void* x, const void* d1, void* kappa,
 
 /* Advances the state by one step dt (n_sub substeps) with grasp velocities
  * grasp_vel [R][G][3]: grasped vertices move with the given velocity.
+ * A substep is the time integration of Section 3.1 / App. A.1: forces from
+ * the energy derivatives with the frames held fixed, symplectic Euler, soft
+ * SDF contact with the rigid scene (Section 3.2), prediction, N_C
+ * inextensibility and self-contact projections (App. A.1, Inextensibility
+ * Constraints and Self-collision), the velocity update from the
+ * corrections, self-friction, parallel transport of the frames and the
+ * plastic creep of the rest curvature (App. A.1, Bending Plasticity).
  * Does not record.  Safe to capture in a HIP graph. */
 int rods_step(RodsHandle* h, const void* grasp_vel, rods_stream_t stream);
 
@@ -203,7 +223,8 @@ int rods_step(RodsHandle* h, const void* grasp_vel, rods_stream_t stream);
  * handle before the replay, outside the graph. */
 int rods_step_graph(RodsHandle* h, const void* grasp_vel, rods_stream_t stream);
 
-/* Advances by n_steps; step s uses grasp_vel[s / steps_per_action] with
+/* Advances by n_steps of rods_step (Section 3.1); step s uses
+ * grasp_vel[s / steps_per_action] with
  * grasp_vel of shape [ceil(n_steps/steps_per_action)][R][G][3].  x_final
  * [V][3] receives the final positions (NULL to skip).  With record != 0 the
  * state at every ckpt_every-th step and a copy of the actions are kept for
@@ -287,12 +308,27 @@ int rods_loss_mse_static(const int32_t* vert_offsets, int32_t n_rods, int32_t pr
                          rods_stream_t stream);
 
 /* Synchronises the stream and copies per-rod status words to flags (host)
- * [R], accumulated since rods_set_state: bit0 = non-finite state seen;
- * bit1 = a self-contact partner list was full (candidate pairs beyond its
- * capacity were dropped for that substep); bit2 = an edge at predicted
- * positions exceeded twice the rod's longest rest edge (a warning: the
- * candidate search still covers it).  Returns ROD_EHIP if a kernel failed. */
+ * [R], accumulated since rods_set_state by the forward kernels (the
+ * time stepping of Section 3.1): bit0 = non-finite state seen;
+ * bit1 = an internal check of the self-contact pair bookkeeping failed (the
+ * two directions of the candidate search disagreed, or a pair had no
+ * place); never set by a correct build, since the pair scratch holds every
+ * admissible pair; bit2 = an edge at predicted positions exceeded twice the
+ * rod's longest rest edge (a warning: the candidate search still covers
+ * it).  Returns ROD_EHIP if a kernel failed. */
 int rods_status(RodsHandle* h, int32_t* flags, rods_stream_t stream);
+
+/* Self-contact candidates (App. A.1, Self-collision and Friction: the edge
+ * pairs (i, j), j - i > k_exclude, whose segments come closer than
+ * r_a + r_b + self_margin at the substep's predicted positions) of rod `rod`
+ * as the forward kernels found them in their last substep: writes *n_pairs
+ * (host) and up to cap pairs (i, j), i < j, into pairs (host) [cap][2],
+ * sorted by i and then by j (pairs may be NULL when cap is 0, to ask for
+ * the count).  0 pairs before the rod's first step.  Synchronises the
+ * stream.  ROD_EINVAL for a rod without self-contact, a NULL n_pairs or a
+ * NULL pairs with cap > 0. */
+int rods_sc_pairs(RodsHandle* h, int32_t rod, int32_t* pairs, int32_t cap, int32_t* n_pairs,
+                  rods_stream_t stream);
 
 /* Launch configuration per size bin: fills up to max_bins entries of
  * (vertices per lane, waves per rod, rods in bin) into out (host) [3*max_bins]

@@ -16,10 +16,12 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           # non-packed FP32 rate, with no v_pk_* FP32 arithmetic
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-# (source, extra flags, object): the kernel source is compiled a second time
-# for the kernels of twisting rods, in parallel with the first
+# (source, extra flags, object): the kernel source is compiled three times,
+# in parallel: the kernels of twisting rods, of rods with self-contact, and
+# of all other rods
 UNITS = [("rod_kernels.hip", [], "rod_kernels.o"),
          ("rod_kernels.hip", ["-DRODS_TU=1"], "rod_kernels_twist.o"),
+         ("rod_kernels.hip", ["-DRODS_TU=2"], "rod_kernels_sc.o"),
          ("rod_optim.hip", [], "rod_optim.o"),
          ("rod_loss.hip", [], "rod_loss.o"),
          ("rods_api.cpp", [], "rods_api.o")]

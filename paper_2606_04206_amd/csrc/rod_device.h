@@ -281,7 +281,9 @@ struct RodArgs {
   double* acc_s;            // [V] per-vertex dL/dsigma partials
   T* sc_tape;               // self-contact rods: projection iterates of one substep
   const int64_t* sc_off;    // [R] offset of the rod's block in sc_tape
-  int32_t* status;          // [R] bit0 non-finite, bit1 partner list full, bit2 stretched edge
+  unsigned char* pblk;      // self-contact rods: pair scratch (bytes)
+  const int64_t* pblk_off;  // [R] byte offset of the rod's pair block
+  int32_t* status;          // [R] bit0 non-finite, bit1 pair bookkeeping fault, bit2 stretched edge
   // twist degree of freedom (rods with the twist flag; edge rows)
   const T* Gt;              // [R] twisting modulus
   const T* jt;              // [V] inverse polar moment of inertia of edge row j

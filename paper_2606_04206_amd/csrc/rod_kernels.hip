@@ -8,8 +8,9 @@
 // iteration of the inextensibility projection needs exactly one neighbour
 // exchange pair (positions to the left, corrections to the right).
 //
-// The file is compiled twice: RODS_TU = 1 instantiates the kernels of rods
-// with the twist degree of freedom, the default everything else.
+// The file is compiled three times: RODS_TU = 1 instantiates the kernels of
+// rods with the twist degree of freedom, RODS_TU = 2 those of rods with
+// self-contact, the default everything else.
 //
 // Physics (DLO-Lab, Section 3.1 and Appendix A.1): bending forces of the
 // discrete elastic rod with frames held fixed, stretching forces for
@@ -22,6 +23,10 @@
 #include "rod_device.h"
 #include "rod_launch.h"
 #include "rod_selfcontact.h"
+
+#ifndef RODS_TU
+#define RODS_TU 0
+#endif
 
 namespace rods {
 
@@ -584,10 +589,14 @@ struct Rod {
   static constexpr int NV = TL * C;   // vertex capacity of the team
   static constexpr int NFIELD = nfield<TW>();
   int rod, N, v0, tl, flags, p0, p1;
-  // self-contact scratch (LDS) and the adjoint's contact-pass inputs (global)
-  T *sc_pos, *sc_aux, *sc_adj, *sc_w, *sc_r, *sc_d0, *sc_vcnt;
-  int *sc_cnt, *sc_start, *sc_pcnt, *sc_tmp;
-  short *sc_items, *sc_plist;
+  // self-contact: LDS staging, counts, hash and list offsets; the rod's
+  // block of global pair scratch; the adjoint's contact-pass inputs (global)
+  T *sc_pos, *sc_aux, *sc_adj, *sc_w, *sc_r, *sc_vc;
+  int *sc_cnt, *sc_fcnt, *sc_hcnt, *sc_hstart, *sc_items, *sc_lo, *sc_hi, *sc_tmp;
+  int *g_hdr, *g_trilo, *g_trihi, *g_hidx, *g_flag;
+  SPair* g_pairs;
+  T *g_d0, *g_d0b, *g_rec;
+  int sc_rv, sc_M, sc_P;
   T sc_cell0, sc_lmax;
   int sc_flags;
   T* ctape;
@@ -960,34 +969,54 @@ struct Rod {
   }
 
   // ------------------------------------------------------------ self-contact
-  // LDS: staging (positions, velocities), statics, first-pass depths, the
-  // hash (counts, starts, items) and the partner lists.  The adjoint's third
-  // staging buffer and the per-vertex pair counts reuse the hash counts and
-  // starts, which are dead once the partner lists are built.
+  // The candidate pairs of a substep live in the rod's block of global pair
+  // scratch (sized for every admissible pair: none is ever dropped), in one
+  // compact list sorted by the lower edge.  Every sweep over the pairs deals
+  // them round-robin to the team's lanes, so each pair is evaluated once and
+  // the work is even across lanes; a pair's result goes to its record, and
+  // each lane then gathers the records of the pairs that touch its own
+  // edges in a fixed order (lower-edge pairs in list order, then upper-edge
+  // pairs in the order of hidx), so every sum is deterministic.
+  //
+  // LDS: staging (positions, velocities, adjoints), statics, per-vertex
+  // counts of active pairs (this pass, first pass, adjoint's recorded
+  // counts), the hash, per-edge list offsets, and the scan buffer.
+  static constexpr int SC_TMP = 4 * TL + 16;   // ints; also holds 2 TL reals
   static constexpr size_t sc_bytes() {
-    static_assert(!SC || (2 * SC_HT + 1) * sizeof(int) >= 4 * NV * sizeof(T),
-                  "adjoint staging and vertex counts alias the hash arrays");
-    return sizeof(T) * (size_t)(2 * NV * 3 + 2 * NV + NV * SC_MAXP) +
-           sizeof(int) * (size_t)(SC_HT + SC_HT + 1 + NV + 2 * TL) +
-           sizeof(short) * (size_t)(NV + NV * SC_MAXP) + 64;
+    return sizeof(T) * (size_t)(12 * NV) +
+           sizeof(int) * (size_t)(2 * NV + SC_HT + (SC_HT + 4) + NV + 2 * (NV + 4) + SC_TMP) + 64;
   }
-  __device__ void sc_layout(unsigned char* base) {
+  __device__ void sc_layout(unsigned char* base, const RodArgs<T>& a, int rv) {
     T* f = reinterpret_cast<T*>(base);
     sc_pos = f; f += 3 * NV;
     sc_aux = f; f += 3 * NV;
+    sc_adj = f; f += 3 * NV;
     sc_w = f; f += NV;
     sc_r = f; f += NV;
-    sc_d0 = f; f += NV * SC_MAXP;
+    sc_vc = f; f += NV;
     int* q = reinterpret_cast<int*>(f);
-    sc_cnt = q; q += SC_HT;
-    sc_start = q; q += SC_HT + 1;
-    sc_adj = reinterpret_cast<T*>(sc_cnt);
-    sc_vcnt = sc_adj + 3 * NV;
-    sc_pcnt = q; q += NV;
-    sc_tmp = q; q += 2 * TL;
-    short* sh = reinterpret_cast<short*>(q);
-    sc_items = sh; sh += NV;
-    sc_plist = sh;
+    sc_cnt = q; q += NV;
+    sc_fcnt = q; q += NV;
+    sc_hcnt = q; q += SC_HT;
+    sc_hstart = q; q += SC_HT + 4;
+    sc_items = q; q += NV;
+    sc_lo = q; q += NV + 4;
+    sc_hi = q; q += NV + 4;
+    sc_tmp = q;
+    sc_rv = rv;
+    sc_M = N - 2 - a.k_ex;
+    const PairBlock pb = sc_block(N, a.k_ex, (int)sizeof(T), rv);
+    unsigned char* g = a.pblk + a.pblk_off[rod];
+    g_hdr = reinterpret_cast<int*>(g);
+    g_trilo = reinterpret_cast<int*>(g + pb.trilo);
+    g_trihi = reinterpret_cast<int*>(g + pb.trihi);
+    g_pairs = reinterpret_cast<SPair*>(g + pb.pairs);
+    g_hidx = reinterpret_cast<int*>(g + pb.hidx);
+    g_flag = reinterpret_cast<int*>(g + pb.flag);
+    g_d0 = reinterpret_cast<T*>(g + pb.d0);
+    g_d0b = reinterpret_cast<T*>(g + pb.d0b);
+    g_rec = reinterpret_cast<T*>(g + pb.rec);
+    sc_P = 0;
   }
   __device__ void sc_stage(T* dst, const V3<T> (&vals)[C]) const {
 #pragma unroll
@@ -1037,13 +1066,65 @@ struct Rod {
     __syncthreads();
   }
 
-  // candidate pairs at the predicted positions p (uniform-grid hash of edge
-  // midpoints; per own edge a sorted, duplicate-free partner list)
+  // exclusive prefix sums over the team of two per-lane counts (lane order);
+  // returns the totals.  Wave scan by lane shuffles, then the wave totals
+  // through LDS.
+  __device__ void sc_scan2(int a0, int a1, int& e0, int& e1, int& t0, int& t1) {
+    const int lane = tl & 63, wave = tl >> 6;
+    int i0 = a0, i1 = a1;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      int u0 = __shfl_up(i0, off, 64), u1 = __shfl_up(i1, off, 64);
+      if (lane >= off) {
+        i0 += u0;
+        i1 += u1;
+      }
+    }
+    if (lane == 63) {
+      sc_tmp[2 * wave] = i0;
+      sc_tmp[2 * wave + 1] = i1;
+    }
+    __syncthreads();
+    int b0 = 0, b1 = 0;
+    t0 = t1 = 0;
+    for (int q = 0; q < W; ++q) {
+      const int s0 = sc_tmp[2 * q], s1 = sc_tmp[2 * q + 1];
+      if (q < wave) {
+        b0 += s0;
+        b1 += s1;
+      }
+      t0 += s0;
+      t1 += s1;
+    }
+    e0 = b0 + i0 - a0;
+    e1 = b1 + i1 - a1;
+    __syncthreads();
+  }
+
+  // the exact candidate test of App. A.1's pairs (segment distance below
+  // r_a + r_b + delta_c), lower edge first whichever edge asks
+  __device__ __forceinline__ bool sc_near(int e, int j, T margin) const {
+    const int lo = e < j ? e : j, hi = e < j ? j : e;
+    V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
+    V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
+    Closest<T> cp = closest_params(P1, Q1, P2, Q2);
+    V3<T> ca = (T(1) - cp.s) * P1 + cp.s * Q1;
+    V3<T> cb = (T(1) - cp.u) * P2 + cp.u * Q2;
+    V3<T> df = ca - cb;
+    T ra = (T(1) - cp.s) * sc_r[lo] + cp.s * sc_r[lo + 1];
+    T rb = (T(1) - cp.u) * sc_r[hi] + cp.u * sc_r[hi + 1];
+    return fsqrt(dot(df, df)) < ra + rb + margin;
+  }
+
+  // candidate pairs at the predicted positions p: a uniform-grid hash of
+  // the edge midpoints (counting sort into buckets, each bucket sorted by
+  // edge), then per own edge a search of the 27 cells around it that keeps
+  // the partners above and below it in its triangular slots, then the
+  // compact pair list and the upper-edge incidence
   __device__ void sc_broadphase(const RodArgs<T>& a, const V3<T> (&p)[C]) {
-    static_assert(!SC || sizeof(T) == 4, "self-contact kernels are FP32");
     sc_stage(sc_pos, p);
-    for (int i = tl; i < SC_HT; i += TL) sc_cnt[i] = 0;
-    int* lsq = sc_tmp;   // longest squared edge (bits of a non-negative float)
+    for (int i = tl; i < SC_HT; i += TL) sc_hcnt[i] = 0;
+    int* lsq = sc_tmp;   // longest squared edge (bits of a non-negative real)
     if (tl == 0) *lsq = 0;
     __syncthreads();
     T l2 = T(0);
@@ -1054,103 +1135,153 @@ struct Rod {
         l2 = fmax(l2, dot(D, D));
       }
     }
-    atomicMax(lsq, __float_as_int(l2));
+    atomicMax(lsq, __float_as_int((float)l2));
     __syncthreads();
-    l2 = __int_as_float(*lsq);   // sc_tmp is next written after the barrier below
+    // the FP32 image of the longest edge, rounded up to the next float, is
+    // an upper bound in either precision
+    l2 = (T)__int_as_float(*lsq + 1);
+    __syncthreads();   // sc_tmp is reused below
     if (l2 > sc_lmax * sc_lmax) sc_flags |= 4;
-    const T ig = frcp(sc_cell0 + fsqrt(l2));
-    unsigned key[C];
-    int slot[C];
+    // one part in 10^4 of slack keeps the 27-cell argument safe from rounding
+    const T ig = frcp((sc_cell0 + fsqrt(l2)) * T(1.0001));
+    int key[C], slot[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       key[c] = 0;
       slot[c] = 0;
       if (evalid(c)) {
         int e = gi(c);
-        V3<T> P = sc_at(sc_pos, e), Q = sc_at(sc_pos, e + 1);
-        V3<T> m = T(0.5) * (P + Q);
-        key[c] = sc_hash((int)floor(m.x * ig), (int)floor(m.y * ig), (int)floor(m.z * ig));
-        slot[c] = atomicAdd(&sc_cnt[key[c]], 1);
+        V3<T> m = T(0.5) * (sc_at(sc_pos, e) + sc_at(sc_pos, e + 1));
+        key[c] = sc_key(sc_cell(m.x * ig), sc_cell(m.y * ig), sc_cell(m.z * ig));
+        slot[c] = atomicAdd(&sc_hcnt[key[c]], 1);
       }
     }
     __syncthreads();
-    constexpr int PER = SC_HT / TL;
-    const int base = tl * PER;
-    int sum = 0;
+    {
+      constexpr int PER = SC_HT / TL;
+      const int base = tl * PER;
+      int sum = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) sum += sc_cnt[base + k];
-    int* src = sc_tmp;
-    int* dst = sc_tmp + TL;
-    src[tl] = sum;
-    __syncthreads();
-    for (int off = 1; off < TL; off <<= 1) {
-      int v = src[tl];
-      if (tl >= off) v += src[tl - off];
-      dst[tl] = v;
+      for (int k = 0; k < PER; ++k) sum += sc_hcnt[base + k];
+      int ex, dummy, tot, tot1;
+      sc_scan2(sum, 0, ex, dummy, tot, tot1);
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        sc_hstart[base + k] = ex;
+        ex += sc_hcnt[base + k];
+      }
+      if (tl == TL - 1) sc_hstart[SC_HT] = ex;
       __syncthreads();
-      int* t_ = src; src = dst; dst = t_;
-    }
-    int excl = src[tl] - sum;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      sc_start[base + k] = excl;
-      excl += sc_cnt[base + k];
-    }
-    if (tl == TL - 1) sc_start[SC_HT] = excl;
-    __syncthreads();
+      for (int c = 0; c < C; ++c)
+        if (evalid(c)) sc_items[sc_hstart[key[c]] + slot[c]] = gi(c);
+      __syncthreads();
+      // the fill order above is that of the atomics: sort every bucket
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      if (evalid(c)) sc_items[sc_start[key[c]] + slot[c]] = (short)gi(c);
-    __syncthreads();
+      for (int k = 0; k < PER; ++k) {
+        const int s0 = sc_hstart[base + k], s1 = sc_hstart[base + k + 1];
+        for (int i = s0 + 1; i < s1; ++i) {
+          const int v = sc_items[i];
+          int j = i - 1;
+          while (j >= s0 && sc_items[j] > v) {
+            sc_items[j + 1] = sc_items[j];
+            --j;
+          }
+          sc_items[j + 1] = v;
+        }
+      }
+      __syncthreads();
+    }
     const T margin = a.self_margin;
-    // a partner must have its midpoint within h_e + h_max + 2 r_max + margin
-    // of the edge's own (segment distance >= midpoint distance minus both
-    // half-lengths); the slack keeps every pair the exact test below accepts
+    // a partner's midpoint is within h_e + h_max + 2 r_max + margin of the
+    // edge's own (segment distance >= midpoint distance minus both
+    // half-lengths); the slack keeps every pair the exact test accepts
     const T h_max = T(0.5) * fsqrt(l2);
+    const int64_t M = sc_M;
+    int nlo[C], nhi[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+      nlo[c] = nhi[c] = 0;
       if (!evalid(c)) continue;
       const int e = gi(c);
-      short* pl = sc_plist + e * SC_MAXP;
-      int cnt = 0;
+      int* lo_out = g_trilo + sc_off_lo(e, M);
+      int* hi_out = g_trihi + sc_off_hi(e, a.k_ex);
+      const int cap_lo = M - e > 0 ? (int)(M - e) : 0;
+      const int cap_hi = e - a.k_ex > 0 ? e - a.k_ex : 0;
       V3<T> P = sc_at(sc_pos, e), Q = sc_at(sc_pos, e + 1);
       V3<T> m = T(0.5) * (P + Q);
       V3<T> PQ = Q - P;
       const T reach = (T(0.5) * fsqrt(dot(PQ, PQ)) + h_max + sc_cell0) * T(1.0001) + T(1e-6);
       const T reach2 = reach * reach;
-      int cx = (int)floor(m.x * ig), cy = (int)floor(m.y * ig), cz = (int)floor(m.z * ig);
+      const int cx = sc_cell(m.x * ig), cy = sc_cell(m.y * ig), cz = sc_cell(m.z * ig);
       for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
           for (int dx = -1; dx <= 1; ++dx) {
-            unsigned kk = sc_hash(cx + dx, cy + dy, cz + dz);
-            for (int q = sc_start[kk]; q < sc_start[kk + 1]; ++q) {
-              int j = sc_items[q];
+            const int kk = sc_key(cx + dx, cy + dy, cz + dz);
+            const int q1 = sc_hstart[kk + 1];
+            for (int q = sc_hstart[kk]; q < q1; ++q) {
+              const int j = sc_items[q];
               if (!(j - e > a.k_ex || e - j > a.k_ex)) continue;
               V3<T> mm = T(0.5) * (sc_at(sc_pos, j) + sc_at(sc_pos, j + 1)) - m;
               if (!(dot(mm, mm) < reach2)) continue;
-              int lo = e < j ? e : j, hi = e < j ? j : e;
-              V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
-              V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
-              Closest<T> cp = closest_params(P1, Q1, P2, Q2);
-              V3<T> ca = (T(1) - cp.s) * P1 + cp.s * Q1;
-              V3<T> cb = (T(1) - cp.u) * P2 + cp.u * Q2;
-              V3<T> df = ca - cb;
-              T ra = (T(1) - cp.s) * sc_r[lo] + cp.s * sc_r[lo + 1];
-              T rb = (T(1) - cp.u) * sc_r[hi] + cp.u * sc_r[hi + 1];
-              if (!(fsqrt(dot(df, df)) < ra + rb + margin)) continue;
-              // sorted insert without duplicates (hash collisions revisit buckets)
-              int at = 0;
-              while (at < cnt && pl[at] < j) ++at;
-              if (at < cnt && pl[at] == j) continue;
-              if (at >= SC_MAXP) { sc_flags |= 2; continue; }
-              if (cnt == SC_MAXP) sc_flags |= 2;
-              int last = cnt < SC_MAXP ? cnt : SC_MAXP - 1;
-              for (int k = last; k > at; --k) pl[k] = pl[k - 1];
-              pl[at] = (short)j;
-              cnt = cnt < SC_MAXP ? cnt + 1 : SC_MAXP;
+              if (!sc_near(e, j, margin)) continue;
+              if (j > e) {
+                if (nlo[c] < cap_lo) lo_out[nlo[c]++] = j; else sc_flags |= 2;
+              } else {
+                if (nhi[c] < cap_hi) hi_out[nhi[c]++] = j; else sc_flags |= 2;
+              }
             }
           }
-      sc_pcnt[e] = cnt;
+    }
+    // list offsets: exclusive prefix sums in vertex-slot order (invalid
+    // edges count 0), the totals at slot NV
+    int slo = 0, shi = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      slo += nlo[c];
+      shi += nhi[c];
+    }
+    int elo, ehi, tlo, thi;
+    sc_scan2(slo, shi, elo, ehi, tlo, thi);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      sc_lo[gi(c)] = elo;
+      sc_hi[gi(c)] = ehi;
+      elo += nlo[c];
+      ehi += nhi[c];
+    }
+    if (tl == 0) {
+      sc_lo[NV] = tlo;
+      sc_hi[NV] = thi;
+      g_hdr[0] = tlo;
+    }
+    if (tlo != thi) sc_flags |= 2;   // the two searches must agree
+    sc_P = tlo;
+    __syncthreads();
+    // compact list, and per upper edge the list index of each of its pairs
+    // (its position in the lower edge's partner slots)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (!evalid(c)) continue;
+      const int e = gi(c);
+      const int* lo_in = g_trilo + sc_off_lo(e, M);
+      const int b0 = sc_lo[e];
+      for (int q = 0; q < nlo[c]; ++q) g_pairs[b0 + q] = SPair{e, lo_in[q]};
+      const int* hi_in = g_trihi + sc_off_hi(e, a.k_ex);
+      const int b1 = sc_hi[e];
+      for (int q = 0; q < nhi[c]; ++q) {
+        const int j = hi_in[q];
+        const int* lj = g_trilo + sc_off_lo(j, M);
+        const int n_j = sc_lo[j + 1] - sc_lo[j];
+        int at = -1;
+        for (int t = 0; t < n_j; ++t)
+          if (lj[t] == e) {
+            at = t;
+            break;
+          }
+        if (at < 0) sc_flags |= 2;
+        g_hidx[b1 + q] = at < 0 ? -1 : sc_lo[j] + at;
+      }
     }
     __syncthreads();
   }
@@ -1160,87 +1291,97 @@ struct Rod {
                     sc_w[lo + 1], sc_w[hi], sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
                     sc_r[hi + 1]);
   }
-
-  // Per-pair divisor of the Jacobi passes: the largest number of counted
-  // pairs touching one of the pair's four vertices.  ne[c] is the number of
-  // counted pairs of own edge c; a vertex is touched by the pairs of the two
-  // edges that meet at it.  Stages the vertex counts into sc_vcnt (the
-  // caller synchronises) and returns them.
-  __device__ void sc_vertex_counts(Team<T, W>& X, const T (&ne)[C], T (&nv)[C]) {
-    T sp[1] = {ne[C - 1]};
-    X.prev(sp);
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      nv[c] = ne[c] + (c ? ne[c - 1] : sp[0]);
-      if (vvalid(c)) sc_vcnt[gi(c)] = nv[c];
+  // per-pair divisor of the Jacobi passes: the largest number of counted
+  // pairs touching one of the pair's four vertices (at least 1)
+  template <typename Q>
+  __device__ __forceinline__ T sc_divisor(const Q* cnt, int lo, int hi) const {
+    const Q a0 = cnt[lo] > cnt[lo + 1] ? cnt[lo] : cnt[lo + 1];
+    const Q a1 = cnt[hi] > cnt[hi + 1] ? cnt[hi] : cnt[hi + 1];
+    const T m = (T)(a0 > a1 ? a0 : a1);
+    return m > T(1) ? m : T(1);
+  }
+  // gather the records of the pairs touching own edge e: f(k, pair, is_lo)
+  // for every flagged pair, lower-edge pairs first
+  template <typename F>
+  __device__ __forceinline__ void sc_gather(int e, F&& f) const {
+    const int k1 = sc_lo[e + 1];
+    for (int k = sc_lo[e]; k < k1; ++k)
+      if (g_flag[k]) f(k, g_pairs[k], true);
+    const int q1 = sc_hi[e + 1];
+    for (int q = sc_hi[e]; q < q1; ++q) {
+      const int k = g_hidx[q];
+      if (k >= 0 && g_flag[k]) f(k, g_pairs[k], false);
     }
   }
-  __device__ __forceinline__ T sc_divisor(int lo, int hi) const {
-    T m = fmax(fmax(sc_vcnt[lo], sc_vcnt[lo + 1]), fmax(sc_vcnt[hi], sc_vcnt[hi + 1]));
-    return fmax(m, T(1));
-  }
 
-  // one Jacobi pass of the self-contact projection (gather per own edge):
-  // a first sweep decides which pairs are active and counts them per
-  // vertex, the second applies every active pair's correction divided by
-  // its divisor
+  // one Jacobi pass of the self-contact projection: a sweep over the pairs
+  // evaluates each once (activity, depth, direction) and counts the active
+  // pairs per vertex; the gather applies every active pair's correction
+  // divided by its divisor.  The first pass keeps the depths d0 and the
+  // counts for friction.
   template <bool REC>
   __device__ void sc_pass(Team<T, W>& X, const V3<T> (&p0)[C], V3<T> (&dl)[C], int it,
                           bool first) {
     V3<T> p[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) p[c] = p0[c] + dl[c];
+    for (int c = 0; c < C; ++c) {
+      p[c] = p0[c] + dl[c];
+      sc_cnt[gi(c)] = 0;
+    }
     sc_stage(sc_pos, p);
     __syncthreads();
-    T ne[C], nv[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      ne[c] = T(0);
-      if (!evalid(c)) continue;
-      const int e = gi(c);
-      const short* pl = sc_plist + e * SC_MAXP;
-      const int n = sc_pcnt[e];
-      for (int k = 0; k < n; ++k) {
-        int j = pl[k];
-        int lo = e < j ? e : j, hi = e < j ? j : e;
-        PairGeo<T> g = sc_pair(sc_pos, lo, hi);
-        if (first) sc_d0[e * SC_MAXP + k] = g.act ? g.d : T(0);
-        if (g.act) ne[c] += T(1);
+    for (int k = tl; k < sc_P; k += TL) {
+      const SPair pr = g_pairs[k];
+      PairGeo<T> g = sc_pair(sc_pos, pr.lo, pr.hi);
+      if (first) g_d0[k] = g.act ? g.d : T(0);
+      g_flag[k] = g.act ? 1 : 0;
+      if (g.act) {
+        const T kk = fdiv(g.d, g.W);
+        T* r = g_rec + (int64_t)k * sc_rv;
+        r[0] = kk * g.n.x;
+        r[1] = kk * g.n.y;
+        r[2] = kk * g.n.z;
+        r[3] = g.cp.s;
+        r[4] = g.cp.u;
+        atomicAdd(&sc_cnt[pr.lo], 1);
+        atomicAdd(&sc_cnt[pr.lo + 1], 1);
+        atomicAdd(&sc_cnt[pr.hi], 1);
+        atomicAdd(&sc_cnt[pr.hi + 1], 1);
       }
     }
-    sc_vertex_counts(X, ne, nv);
+    __syncthreads();
+    if (first) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) sc_fcnt[gi(c)] = sc_cnt[gi(c)];
+    }
     if constexpr (REC) {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        Q4<T> q = {p[c].x, p[c].y, p[c].z, nv[c]};
+        Q4<T> q = {p[c].x, p[c].y, p[c].z, (T)sc_cnt[gi(c)]};
         reinterpret_cast<Q4<T>*>(ctape)[(it * C + c) * TL + tl] = q;
       }
     }
-    __syncthreads();
     V3<T> dA[C], dB[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       dA[c] = zero3<T>();
       dB[c] = zero3<T>();
-      if (!(ne[c] > T(0))) continue;
+      if (!evalid(c)) continue;
       const int e = gi(c);
-      const short* pl = sc_plist + e * SC_MAXP;
-      const int n = sc_pcnt[e];
-      for (int k = 0; k < n; ++k) {
-        int j = pl[k];
-        int lo = e < j ? e : j, hi = e < j ? j : e;
-        PairGeo<T> g = sc_pair(sc_pos, lo, hi);
-        if (g.act) {
-          T kk = fdiv(g.d, g.W * sc_divisor(lo, hi));
-          if (e == lo) {
-            dA[c] += (kk * sc_w[lo] * (T(1) - g.cp.s)) * g.n;
-            dB[c] += (kk * sc_w[lo + 1] * g.cp.s) * g.n;
-          } else {
-            dA[c] -= (kk * sc_w[hi] * (T(1) - g.cp.u)) * g.n;
-            dB[c] -= (kk * sc_w[hi + 1] * g.cp.u) * g.n;
-          }
+      sc_gather(e, [&](int k, SPair pr, bool is_lo) {
+        const T* r = g_rec + (int64_t)k * sc_rv;
+        const V3<T> kn = mk(r[0], r[1], r[2]);
+        const T im = frcp(sc_divisor(sc_cnt, pr.lo, pr.hi));
+        if (is_lo) {
+          const T s = r[3];
+          dA[c] += (sc_w[e] * (T(1) - s) * im) * kn;
+          dB[c] += (sc_w[e + 1] * s * im) * kn;
+        } else {
+          const T u = r[4];
+          dA[c] -= (sc_w[e] * (T(1) - u) * im) * kn;
+          dB[c] -= (sc_w[e + 1] * u * im) * kn;
         }
-      }
+      });
     }
     __syncthreads();
     T s3[3] = {dB[C - 1].x, dB[C - 1].y, dB[C - 1].z};
@@ -1249,27 +1390,38 @@ struct Rod {
     for (int c = 0; c < C; ++c) dl[c] += dA[c] + (c ? dB[c - 1] : mk(s3[0], s3[1], s3[2]));
   }
 
-  // pairs with a positive first-pass depth per own edge (friction's counts)
-  __device__ void sc_friction_counts(Team<T, W>& X) {
-    T ne[C], nv[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      ne[c] = T(0);
-      if (!evalid(c)) continue;
-      const int e = gi(c);
-      const int n = sc_pcnt[e];
-      for (int k = 0; k < n; ++k)
-        if (sc_d0[e * SC_MAXP + k] > T(0)) ne[c] += T(1);
-    }
-    sc_vertex_counts(X, ne, nv);
-  }
-
-  // self-friction on velocities v at final positions x1
+  // self-friction on velocities v at final positions x1, for the pairs with
+  // a positive first-pass depth; divisors from the first pass's counts
   __device__ void sc_friction(const RodArgs<T>& a, Team<T, W>& X, const V3<T> (&x1)[C],
                               V3<T> (&v)[C]) {
     sc_stage(sc_pos, x1);
     sc_stage(sc_aux, v);
-    sc_friction_counts(X);
+    __syncthreads();
+    for (int k = tl; k < sc_P; k += TL) {
+      const T d0 = g_d0[k];
+      int fl = 0;
+      if (d0 > T(0)) {
+        const SPair pr = g_pairs[k];
+        const int lo = pr.lo, hi = pr.hi;
+        FricGeo<T> f = pair_friction(sc_at(sc_pos, lo), sc_at(sc_pos, lo + 1), sc_at(sc_pos, hi),
+                                     sc_at(sc_pos, hi + 1), sc_at(sc_aux, lo),
+                                     sc_at(sc_aux, lo + 1), sc_at(sc_aux, hi),
+                                     sc_at(sc_aux, hi + 1), sc_w[lo], sc_w[lo + 1], sc_w[hi],
+                                     sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
+                                     sc_r[hi + 1], d0, mu, a.h);
+        if (f.ok) {
+          fl = 1;
+          T* r = g_rec + (int64_t)k * sc_rv;
+          r[0] = f.dvt.x;
+          r[1] = f.dvt.y;
+          r[2] = f.dvt.z;
+          r[3] = f.g.cp.s;
+          r[4] = f.g.cp.u;
+          r[5] = f.g.W;
+        }
+      }
+      g_flag[k] = fl;
+    }
     __syncthreads();
     V3<T> dA[C], dB[C];
 #pragma unroll
@@ -1278,29 +1430,20 @@ struct Rod {
       dB[c] = zero3<T>();
       if (!evalid(c)) continue;
       const int e = gi(c);
-      const short* pl = sc_plist + e * SC_MAXP;
-      const int n = sc_pcnt[e];
-      for (int k = 0; k < n; ++k) {
-        T d0 = sc_d0[e * SC_MAXP + k];
-        if (!(d0 > T(0))) continue;
-        int j = pl[k];
-        int lo = e < j ? e : j, hi = e < j ? j : e;
-        FricGeo<T> f = pair_friction(sc_at(sc_pos, lo), sc_at(sc_pos, lo + 1), sc_at(sc_pos, hi),
-                                     sc_at(sc_pos, hi + 1), sc_at(sc_aux, lo),
-                                     sc_at(sc_aux, lo + 1), sc_at(sc_aux, hi),
-                                     sc_at(sc_aux, hi + 1), sc_w[lo], sc_w[lo + 1], sc_w[hi],
-                                     sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
-                                     sc_r[hi + 1], d0, mu, a.h);
-        if (!f.ok) continue;
-        T iW = frcp(f.g.W * sc_divisor(lo, hi));
-        if (e == lo) {
-          dA[c] += (sc_w[lo] * (T(1) - f.g.cp.s) * iW) * f.dvt;
-          dB[c] += (sc_w[lo + 1] * f.g.cp.s * iW) * f.dvt;
+      sc_gather(e, [&](int k, SPair pr, bool is_lo) {
+        const T* r = g_rec + (int64_t)k * sc_rv;
+        const V3<T> dvt = mk(r[0], r[1], r[2]);
+        const T iW = frcp(r[5] * sc_divisor(sc_fcnt, pr.lo, pr.hi));
+        if (is_lo) {
+          const T s = r[3];
+          dA[c] += (sc_w[e] * (T(1) - s) * iW) * dvt;
+          dB[c] += (sc_w[e + 1] * s * iW) * dvt;
         } else {
-          dA[c] -= (sc_w[hi] * (T(1) - f.g.cp.u) * iW) * f.dvt;
-          dB[c] -= (sc_w[hi + 1] * f.g.cp.u * iW) * f.dvt;
+          const T u = r[4];
+          dA[c] -= (sc_w[e] * (T(1) - u) * iW) * dvt;
+          dB[c] -= (sc_w[e + 1] * u * iW) * dvt;
         }
-      }
+      });
     }
     __syncthreads();
     T s3[3] = {dB[C - 1].x, dB[C - 1].y, dB[C - 1].z};
@@ -1311,27 +1454,20 @@ struct Rod {
 
   // adjoint of sc_friction: lv (adjoint of friction's output velocity) ->
   // adjoint of its input velocity; adds position adjoints to xb; leaves the
-  // adjoint of each pair's first-pass depth in sc_d0
+  // adjoint of each pair's first-pass depth in g_d0b
   __device__ void sc_friction_vjp(const RodArgs<T>& a, Team<T, W>& X, const Rec<T, C>& r,
                                   V3<T> (&lv)[C], V3<T> (&xb)[C]) {
     sc_stage(sc_pos, r.x1);
     sc_stage(sc_aux, r.v3);
     sc_stage(sc_adj, lv);
-    sc_friction_counts(X);
     __syncthreads();
-    V3<T> vA[C], vB[C], xA[C], xB[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      vA[c] = vB[c] = xA[c] = xB[c] = zero3<T>();
-      if (!evalid(c)) continue;
-      const int e = gi(c);
-      const short* pl = sc_plist + e * SC_MAXP;
-      const int n = sc_pcnt[e];
-      for (int k = 0; k < n; ++k) {
-        T d0 = sc_d0[e * SC_MAXP + k];
-        if (!(d0 > T(0))) continue;
-        int j = pl[k];
-        int lo = e < j ? e : j, hi = e < j ? j : e;
+    for (int k = tl; k < sc_P; k += TL) {
+      const T d0 = g_d0[k];
+      int fl = 0;
+      T d0b = T(0);
+      if (d0 > T(0)) {
+        const SPair pr = g_pairs[k];
+        const int lo = pr.lo, hi = pr.hi;
         V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
         V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
         V3<T> vi = sc_at(sc_aux, lo), vi1 = sc_at(sc_aux, lo + 1);
@@ -1339,20 +1475,37 @@ struct Rod {
         FricGeo<T> f = pair_friction(P1, Q1, P2, Q2, vi, vi1, vj, vj1, sc_w[lo], sc_w[lo + 1],
                                      sc_w[hi], sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
                                      sc_r[hi + 1], d0, mu, a.h);
-        V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
-        V3<T> q0 = zero3<T>(), q1 = zero3<T>(), q2 = zero3<T>(), q3 = zero3<T>();
-        const T im = frcp(sc_divisor(lo, hi));
-        T d0b = pair_friction_vjp(P1, Q1, P2, Q2, vi, vi1, vj, vj1, f, sc_w[lo], sc_w[lo + 1],
+        if (f.ok) {
+          fl = 1;
+          V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
+          V3<T> q0 = zero3<T>(), q1 = zero3<T>(), q2 = zero3<T>(), q3 = zero3<T>();
+          const T im = frcp(sc_divisor(sc_fcnt, lo, hi));
+          d0b = pair_friction_vjp(P1, Q1, P2, Q2, vi, vi1, vj, vj1, f, sc_w[lo], sc_w[lo + 1],
                                   sc_w[hi], sc_w[hi + 1], mu, a.h, im * sc_at(sc_adj, lo),
                                   im * sc_at(sc_adj, lo + 1), im * sc_at(sc_adj, hi),
                                   im * sc_at(sc_adj, hi + 1), b0, b1, b2, b3, q0, q1, q2, q3);
-        sc_d0[e * SC_MAXP + k] = d0b;
-        if (e == lo) {
-          vA[c] += b0; vB[c] += b1; xA[c] += q0; xB[c] += q1;
-        } else {
-          vA[c] += b2; vB[c] += b3; xA[c] += q2; xB[c] += q3;
+          T* o = g_rec + (int64_t)k * sc_rv;
+          put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, b2); put3(o, 9, b3);
+          put3(o, 12, q0); put3(o, 15, q1); put3(o, 18, q2); put3(o, 21, q3);
         }
       }
+      g_flag[k] = fl;
+      g_d0b[k] = d0b;
+    }
+    __syncthreads();
+    V3<T> vA[C], vB[C], xA[C], xB[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      vA[c] = vB[c] = xA[c] = xB[c] = zero3<T>();
+      if (!evalid(c)) continue;
+      sc_gather(gi(c), [&](int k, SPair, bool is_lo) {
+        const T* o = g_rec + (int64_t)k * sc_rv;
+        const int s = is_lo ? 0 : 6;
+        vA[c] += get3(o, s);
+        vB[c] += get3(o, s + 3);
+        xA[c] += get3(o, s + 12);
+        xB[c] += get3(o, s + 15);
+      });
     }
     __syncthreads();
     T s6[6] = {vB[C - 1].x, vB[C - 1].y, vB[C - 1].z, xB[C - 1].x, xB[C - 1].y, xB[C - 1].z};
@@ -1364,52 +1517,55 @@ struct Rod {
     }
   }
 
-  // adjoint of the contact pass of iteration it (inputs read back from ctape);
-  // at it == 0 also the adjoint of the first-pass depths left in sc_d0
+  // adjoint of the contact pass of iteration it (inputs and counts read
+  // back from ctape); at it == 0 also the adjoint of the first-pass depths
+  // left in g_d0b
   __device__ void sc_pass_vjp(Team<T, W>& X, V3<T> (&pb)[C], int it, bool with_depth) {
     V3<T> pin[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       Q4<T> q = reinterpret_cast<const Q4<T>*>(ctape)[(it * C + c) * TL + tl];
       pin[c] = mk(q.x, q.y, q.z);
-      if (vvalid(c)) sc_vcnt[gi(c)] = q.w;
+      sc_vc[gi(c)] = q.w;
     }
     sc_stage(sc_pos, pin);
     sc_stage(sc_adj, pb);
+    __syncthreads();
+    for (int k = tl; k < sc_P; k += TL) {
+      const SPair pr = g_pairs[k];
+      const int lo = pr.lo, hi = pr.hi;
+      PairGeo<T> g = sc_pair(sc_pos, lo, hi);
+      g_flag[k] = g.act ? 1 : 0;
+      if (!g.act) continue;
+      V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
+      V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
+      V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
+      const T im = frcp(sc_divisor(sc_vc, lo, hi));
+      pair_proj_vjp(P1, Q1, P2, Q2, g, sc_w[lo], sc_w[lo + 1], sc_w[hi], sc_w[hi + 1], sc_r[lo],
+                    sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], im * sc_at(sc_adj, lo),
+                    im * sc_at(sc_adj, lo + 1), im * sc_at(sc_adj, hi),
+                    im * sc_at(sc_adj, hi + 1), b0, b1, b2, b3);
+      if (with_depth) {
+        const T d0b = g_d0b[k];
+        if (d0b != T(0))
+          pair_depth_vjp(P1, Q1, P2, Q2, g, sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], d0b,
+                         b0, b1, b2, b3);
+      }
+      T* o = g_rec + (int64_t)k * sc_rv;
+      put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, b2); put3(o, 9, b3);
+    }
     __syncthreads();
     V3<T> cA[C], cB[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       cA[c] = cB[c] = zero3<T>();
       if (!evalid(c)) continue;
-      const int e = gi(c);
-      const short* pl = sc_plist + e * SC_MAXP;
-      const int n = sc_pcnt[e];
-      for (int k = 0; k < n; ++k) {
-        int j = pl[k];
-        int lo = e < j ? e : j, hi = e < j ? j : e;
-        PairGeo<T> g = sc_pair(sc_pos, lo, hi);
-        if (!g.act) continue;
-        V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
-        V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
-        V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
-        const T im = frcp(sc_divisor(lo, hi));
-        pair_proj_vjp(P1, Q1, P2, Q2, g, sc_w[lo], sc_w[lo + 1], sc_w[hi], sc_w[hi + 1],
-                      sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], im * sc_at(sc_adj, lo),
-                      im * sc_at(sc_adj, lo + 1), im * sc_at(sc_adj, hi),
-                      im * sc_at(sc_adj, hi + 1), b0, b1, b2, b3);
-        if (with_depth) {
-          T d0b = sc_d0[e * SC_MAXP + k];
-          if (d0b != T(0))
-            pair_depth_vjp(P1, Q1, P2, Q2, g, sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], d0b,
-                           b0, b1, b2, b3);
-        }
-        if (e == lo) {
-          cA[c] += b0; cB[c] += b1;
-        } else {
-          cA[c] += b2; cB[c] += b3;
-        }
-      }
+      sc_gather(gi(c), [&](int k, SPair, bool is_lo) {
+        const T* o = g_rec + (int64_t)k * sc_rv;
+        const int s = is_lo ? 0 : 6;
+        cA[c] += get3(o, s);
+        cB[c] += get3(o, s + 3);
+      });
     }
     __syncthreads();
     T s3[3] = {cB[C - 1].x, cB[C - 1].y, cB[C - 1].z};
@@ -1417,7 +1573,6 @@ struct Rod {
 #pragma unroll
     for (int c = 0; c < C; ++c) pb[c] += cA[c] + (c ? cB[c - 1] : mk(s3[0], s3[1], s3[2]));
   }
-
   // gather the previous lane's last edge: tangent, inverse length, d1
   __device__ void prev_edge(Team<T, W>& X, const V3<T> (&t)[C], const T (&il)[C],
                             const V3<T> (&dd)[C], V3<T>& tp, T& ilp, V3<T>& dp) const {
@@ -1667,9 +1822,9 @@ struct Rod {
       v[c] += ih * dl[c];
       x[c] = p0[c] + dl[c];
     }
-    // S9 self-friction
+    // S9 self-friction (its depths come from the first contact pass)
     if constexpr (SC) {
-      if (self_on) {
+      if (self_on && a.n_iters > 0) {
         if constexpr (REC) {
 #pragma unroll
           for (int c = 0; c < C; ++c) {
@@ -1831,7 +1986,7 @@ struct Rod {
     edges_vjp(X, r.t1, r.il1, t1b, l1b, pb);
     // S9 self-friction
     if constexpr (SC) {
-      if (flags & FLAG_SELF) sc_friction_vjp(a, X, r, lv, pb);
+      if ((flags & FLAG_SELF) && a.n_iters > 0) sc_friction_vjp(a, X, r, lv, pb);
     }
     // S8: v' = v2 + (p - p0)/h, x' = p
     V3<T> v2b[C], p0b[C];
@@ -2187,7 +2342,7 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
   Rod<T, C, W, SC, TW, BD> R;
   R.load_static(a, X);
   if constexpr (SC) {
-    R.sc_layout(smem + xchg_bytes<T, W>());
+    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_RV_FWD);
     R.ctape = nullptr;
     R.sc_setup(a);
   }
@@ -2251,7 +2406,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
     // LDS holds the self-contact buffers; the contact-pass inputs follow the
     // projection iterates in the rod's scratch block (written and read
     // within a substep)
-    R.sc_layout(smem + xchg_bytes<T, W>());
+    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_RV_ADJ);
     R.ctape = lds_tape + (size_t)a.n_iters * C * PROJ_TAPE * 64 * W;
     R.sc_setup(a);
   }
@@ -2397,7 +2552,7 @@ __global__ void k_fill(T* p, int64_t n, T val) {
   if (i < n) p[i] = val;
 }
 
-#if RODS_TU != 1
+#if RODS_TU == 0
 __global__ void k_selftest_exchange(int* out) {
   int l = threadIdx.x;
   int nx = dpp_from_next_i(l + 1) - 1;
@@ -2464,13 +2619,46 @@ template hipError_t launch_rods_twist<float>(int, int, int, bool, const RodArgs<
                                              hipStream_t);
 template hipError_t launch_rods_twist<double>(int, int, int, bool, const RodArgs<double>&, int,
                                               hipStream_t);
+#elif RODS_TU == 2
+// Rods with self-contact: FP32 teams of two vertices per lane and 1-8 waves
+// or four vertices per lane and 4 waves, FP64 teams of two vertices per lane
+// (this translation unit instantiates only these kernels).
+template <typename T>
+hipError_t launch_rods_sc(int which, int C, int W, const RodArgs<T>& a, int n_blocks,
+                          hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  if (C == 2 && W == 1) return launch_shape<T, 2, 1, true>(which, true, a, n_blocks, st);
+  if (C == 2 && W == 2) return launch_shape<T, 2, 2, true>(which, true, a, n_blocks, st);
+  if (C == 2 && W == 4) return launch_shape<T, 2, 4, true>(which, true, a, n_blocks, st);
+  if (C == 2 && W == 8) return launch_shape<T, 2, 8, true>(which, true, a, n_blocks, st);
+  if constexpr (sizeof(T) == 4) {
+    if (C == 4 && W == 4) return launch_shape<T, 4, 4, true>(which, true, a, n_blocks, st);
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T>
+size_t sc_lds_bytes(int C, int W) {
+  size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
+  if (C == 2 && W == 1) return xb + Rod<T, 2, 1, true>::sc_bytes();
+  if (C == 2 && W == 2) return xb + Rod<T, 2, 2, true>::sc_bytes();
+  if (C == 2 && W == 4) return xb + Rod<T, 2, 4, true>::sc_bytes();
+  if (C == 2 && W == 8) return xb + Rod<T, 2, 8, true>::sc_bytes();
+  if (sizeof(T) == 4 && C == 4 && W == 4) return xb + Rod<T, 4, 4, true>::sc_bytes();
+  return (size_t)1 << 30;   // no self-contact kernel for this shape
+}
+template hipError_t launch_rods_sc<float>(int, int, int, const RodArgs<float>&, int, hipStream_t);
+template hipError_t launch_rods_sc<double>(int, int, int, const RodArgs<double>&, int,
+                                           hipStream_t);
+template size_t sc_lds_bytes<float>(int, int);
+template size_t sc_lds_bytes<double>(int, int);
 #else
 template <typename T>
 hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<T>& a,
                        int n_blocks, hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
+  if (SC) return launch_rods_sc<T>(which, C, W, a, n_blocks, st);
 #define RODS_SHAPE(CC, WW) \
-  if (!SC && C == CC && W == WW) return launch_shape<T, CC, WW, false>(which, GT, a, n_blocks, st);
+  if (C == CC && W == WW) return launch_shape<T, CC, WW, false>(which, GT, a, n_blocks, st);
   RODS_SHAPE(2, 1)
   RODS_SHAPE(2, 2)
   RODS_SHAPE(2, 4)
@@ -2479,14 +2667,6 @@ hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<
     RODS_SHAPE(4, 1)
     RODS_SHAPE(4, 2)
     RODS_SHAPE(4, 4)
-#define RODS_SC_SHAPE(CC, WW) \
-  if (SC && C == CC && W == WW) return launch_shape<T, CC, WW, true>(which, true, a, n_blocks, st);
-    RODS_SC_SHAPE(2, 1)
-    RODS_SC_SHAPE(2, 2)
-    RODS_SC_SHAPE(2, 4)
-    RODS_SC_SHAPE(2, 8)
-    RODS_SC_SHAPE(4, 4)
-#undef RODS_SC_SHAPE
   }
 #undef RODS_SHAPE
   return hipErrorInvalidValue;
@@ -2509,16 +2689,7 @@ hipError_t launch_rods_bodies(int which, int C, int W, bool GT, const RodArgs<T>
 template <typename T>
 size_t kernel_lds_bytes(int which, int C, int W, bool SC, bool GT, int n_iters) {
   size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;
-  if (SC) {
-    if constexpr (sizeof(T) == 4) {
-      if (C == 2 && W == 1) return xb + Rod<T, 2, 1, true>::sc_bytes();
-      if (C == 2 && W == 2) return xb + Rod<T, 2, 2, true>::sc_bytes();
-      if (C == 2 && W == 4) return xb + Rod<T, 2, 4, true>::sc_bytes();
-      if (C == 2 && W == 8) return xb + Rod<T, 2, 8, true>::sc_bytes();
-      if (C == 4 && W == 4) return xb + Rod<T, 4, 4, true>::sc_bytes();
-    }
-    return (size_t)1 << 30;   // no self-contact kernel for this shape or precision
-  }
+  if (SC) return sc_lds_bytes<T>(C, W);
   if (which == 2 && !GT) return xb + (size_t)n_iters * C * PROJ_TAPE * 64 * W * sizeof(T);
   return xb;
 }

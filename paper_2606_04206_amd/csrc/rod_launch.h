@@ -7,12 +7,20 @@
 namespace rods {
 
 // which: 0 = forward, 1 = forward writing the substep tape, 2 = adjoint
-// SC: rods with self-contact (FP32 only)
+// SC: rods with self-contact (their pair scratch in a.pblk / a.pblk_off,
+//     blocks laid out by sc_block with SC_RV_FWD values per pair record for
+//     kinds 0 and 1, SC_RV_ADJ for kind 2)
 // GT: the adjoint keeps a substep's projection iterates in the rod's block
 //     of global scratch (sc_tape/sc_off) rather than in LDS (implied by SC)
 template <typename T>
 hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<T>& a,
                        int n_blocks, hipStream_t st);
+// rods with self-contact (kernels of their own translation unit)
+template <typename T>
+hipError_t launch_rods_sc(int which, int C, int W, const RodArgs<T>& a, int n_blocks,
+                          hipStream_t st);
+template <typename T>
+size_t sc_lds_bytes(int C, int W);
 // rods with the twist degree of freedom (C = 2, no self-contact)
 template <typename T>
 hipError_t launch_rods_twist(int which, int C, int W, bool GT, const RodArgs<T>& a,

@@ -3,15 +3,70 @@
 // segments (clamped segment-segment method, Ericson 5.1.9, with a parallel
 // fallback), the per-pair position correction and velocity friction, and
 // their vector-Jacobian products.  Pairs are always evaluated with the
-// lower-indexed edge first, so both lanes that own a pair's edges compute
-// bitwise identical pair quantities.
+// lower-indexed edge first, so the candidate test gives the same answer
+// whichever of the two edges searches for the other.
+//
+// Also the layout of a rod's block of pair scratch in global memory, shared
+// by the host (which sizes it) and the kernels.
 #pragma once
 #include "rod_device.h"
 
 namespace rods {
 
-constexpr int SC_MAXP = 16;    // partner capacity per edge
-constexpr int SC_HT = 2048;    // hash buckets (power of two)
+// hash buckets of the broadphase grid: 64 groups of 27 (SC_NKEY) are used,
+// the table is padded to a multiple of every team size
+constexpr int SC_NKEY = 64 * 27;
+constexpr int SC_HT = 2048;
+
+// one candidate pair, lower edge first
+struct alignas(8) SPair {
+  int lo, hi;
+};
+
+// Largest number of admissible pairs (j - i > k_ex) among the n - 1 edges of
+// a rod of n vertices: the pair scratch has room for all of them, so no
+// candidate is ever dropped.  Edge e has at most cap_lo(e) = max(0, M - e)
+// partners above it and cap_hi(e) = max(0, e - k_ex) below it, M = n-2-k_ex.
+__host__ __device__ inline int64_t sc_pair_cap(int n, int k_ex) {
+  const int64_t M = (int64_t)n - 2 - k_ex;
+  return M > 0 ? M * (M + 1) / 2 : 0;
+}
+__host__ __device__ inline int64_t sc_off_lo(int64_t e, int64_t M) {
+  if (M <= 0) return 0;
+  return e <= M ? e * M - e * (e - 1) / 2 : M * (M + 1) / 2;
+}
+__host__ __device__ inline int64_t sc_off_hi(int64_t e, int64_t k_ex) {
+  return e <= k_ex + 1 ? 0 : (e - 1 - k_ex) * (e - k_ex) / 2;
+}
+
+// byte offsets inside a rod's pair block (each section 256-byte aligned):
+// the count of the current substep's pairs, the partners found by each edge
+// above (trilo) and below it (trihi) in triangular per-edge slots, the
+// compact pair list (sorted by lower edge), per edge the indices of the
+// pairs it is the upper edge of (hidx), a per-pair flag of the current
+// sweep, the first-pass depths d0, their adjoints d0b, and rv values of
+// per-pair results
+struct PairBlock {
+  int64_t trilo, trihi, pairs, hidx, flag, d0, d0b, rec, bytes;
+};
+__host__ __device__ inline int64_t sc_align(int64_t b) { return (b + 255) / 256 * 256; }
+__host__ __device__ inline PairBlock sc_block(int n, int k_ex, int tsize, int rv) {
+  const int64_t P = sc_pair_cap(n, k_ex);
+  PairBlock b;
+  int64_t o = 256;
+  b.trilo = o; o = sc_align(o + 4 * P);
+  b.trihi = o; o = sc_align(o + 4 * P);
+  b.pairs = o; o = sc_align(o + 8 * P);
+  b.hidx = o;  o = sc_align(o + 4 * P);
+  b.flag = o;  o = sc_align(o + 4 * P);
+  b.d0 = o;    o = sc_align(o + (int64_t)tsize * P);
+  b.d0b = o;   o = sc_align(o + (int64_t)tsize * P);
+  b.rec = o;   o = sc_align(o + (int64_t)tsize * rv * P);
+  b.bytes = o;
+  return b;
+}
+// per-pair result values: forward kernels 6, the adjoint 24
+constexpr int SC_RV_FWD = 6, SC_RV_ADJ = 24;
 
 template <typename T>
 struct Closest {
@@ -254,9 +309,25 @@ __device__ __forceinline__ T pair_friction_vjp(V3<T> P1, V3<T> Q1, V3<T> P2, V3<
   return d0_b;
 }
 
-__device__ __forceinline__ unsigned sc_hash(int ix, int iy, int iz) {
-  return ((unsigned)ix * 73856093u ^ (unsigned)iy * 19349663u ^ (unsigned)iz * 83492791u) &
-         (unsigned)(SC_HT - 1);
+// Bucket of grid cell (ix, iy, iz): cells are grouped in blocks of 3x3x3;
+// the cell's place in its block picks one of 27 residues and a
+// multiplicative hash of the block one of 64 groups.  Two cells of any
+// 3x3x3 neighbourhood differ by at most 2 along every axis, so their
+// residues (and keys) differ: a search over the 27 cells around a cell
+// visits every bucket at most once and finds every edge at most once.
+// Coordinates are clamped to +-2^20 cells beforehand.
+__device__ __forceinline__ int floor_div3(int i) { return i >= 0 ? i / 3 : -((2 - i) / 3); }
+__device__ __forceinline__ int sc_key(int ix, int iy, int iz) {
+  const int bx = floor_div3(ix), by = floor_div3(iy), bz = floor_div3(iz);
+  const int res = (ix - 3 * bx) + 3 * (iy - 3 * by) + 9 * (iz - 3 * bz);
+  const unsigned g = ((unsigned)bx * 73856093u ^ (unsigned)by * 19349663u ^
+                      (unsigned)bz * 83492791u) & 63u;
+  return (int)g * 27 + res;
+}
+template <typename T>
+__device__ __forceinline__ int sc_cell(T c) {
+  const T lim = T(1 << 20);
+  return (int)floor(fmin(fmax(c, -lim), lim));
 }
 
 }  // namespace rods

@@ -15,6 +15,7 @@
 
 #include "rods.h"
 #include "rod_launch.h"
+#include "rod_selfcontact.h"
 
 using rods::RodArgs;
 
@@ -35,7 +36,8 @@ struct Bin {
   bool bd;        // rods with moving rigid bodies
 };
 
-// self-contact kernels exist for these shapes (FP32)
+// self-contact kernels exist for these shapes (FP64: C = 2 only, which
+// shapes_for already requires)
 static bool sc_shape_ok(int C, int W) {
   return (C == 2 && (W == 1 || W == 2 || W == 4 || W == 8)) || (C == 4 && W == 4);
 }
@@ -113,6 +115,12 @@ struct Impl : HandleBase {
   T* sc_tape = nullptr;          // self-contact projection iterates (one substep per rod)
   int64_t* sc_off = nullptr;
   int64_t sc_cap = 0;
+  // self-contact pair scratch: one block per rod for the forward kernels and
+  // one for the adjoint (the pipelined backward runs both at once), each with
+  // room for every admissible pair of the rod
+  unsigned char *pblk_f = nullptr, *pblk_a = nullptr;
+  int64_t *pblk_off_f = nullptr, *pblk_off_a = nullptr;
+  std::vector<int64_t> pblk_off_h;
   size_t lds_max = 65536;
   T *lx = nullptr, *lv = nullptr, *lkb = nullptr, *ld1 = nullptr;
   double *acc_b = nullptr, *acc_s = nullptr, *loss_part = nullptr;
@@ -325,7 +333,6 @@ struct Impl : HandleBase {
       const bool tw = (fl_h[r] & ROD_FLAG_TWIST) != 0;
       bool bd = false;
       for (int k = po_h[r]; k < po_h[r + 1]; ++k) bd |= bw_h[k] > T(0);
-      if (sc && prec != 4) return ROD_EDTYPE;
       auto sh = shapes_for(voff_h[r + 1] - voff_h[r], prec, sc, tw || bd);
       if (sh.empty()) return ROD_EINVAL;
       auto key = std::make_tuple(sh.front().first, sh.front().second, sc, tw, bd);
@@ -358,6 +365,18 @@ struct Impl : HandleBase {
     sc_cap = 0;
     for (const Bin& bn : bins)
       sc_cap += (int64_t)bn.n * 2 * scratch_per_rod(bn.C, bn.W);
+    // pair scratch of the rods with self-contact (byte offsets per rod)
+    std::vector<int64_t> pof_h(R, 0), poa_h(R, 0);
+    int64_t pbytes_f = 0, pbytes_a = 0;
+    for (int r = 0; r < R; ++r) {
+      if (!(fl_h[r] & ROD_FLAG_SELF)) continue;
+      const int n = voff_h[r + 1] - voff_h[r];
+      pof_h[r] = pbytes_f;
+      poa_h[r] = pbytes_a;
+      pbytes_f += rods::sc_block(n, d.k_exclude, (int)sizeof(T), rods::SC_RV_FWD).bytes;
+      pbytes_a += rods::sc_block(n, d.k_exclude, (int)sizeof(T), rods::SC_RV_ADJ).bytes;
+    }
+    pblk_off_h = pof_h;
     n_ck = std::max(1, (d.max_steps + d.ckpt_every - 1) / d.ckpt_every);
     n_act_max = std::max(1, (d.max_steps + d.steps_per_action - 1) / d.steps_per_action);
 
@@ -370,8 +389,12 @@ struct Impl : HandleBase {
         (e = upload(Gt, G_h)) || (e = upload(jt, jt_h)) ||
         (e = upload(prim_a, pa_h)) || (e = upload(prim_b, pb_h)) || (e = upload(prim_r, pr_h)) ||
         (e = upload(bin_rods, bin_rods_h)) || (e = upload(tape_off, toff_h)) ||
-        (e = upload(sc_off, soff_h)) || (e = alloc(sc_tape, (size_t)sc_cap)))
+        (e = upload(sc_off, soff_h)) || (e = alloc(sc_tape, (size_t)sc_cap)) ||
+        (e = upload(pblk_off_f, pof_h)) || (e = upload(pblk_off_a, poa_h)) ||
+        (e = alloc(pblk_f, (size_t)pbytes_f)) || (e = alloc(pblk_a, (size_t)pbytes_a)))
       return e;
+    for (int r = 0; r < R; ++r)   // pair counts read 0 until a step has run
+      if (fl_h[r] & ROD_FLAG_SELF) HIPCHK(hipMemset(pblk_f + pof_h[r], 0, sizeof(int32_t)));
     if ((e = alloc(x, 3 * (size_t)V)) || (e = alloc(v, 3 * (size_t)V)) ||
         (e = alloc(kb, 2 * (size_t)V)) || (e = alloc(d1, 3 * (size_t)V)) ||
         (e = alloc(sx, 3 * (size_t)V)) || (e = alloc(sv, 3 * (size_t)V)) ||
@@ -483,6 +506,7 @@ struct Impl : HandleBase {
     a.lx = lx; a.lv = lv; a.lkb = lkb; a.ld1 = ld1;
     a.acc_b = acc_b; a.acc_s = acc_s;
     a.sc_tape = sc_tape; a.sc_off = sc_off;
+    a.pblk = pblk_f; a.pblk_off = pblk_off_f;
     a.status = status;
     a.Gt = Gt; a.jt = jt; a.th = th; a.om = om; a.lth = lth; a.lom = lom;
     if (has_bodies) {
@@ -517,6 +541,10 @@ struct Impl : HandleBase {
   }
 
   int launch_all_(int which, RodArgs<T> a, hipStream_t st) {
+    if (which == 2) {   // the adjoint's own pair scratch
+      a.pblk = pblk_a;
+      a.pblk_off = pblk_off_a;
+    }
     if (!plain) {
       for (const Bin& bn : bins) {
         a.rods = bin_rods + bn.off;
@@ -798,6 +826,36 @@ struct Impl : HandleBase {
     if (stiff) HIPCHK(rods::launch_exp<T>(opt_logb, b, R, st));
     *n_done = done;
     recorded = false;
+    return ROD_OK;
+  }
+
+  // the forward block's candidate pairs of rod r, sorted
+  int sc_pairs(int r, int32_t* out, int cap, int32_t* n_out, hipStream_t st) {
+    if (r < 0 || r >= R || (!out && cap > 0) || !n_out || cap < 0) return ROD_EINVAL;
+    std::vector<int32_t> fl(1);
+    HIPCHK(hipMemcpyAsync(fl.data(), flags + r, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!(fl[0] & ROD_FLAG_SELF)) return ROD_EINVAL;
+    const int n = voff_h[r + 1] - voff_h[r];
+    const rods::PairBlock pb = rods::sc_block(n, d.k_exclude, (int)sizeof(T), rods::SC_RV_FWD);
+    const unsigned char* base = pblk_f + pblk_off_h[r];
+    int32_t np = 0;
+    HIPCHK(hipMemcpyAsync(&np, base, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (np < 0 || np > rods::sc_pair_cap(n, d.k_exclude)) return ROD_ESTATE;
+    std::vector<rods::SPair> pr((size_t)np);
+    if (np > 0)
+      HIPCHK(hipMemcpyAsync(pr.data(), base + pb.pairs, sizeof(rods::SPair) * np,
+                            hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::sort(pr.begin(), pr.end(), [](const rods::SPair& a, const rods::SPair& b) {
+      return a.lo != b.lo ? a.lo < b.lo : a.hi < b.hi;
+    });
+    for (int k = 0; k < np && k < cap; ++k) {
+      out[2 * k] = pr[k].lo;
+      out[2 * k + 1] = pr[k].hi;
+    }
+    *n_out = np;
     return ROD_OK;
   }
 
@@ -1237,6 +1295,13 @@ int rods_status(RodsHandle* h, int32_t* flags, rods_stream_t stream) {
     if (hipMemcpy(flags, I->status, sizeof(int32_t) * I->R, hipMemcpyDeviceToHost) != hipSuccess)
       return (int)ROD_EHIP;
     return (int)ROD_OK;
+  });
+}
+
+int rods_sc_pairs(RodsHandle* h, int32_t rod, int32_t* pairs, int32_t cap, int32_t* n_pairs,
+                  rods_stream_t stream) {
+  return dispatch(h, [&](auto* I) {
+    return I->sc_pairs(rod, pairs, cap, n_pairs, (hipStream_t)stream);
   });
 }
 

@@ -50,7 +50,7 @@ EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "ro
            "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_launch_shape",
            "rods_set_plain",
            "rods_set_profiling", "rods_profile", "rods_selftest_exchange",
-           "rods_loss_mse_static"]
+           "rods_loss_mse_static", "rods_sc_pairs"]
 
 _lib = None
 
@@ -99,6 +99,8 @@ def load():
         "rods_profile": ([vp, POINTER(c_double), vp], c_int32),
         "rods_selftest_exchange": ([vp, vp], c_int32),
         "rods_loss_mse_static": ([vp, c_int32, c_int32, vp, vp, vp, vp, vp], c_int32),
+        "rods_sc_pairs": ([vp, c_int32, POINTER(c_int32), c_int32, POINTER(c_int32), vp],
+                          c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -346,6 +348,17 @@ class RodsHandle:
         flags = (c_int32 * self.R)()
         _check(self._lib.rods_status(self._h, flags, _stream()), "rods_status")
         return np.frombuffer(flags, dtype=np.int32).copy()
+
+    def sc_pairs(self, rod):
+        """Self-contact candidate pairs (i, j) of `rod` from the forward
+        kernels' last substep, sorted, as an int array [n, 2]."""
+        n = c_int32(0)
+        _check(self._lib.rods_sc_pairs(self._h, int(rod), None, 0, ctypes.byref(n), _stream()),
+               "rods_sc_pairs")
+        buf = (c_int32 * max(1, 2 * n.value))()
+        _check(self._lib.rods_sc_pairs(self._h, int(rod), buf, n.value, ctypes.byref(n),
+                                       _stream()), "rods_sc_pairs")
+        return np.frombuffer(buf, dtype=np.int32)[:2 * n.value].reshape(-1, 2).copy()
 
     def bins(self):
         out = (c_int32 * 48)()

@@ -141,12 +141,11 @@ def _last_step_parity(wl, n_before, tol=1e-4, ties=False):
     h.step(to_dev(u, dt))
     after, body_after = state(), body()
     status = h.status()
-    # a non-finite state anywhere, or any flag on a compared rod, fails; a
-    # full partner list (bit1: pairs dropped) is tolerated on a few other
-    # rods, the stretched-edge warning (bit2: search still exact) anywhere
-    assert not (status & 1).any(), np.unique(status, return_counts=True)
+    # a non-finite state or a failed pair-bookkeeping check (bit1) anywhere,
+    # or any flag on a compared rod, fails; the stretched-edge warning (bit2:
+    # the candidate search still covers it) is allowed on other rods
+    assert not (status & 3).any(), np.unique(status, return_counts=True)
     assert not status[list(wl.oracle_rods)].any(), status[list(wl.oracle_rods)]
-    assert ((status & 2) != 0).mean() <= 0.02, np.unique(status, return_counts=True)
     for r in wl.oracle_rods:
         st = gather_state(wl, [r], before, body_before)
         orods, osim = rods_from_workload(wl, [r]), sim_from_workload(wl)
