@@ -591,12 +591,28 @@ struct Rod {
   int rod, N, v0, tl, flags, p0, p1;
   // self-contact: LDS staging, counts, hash and list offsets; the rod's
   // block of global pair scratch; the adjoint's contact-pass inputs (global)
-  T *sc_pos, *sc_aux, *sc_adj, *sc_w, *sc_r, *sc_vc;
-  int *sc_cnt, *sc_fcnt, *sc_hcnt, *sc_hstart, *sc_items, *sc_lo, *sc_hi, *sc_tmp;
-  int *g_hdr, *g_trilo, *g_trihi, *g_hidx, *g_flag;
-  SPair* g_pairs;
-  T *g_d0, *g_d0b, *g_rec;
-  int sc_rv, sc_M, sc_P;
+  T *sc_pos, *sc_aux, *sc_adj, *sc_w, *sc_r;
+  float* sc_vc;   // the adjoint's recorded per-vertex counts
+  int *sc_cnt, *sc_fcnt, *sc_hcnt, *sc_hstart, *sc_items, *sc_lo, *sc_hi, *sc_slo, *sc_shi,
+      *sc_tmp;
+  int *g_hdr, *g_trilo, *g_hpos, *g_suphi, *g_cidx;
+  SPair *g_pairs, *g_sup;
+  // the substep's pair arrays: g_pairs, g_hpos, g_d0, g_d0b and g_con point
+  // either into the rod's global block (gb_*) or, when the substep's pairs
+  // fit, into the LDS left over past the fixed layout (the hash, dead after
+  // a build, and the rest of the workgroup's allocation)
+  int* gb_hpos;
+  SPair* gb_pairs;
+  T *gb_d0, *gb_d0b, *gb_con;
+  unsigned char* sc_cache;
+  int sc_cache_bytes;
+  // the superset of candidates (pairs within the margin plus a skin at the
+  // positions xb of its last build) and its size
+  V3<T> sc_xb[C];
+  bool sc_built;
+  int sc_S;
+  T *g_d0, *g_d0b, *g_con;
+  int sc_cw, sc_M, sc_P;
   T sc_cell0, sc_lmax;
   int sc_flags;
   T* ctape;
@@ -981,42 +997,56 @@ struct Rod {
   // LDS: staging (positions, velocities, adjoints), statics, per-vertex
   // counts of active pairs (this pass, first pass, adjoint's recorded
   // counts), the hash, per-edge list offsets, and the scan buffer.
-  static constexpr int SC_TMP = 4 * TL + 16;   // ints; also holds 2 TL reals
-  static constexpr size_t sc_bytes() {
-    return sizeof(T) * (size_t)(12 * NV) +
-           sizeof(int) * (size_t)(2 * NV + SC_HT + (SC_HT + 4) + NV + 2 * (NV + 4) + SC_TMP) + 64;
+  static constexpr int SC_TMP = 64;           // ints: scan and reduction slots
+  // fixed part of the layout (the hash follows it, then the pair cache
+  // reuses the hash's space and whatever more the launch allocates)
+  static constexpr size_t sc_fixed_bytes() {
+    return (sizeof(T) * (size_t)(11 * NV) + sizeof(float) * (size_t)NV +
+            sizeof(int) * (size_t)(2 * NV + 4 * (NV + 4) + SC_TMP) + 15) / 16 * 16;
   }
-  __device__ void sc_layout(unsigned char* base, const RodArgs<T>& a, int rv) {
+  static constexpr size_t sc_bytes() {
+    return sc_fixed_bytes() + sizeof(int) * (size_t)(SC_HT + (SC_HT + 4) + NV) + 64;
+  }
+  // cw: values of a pair's contribution to the two vertices of one of its
+  // edges (6 in the forward kernels, 12 in the adjoint)
+  __device__ void sc_layout(unsigned char* base, const RodArgs<T>& a, int cw, size_t xchg_off) {
     T* f = reinterpret_cast<T*>(base);
     sc_pos = f; f += 3 * NV;
     sc_aux = f; f += 3 * NV;
     sc_adj = f; f += 3 * NV;
     sc_w = f; f += NV;
     sc_r = f; f += NV;
-    sc_vc = f; f += NV;
-    int* q = reinterpret_cast<int*>(f);
+    sc_vc = reinterpret_cast<float*>(f);
+    int* q = reinterpret_cast<int*>(sc_vc + NV);
     sc_cnt = q; q += NV;
     sc_fcnt = q; q += NV;
-    sc_hcnt = q; q += SC_HT;
-    sc_hstart = q; q += SC_HT + 4;
-    sc_items = q; q += NV;
     sc_lo = q; q += NV + 4;
     sc_hi = q; q += NV + 4;
+    sc_slo = q; q += NV + 4;
+    sc_shi = q; q += NV + 4;
     sc_tmp = q;
-    sc_rv = rv;
+    sc_cache = base + sc_fixed_bytes();
+    q = reinterpret_cast<int*>(sc_cache);
+    sc_hcnt = q; q += SC_HT;
+    sc_hstart = q; q += SC_HT + 4;
+    sc_items = q;
+    sc_cache_bytes = a.sc_lds - (int)(sc_cache - base) - (int)xchg_off;
+    sc_cw = cw;
     sc_M = N - 2 - a.k_ex;
-    const PairBlock pb = sc_block(N, a.k_ex, (int)sizeof(T), rv);
+    const PairBlock pb = sc_block(N, a.k_ex, (int)sizeof(T), 2 * cw);
     unsigned char* g = a.pblk + a.pblk_off[rod];
     g_hdr = reinterpret_cast<int*>(g);
     g_trilo = reinterpret_cast<int*>(g + pb.trilo);
-    g_trihi = reinterpret_cast<int*>(g + pb.trihi);
-    g_pairs = reinterpret_cast<SPair*>(g + pb.pairs);
-    g_hidx = reinterpret_cast<int*>(g + pb.hidx);
-    g_flag = reinterpret_cast<int*>(g + pb.flag);
-    g_d0 = reinterpret_cast<T*>(g + pb.d0);
-    g_d0b = reinterpret_cast<T*>(g + pb.d0b);
-    g_rec = reinterpret_cast<T*>(g + pb.rec);
-    sc_P = 0;
+    g_sup = reinterpret_cast<SPair*>(g + pb.sup);
+    g_suphi = reinterpret_cast<int*>(g + pb.suphi);
+    g_cidx = reinterpret_cast<int*>(g + pb.cidx);
+    g_pairs = gb_pairs = reinterpret_cast<SPair*>(g + pb.pairs);
+    g_hpos = gb_hpos = reinterpret_cast<int*>(g + pb.hpos);
+    g_d0 = gb_d0 = reinterpret_cast<T*>(g + pb.d0);
+    g_d0b = gb_d0b = reinterpret_cast<T*>(g + pb.d0b);
+    g_con = gb_con = reinterpret_cast<T*>(g + pb.rec);
+    sc_P = sc_S = 0;
+    sc_built = false;
   }
   __device__ void sc_stage(T* dst, const V3<T> (&vals)[C]) const {
 #pragma unroll
@@ -1046,21 +1076,24 @@ struct Rod {
       m_r = rad[c] > m_r ? rad[c] : m_r;
       m_l = rest[c] > m_l ? rest[c] : m_l;
     }
+    // team maxima: wave maxima by lane shuffles, then the W wave values
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const T r2 = __shfl_xor(m_r, off, 64), l2 = __shfl_xor(m_l, off, 64);
+      m_r = r2 > m_r ? r2 : m_r;
+      m_l = l2 > m_l ? l2 : m_l;
+    }
     T* red = reinterpret_cast<T*>(sc_tmp);
-    red[2 * tl] = m_r;
-    red[2 * tl + 1] = m_l;
-    __syncthreads();
-    if (tl == 0) {
-      T rr = T(0), ll = T(0);
-      for (int k = 0; k < TL; ++k) {
-        rr = red[2 * k] > rr ? red[2 * k] : rr;
-        ll = red[2 * k + 1] > ll ? red[2 * k + 1] : ll;
-      }
-      red[0] = rr;
-      red[1] = ll;
+    if ((tl & 63) == 0) {
+      red[2 * (tl >> 6)] = m_r;
+      red[2 * (tl >> 6) + 1] = m_l;
     }
     __syncthreads();
-    T rmax = red[0], lmax = red[1];
+    T rmax = T(0), lmax = T(0);
+    for (int q = 0; q < W; ++q) {
+      rmax = red[2 * q] > rmax ? red[2 * q] : rmax;
+      lmax = red[2 * q + 1] > lmax ? red[2 * q + 1] : lmax;
+    }
     sc_lmax = T(2) * lmax;
     sc_cell0 = T(2) * rmax + a.self_margin;
     __syncthreads();
@@ -1116,13 +1149,49 @@ struct Rod {
     return fsqrt(dot(df, df)) < ra + rb + margin;
   }
 
-  // candidate pairs at the predicted positions p: a uniform-grid hash of
-  // the edge midpoints (counting sort into buckets, each bucket sorted by
-  // edge), then per own edge a search of the 27 cells around it that keeps
-  // the partners above and below it in its triangular slots, then the
-  // compact pair list and the upper-edge incidence
+  // Candidate pairs at the predicted positions p (App. A.1's pairs: segment
+  // distance below r_a + r_b + delta_c, j - i > K_ex), by a neighbour list
+  // with a skin: a superset of the pairs within delta_c + skin is built at
+  // positions xb and kept while no vertex has moved by half the skin from
+  // xb (a segment distance changes by at most the largest move of its two
+  // segments' endpoints, so no pair outside the superset can be a
+  // candidate); every substep tests each superset pair exactly.  The
+  // superset is sorted by (lower, upper) edge, so the candidate list is the
+  // same whenever the superset was built.
+  __device__ T sc_skin() const { return T(0.25) * sc_cell0; }
   __device__ void sc_broadphase(const RodArgs<T>& a, const V3<T> (&p)[C]) {
     sc_stage(sc_pos, p);
+    T d2 = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (vvalid(c)) {
+        const V3<T> d = p[c] - sc_xb[c];
+        d2 = fmax(d2, dot(d, d));
+      }
+    }
+    if (!sc_built) d2 = T(1e30);
+    // team maximum of the moves (bits of a non-negative float, rounded up)
+    int* mx = sc_tmp + 32;
+    if (tl == 0) *mx = 0;
+    __syncthreads();
+    atomicMax(mx, __float_as_int((float)d2));
+    __syncthreads();
+    const T dmax = fsqrt((T)__int_as_float(*mx + 1));
+    __syncthreads();
+    const T skin = sc_skin();
+    // slack of 1e-3 of the skin covers the rounding of the distance tests
+    if (!(T(2) * dmax + T(1e-3) * skin < skin)) sc_build(a, p, skin);
+    sc_filter(a);
+  }
+
+  // the superset at positions p: hash of edge midpoints (counting sort into
+  // buckets, each sorted by edge), a search of the 27 cells around each
+  // own edge for partners within delta_c + skin, their per-edge lists
+  // sorted, the compact superset and its per-edge upper incidence
+  __device__ void sc_build(const RodArgs<T>& a, const V3<T> (&p)[C], T skin) {
+    sc_built = true;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sc_xb[c] = p[c];
     for (int i = tl; i < SC_HT; i += TL) sc_hcnt[i] = 0;
     int* lsq = sc_tmp;   // longest squared edge (bits of a non-negative real)
     if (tl == 0) *lsq = 0;
@@ -1142,16 +1211,17 @@ struct Rod {
     l2 = (T)__int_as_float(*lsq + 1);
     __syncthreads();   // sc_tmp is reused below
     if (l2 > sc_lmax * sc_lmax) sc_flags |= 4;
+    const T cell0 = sc_cell0 + skin;
     // one part in 10^4 of slack keeps the 27-cell argument safe from rounding
-    const T ig = frcp((sc_cell0 + fsqrt(l2)) * T(1.0001));
+    const T ig = frcp((cell0 + fsqrt(l2)) * T(1.0001));
     int key[C], slot[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       key[c] = 0;
       slot[c] = 0;
       if (evalid(c)) {
-        int e = gi(c);
-        V3<T> m = T(0.5) * (sc_at(sc_pos, e) + sc_at(sc_pos, e + 1));
+        const int e = gi(c);
+        const V3<T> m = T(0.5) * (sc_at(sc_pos, e) + sc_at(sc_pos, e + 1));
         key[c] = sc_key(sc_cell(m.x * ig), sc_cell(m.y * ig), sc_cell(m.z * ig));
         slot[c] = atomicAdd(&sc_hcnt[key[c]], 1);
       }
@@ -1192,7 +1262,7 @@ struct Rod {
       }
       __syncthreads();
     }
-    const T margin = a.self_margin;
+    const T margin = a.self_margin + skin;
     // a partner's midpoint is within h_e + h_max + 2 r_max + margin of the
     // edge's own (segment distance >= midpoint distance minus both
     // half-lengths); the slack keeps every pair the exact test accepts
@@ -1205,13 +1275,11 @@ struct Rod {
       if (!evalid(c)) continue;
       const int e = gi(c);
       int* lo_out = g_trilo + sc_off_lo(e, M);
-      int* hi_out = g_trihi + sc_off_hi(e, a.k_ex);
       const int cap_lo = M - e > 0 ? (int)(M - e) : 0;
-      const int cap_hi = e - a.k_ex > 0 ? e - a.k_ex : 0;
       V3<T> P = sc_at(sc_pos, e), Q = sc_at(sc_pos, e + 1);
       V3<T> m = T(0.5) * (P + Q);
       V3<T> PQ = Q - P;
-      const T reach = (T(0.5) * fsqrt(dot(PQ, PQ)) + h_max + sc_cell0) * T(1.0001) + T(1e-6);
+      const T reach = (T(0.5) * fsqrt(dot(PQ, PQ)) + h_max + cell0) * T(1.0001) + T(1e-6);
       const T reach2 = reach * reach;
       const int cx = sc_cell(m.x * ig), cy = sc_cell(m.y * ig), cz = sc_cell(m.z * ig);
       for (int dz = -1; dz <= 1; ++dz)
@@ -1228,16 +1296,136 @@ struct Rod {
               if (j > e) {
                 if (nlo[c] < cap_lo) lo_out[nlo[c]++] = j; else sc_flags |= 2;
               } else {
-                if (nhi[c] < cap_hi) hi_out[nhi[c]++] = j; else sc_flags |= 2;
+                ++nhi[c];
               }
             }
           }
+      // partners in increasing order
+      for (int i = 1; i < nlo[c]; ++i) {
+        const int v = lo_out[i];
+        int j = i - 1;
+        while (j >= 0 && lo_out[j] > v) {
+          lo_out[j + 1] = lo_out[j];
+          --j;
+        }
+        lo_out[j + 1] = v;
+      }
     }
-    // list offsets: exclusive prefix sums in vertex-slot order (invalid
-    // edges count 0), the totals at slot NV
     int slo = 0, shi = 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+      slo += nlo[c];
+      shi += nhi[c];
+      sc_cnt[gi(c)] = 0;   // fill counters of the upper-edge lists
+    }
+    int elo, ehi, tlo, thi;
+    sc_scan2(slo, shi, elo, ehi, tlo, thi);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      sc_slo[gi(c)] = elo;
+      sc_shi[gi(c)] = ehi;
+      elo += nlo[c];
+      ehi += nhi[c];
+    }
+    if (tl == 0) {
+      sc_slo[NV] = tlo;
+      sc_shi[NV] = thi;
+    }
+    if (tlo != thi) sc_flags |= 2;   // the two directions of the search must agree
+    sc_S = tlo;
+    __syncthreads();
+    // compact superset; each pair also takes a place in its upper edge's list
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (!evalid(c)) continue;
+      const int e = gi(c);
+      const int* lo_in = g_trilo + sc_off_lo(e, M);
+      const int b0 = sc_slo[e];
+      for (int q = 0; q < nlo[c]; ++q) {
+        const int j = lo_in[q];
+        g_sup[b0 + q] = SPair{e, j};
+        const int at = atomicAdd(&sc_cnt[j], 1);
+        if (at < sc_shi[j + 1] - sc_shi[j]) g_suphi[sc_shi[j] + at] = b0 + q;
+        else sc_flags |= 2;
+      }
+    }
+    __syncthreads();
+    // the fill order of the upper-edge lists is that of the atomics: sort
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (!evalid(c)) continue;
+      const int e = gi(c);
+      if (sc_cnt[e] != nhi[c]) sc_flags |= 2;
+      int* L = g_suphi + sc_shi[e];
+      for (int i = 1; i < nhi[c]; ++i) {
+        const int v = L[i];
+        int j = i - 1;
+        while (j >= 0 && L[j] > v) {
+          L[j + 1] = L[j];
+          --j;
+        }
+        L[j + 1] = v;
+      }
+    }
+    __syncthreads();
+  }
+
+  // this substep's candidates: every superset pair tested exactly at the
+  // staged positions, each lane a contiguous run of the superset, so the
+  // compact list keeps the superset's order; then per edge the offsets of
+  // its lower-edge run and its upper-edge list (indices, in order)
+  __device__ void sc_filter(const RodArgs<T>& a) {
+    const int run = (sc_S + TL - 1) / TL;
+    const int s0 = tl * run < sc_S ? tl * run : sc_S;
+    const int s1 = s0 + run < sc_S ? s0 + run : sc_S;
+    int n = 0;
+    for (int s = s0; s < s1; ++s) {
+      const SPair pr = g_sup[s];
+      const bool ok = sc_near(pr.lo, pr.hi, a.self_margin);
+      g_cidx[s] = ok ? 1 : -1;
+      n += ok ? 1 : 0;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      sc_lo[gi(c)] = 0;   // per-edge counts, then offsets
+      sc_hi[gi(c)] = 0;
+    }
+    int base, dummy, tot, tot1;
+    sc_scan2(n, 0, base, dummy, tot, tot1);
+    // the substep's pair arrays go to LDS when they fit
+    const int per = (int)(sizeof(SPair) + sizeof(int) + (2 + 2 * sc_cw) * sizeof(T));
+    if (tot <= (sc_cache_bytes - (int)sizeof(T)) / per) {
+      unsigned char* c = sc_cache;
+      g_pairs = reinterpret_cast<SPair*>(c); c += sizeof(SPair) * tot;
+      g_hpos = reinterpret_cast<int*>(c); c += sizeof(int) * tot;
+      c = sc_cache + (c - sc_cache + sizeof(T) - 1) / sizeof(T) * sizeof(T);
+      g_d0 = reinterpret_cast<T*>(c); c += sizeof(T) * tot;
+      g_d0b = reinterpret_cast<T*>(c); c += sizeof(T) * tot;
+      g_con = reinterpret_cast<T*>(c);
+    } else {
+      g_pairs = gb_pairs;
+      g_hpos = gb_hpos;
+      g_d0 = gb_d0;
+      g_d0b = gb_d0b;
+      g_con = gb_con;
+    }
+    for (int s = s0; s < s1; ++s) {
+      if (g_cidx[s] < 0) continue;
+      const SPair pr = g_sup[s];
+      g_pairs[base] = pr;
+      gb_pairs[base] = pr;   // kept in global memory for rods_sc_pairs
+      g_cidx[s] = base++;
+      atomicAdd(&sc_lo[pr.lo], 1);
+      atomicAdd(&sc_hi[pr.hi], 1);
+    }
+    sc_P = tot;
+    if (tl == 0) g_hdr[0] = tot;
+    __syncthreads();
+    int nlo[C], nhi[C], slo = 0, shi = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      nlo[c] = sc_lo[gi(c)];
+      nhi[c] = sc_hi[gi(c)];
       slo += nlo[c];
       shi += nhi[c];
     }
@@ -1253,35 +1441,20 @@ struct Rod {
     if (tl == 0) {
       sc_lo[NV] = tlo;
       sc_hi[NV] = thi;
-      g_hdr[0] = tlo;
     }
-    if (tlo != thi) sc_flags |= 2;   // the two searches must agree
-    sc_P = tlo;
-    __syncthreads();
-    // compact list, and per upper edge the list index of each of its pairs
-    // (its position in the lower edge's partner slots)
+    // upper-edge lists: the superset's, filtered (the order carries over);
+    // each pair learns its place in its upper edge's list
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       if (!evalid(c)) continue;
       const int e = gi(c);
-      const int* lo_in = g_trilo + sc_off_lo(e, M);
-      const int b0 = sc_lo[e];
-      for (int q = 0; q < nlo[c]; ++q) g_pairs[b0 + q] = SPair{e, lo_in[q]};
-      const int* hi_in = g_trihi + sc_off_hi(e, a.k_ex);
-      const int b1 = sc_hi[e];
-      for (int q = 0; q < nhi[c]; ++q) {
-        const int j = hi_in[q];
-        const int* lj = g_trilo + sc_off_lo(j, M);
-        const int n_j = sc_lo[j + 1] - sc_lo[j];
-        int at = -1;
-        for (int t = 0; t < n_j; ++t)
-          if (lj[t] == e) {
-            at = t;
-            break;
-          }
-        if (at < 0) sc_flags |= 2;
-        g_hidx[b1 + q] = at < 0 ? -1 : sc_lo[j] + at;
+      int o = sc_hi[e];
+      const int q1 = sc_shi[e + 1];
+      for (int q = sc_shi[e]; q < q1; ++q) {
+        const int k = g_cidx[g_suphi[q]];
+        if (k >= 0) g_hpos[k] = o++;
       }
+      if (o != sc_hi[e] + nhi[c]) sc_flags |= 2;
     }
     __syncthreads();
   }
@@ -1300,25 +1473,38 @@ struct Rod {
     const T m = (T)(a0 > a1 ? a0 : a1);
     return m > T(1) ? m : T(1);
   }
-  // gather the records of the pairs touching own edge e: f(k, pair, is_lo)
-  // for every flagged pair, lower-edge pairs first
-  template <typename F>
-  __device__ __forceinline__ void sc_gather(int e, F&& f) const {
-    const int k1 = sc_lo[e + 1];
-    for (int k = sc_lo[e]; k < k1; ++k)
-      if (g_flag[k]) f(k, g_pairs[k], true);
-    const int q1 = sc_hi[e + 1];
-    for (int q = sc_hi[e]; q < q1; ++q) {
-      const int k = g_hidx[q];
-      if (k >= 0 && g_flag[k]) f(k, g_pairs[k], false);
-    }
+  // Contributions of the pairs to their edges' vertices: pair k's to the
+  // two vertices of its lower edge at g_con[k * cw], to those of its upper
+  // edge at g_con[(P + hpos[k]) * cw], so the pairs touching an edge form
+  // two contiguous runs (lower-edge pairs in list order, upper-edge pairs
+  // in the order of their lower edges) that its lane sums in that fixed
+  // order.  Inactive pairs contribute zeros.
+  __device__ __forceinline__ T* sc_con_lo(int k) const { return g_con + (int64_t)k * sc_cw; }
+  __device__ __forceinline__ T* sc_con_hi(int k) const {
+    return g_con + (int64_t)(sc_P + g_hpos[k]) * sc_cw;
+  }
+  // sum of the first n values of the contributions touching own edge e
+  template <int NVAL>
+  __device__ __forceinline__ void sc_gather(int e, T (&out)[NVAL]) const {
+#pragma unroll
+    for (int i = 0; i < NVAL; ++i) out[i] = T(0);
+    const T* lo = g_con + (int64_t)sc_lo[e] * sc_cw;
+    const int nl = sc_lo[e + 1] - sc_lo[e];
+    for (int k = 0; k < nl; ++k)
+#pragma unroll
+      for (int i = 0; i < NVAL; ++i) out[i] += lo[k * sc_cw + i];
+    const T* hi = g_con + (int64_t)(sc_P + sc_hi[e]) * sc_cw;
+    const int nh = sc_hi[e + 1] - sc_hi[e];
+    for (int k = 0; k < nh; ++k)
+#pragma unroll
+      for (int i = 0; i < NVAL; ++i) out[i] += hi[k * sc_cw + i];
   }
 
   // one Jacobi pass of the self-contact projection: a sweep over the pairs
   // evaluates each once (activity, depth, direction) and counts the active
-  // pairs per vertex; the gather applies every active pair's correction
-  // divided by its divisor.  The first pass keeps the depths d0 and the
-  // counts for friction.
+  // pairs per vertex; a second sweep turns each into its four vertex
+  // corrections divided by its divisor; each lane sums those of its own
+  // edges.  The first pass keeps the depths d0 and the counts for friction.
   template <bool REC>
   __device__ void sc_pass(Team<T, W>& X, const V3<T> (&p0)[C], V3<T> (&dl)[C], int it,
                           bool first) {
@@ -1330,19 +1516,20 @@ struct Rod {
     }
     sc_stage(sc_pos, p);
     __syncthreads();
+    // sweep 1: k n (n the unit direction, k = d / W) and s, u in the
+    // pair's lower-edge slot
     for (int k = tl; k < sc_P; k += TL) {
       const SPair pr = g_pairs[k];
       PairGeo<T> g = sc_pair(sc_pos, pr.lo, pr.hi);
       if (first) g_d0[k] = g.act ? g.d : T(0);
-      g_flag[k] = g.act ? 1 : 0;
+      const T kk = g.act ? fdiv(g.d, g.W) : T(0);
+      T* r = sc_con_lo(k);
+      r[0] = kk * g.n.x;
+      r[1] = kk * g.n.y;
+      r[2] = kk * g.n.z;
+      r[3] = g.cp.s;
+      r[4] = g.cp.u;
       if (g.act) {
-        const T kk = fdiv(g.d, g.W);
-        T* r = g_rec + (int64_t)k * sc_rv;
-        r[0] = kk * g.n.x;
-        r[1] = kk * g.n.y;
-        r[2] = kk * g.n.z;
-        r[3] = g.cp.s;
-        r[4] = g.cp.u;
         atomicAdd(&sc_cnt[pr.lo], 1);
         atomicAdd(&sc_cnt[pr.lo + 1], 1);
         atomicAdd(&sc_cnt[pr.hi], 1);
@@ -1350,6 +1537,19 @@ struct Rod {
       }
     }
     __syncthreads();
+    // sweep 2: the four corrections, divided by the pair's divisor
+    for (int k = tl; k < sc_P; k += TL) {
+      const SPair pr = g_pairs[k];
+      T* r = sc_con_lo(k);
+      const V3<T> kn = mk(r[0], r[1], r[2]);
+      const T s = r[3], u = r[4];
+      const T im = frcp(sc_divisor(sc_cnt, pr.lo, pr.hi));
+      put3(r, 0, (sc_w[pr.lo] * (T(1) - s) * im) * kn);
+      put3(r, 3, (sc_w[pr.lo + 1] * s * im) * kn);
+      T* q = sc_con_hi(k);
+      put3(q, 0, (-(sc_w[pr.hi] * (T(1) - u) * im)) * kn);
+      put3(q, 3, (-(sc_w[pr.hi + 1] * u * im)) * kn);
+    }
     if (first) {
 #pragma unroll
       for (int c = 0; c < C; ++c) sc_fcnt[gi(c)] = sc_cnt[gi(c)];
@@ -1361,27 +1561,16 @@ struct Rod {
         reinterpret_cast<Q4<T>*>(ctape)[(it * C + c) * TL + tl] = q;
       }
     }
+    __syncthreads();
     V3<T> dA[C], dB[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      dA[c] = zero3<T>();
-      dB[c] = zero3<T>();
+      dA[c] = dB[c] = zero3<T>();
       if (!evalid(c)) continue;
-      const int e = gi(c);
-      sc_gather(e, [&](int k, SPair pr, bool is_lo) {
-        const T* r = g_rec + (int64_t)k * sc_rv;
-        const V3<T> kn = mk(r[0], r[1], r[2]);
-        const T im = frcp(sc_divisor(sc_cnt, pr.lo, pr.hi));
-        if (is_lo) {
-          const T s = r[3];
-          dA[c] += (sc_w[e] * (T(1) - s) * im) * kn;
-          dB[c] += (sc_w[e + 1] * s * im) * kn;
-        } else {
-          const T u = r[4];
-          dA[c] -= (sc_w[e] * (T(1) - u) * im) * kn;
-          dB[c] -= (sc_w[e + 1] * u * im) * kn;
-        }
-      });
+      T o[6];
+      sc_gather(gi(c), o);
+      dA[c] = mk(o[0], o[1], o[2]);
+      dB[c] = mk(o[3], o[4], o[5]);
     }
     __syncthreads();
     T s3[3] = {dB[C - 1].x, dB[C - 1].y, dB[C - 1].z};
@@ -1399,10 +1588,10 @@ struct Rod {
     __syncthreads();
     for (int k = tl; k < sc_P; k += TL) {
       const T d0 = g_d0[k];
-      int fl = 0;
+      const SPair pr = g_pairs[k];
+      const int lo = pr.lo, hi = pr.hi;
+      V3<T> cA = zero3<T>(), cB = zero3<T>(), cC = zero3<T>(), cD = zero3<T>();
       if (d0 > T(0)) {
-        const SPair pr = g_pairs[k];
-        const int lo = pr.lo, hi = pr.hi;
         FricGeo<T> f = pair_friction(sc_at(sc_pos, lo), sc_at(sc_pos, lo + 1), sc_at(sc_pos, hi),
                                      sc_at(sc_pos, hi + 1), sc_at(sc_aux, lo),
                                      sc_at(sc_aux, lo + 1), sc_at(sc_aux, hi),
@@ -1410,40 +1599,31 @@ struct Rod {
                                      sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
                                      sc_r[hi + 1], d0, mu, a.h);
         if (f.ok) {
-          fl = 1;
-          T* r = g_rec + (int64_t)k * sc_rv;
-          r[0] = f.dvt.x;
-          r[1] = f.dvt.y;
-          r[2] = f.dvt.z;
-          r[3] = f.g.cp.s;
-          r[4] = f.g.cp.u;
-          r[5] = f.g.W;
+          const T iW = frcp(f.g.W * sc_divisor(sc_fcnt, lo, hi));
+          const T s = f.g.cp.s, u = f.g.cp.u;
+          cA = (sc_w[lo] * (T(1) - s) * iW) * f.dvt;
+          cB = (sc_w[lo + 1] * s * iW) * f.dvt;
+          cC = (-(sc_w[hi] * (T(1) - u) * iW)) * f.dvt;
+          cD = (-(sc_w[hi + 1] * u * iW)) * f.dvt;
         }
       }
-      g_flag[k] = fl;
+      T* r = sc_con_lo(k);
+      put3(r, 0, cA);
+      put3(r, 3, cB);
+      T* q = sc_con_hi(k);
+      put3(q, 0, cC);
+      put3(q, 3, cD);
     }
     __syncthreads();
     V3<T> dA[C], dB[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      dA[c] = zero3<T>();
-      dB[c] = zero3<T>();
+      dA[c] = dB[c] = zero3<T>();
       if (!evalid(c)) continue;
-      const int e = gi(c);
-      sc_gather(e, [&](int k, SPair pr, bool is_lo) {
-        const T* r = g_rec + (int64_t)k * sc_rv;
-        const V3<T> dvt = mk(r[0], r[1], r[2]);
-        const T iW = frcp(r[5] * sc_divisor(sc_fcnt, pr.lo, pr.hi));
-        if (is_lo) {
-          const T s = r[3];
-          dA[c] += (sc_w[e] * (T(1) - s) * iW) * dvt;
-          dB[c] += (sc_w[e + 1] * s * iW) * dvt;
-        } else {
-          const T u = r[4];
-          dA[c] -= (sc_w[e] * (T(1) - u) * iW) * dvt;
-          dB[c] -= (sc_w[e + 1] * u * iW) * dvt;
-        }
-      });
+      T o[6];
+      sc_gather(gi(c), o);
+      dA[c] = mk(o[0], o[1], o[2]);
+      dB[c] = mk(o[3], o[4], o[5]);
     }
     __syncthreads();
     T s3[3] = {dB[C - 1].x, dB[C - 1].y, dB[C - 1].z};
@@ -1463,11 +1643,12 @@ struct Rod {
     __syncthreads();
     for (int k = tl; k < sc_P; k += TL) {
       const T d0 = g_d0[k];
-      int fl = 0;
+      const SPair pr = g_pairs[k];
+      const int lo = pr.lo, hi = pr.hi;
       T d0b = T(0);
+      V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
+      V3<T> q0 = zero3<T>(), q1 = zero3<T>(), q2 = zero3<T>(), q3 = zero3<T>();
       if (d0 > T(0)) {
-        const SPair pr = g_pairs[k];
-        const int lo = pr.lo, hi = pr.hi;
         V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
         V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
         V3<T> vi = sc_at(sc_aux, lo), vi1 = sc_at(sc_aux, lo + 1);
@@ -1476,21 +1657,18 @@ struct Rod {
                                      sc_w[hi], sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
                                      sc_r[hi + 1], d0, mu, a.h);
         if (f.ok) {
-          fl = 1;
-          V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
-          V3<T> q0 = zero3<T>(), q1 = zero3<T>(), q2 = zero3<T>(), q3 = zero3<T>();
           const T im = frcp(sc_divisor(sc_fcnt, lo, hi));
           d0b = pair_friction_vjp(P1, Q1, P2, Q2, vi, vi1, vj, vj1, f, sc_w[lo], sc_w[lo + 1],
                                   sc_w[hi], sc_w[hi + 1], mu, a.h, im * sc_at(sc_adj, lo),
                                   im * sc_at(sc_adj, lo + 1), im * sc_at(sc_adj, hi),
                                   im * sc_at(sc_adj, hi + 1), b0, b1, b2, b3, q0, q1, q2, q3);
-          T* o = g_rec + (int64_t)k * sc_rv;
-          put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, b2); put3(o, 9, b3);
-          put3(o, 12, q0); put3(o, 15, q1); put3(o, 18, q2); put3(o, 21, q3);
         }
       }
-      g_flag[k] = fl;
       g_d0b[k] = d0b;
+      T* o = sc_con_lo(k);
+      put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, q0); put3(o, 9, q1);
+      T* h = sc_con_hi(k);
+      put3(h, 0, b2); put3(h, 3, b3); put3(h, 6, q2); put3(h, 9, q3);
     }
     __syncthreads();
     V3<T> vA[C], vB[C], xA[C], xB[C];
@@ -1498,14 +1676,12 @@ struct Rod {
     for (int c = 0; c < C; ++c) {
       vA[c] = vB[c] = xA[c] = xB[c] = zero3<T>();
       if (!evalid(c)) continue;
-      sc_gather(gi(c), [&](int k, SPair, bool is_lo) {
-        const T* o = g_rec + (int64_t)k * sc_rv;
-        const int s = is_lo ? 0 : 6;
-        vA[c] += get3(o, s);
-        vB[c] += get3(o, s + 3);
-        xA[c] += get3(o, s + 12);
-        xB[c] += get3(o, s + 15);
-      });
+      T o[12];
+      sc_gather(gi(c), o);
+      vA[c] = mk(o[0], o[1], o[2]);
+      vB[c] = mk(o[3], o[4], o[5]);
+      xA[c] = mk(o[6], o[7], o[8]);
+      xB[c] = mk(o[9], o[10], o[11]);
     }
     __syncthreads();
     T s6[6] = {vB[C - 1].x, vB[C - 1].y, vB[C - 1].z, xB[C - 1].x, xB[C - 1].y, xB[C - 1].z};
@@ -1526,7 +1702,7 @@ struct Rod {
     for (int c = 0; c < C; ++c) {
       Q4<T> q = reinterpret_cast<const Q4<T>*>(ctape)[(it * C + c) * TL + tl];
       pin[c] = mk(q.x, q.y, q.z);
-      sc_vc[gi(c)] = q.w;
+      sc_vc[gi(c)] = (float)q.w;
     }
     sc_stage(sc_pos, pin);
     sc_stage(sc_adj, pb);
@@ -1535,24 +1711,26 @@ struct Rod {
       const SPair pr = g_pairs[k];
       const int lo = pr.lo, hi = pr.hi;
       PairGeo<T> g = sc_pair(sc_pos, lo, hi);
-      g_flag[k] = g.act ? 1 : 0;
-      if (!g.act) continue;
-      V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
-      V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
       V3<T> b0 = zero3<T>(), b1 = zero3<T>(), b2 = zero3<T>(), b3 = zero3<T>();
-      const T im = frcp(sc_divisor(sc_vc, lo, hi));
-      pair_proj_vjp(P1, Q1, P2, Q2, g, sc_w[lo], sc_w[lo + 1], sc_w[hi], sc_w[hi + 1], sc_r[lo],
-                    sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], im * sc_at(sc_adj, lo),
-                    im * sc_at(sc_adj, lo + 1), im * sc_at(sc_adj, hi),
-                    im * sc_at(sc_adj, hi + 1), b0, b1, b2, b3);
-      if (with_depth) {
-        const T d0b = g_d0b[k];
-        if (d0b != T(0))
-          pair_depth_vjp(P1, Q1, P2, Q2, g, sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], d0b,
-                         b0, b1, b2, b3);
+      if (g.act) {
+        V3<T> P1 = sc_at(sc_pos, lo), Q1 = sc_at(sc_pos, lo + 1);
+        V3<T> P2 = sc_at(sc_pos, hi), Q2 = sc_at(sc_pos, hi + 1);
+        const T im = frcp(sc_divisor(sc_vc, lo, hi));
+        pair_proj_vjp(P1, Q1, P2, Q2, g, sc_w[lo], sc_w[lo + 1], sc_w[hi], sc_w[hi + 1],
+                      sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1], im * sc_at(sc_adj, lo),
+                      im * sc_at(sc_adj, lo + 1), im * sc_at(sc_adj, hi),
+                      im * sc_at(sc_adj, hi + 1), b0, b1, b2, b3);
+        if (with_depth) {
+          const T d0b = g_d0b[k];
+          if (d0b != T(0))
+            pair_depth_vjp(P1, Q1, P2, Q2, g, sc_r[lo], sc_r[lo + 1], sc_r[hi], sc_r[hi + 1],
+                           d0b, b0, b1, b2, b3);
+        }
       }
-      T* o = g_rec + (int64_t)k * sc_rv;
-      put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, b2); put3(o, 9, b3);
+      T* o = sc_con_lo(k);
+      put3(o, 0, b0); put3(o, 3, b1);
+      T* h = sc_con_hi(k);
+      put3(h, 0, b2); put3(h, 3, b3);
     }
     __syncthreads();
     V3<T> cA[C], cB[C];
@@ -1560,12 +1738,10 @@ struct Rod {
     for (int c = 0; c < C; ++c) {
       cA[c] = cB[c] = zero3<T>();
       if (!evalid(c)) continue;
-      sc_gather(gi(c), [&](int k, SPair, bool is_lo) {
-        const T* o = g_rec + (int64_t)k * sc_rv;
-        const int s = is_lo ? 0 : 6;
-        cA[c] += get3(o, s);
-        cB[c] += get3(o, s + 3);
-      });
+      T o[6];
+      sc_gather(gi(c), o);
+      cA[c] = mk(o[0], o[1], o[2]);
+      cB[c] = mk(o[3], o[4], o[5]);
     }
     __syncthreads();
     T s3[3] = {cB[C - 1].x, cB[C - 1].y, cB[C - 1].z};
@@ -1573,6 +1749,7 @@ struct Rod {
 #pragma unroll
     for (int c = 0; c < C; ++c) pb[c] += cA[c] + (c ? cB[c - 1] : mk(s3[0], s3[1], s3[2]));
   }
+
   // gather the previous lane's last edge: tangent, inverse length, d1
   __device__ void prev_edge(Team<T, W>& X, const V3<T> (&t)[C], const T (&il)[C],
                             const V3<T> (&dd)[C], V3<T>& tp, T& ilp, V3<T>& dp) const {
@@ -2342,7 +2519,7 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
   Rod<T, C, W, SC, TW, BD> R;
   R.load_static(a, X);
   if constexpr (SC) {
-    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_RV_FWD);
+    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_CW_FWD, xchg_bytes<T, W>());
     R.ctape = nullptr;
     R.sc_setup(a);
   }
@@ -2406,7 +2583,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
     // LDS holds the self-contact buffers; the contact-pass inputs follow the
     // projection iterates in the rod's scratch block (written and read
     // within a substep)
-    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_RV_ADJ);
+    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_CW_ADJ, xchg_bytes<T, W>());
     R.ctape = lds_tape + (size_t)a.n_iters * C * PROJ_TAPE * 64 * W;
     R.sc_setup(a);
   }
@@ -2579,6 +2756,12 @@ static hipError_t launch_shape(int which, bool gt, const RodArgs<T>& a, int n_bl
                                hipStream_t st) {
   size_t lds = lds_bytes<T, C, W, SC>(which, gt, a.n_iters);
   RodArgs<T> b = a;
+  if constexpr (SC) {
+    // the pair cache takes whatever more the host offers (one workgroup
+    // per CU either way)
+    if ((size_t)a.sc_lds > lds) lds = (size_t)a.sc_lds;
+    b.sc_lds = (int32_t)lds;
+  }
   if constexpr (BD) {
     // moving bodies: state and adjoint blocks after everything else
     b.body_lds = (int32_t)((lds + 15) / 16 * 16);

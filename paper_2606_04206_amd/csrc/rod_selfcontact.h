@@ -40,14 +40,17 @@ __host__ __device__ inline int64_t sc_off_hi(int64_t e, int64_t k_ex) {
 }
 
 // byte offsets inside a rod's pair block (each section 256-byte aligned):
-// the count of the current substep's pairs, the partners found by each edge
-// above (trilo) and below it (trihi) in triangular per-edge slots, the
-// compact pair list (sorted by lower edge), per edge the indices of the
-// pairs it is the upper edge of (hidx), a per-pair flag of the current
-// sweep, the first-pass depths d0, their adjoints d0b, and rv values of
-// per-pair results
+// the count of the current substep's pairs; for the superset of a neighbour
+// list, the partners found by each edge above it (trilo, triangular per-edge
+// slots), the compact superset (sup, sorted by lower and then upper edge),
+// per edge the sorted superset indices of the pairs it is the upper edge of
+// (suphi), and each superset pair's place in the substep's list or -1
+// (cidx); the substep's compact pair list (sorted likewise), each pair's
+// place in its upper edge's list (hpos), the first-pass depths d0, their
+// adjoints d0b, and rv values of per-pair results (a pair's contributions
+// to the vertices of its two edges)
 struct PairBlock {
-  int64_t trilo, trihi, pairs, hidx, flag, d0, d0b, rec, bytes;
+  int64_t trilo, sup, suphi, cidx, pairs, hpos, d0, d0b, rec, bytes;
 };
 __host__ __device__ inline int64_t sc_align(int64_t b) { return (b + 255) / 256 * 256; }
 __host__ __device__ inline PairBlock sc_block(int n, int k_ex, int tsize, int rv) {
@@ -55,18 +58,21 @@ __host__ __device__ inline PairBlock sc_block(int n, int k_ex, int tsize, int rv
   PairBlock b;
   int64_t o = 256;
   b.trilo = o; o = sc_align(o + 4 * P);
-  b.trihi = o; o = sc_align(o + 4 * P);
+  b.sup = o;   o = sc_align(o + 8 * P);
+  b.suphi = o; o = sc_align(o + 4 * P);
+  b.cidx = o;  o = sc_align(o + 4 * P);
   b.pairs = o; o = sc_align(o + 8 * P);
-  b.hidx = o;  o = sc_align(o + 4 * P);
-  b.flag = o;  o = sc_align(o + 4 * P);
+  b.hpos = o;  o = sc_align(o + 4 * P);
   b.d0 = o;    o = sc_align(o + (int64_t)tsize * P);
   b.d0b = o;   o = sc_align(o + (int64_t)tsize * P);
   b.rec = o;   o = sc_align(o + (int64_t)tsize * rv * P);
   b.bytes = o;
   return b;
 }
-// per-pair result values: forward kernels 6, the adjoint 24
-constexpr int SC_RV_FWD = 6, SC_RV_ADJ = 24;
+// values of a pair's contribution to the two vertices of one of its edges:
+// forward kernels 6 (two corrections), the adjoint 12 (two velocity and two
+// position adjoints); a pair block holds twice that per pair
+constexpr int SC_CW_FWD = 6, SC_CW_ADJ = 12;
 
 template <typename T>
 struct Closest {
