@@ -236,7 +236,8 @@ int rods_rollout(RodsHandle* h, int32_t n_steps, const void* grasp_vel, void* x_
  * segment from its checkpoint and back-propagates the cotangents dL_dxT
  * [V][3] and dL_dvT [V][3] (NULL = 0) of the final state.  Writes (each
  * may be NULL): dL_du [A][R][G][3], dL_db [R], dL_dsigma [R], dL_dx0 [V][3],
- * dL_dv0 [V][3].  Outputs are overwritten.  ROD_ESTATE without a recorded
+ * dL_dv0 [V][3].  dL_dx0 holds the initial frames fixed; their own adjoint
+ * stays in the handle for rods_frames_vjp.  Outputs are overwritten.  ROD_ESTATE without a recorded
  * rollout.  The recorded rollout stays valid (backward may run again).
  * The replay of the next segment runs on a stream of the handle while the
  * current segment's adjoint runs on the given stream; events order them,
@@ -245,6 +246,26 @@ int rods_rollout(RodsHandle* h, int32_t n_steps, const void* grasp_vel, void* x_
 int rods_backward(RodsHandle* h, const void* dL_dxT, const void* dL_dvT, void* dL_du,
                   void* dL_db, void* dL_dsigma, void* dL_dx0, void* dL_dv0,
                   rods_stream_t stream);
+
+/* Adds to dL_dx0 [V][3] the part of the initial positions' gradient that
+ * passes through the initial frames when these came from the initial-frame
+ * rule (rods_set_state with d1 = NULL): the frame adjoint left by the last
+ * rods_backward, taken back through the rule evaluated at x0 [V][3] (the
+ * rollout's initial positions).  The rule itself is App. A.1's predefined
+ * reference frame read as the first edge's frame from z (or x) followed by
+ * parallel transport along the rod; its reference-axis choice is piecewise
+ * constant.  Use only after a backward of a rollout that started from
+ * rule-derived frames. */
+int rods_frames_vjp(RodsHandle* h, const void* x0, void* dL_dx0, rods_stream_t stream);
+
+/* Number of the handle's current recording: each recorded rods_rollout
+ * gets the next number (1, 2, ...); 0 when there is none (a call that
+ * clears the recording: rods_set_state, rods_set_params, rods_step, an
+ * unrecorded rods_rollout, rods_set_plain, ...).  A caller that keeps the
+ * number of its own recorded rollout can check, before rods_backward, that
+ * the handle still holds it (Section 3.3: the backward replays the
+ * rollout's checkpoints).  ROD_EINVAL for a NULL handle. */
+int64_t rods_recording(RodsHandle* h);
 
 /* Gradient-based trajectory optimisation and system identification
  * (App. B, Trajectory Optimization Setup and System Identification).
@@ -329,6 +350,15 @@ int rods_status(RodsHandle* h, int32_t* flags, rods_stream_t stream);
  * NULL pairs with cap > 0. */
 int rods_sc_pairs(RodsHandle* h, int32_t rod, int32_t* pairs, int32_t cap, int32_t* n_pairs,
                   rods_stream_t stream);
+
+/* Work counters of the self-contact kernels, for measurement: writes out
+ * (host) [2][5], the sums over the rods for the forward kernels and then
+ * for the adjoint, of: candidate pairs summed over substeps, superset pairs
+ * tested, superset builds, active pair-passes of the Jacobi projection,
+ * and pairs that took self-friction.  The counts accumulate over calls
+ * since rods_create; reset != 0 zeroes them afterwards.  Synchronises the
+ * stream. */
+int rods_sc_stats(RodsHandle* h, int64_t* out, int32_t reset, rods_stream_t stream);
 
 /* Launch configuration per size bin: fills up to max_bins entries of
  * (vertices per lane, waves per rod, rods in bin) into out (host) [3*max_bins]

@@ -283,6 +283,9 @@ struct RodArgs {
   const int64_t* sc_off;    // [R] offset of the rod's block in sc_tape
   unsigned char* pblk;      // self-contact rods: pair scratch (bytes)
   const int64_t* pblk_off;  // [R] byte offset of the rod's pair block
+  unsigned long long* sc_stats;  // self-contact work counters, [R][8] (nullable): pair-
+                            // substeps, superset tests, superset builds, active
+                            // pair-passes, pairs in friction
   int32_t sc_lds;           // self-contact launches: dynamic LDS bytes (the host's
                             // offer; the launch sets the amount it allocates)
   int32_t* status;          // [R] bit0 non-finite, bit1 pair bookkeeping fault, bit2 stretched edge

@@ -615,6 +615,9 @@ struct Rod {
   int sc_cw, sc_M, sc_P;
   T sc_cell0, sc_lmax;
   int sc_flags;
+  // work counters of the self-contact sweeps: active pair-passes and pairs
+  // in friction, summed into a.sc_stats at the end of the launch
+  unsigned st_act, st_fric;
   T* ctape;
   T b, sig, rc, mu, e, K;
   T w[C], rest[C], lbar[C], ks[C], rad[C];
@@ -1047,6 +1050,12 @@ struct Rod {
     g_con = gb_con = reinterpret_cast<T*>(g + pb.rec);
     sc_P = sc_S = 0;
     sc_built = false;
+    st_act = st_fric = 0;
+  }
+  __device__ void sc_stats_out(const RodArgs<T>& a) const {
+    if (!a.sc_stats) return;
+    if (st_act) atomicAdd(a.sc_stats + 8 * rod + 3, (unsigned long long)st_act);
+    if (st_fric) atomicAdd(a.sc_stats + 8 * rod + 4, (unsigned long long)st_fric);
   }
   __device__ void sc_stage(T* dst, const V3<T> (&vals)[C]) const {
 #pragma unroll
@@ -1190,6 +1199,7 @@ struct Rod {
   // sorted, the compact superset and its per-edge upper incidence
   __device__ void sc_build(const RodArgs<T>& a, const V3<T> (&p)[C], T skin) {
     sc_built = true;
+    if (tl == 0 && a.sc_stats) atomicAdd(a.sc_stats + 8 * rod + 2, 1ull);
 #pragma unroll
     for (int c = 0; c < C; ++c) sc_xb[c] = p[c];
     for (int i = tl; i < SC_HT; i += TL) sc_hcnt[i] = 0;
@@ -1419,7 +1429,13 @@ struct Rod {
       atomicAdd(&sc_hi[pr.hi], 1);
     }
     sc_P = tot;
-    if (tl == 0) g_hdr[0] = tot;
+    if (tl == 0) {
+      g_hdr[0] = tot;
+      if (a.sc_stats) {
+        atomicAdd(a.sc_stats + 8 * rod, (unsigned long long)tot);
+        atomicAdd(a.sc_stats + 8 * rod + 1, (unsigned long long)sc_S);
+      }
+    }
     __syncthreads();
     int nlo[C], nhi[C], slo = 0, shi = 0;
 #pragma unroll
@@ -1530,6 +1546,7 @@ struct Rod {
       r[3] = g.cp.s;
       r[4] = g.cp.u;
       if (g.act) {
+        ++st_act;
         atomicAdd(&sc_cnt[pr.lo], 1);
         atomicAdd(&sc_cnt[pr.lo + 1], 1);
         atomicAdd(&sc_cnt[pr.hi], 1);
@@ -1599,6 +1616,7 @@ struct Rod {
                                      sc_w[hi + 1], sc_r[lo], sc_r[lo + 1], sc_r[hi],
                                      sc_r[hi + 1], d0, mu, a.h);
         if (f.ok) {
+          ++st_fric;
           const T iW = frcp(f.g.W * sc_divisor(sc_fcnt, lo, hi));
           const T s = f.g.cp.s, u = f.g.cp.u;
           cA = (sc_w[lo] * (T(1) - s) * iW) * f.dvt;
@@ -2556,7 +2574,10 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
     bad |= !(s == s) || s > T(1e30);
   }
   int fl = bad ? 1 : 0;
-  if constexpr (SC) fl |= R.sc_flags;
+  if constexpr (SC) {
+    fl |= R.sc_flags;
+    R.sc_stats_out(a);
+  }
   if (fl) atomicOr(a.status + R.rod, fl);
 }
 
@@ -2659,6 +2680,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
     }
   }
   if (BD && R.dyn) R.store_bodies(a.lbody, R.lbs);
+  if constexpr (SC) R.sc_stats_out(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -2687,6 +2709,66 @@ __global__ void k_init_frames(const int32_t* voff, int R, const T* x, T* d1) {
     t = tn;
   }
   put3(d1, 3 * (v0 + N - 1), zero3<T>());
+}
+
+// Adjoint of the initial-frame rule: the frame adjoint d1b [V][3] (edge
+// rows) maps onto the positions through the first frame's construction and
+// the parallel transport along the rod; adds the result to xb.  One thread
+// per rod: the frames are rebuilt forward into tmp, then the transports
+// are reversed from the last edge to the first (the choice of the first
+// frame's reference axis is piecewise constant).
+template <typename T>
+__global__ void k_init_frames_vjp(const int32_t* voff, int R, const T* x, const T* d1b, T* tmp,
+                                  T* xb) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  int v0 = voff[r], N = voff[r + 1] - v0;
+  if (N < 2) return;
+  auto edge = [&](int j, T& l) {
+    V3<T> e = get3(x, 3 * (v0 + j + 1)) - get3(x, 3 * (v0 + j));
+    l = sqrt(dot(e, e));
+    return (T(1) / l) * e;
+  };
+  T l0;
+  V3<T> t = edge(0, l0);
+  const V3<T> t0 = t;
+  V3<T> az = mk(T(0), T(0), T(1));
+  V3<T> cz = cross(t, az);
+  V3<T> av = sqrt(dot(cz, cz)) < T(1e-6) ? mk(T(1), T(0), T(0)) : az;
+  V3<T> dd = av - dot(av, t) * t;
+  const T nd = sqrt(dot(dd, dd));
+  V3<T> d = (T(1) / nd) * dd;
+  put3(tmp, 3 * v0, d);
+  for (int j = 1; j < N - 1; ++j) {
+    T lj;
+    V3<T> tn = edge(j, lj);
+    d = transport(d, t, tn);
+    put3(tmp, 3 * (v0 + j), d);
+    t = tn;
+  }
+  // reverse: edge j's tangent adjoint is complete once the transports into
+  // and out of it are reversed
+  V3<T> carry = zero3<T>(), pend = zero3<T>();
+  for (int j = N - 2; j >= 1; --j) {
+    T la, lb;
+    const V3<T> ta = edge(j - 1, la), tb = edge(j, lb);
+    V3<T> ta_b = zero3<T>(), tb_b = zero3<T>();
+    carry = transport_vjp(get3(tmp, 3 * (v0 + j - 1)), ta, tb, get3(d1b, 3 * (v0 + j)) + carry,
+                          ta_b, tb_b);
+    const V3<T> tj = pend + tb_b;
+    const V3<T> eb = (T(1) / lb) * (tj - dot(tb, tj) * tb);
+    put3(xb, 3 * (v0 + j + 1), get3(xb, 3 * (v0 + j + 1)) + eb);
+    put3(xb, 3 * (v0 + j), get3(xb, 3 * (v0 + j)) - eb);
+    pend = ta_b;
+  }
+  // first frame: d1 = dd / |dd|, dd = a - (a.t) t
+  const V3<T> g = get3(d1b, 3 * v0) + carry;
+  const V3<T> u = (T(1) / nd) * dd;
+  const V3<T> ddb = (T(1) / nd) * (g - dot(u, g) * u);
+  const V3<T> t0b = pend - dot(av, t0) * ddb - dot(ddb, t0) * av;
+  const V3<T> eb = (T(1) / l0) * (t0b - dot(t0, t0b) * t0);
+  put3(xb, 3 * (v0 + 1), get3(xb, 3 * (v0 + 1)) + eb);
+  put3(xb, 3 * v0, get3(xb, 3 * v0) - eb);
 }
 
 // Material curvature of a shape at every interior vertex.
@@ -2884,6 +2966,14 @@ hipError_t launch_init_frames(const int32_t* voff, int R, const T* x, T* d1, hip
 }
 
 template <typename T>
+hipError_t launch_init_frames_vjp(const int32_t* voff, int R, const T* x, const T* d1b, T* tmp,
+                                  T* xb, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_frames_vjp<T>, dim3((R + 63) / 64), dim3(64), 0, st, voff, R, x, d1b,
+                     tmp, xb);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_curvature(const int32_t* voff, const int32_t* rod_of, int V, const T* x,
                             const T* d1, T* kappa, hipStream_t st) {
   hipLaunchKernelGGL(k_curvature<T>, dim3((V + 255) / 256), dim3(256), 0, st, voff, rod_of, V, x,
@@ -2918,6 +3008,8 @@ hipError_t launch_selftest_exchange(int* out, hipStream_t st) {
                                             hipStream_t);                                     \
   template size_t kernel_lds_bytes<T>(int, int, int, bool, bool, int);                         \
   template hipError_t launch_init_frames<T>(const int32_t*, int, const T*, T*, hipStream_t);  \
+  template hipError_t launch_init_frames_vjp<T>(const int32_t*, int, const T*, const T*, T*, T*, \
+                                                hipStream_t);                                 \
   template hipError_t launch_curvature<T>(const int32_t*, const int32_t*, int, const T*,      \
                                           const T*, T*, hipStream_t);                         \
   template hipError_t launch_reduce_params<T>(const int32_t*, int, const double*,             \

@@ -34,6 +34,11 @@ template <typename T>
 size_t kernel_lds_bytes(int which, int C, int W, bool SC, bool GT, int n_iters);
 template <typename T>
 hipError_t launch_init_frames(const int32_t* voff, int R, const T* x, T* d1, hipStream_t st);
+// adds to xb the position adjoint that the frame adjoint d1b induces
+// through the initial-frame rule at positions x (tmp: [V][3] scratch)
+template <typename T>
+hipError_t launch_init_frames_vjp(const int32_t* voff, int R, const T* x, const T* d1b, T* tmp,
+                                  T* xb, hipStream_t st);
 template <typename T>
 hipError_t launch_curvature(const int32_t* voff, const int32_t* rod_of, int V, const T* x,
                             const T* d1, T* kappa, hipStream_t st);

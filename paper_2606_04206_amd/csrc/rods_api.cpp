@@ -11,6 +11,7 @@
 #include <memory>
 #include <new>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "rods.h"
@@ -121,12 +122,18 @@ struct Impl : HandleBase {
   unsigned char *pblk_f = nullptr, *pblk_a = nullptr;
   int64_t *pblk_off_f = nullptr, *pblk_off_a = nullptr;
   std::vector<int64_t> pblk_off_h;
+  // self-contact work counters [2][R][8] (forward kernels, adjoint)
+  unsigned long long* sc_stats = nullptr;
   size_t lds_max = 65536;
   T *lx = nullptr, *lv = nullptr, *lkb = nullptr, *ld1 = nullptr;
   double *acc_b = nullptr, *acc_s = nullptr, *loss_part = nullptr;
   std::vector<Bin> bins;
   std::vector<int32_t> bin_rods_h;
   bool recorded = false;
+  // number of the current recording (1, 2, ... for each recorded rollout;
+  // 0 when there is none): lets a caller check that a backward reads the
+  // rollout it means
+  int64_t rec_gen = 0, rec_count = 0;
   int n_rec = 0;
   int plain = 0;
   // graph of one step (all size bins) over the handle's own buffers
@@ -391,8 +398,10 @@ struct Impl : HandleBase {
         (e = upload(bin_rods, bin_rods_h)) || (e = upload(tape_off, toff_h)) ||
         (e = upload(sc_off, soff_h)) || (e = alloc(sc_tape, (size_t)sc_cap)) ||
         (e = upload(pblk_off_f, pof_h)) || (e = upload(pblk_off_a, poa_h)) ||
-        (e = alloc(pblk_f, (size_t)pbytes_f)) || (e = alloc(pblk_a, (size_t)pbytes_a)))
+        (e = alloc(pblk_f, (size_t)pbytes_f)) || (e = alloc(pblk_a, (size_t)pbytes_a)) ||
+        (e = alloc(sc_stats, (size_t)16 * R)))
       return e;
+    HIPCHK(hipMemset(sc_stats, 0, sizeof(unsigned long long) * 16 * R));
     for (int r = 0; r < R; ++r)   // pair counts read 0 until a step has run
       if (fl_h[r] & ROD_FLAG_SELF) HIPCHK(hipMemset(pblk_f + pof_h[r], 0, sizeof(int32_t)));
     if ((e = alloc(x, 3 * (size_t)V)) || (e = alloc(v, 3 * (size_t)V)) ||
@@ -542,9 +551,11 @@ struct Impl : HandleBase {
   }
 
   int launch_all_(int which, RodArgs<T> a, hipStream_t st) {
-    if (which == 2) {   // the adjoint's own pair scratch
+    a.sc_stats = sc_stats;
+    if (which == 2) {   // the adjoint's own pair scratch and counters
       a.pblk = pblk_a;
       a.pblk_off = pblk_off_a;
+      a.sc_stats = sc_stats + 8 * (size_t)R;
     }
     if (!plain) {
       for (const Bin& bn : bins) {
@@ -656,6 +667,7 @@ struct Impl : HandleBase {
       recorded = true;
       last_tape_ok = true;
       n_rec = n_steps;
+      rec_gen = ++rec_count;
     } else {
       a.u = u;
       a.step_off = 0;
@@ -857,6 +869,24 @@ struct Impl : HandleBase {
       out[2 * k + 1] = pr[k].hi;
     }
     *n_out = np;
+    return ROD_OK;
+  }
+
+  // sums over the rods of the self-contact work counters, forward kernels
+  // then adjoint: out (host) [2][5]; reset zeroes them afterwards
+  int sc_stats_read(int64_t* out, int reset, hipStream_t st) {
+    if (!out) return ROD_EINVAL;
+    std::vector<unsigned long long> h((size_t)16 * R);
+    HIPCHK(hipMemcpyAsync(h.data(), sc_stats, sizeof(unsigned long long) * h.size(),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < 2; ++k)
+      for (int i = 0; i < 5; ++i) {
+        unsigned long long s = 0;
+        for (int r = 0; r < R; ++r) s += h[(size_t)8 * (k * R + r) + i];
+        out[5 * k + i] = (int64_t)s;
+      }
+    if (reset) HIPCHK(rods::launch_fill<int32_t>((int32_t*)sc_stats, 32 * (int64_t)R, 0, st));
     return ROD_OK;
   }
 
@@ -1306,6 +1336,10 @@ int rods_sc_pairs(RodsHandle* h, int32_t rod, int32_t* pairs, int32_t cap, int32
   });
 }
 
+int rods_sc_stats(RodsHandle* h, int64_t* out, int32_t reset, rods_stream_t stream) {
+  return dispatch(h, [&](auto* I) { return I->sc_stats_read(out, reset, (hipStream_t)stream); });
+}
+
 int rods_bins(RodsHandle* h, int32_t* out, int32_t max_bins) {
   if (!h || !out) return ROD_EINVAL;
   return dispatch(h, [&](auto* I) {
@@ -1337,8 +1371,33 @@ int rods_set_plain(RodsHandle* h, int32_t plain) {
   return dispatch(h, [&](auto* I) {
     I->plain = plain ? 1 : 0;
     I->drop_graph();
+    // the tape buffers the backward reads depend on the path: a recording
+    // made on the other path is not valid any more
+    I->recorded = false;
+    I->last_tape_ok = false;
     return (int)ROD_OK;
   });
+}
+
+int rods_frames_vjp(RodsHandle* h, const void* x0, void* dL_dx0, rods_stream_t stream) {
+  if (!h || !x0 || !dL_dx0) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) -> int {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    HIPCHK(rods::launch_init_frames_vjp<T>(I->voff, I->R, (const T*)x0, I->ld1, I->sd1,
+                                           (T*)dL_dx0, (hipStream_t)stream));
+    return ROD_OK;
+  });
+}
+
+int64_t rods_recording(RodsHandle* h) {
+  if (!h) return ROD_EINVAL;
+  Holder* H = reinterpret_cast<Holder*>(h);
+  if (H->prec == 4) {
+    auto* I = static_cast<Impl<float>*>(H->impl);
+    return I->recorded ? I->rec_gen : 0;
+  }
+  auto* I = static_cast<Impl<double>*>(H->impl);
+  return I->recorded ? I->rec_gen : 0;
 }
 
 int rods_set_profiling(RodsHandle* h, int32_t on) {

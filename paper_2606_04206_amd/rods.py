@@ -50,7 +50,8 @@ EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "ro
            "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_launch_shape",
            "rods_set_plain",
            "rods_set_profiling", "rods_profile", "rods_selftest_exchange",
-           "rods_loss_mse_static", "rods_sc_pairs"]
+           "rods_loss_mse_static", "rods_sc_pairs", "rods_sc_stats", "rods_recording",
+           "rods_frames_vjp"]
 
 _lib = None
 
@@ -101,6 +102,9 @@ def load():
         "rods_loss_mse_static": ([vp, c_int32, c_int32, vp, vp, vp, vp, vp], c_int32),
         "rods_sc_pairs": ([vp, c_int32, POINTER(c_int32), c_int32, POINTER(c_int32), vp],
                           c_int32),
+        "rods_sc_stats": ([vp, POINTER(ctypes.c_int64), c_int32, vp], c_int32),
+        "rods_recording": ([vp], ctypes.c_int64),
+        "rods_frames_vjp": ([vp, vp, vp, vp], c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -360,6 +364,31 @@ class RodsHandle:
                                        _stream()), "rods_sc_pairs")
         return np.frombuffer(buf, dtype=np.int32)[:2 * n.value].reshape(-1, 2).copy()
 
+    def frames_vjp(self, x0, dL_dx0):
+        """Adds to dL_dx0 (in place) the gradient through the initial frames
+        of the last backward, when they came from the initial-frame rule."""
+        _require(x0, (self.V, 3), self.dtype, "x0")
+        _require(dL_dx0, (self.V, 3), self.dtype, "dL_dx0")
+        _check(self._lib.rods_frames_vjp(self._h, _ptr(x0), _ptr(dL_dx0), _stream()),
+               "rods_frames_vjp")
+        return dL_dx0
+
+    def recording(self):
+        """Number of the current recorded rollout (0: none)."""
+        return int(self._lib.rods_recording(self._h))
+
+    def sc_stats(self, reset=True):
+        """Self-contact work counters summed over the rods, per kernel kind
+        ('forward', 'adjoint'): pair_substeps, superset_tests, builds,
+        active_pair_passes, friction_pairs."""
+        out = (ctypes.c_int64 * 10)()
+        _check(self._lib.rods_sc_stats(self._h, out, 1 if reset else 0, _stream()),
+               "rods_sc_stats")
+        keys = ("pair_substeps", "superset_tests", "builds", "active_pair_passes",
+                "friction_pairs")
+        return {kind: dict(zip(keys, out[5 * i:5 * i + 5]))
+                for i, kind in enumerate(("forward", "adjoint"))}
+
     def bins(self):
         out = (c_int32 * 48)()
         n = self._lib.rods_bins(self._h, out, 16)
@@ -418,10 +447,12 @@ def loss_mse_static(vert_offsets, x, target, want_grad=True):
 
 class RodsRollout(torch.autograd.Function):
     """x_T = rollout(x0, v0, U; b, sigma_y) through librods; backward runs the
-    library's checkpointed adjoint.  kappa_bar0 is a fixed input.  body0
-    ([P, 9], optional) is the moving bodies' start state, set before the
-    rollout and differentiated through them; without it the bodies start
-    from the handle's current state and get no gradient."""
+    library's checkpointed adjoint.  The initial frames come from x0 by the
+    initial-frame rule, and x0's gradient includes the path through them.
+    kappa_bar0 is a fixed input.  body0 ([P, 9], optional) is the moving
+    bodies' start state, set before the rollout and differentiated through
+    them; without it the bodies start from the handle's current state and
+    get no gradient."""
 
     @staticmethod
     def forward(ctx, handle, n_steps, x0, v0, U, b, sigma_y, kappa_bar0=None, body0=None):
@@ -433,6 +464,8 @@ class RodsRollout(torch.autograd.Function):
         xT = handle.tensor(handle.V, 3)
         handle.rollout(n_steps, U.detach().contiguous(), record=True, x_final=xT)
         ctx.handle = handle
+        ctx.save_for_backward(x0.detach().contiguous())
+        ctx.recording = handle.recording()
         ctx.n_steps = n_steps
         ctx.with_body = body0 is not None
         return xT
@@ -440,8 +473,14 @@ class RodsRollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gx):
         h = ctx.handle
+        if h.recording() != ctx.recording:
+            raise RodsError("RodsRollout.backward: the handle no longer holds this forward's "
+                            "recorded rollout (another recorded rollout, a state or parameter "
+                            "change, or a path switch came in between); run the forward again")
         if ctx.with_body:
             h.set_body_adjoint(None)      # the bodies' final state is not an output
         g = h.backward(gx.contiguous(), n_steps=ctx.n_steps)
+        (x0,) = ctx.saved_tensors
+        gx0 = h.frames_vjp(x0, g["x0"])   # the frames were derived from x0
         gb0 = h.get_body_adjoint() if ctx.with_body else None
-        return None, None, g["x0"], g["v0"], g["u"], g["b"], g["sigma"], None, gb0
+        return None, None, gx0, g["v0"], g["u"], g["b"], g["sigma"], None, gb0

@@ -7,8 +7,10 @@ the twist degree of freedom) or 7 (with moving spheres: also their final
 state and the adjoint of their initial state).  Also stores, per rod and quantity, how far
 the same run moves when the initial positions change by 1e-15 relative
 (`spread_<name>`): the trajectory's own sensitivity to FP64 rounding, which
-a comparison over 15000 substeps cannot beat.  Calls only the oracle and the
-input generators; run from the repository root:
+a comparison over 15000 substeps cannot beat; and by 6e-8 relative, the
+size of rounding the start to FP32 (`spread32_<name>`), the scale against
+which an FP32 run is read.  Calls only the oracle and the input generators;
+run from the repository root:
     python tests/golden/make_golden.py 3
     python tests/golden/make_golden.py 6
     python tests/golden/make_golden.py 7
@@ -60,12 +62,16 @@ def main():
     out = os.path.join(ROOT, "tests", "golden", f"c{cid}_oracle_1000steps.npz")
     rods = list(make_workload(cid, steps=1).oracle_rods)
     with get_context("spawn").Pool(len(rods)) as pool:
-        res = pool.starmap(partial(one_rod, cid), [(r, 0.0) for r in rods] + [(r, 1e-15) for r in rods])
-    base, moved = res[:len(rods)], res[len(rods):]
+        res = pool.starmap(partial(one_rod, cid), [(r, 0.0) for r in rods] +
+                           [(r, 1e-15) for r in rods] + [(r, 6e-8) for r in rods])
+    n = len(rods)
+    base, moved, moved32 = res[:n], res[n:2 * n], res[2 * n:]
     names = NAMES + (("bodyT", "body0") if "bodyT" in base[0] else ())
-    spread = {"spread_" + k: np.array([np.linalg.norm(np.ravel(m[k]) - np.ravel(b[k]))
-                                       / max(np.linalg.norm(np.ravel(b[k])), 1e-300)
-                                       for b, m in zip(base, moved)]) for k in names}
+    spread = {}
+    for tag, alt in (("spread_", moved), ("spread32_", moved32)):
+        spread.update({tag + k: np.array([np.linalg.norm(np.ravel(m[k]) - np.ravel(b[k]))
+                                          / max(np.linalg.norm(np.ravel(b[k])), 1e-300)
+                                          for b, m in zip(base, alt)]) for k in names})
     np.savez_compressed(out, rods=np.array(rods),
                         **{k: np.stack([r[k] for r in base]) for k in base[0]}, **spread)
     print("wrote", out)

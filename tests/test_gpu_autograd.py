@@ -1,12 +1,15 @@
 """The torch.autograd.Function over rods_rollout / rods_backward: gradients
 from loss.backward() equal the library's backward called directly with the
-same loss gradient."""
+same loss gradient (x0's gradient including the path through the initial
+frames that the rule derives from x0); a backward refuses a recording that
+is not its forward's; and the frames' part of x0's gradient matches the
+oracle's adjoint of the initial-frame rule in FP64."""
 import numpy as np
 import pytest
 import torch
 
 from synth import make_workload
-from tests.gpukit import to_dev
+from tests.gpukit import to_dev, gather_state, initial_full_state, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +37,11 @@ def test_autograd_function_matches_direct_backward():
     h.rollout(n, U.detach(), record=True, x_final=xT2)
     assert torch.equal(xT.detach(), xT2)
     g = h.backward(gx, n_steps=n)
+    g["x0"] = h.frames_vjp(x0.detach(), g["x0"])
     for leafv, key in ((x0, "x0"), (v0, "v0"), (U, "u"), (b, "b"), (sig, "sigma")):
         assert leafv.grad is not None, key
         torch.testing.assert_close(leafv.grad, g[key], rtol=1e-6, atol=1e-12)
-    assert float(loss) > 0 and torch.isfinite(x0.grad).all()
+    assert float(loss.detach()) > 0 and torch.isfinite(x0.grad).all()
 
 
 def test_autograd_function_with_moving_spheres():
@@ -72,8 +76,75 @@ def test_autograd_function_with_moving_spheres():
     assert torch.equal(xT.detach(), xT2)
     g = h.backward(gx, n_steps=n)
     torch.testing.assert_close(b0.grad, h.get_body_adjoint(), rtol=1e-6, atol=1e-12)
+    g["x0"] = h.frames_vjp(x0.detach(), g["x0"])
     for leafv, key in ((x0, "x0"), (U, "u"), (b, "b")):
         torch.testing.assert_close(leafv.grad, g[key], rtol=1e-6, atol=1e-12)
     # a second call restarts the spheres from body0
     xT3 = RodsRollout.apply(h, n, x0, v0, U, b, sig, None, b0)
     assert torch.equal(xT3.detach(), xT.detach())
+
+
+def test_backward_refuses_a_later_recording():
+    """Two forwards on one handle, then the first output's backward: the
+    handle holds the second recording, so the backward raises instead of
+    returning the second rollout's gradients; the second's backward works."""
+    from paper_2606_04206_amd import RodsHandle, RodsRollout, RodsError
+    n, K = 2, 1
+    wl = make_workload(3, steps=n)
+    sub = wl.subset(list(wl.oracle_rods[:2]))
+    h = RodsHandle(sub, max_steps=n, ckpt_every=K)
+    leaf = lambda a: to_dev(a).requires_grad_()
+    args = [leaf(a) for a in (sub.x0, sub.v0, sub.actions, sub.rod_params[:, 2],
+                              sub.rod_params[:, 3])]
+    xa = RodsRollout.apply(h, n, *args)
+    xb = RodsRollout.apply(h, n, *args)
+    with pytest.raises(RodsError):
+        xa.sum().backward()
+    xb.sum().backward()
+    assert torch.isfinite(args[0].grad).all()
+    # a path switch also ends the recording
+    xc = RodsRollout.apply(h, n, *args)
+    h.set_plain(True)
+    with pytest.raises(RodsError):
+        xc.sum().backward()
+
+
+def test_frames_vjp_matches_oracle_fp64():
+    """Helices (rest shape coiled, so the frames carry bending), frames from
+    the initial-frame rule, 3 steps in FP64: the backward's dL/dx0 (frames
+    held fixed) matches the oracle's x0 adjoint, and with rods_frames_vjp
+    added the total matches the oracle's x0_b + init_frames_vjp(x0, d1_b),
+    both within 1e-9; the frames' part is not negligible (over 1e-3 of the
+    total on at least one rod, so leaving it out fails the comparison)."""
+    from paper_2606_04206_amd import RodsHandle
+    from oracle import forward as ofw, adjoint as oadj
+    from oracle.geometry import init_frames_vjp
+    from oracle.model import rods_from_workload, sim_from_workload
+    f64 = torch.float64
+    n, K = 3, 1
+    wl = make_workload(5, steps=n, n_vert=64, n_rods=4)
+    full = initial_full_state(wl)
+    h = RodsHandle(wl, precision=8, max_steps=n, ckpt_every=K)
+    x0 = to_dev(full[0], f64)
+    h.set_state(x0, to_dev(full[1], f64), to_dev(full[2], f64), None)
+    xT = h.tensor(wl.n_vert, 3)
+    h.rollout(n, to_dev(wl.actions, f64), record=True, x_final=xT)
+    _, g = h.loss_mse(xT, to_dev(wl.target, f64))
+    gg = h.backward(g, n_steps=n)
+    fixed = gg["x0"].clone().cpu().numpy()
+    total = h.frames_vjp(x0, gg["x0"]).cpu().numpy()
+    rods = list(range(wl.n_rods))
+    orods, osim = rods_from_workload(wl, rods), sim_from_workload(wl)
+    st = gather_state(wl, rods, full)
+    _, ck = ofw.rollout(orods, osim, st, wl.actions, n, K)
+    gxo = g.cpu().numpy().reshape(wl.n_rods, -1, 3)
+    x0b, v0b, Ub, bb, sb, d1b = oadj.backward(orods, osim, ck, wl.actions, n, K, gxo,
+                                              with_frames=True)
+    tot_o = x0b + init_frames_vjp(st.x, d1b)
+    part = []
+    for r in rods:
+        a, b = wl.rod_range(r)
+        assert rel_err(fixed[a:b], x0b[r]) <= 1e-9, r
+        assert rel_err(total[a:b], tot_o[r]) <= 1e-9, r
+        part.append(np.linalg.norm(tot_o[r] - x0b[r]) / np.linalg.norm(tot_o[r]))
+    assert max(part) > 1e-3, part   # dropping it would miss 1e-9 by far
