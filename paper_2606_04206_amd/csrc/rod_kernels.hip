@@ -595,15 +595,16 @@ struct Rod {
   float* sc_vc;   // the adjoint's recorded per-vertex counts
   int *sc_cnt, *sc_fcnt, *sc_hcnt, *sc_hstart, *sc_items, *sc_lo, *sc_hi, *sc_slo, *sc_shi,
       *sc_tmp;
-  int *g_hdr, *g_trilo, *g_hpos, *g_suphi, *g_cidx;
+  int *g_hdr, *g_trilo, *g_hidx, *g_suphi, *g_cidx;
   SPair *g_pairs, *g_sup;
-  // the substep's pair arrays: g_pairs, g_hpos, g_d0, g_d0b and g_con point
+  // the substep's pair arrays: g_pairs, g_hidx, g_d0, g_d0b and g_rec point
   // either into the rod's global block (gb_*) or, when the substep's pairs
   // fit, into the LDS left over past the fixed layout (the hash, dead after
-  // a build, and the rest of the workgroup's allocation)
-  int* gb_hpos;
+  // a build, and the rest of the workgroup's allocation); g_rec2 (the
+  // adjoint's friction position adjoints) stays global
+  int* gb_hidx;
   SPair* gb_pairs;
-  T *gb_d0, *gb_d0b, *gb_con;
+  T *gb_d0, *gb_d0b, *gb_rec, *g_rec2;
   unsigned char* sc_cache;
   int sc_cache_bytes;
   // the superset of candidates (pairs within the margin plus a skin at the
@@ -611,8 +612,8 @@ struct Rod {
   V3<T> sc_xb[C];
   bool sc_built;
   int sc_S;
-  T *g_d0, *g_d0b, *g_con;
-  int sc_cw, sc_M, sc_P;
+  T *g_d0, *g_d0b, *g_rec;
+  int sc_rv, sc_M, sc_P;
   T sc_cell0, sc_lmax;
   int sc_flags;
   // work counters of the self-contact sweeps: active pair-passes and pairs
@@ -1010,9 +1011,9 @@ struct Rod {
   static constexpr size_t sc_bytes() {
     return sc_fixed_bytes() + sizeof(int) * (size_t)(SC_HT + (SC_HT + 4) + NV) + 64;
   }
-  // cw: values of a pair's contribution to the two vertices of one of its
-  // edges (6 in the forward kernels, 12 in the adjoint)
-  __device__ void sc_layout(unsigned char* base, const RodArgs<T>& a, int cw, size_t xchg_off) {
+  // rv: values of a pair's record (SC_RV_FWD in the forward kernels,
+  // SC_RV_ADJ in the adjoint)
+  __device__ void sc_layout(unsigned char* base, const RodArgs<T>& a, int rv, size_t xchg_off) {
     T* f = reinterpret_cast<T*>(base);
     sc_pos = f; f += 3 * NV;
     sc_aux = f; f += 3 * NV;
@@ -1034,9 +1035,9 @@ struct Rod {
     sc_hstart = q; q += SC_HT + 4;
     sc_items = q;
     sc_cache_bytes = a.sc_lds - (int)(sc_cache - base) - (int)xchg_off;
-    sc_cw = cw;
+    sc_rv = rv;
     sc_M = N - 2 - a.k_ex;
-    const PairBlock pb = sc_block(N, a.k_ex, (int)sizeof(T), 2 * cw);
+    const PairBlock pb = sc_block(N, a.k_ex, (int)sizeof(T), rv);
     unsigned char* g = a.pblk + a.pblk_off[rod];
     g_hdr = reinterpret_cast<int*>(g);
     g_trilo = reinterpret_cast<int*>(g + pb.trilo);
@@ -1044,10 +1045,11 @@ struct Rod {
     g_suphi = reinterpret_cast<int*>(g + pb.suphi);
     g_cidx = reinterpret_cast<int*>(g + pb.cidx);
     g_pairs = gb_pairs = reinterpret_cast<SPair*>(g + pb.pairs);
-    g_hpos = gb_hpos = reinterpret_cast<int*>(g + pb.hpos);
+    g_hidx = gb_hidx = reinterpret_cast<int*>(g + pb.hidx);
     g_d0 = gb_d0 = reinterpret_cast<T*>(g + pb.d0);
     g_d0b = gb_d0b = reinterpret_cast<T*>(g + pb.d0b);
-    g_con = gb_con = reinterpret_cast<T*>(g + pb.rec);
+    g_rec = gb_rec = reinterpret_cast<T*>(g + pb.rec);
+    g_rec2 = reinterpret_cast<T*>(g + pb.rec2);
     sc_P = sc_S = 0;
     sc_built = false;
     st_act = st_fric = 0;
@@ -1353,7 +1355,7 @@ struct Rod {
       const int b0 = sc_slo[e];
       for (int q = 0; q < nlo[c]; ++q) {
         const int j = lo_in[q];
-        g_sup[b0 + q] = SPair{e, j};
+        g_sup[b0 + q] = SPair{(short)e, (short)j};
         const int at = atomicAdd(&sc_cnt[j], 1);
         if (at < sc_shi[j + 1] - sc_shi[j]) g_suphi[sc_shi[j] + at] = b0 + q;
         else sc_flags |= 2;
@@ -1402,22 +1404,27 @@ struct Rod {
     }
     int base, dummy, tot, tot1;
     sc_scan2(n, 0, base, dummy, tot, tot1);
-    // the substep's pair arrays go to LDS when they fit
-    const int per = (int)(sizeof(SPair) + sizeof(int) + (2 + 2 * sc_cw) * sizeof(T));
+    // the substep's pair arrays go to LDS when they fit (the forward
+    // kernels need no depth adjoints)
+    const bool adj = sc_rv == SC_RV_ADJ;
+    const int per = (int)(sizeof(SPair) + sizeof(int) + ((adj ? 2 : 1) + sc_rv) * sizeof(T));
     if (tot <= (sc_cache_bytes - (int)sizeof(T)) / per) {
       unsigned char* c = sc_cache;
       g_pairs = reinterpret_cast<SPair*>(c); c += sizeof(SPair) * tot;
-      g_hpos = reinterpret_cast<int*>(c); c += sizeof(int) * tot;
+      g_hidx = reinterpret_cast<int*>(c); c += sizeof(int) * tot;
       c = sc_cache + (c - sc_cache + sizeof(T) - 1) / sizeof(T) * sizeof(T);
       g_d0 = reinterpret_cast<T*>(c); c += sizeof(T) * tot;
-      g_d0b = reinterpret_cast<T*>(c); c += sizeof(T) * tot;
-      g_con = reinterpret_cast<T*>(c);
+      if (adj) {
+        g_d0b = reinterpret_cast<T*>(c);
+        c += sizeof(T) * tot;
+      }
+      g_rec = reinterpret_cast<T*>(c);
     } else {
       g_pairs = gb_pairs;
-      g_hpos = gb_hpos;
+      g_hidx = gb_hidx;
       g_d0 = gb_d0;
       g_d0b = gb_d0b;
-      g_con = gb_con;
+      g_rec = gb_rec;
     }
     for (int s = s0; s < s1; ++s) {
       if (g_cidx[s] < 0) continue;
@@ -1458,8 +1465,7 @@ struct Rod {
       sc_lo[NV] = tlo;
       sc_hi[NV] = thi;
     }
-    // upper-edge lists: the superset's, filtered (the order carries over);
-    // each pair learns its place in its upper edge's list
+    // upper-edge lists: the superset's, filtered (the order carries over)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       if (!evalid(c)) continue;
@@ -1468,7 +1474,7 @@ struct Rod {
       const int q1 = sc_shi[e + 1];
       for (int q = sc_shi[e]; q < q1; ++q) {
         const int k = g_cidx[g_suphi[q]];
-        if (k >= 0) g_hpos[k] = o++;
+        if (k >= 0) g_hidx[o++] = k;
       }
       if (o != sc_hi[e] + nhi[c]) sc_flags |= 2;
     }
@@ -1489,38 +1495,57 @@ struct Rod {
     const T m = (T)(a0 > a1 ? a0 : a1);
     return m > T(1) ? m : T(1);
   }
-  // Contributions of the pairs to their edges' vertices: pair k's to the
-  // two vertices of its lower edge at g_con[k * cw], to those of its upper
-  // edge at g_con[(P + hpos[k]) * cw], so the pairs touching an edge form
-  // two contiguous runs (lower-edge pairs in list order, upper-edge pairs
-  // in the order of their lower edges) that its lane sums in that fixed
-  // order.  Inactive pairs contribute zeros.
-  __device__ __forceinline__ T* sc_con_lo(int k) const { return g_con + (int64_t)k * sc_cw; }
-  __device__ __forceinline__ T* sc_con_hi(int k) const {
-    return g_con + (int64_t)(sc_P + g_hpos[k]) * sc_cw;
+  // Per-pair records (sc_rv values at g_rec[k * rv]) and the fixed-order
+  // gather of the pairs touching an own edge: its pairs as lower edge (a
+  // contiguous run of the list), then as upper edge (its run of g_hidx, in
+  // list order).  Inactive pairs have zero records.
+  __device__ __forceinline__ T* sc_rec(int k) const { return g_rec + (int64_t)k * sc_rv; }
+  // forward records (k n or dv_t, s, u, reciprocal divisor): the
+  // corrections of own edge e's two vertices, summed
+  __device__ __forceinline__ void sc_gather_fwd(int e, V3<T>& dA, V3<T>& dB) const {
+    dA = dB = zero3<T>();
+    const T wa = sc_w[e], wb = sc_w[e + 1];
+    const int k1 = sc_lo[e + 1];
+    for (int k = sc_lo[e]; k < k1; ++k) {
+      const T* r = sc_rec(k);
+      const V3<T> kn = mk(r[0], r[1], r[2]);
+      const T s = r[3], im = r[5];
+      dA += (wa * (T(1) - s) * im) * kn;
+      dB += (wb * s * im) * kn;
+    }
+    const int q1 = sc_hi[e + 1];
+    for (int q = sc_hi[e]; q < q1; ++q) {
+      const T* r = sc_rec(g_hidx[q]);
+      const V3<T> kn = mk(r[0], r[1], r[2]);
+      const T u = r[4], im = r[5];
+      dA -= (wa * (T(1) - u) * im) * kn;
+      dB -= (wb * u * im) * kn;
+    }
   }
-  // sum of the first n values of the contributions touching own edge e
-  template <int NVAL>
-  __device__ __forceinline__ void sc_gather(int e, T (&out)[NVAL]) const {
-#pragma unroll
-    for (int i = 0; i < NVAL; ++i) out[i] = T(0);
-    const T* lo = g_con + (int64_t)sc_lo[e] * sc_cw;
-    const int nl = sc_lo[e + 1] - sc_lo[e];
-    for (int k = 0; k < nl; ++k)
-#pragma unroll
-      for (int i = 0; i < NVAL; ++i) out[i] += lo[k * sc_cw + i];
-    const T* hi = g_con + (int64_t)(sc_P + sc_hi[e]) * sc_cw;
-    const int nh = sc_hi[e + 1] - sc_hi[e];
-    for (int k = 0; k < nh; ++k)
-#pragma unroll
-      for (int i = 0; i < NVAL; ++i) out[i] += hi[k * sc_cw + i];
+  // adjoint records (four vertex adjoints, lower edge's first) from rec
+  // (off = 0) or rec2: the sums for own edge e's two vertices
+  __device__ __forceinline__ void sc_gather_adj(int e, const T* base, V3<T>& gA,
+                                                V3<T>& gB) const {
+    gA = gB = zero3<T>();
+    const int k1 = sc_lo[e + 1];
+    for (int k = sc_lo[e]; k < k1; ++k) {
+      const T* r = base + (int64_t)k * 12;
+      gA += get3(r, 0);
+      gB += get3(r, 3);
+    }
+    const int q1 = sc_hi[e + 1];
+    for (int q = sc_hi[e]; q < q1; ++q) {
+      const T* r = base + (int64_t)g_hidx[q] * 12;
+      gA += get3(r, 6);
+      gB += get3(r, 9);
+    }
   }
 
   // one Jacobi pass of the self-contact projection: a sweep over the pairs
   // evaluates each once (activity, depth, direction) and counts the active
-  // pairs per vertex; a second sweep turns each into its four vertex
-  // corrections divided by its divisor; each lane sums those of its own
-  // edges.  The first pass keeps the depths d0 and the counts for friction.
+  // pairs per vertex; a second sweep adds each pair's reciprocal divisor;
+  // each lane then sums the corrections of the pairs touching its edges.
+  // The first pass keeps the depths d0 and the counts for friction.
   template <bool REC>
   __device__ void sc_pass(Team<T, W>& X, const V3<T> (&p0)[C], V3<T> (&dl)[C], int it,
                           bool first) {
@@ -1532,14 +1557,13 @@ struct Rod {
     }
     sc_stage(sc_pos, p);
     __syncthreads();
-    // sweep 1: k n (n the unit direction, k = d / W) and s, u in the
-    // pair's lower-edge slot
+    // sweep 1: k n (n the unit direction, k = d / W), s, u
     for (int k = tl; k < sc_P; k += TL) {
       const SPair pr = g_pairs[k];
       PairGeo<T> g = sc_pair(sc_pos, pr.lo, pr.hi);
       if (first) g_d0[k] = g.act ? g.d : T(0);
       const T kk = g.act ? fdiv(g.d, g.W) : T(0);
-      T* r = sc_con_lo(k);
+      T* r = sc_rec(k);
       r[0] = kk * g.n.x;
       r[1] = kk * g.n.y;
       r[2] = kk * g.n.z;
@@ -1554,18 +1578,10 @@ struct Rod {
       }
     }
     __syncthreads();
-    // sweep 2: the four corrections, divided by the pair's divisor
+    // sweep 2: the pair's divisor, from the completed counts
     for (int k = tl; k < sc_P; k += TL) {
       const SPair pr = g_pairs[k];
-      T* r = sc_con_lo(k);
-      const V3<T> kn = mk(r[0], r[1], r[2]);
-      const T s = r[3], u = r[4];
-      const T im = frcp(sc_divisor(sc_cnt, pr.lo, pr.hi));
-      put3(r, 0, (sc_w[pr.lo] * (T(1) - s) * im) * kn);
-      put3(r, 3, (sc_w[pr.lo + 1] * s * im) * kn);
-      T* q = sc_con_hi(k);
-      put3(q, 0, (-(sc_w[pr.hi] * (T(1) - u) * im)) * kn);
-      put3(q, 3, (-(sc_w[pr.hi + 1] * u * im)) * kn);
+      sc_rec(k)[5] = frcp(sc_divisor(sc_cnt, pr.lo, pr.hi));
     }
     if (first) {
 #pragma unroll
@@ -1583,11 +1599,7 @@ struct Rod {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       dA[c] = dB[c] = zero3<T>();
-      if (!evalid(c)) continue;
-      T o[6];
-      sc_gather(gi(c), o);
-      dA[c] = mk(o[0], o[1], o[2]);
-      dB[c] = mk(o[3], o[4], o[5]);
+      if (evalid(c)) sc_gather_fwd(gi(c), dA[c], dB[c]);
     }
     __syncthreads();
     T s3[3] = {dB[C - 1].x, dB[C - 1].y, dB[C - 1].z};
@@ -1607,7 +1619,8 @@ struct Rod {
       const T d0 = g_d0[k];
       const SPair pr = g_pairs[k];
       const int lo = pr.lo, hi = pr.hi;
-      V3<T> cA = zero3<T>(), cB = zero3<T>(), cC = zero3<T>(), cD = zero3<T>();
+      V3<T> dvt = zero3<T>();
+      T s = T(0), u = T(0), iW = T(0);
       if (d0 > T(0)) {
         FricGeo<T> f = pair_friction(sc_at(sc_pos, lo), sc_at(sc_pos, lo + 1), sc_at(sc_pos, hi),
                                      sc_at(sc_pos, hi + 1), sc_at(sc_aux, lo),
@@ -1617,31 +1630,24 @@ struct Rod {
                                      sc_r[hi + 1], d0, mu, a.h);
         if (f.ok) {
           ++st_fric;
-          const T iW = frcp(f.g.W * sc_divisor(sc_fcnt, lo, hi));
-          const T s = f.g.cp.s, u = f.g.cp.u;
-          cA = (sc_w[lo] * (T(1) - s) * iW) * f.dvt;
-          cB = (sc_w[lo + 1] * s * iW) * f.dvt;
-          cC = (-(sc_w[hi] * (T(1) - u) * iW)) * f.dvt;
-          cD = (-(sc_w[hi + 1] * u * iW)) * f.dvt;
+          dvt = f.dvt;
+          s = f.g.cp.s;
+          u = f.g.cp.u;
+          iW = frcp(f.g.W * sc_divisor(sc_fcnt, lo, hi));
         }
       }
-      T* r = sc_con_lo(k);
-      put3(r, 0, cA);
-      put3(r, 3, cB);
-      T* q = sc_con_hi(k);
-      put3(q, 0, cC);
-      put3(q, 3, cD);
+      T* r = sc_rec(k);
+      put3(r, 0, dvt);
+      r[3] = s;
+      r[4] = u;
+      r[5] = iW;
     }
     __syncthreads();
     V3<T> dA[C], dB[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       dA[c] = dB[c] = zero3<T>();
-      if (!evalid(c)) continue;
-      T o[6];
-      sc_gather(gi(c), o);
-      dA[c] = mk(o[0], o[1], o[2]);
-      dB[c] = mk(o[3], o[4], o[5]);
+      if (evalid(c)) sc_gather_fwd(gi(c), dA[c], dB[c]);
     }
     __syncthreads();
     T s3[3] = {dB[C - 1].x, dB[C - 1].y, dB[C - 1].z};
@@ -1652,7 +1658,8 @@ struct Rod {
 
   // adjoint of sc_friction: lv (adjoint of friction's output velocity) ->
   // adjoint of its input velocity; adds position adjoints to xb; leaves the
-  // adjoint of each pair's first-pass depth in g_d0b
+  // adjoint of each pair's first-pass depth in g_d0b.  The velocity
+  // adjoints of a pair go to its record, the position adjoints to rec2.
   __device__ void sc_friction_vjp(const RodArgs<T>& a, Team<T, W>& X, const Rec<T, C>& r,
                                   V3<T> (&lv)[C], V3<T> (&xb)[C]) {
     sc_stage(sc_pos, r.x1);
@@ -1683,10 +1690,10 @@ struct Rod {
         }
       }
       g_d0b[k] = d0b;
-      T* o = sc_con_lo(k);
-      put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, q0); put3(o, 9, q1);
-      T* h = sc_con_hi(k);
-      put3(h, 0, b2); put3(h, 3, b3); put3(h, 6, q2); put3(h, 9, q3);
+      T* o = sc_rec(k);
+      put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, b2); put3(o, 9, b3);
+      T* o2 = g_rec2 + (int64_t)k * 12;
+      put3(o2, 0, q0); put3(o2, 3, q1); put3(o2, 6, q2); put3(o2, 9, q3);
     }
     __syncthreads();
     V3<T> vA[C], vB[C], xA[C], xB[C];
@@ -1694,12 +1701,8 @@ struct Rod {
     for (int c = 0; c < C; ++c) {
       vA[c] = vB[c] = xA[c] = xB[c] = zero3<T>();
       if (!evalid(c)) continue;
-      T o[12];
-      sc_gather(gi(c), o);
-      vA[c] = mk(o[0], o[1], o[2]);
-      vB[c] = mk(o[3], o[4], o[5]);
-      xA[c] = mk(o[6], o[7], o[8]);
-      xB[c] = mk(o[9], o[10], o[11]);
+      sc_gather_adj(gi(c), g_rec, vA[c], vB[c]);
+      sc_gather_adj(gi(c), g_rec2, xA[c], xB[c]);
     }
     __syncthreads();
     T s6[6] = {vB[C - 1].x, vB[C - 1].y, vB[C - 1].z, xB[C - 1].x, xB[C - 1].y, xB[C - 1].z};
@@ -1745,21 +1748,15 @@ struct Rod {
                            d0b, b0, b1, b2, b3);
         }
       }
-      T* o = sc_con_lo(k);
-      put3(o, 0, b0); put3(o, 3, b1);
-      T* h = sc_con_hi(k);
-      put3(h, 0, b2); put3(h, 3, b3);
+      T* o = sc_rec(k);
+      put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, b2); put3(o, 9, b3);
     }
     __syncthreads();
     V3<T> cA[C], cB[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       cA[c] = cB[c] = zero3<T>();
-      if (!evalid(c)) continue;
-      T o[6];
-      sc_gather(gi(c), o);
-      cA[c] = mk(o[0], o[1], o[2]);
-      cB[c] = mk(o[3], o[4], o[5]);
+      if (evalid(c)) sc_gather_adj(gi(c), g_rec, cA[c], cB[c]);
     }
     __syncthreads();
     T s3[3] = {cB[C - 1].x, cB[C - 1].y, cB[C - 1].z};
@@ -2537,7 +2534,7 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
   Rod<T, C, W, SC, TW, BD> R;
   R.load_static(a, X);
   if constexpr (SC) {
-    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_CW_FWD, xchg_bytes<T, W>());
+    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_RV_FWD, xchg_bytes<T, W>());
     R.ctape = nullptr;
     R.sc_setup(a);
   }
@@ -2604,7 +2601,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
     // LDS holds the self-contact buffers; the contact-pass inputs follow the
     // projection iterates in the rod's scratch block (written and read
     // within a substep)
-    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_CW_ADJ, xchg_bytes<T, W>());
+    R.sc_layout(smem + xchg_bytes<T, W>(), a, SC_RV_ADJ, xchg_bytes<T, W>());
     R.ctape = lds_tape + (size_t)a.n_iters * C * PROJ_TAPE * 64 * W;
     R.sc_setup(a);
   }

@@ -18,10 +18,16 @@ namespace rods {
 constexpr int SC_NKEY = 64 * 27;
 constexpr int SC_HT = 2048;
 
-// one candidate pair, lower edge first
-struct alignas(8) SPair {
-  int lo, hi;
+// one candidate pair, lower edge first (edge indices of a self-contact
+// rod, at most 1023, fit 16 bits)
+struct alignas(4) SPair {
+  short lo, hi;
 };
+
+// values of a pair's record: forward kernels 6 (k n, s, u and the
+// reciprocal divisor, from which both edges' corrections follow), the
+// adjoint 12 (the adjoints of the four vertices' positions or velocities)
+constexpr int SC_RV_FWD = 6, SC_RV_ADJ = 12;
 
 // Largest number of admissible pairs (j - i > k_ex) among the n - 1 edges of
 // a rod of n vertices: the pair scratch has room for all of them, so no
@@ -45,12 +51,13 @@ __host__ __device__ inline int64_t sc_off_hi(int64_t e, int64_t k_ex) {
 // slots), the compact superset (sup, sorted by lower and then upper edge),
 // per edge the sorted superset indices of the pairs it is the upper edge of
 // (suphi), and each superset pair's place in the substep's list or -1
-// (cidx); the substep's compact pair list (sorted likewise), each pair's
-// place in its upper edge's list (hpos), the first-pass depths d0, their
-// adjoints d0b, and rv values of per-pair results (a pair's contributions
-// to the vertices of its two edges)
+// (cidx); the substep's compact pair list (sorted likewise), per edge the
+// indices of the pairs it is the upper edge of (hidx), the first-pass
+// depths d0, their adjoints d0b, rv values of per-pair results, and (the
+// adjoint's blocks, rv = SC_RV_ADJ) 12 more per pair for the position
+// adjoints of friction
 struct PairBlock {
-  int64_t trilo, sup, suphi, cidx, pairs, hpos, d0, d0b, rec, bytes;
+  int64_t trilo, sup, suphi, cidx, pairs, hidx, d0, d0b, rec, rec2, bytes;
 };
 __host__ __device__ inline int64_t sc_align(int64_t b) { return (b + 255) / 256 * 256; }
 __host__ __device__ inline PairBlock sc_block(int n, int k_ex, int tsize, int rv) {
@@ -58,21 +65,18 @@ __host__ __device__ inline PairBlock sc_block(int n, int k_ex, int tsize, int rv
   PairBlock b;
   int64_t o = 256;
   b.trilo = o; o = sc_align(o + 4 * P);
-  b.sup = o;   o = sc_align(o + 8 * P);
+  b.sup = o;   o = sc_align(o + 4 * P);
   b.suphi = o; o = sc_align(o + 4 * P);
   b.cidx = o;  o = sc_align(o + 4 * P);
-  b.pairs = o; o = sc_align(o + 8 * P);
-  b.hpos = o;  o = sc_align(o + 4 * P);
+  b.pairs = o; o = sc_align(o + 4 * P);
+  b.hidx = o;  o = sc_align(o + 4 * P);
   b.d0 = o;    o = sc_align(o + (int64_t)tsize * P);
   b.d0b = o;   o = sc_align(o + (int64_t)tsize * P);
   b.rec = o;   o = sc_align(o + (int64_t)tsize * rv * P);
+  b.rec2 = o;  o = sc_align(o + (rv == SC_RV_ADJ ? (int64_t)tsize * 12 * P : 0));
   b.bytes = o;
   return b;
 }
-// values of a pair's contribution to the two vertices of one of its edges:
-// forward kernels 6 (two corrections), the adjoint 12 (two velocity and two
-// position adjoints); a pair block holds twice that per pair
-constexpr int SC_CW_FWD = 6, SC_CW_ADJ = 12;
 
 template <typename T>
 struct Closest {

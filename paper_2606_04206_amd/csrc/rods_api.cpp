@@ -380,8 +380,8 @@ struct Impl : HandleBase {
       const int n = voff_h[r + 1] - voff_h[r];
       pof_h[r] = pbytes_f;
       poa_h[r] = pbytes_a;
-      pbytes_f += rods::sc_block(n, d.k_exclude, (int)sizeof(T), 2 * rods::SC_CW_FWD).bytes;
-      pbytes_a += rods::sc_block(n, d.k_exclude, (int)sizeof(T), 2 * rods::SC_CW_ADJ).bytes;
+      pbytes_f += rods::sc_block(n, d.k_exclude, (int)sizeof(T), rods::SC_RV_FWD).bytes;
+      pbytes_a += rods::sc_block(n, d.k_exclude, (int)sizeof(T), rods::SC_RV_ADJ).bytes;
     }
     pblk_off_h = pof_h;
     n_ck = std::max(1, (d.max_steps + d.ckpt_every - 1) / d.ckpt_every);
@@ -850,7 +850,7 @@ struct Impl : HandleBase {
     HIPCHK(hipStreamSynchronize(st));
     if (!(fl[0] & ROD_FLAG_SELF)) return ROD_EINVAL;
     const int n = voff_h[r + 1] - voff_h[r];
-    const rods::PairBlock pb = rods::sc_block(n, d.k_exclude, (int)sizeof(T), 2 * rods::SC_CW_FWD);
+    const rods::PairBlock pb = rods::sc_block(n, d.k_exclude, (int)sizeof(T), rods::SC_RV_FWD);
     const unsigned char* base = pblk_f + pblk_off_h[r];
     int32_t np = 0;
     HIPCHK(hipMemcpyAsync(&np, base, sizeof(int32_t), hipMemcpyDeviceToHost, st));
