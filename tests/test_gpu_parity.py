@@ -5,7 +5,10 @@ Tolerances:
   stated bound), and yield decisions whose oracle margin exceeds 1e-5 agree
   exactly.
 * FP32 gradients over a rollout: relative error <= 1e-3 per block.
-* FP64 GPU path: <= 1e-9 relative (same algorithm, different rounding order).
+* FP32 step displacement and velocities: <= 5e-3 relative per rod (FP32
+  rounding of positions turned into velocity by 1/h, see the test).
+* FP64 GPU path: <= 1e-9 relative, positions, displacement, velocities and
+  frames (same algorithm, different rounding order).
 """
 from dataclasses import replace
 
@@ -134,20 +137,37 @@ def test_fp32_substep_teacher_forced_parity_and_yield_branches():
 
 
 def test_fp32_step_teacher_forced_parity():
-    """Configuration 2, full steps (15 substeps): positions <= 1e-4."""
+    """Configuration 2, full steps (15 substeps): positions <= 1e-4; and,
+    since positions of ~0.5 m hide sub-mm motion, the step's displacement
+    x' - x and the velocities within 5e-3 relative per rod.  That bound
+    follows from FP32 positions: each substep stores x rounded to half an ulp
+    at 0.5 m (3e-8 m), which the projection turns into velocity changes of
+    up to 3e-8 m / h = 4.5e-4 m/s; over 15 substeps they add up to about
+    1.7e-3 m/s against velocities of 0.3-1 m/s (measured: 1.1e-3 and
+    1.5e-3 at worst)."""
+    worst = [0.0, 0.0]
     for start, ref, gpu, _ in _teacher_forced(2, False):
         for r in range(ref.x.shape[0]):
             assert rel_err(gpu.x[r], ref.x[r]) <= 1e-4
+            ed = rel_err(gpu.x[r] - start.x[r], ref.x[r] - start.x[r])
+            ev = rel_err(gpu.v[r], ref.v[r])
+            worst = [max(worst[0], ed), max(worst[1], ev)]
+            assert ed <= 5e-3 and ev <= 5e-3, (r, ed, ev)
+    print(f"worst displacement error {worst[0]:.2e}, velocity error {worst[1]:.2e}")
 
 
 def test_fp64_step_matches_oracle_tightly():
     """The same teacher-forced steps in FP64 on the GPU agree to 1e-9: the
     kernels implement the oracle's algorithm, not an approximation of it."""
+    worst = 0.0
     for start, ref, gpu, _ in _teacher_forced(2, False, precision=8):
         for r in range(ref.x.shape[0]):
             assert rel_err(gpu.x[r], ref.x[r]) <= 1e-9
-            assert rel_err(gpu.v[r], ref.v[r]) <= 1e-6
+            assert rel_err(gpu.x[r] - start.x[r], ref.x[r] - start.x[r]) <= 1e-9
+            worst = max(worst, rel_err(gpu.v[r], ref.v[r]))
+            assert rel_err(gpu.v[r], ref.v[r]) <= 1e-9
             assert rel_err(gpu.d1[r], ref.d1[r]) <= 1e-9
+    print(f"worst FP64 velocity error {worst:.2e}")
 
 
 def _fp32_rounded(full):
