@@ -129,6 +129,21 @@ __device__ __forceinline__ T wave_sum(T v) {
   return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
 }
 
+// slots for the active lanes of a wave whose pred holds: consecutive
+// entries of the LDS counter *ctr in lane order, one atomic per wave (the
+// leader's); -1 where pred is false
+__device__ __forceinline__ int wave_alloc(int* ctr, bool pred) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return -1;
+  const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  int base = 0;
+  if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(ctr, __popcll(m));
+  base = __shfl(base, leader, 64);
+  return pred ? base + rank : -1;
+}
+
 constexpr int XK = 12;   // largest exchange group (values)
 // moving rigid bodies: at most NB_MAX primitives on a rod with moving bodies;
 // per primitive 9 values (centre, velocity, angular velocity)

@@ -1002,6 +1002,10 @@ struct Rod {
   // counts of active pairs (this pass, first pass, adjoint's recorded
   // counts), the hash, per-edge list offsets, and the scan buffer.
   static constexpr int SC_TMP = 64;           // ints: scan and reduction slots
+  // hash: groups of 27 buckets and the padded table (more groups where the
+  // LDS has room: FP32 teams of 512 vertices and more)
+  static constexpr int SC_G = sc_groups((int)sizeof(T), NV);
+  static constexpr int SC_HT = sc_table((int)sizeof(T), NV, TL);
   // fixed part of the layout (the hash follows it, then the pair cache
   // reuses the hash's space and whatever more the launch allocates)
   static constexpr size_t sc_fixed_bytes() {
@@ -1169,7 +1173,10 @@ struct Rod {
   // candidate); every substep tests each superset pair exactly.  The
   // superset is sorted by (lower, upper) edge, so the candidate list is the
   // same whenever the superset was built.
-  __device__ T sc_skin() const { return T(0.25) * sc_cell0; }
+  // skin: half of 2 r_max + delta_c (a larger skin rebuilds less often and
+  // filters a larger superset every substep; half measured fastest of a
+  // quarter, a half and one on the 256 x 1024 helices)
+  __device__ T sc_skin() const { return T(0.5) * sc_cell0; }
   __device__ void sc_broadphase(const RodArgs<T>& a, const V3<T> (&p)[C]) {
     sc_stage(sc_pos, p);
     T d2 = T(0);
@@ -1203,10 +1210,18 @@ struct Rod {
     sc_built = true;
     if (tl == 0 && a.sc_stats) atomicAdd(a.sc_stats + 8 * rod + 2, 1ull);
 #pragma unroll
-    for (int c = 0; c < C; ++c) sc_xb[c] = p[c];
+    for (int c = 0; c < C; ++c) {
+      sc_xb[c] = p[c];
+      sc_cnt[gi(c)] = 0;   // counts of the pairs each edge is the upper edge of
+      sc_slo[gi(c)] = 0;   // and the lower edge of
+    }
     for (int i = tl; i < SC_HT; i += TL) sc_hcnt[i] = 0;
     int* lsq = sc_tmp;   // longest squared edge (bits of a non-negative real)
-    if (tl == 0) *lsq = 0;
+    int* ncand = sc_tmp + 48;   // pairs that pass the midpoint test
+    if (tl == 0) {
+      *lsq = 0;
+      *ncand = 0;
+    }
     __syncthreads();
     T l2 = T(0);
 #pragma unroll
@@ -1226,15 +1241,19 @@ struct Rod {
     const T cell0 = sc_cell0 + skin;
     // one part in 10^4 of slack keeps the 27-cell argument safe from rounding
     const T ig = frcp((cell0 + fsqrt(l2)) * T(1.0001));
+    // edge midpoints (staged in sc_aux for the search) and their buckets
     int key[C], slot[C];
+    V3<T> mid[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       key[c] = 0;
       slot[c] = 0;
+      mid[c] = zero3<T>();
       if (evalid(c)) {
         const int e = gi(c);
-        const V3<T> m = T(0.5) * (sc_at(sc_pos, e) + sc_at(sc_pos, e + 1));
-        key[c] = sc_key(sc_cell(m.x * ig), sc_cell(m.y * ig), sc_cell(m.z * ig));
+        mid[c] = T(0.5) * (sc_at(sc_pos, e) + sc_at(sc_pos, e + 1));
+        key[c] = sc_key<SC_G>(sc_cell(mid[c].x * ig), sc_cell(mid[c].y * ig),
+                              sc_cell(mid[c].z * ig));
         slot[c] = atomicAdd(&sc_hcnt[key[c]], 1);
       }
     }
@@ -1271,48 +1290,111 @@ struct Rod {
           }
           sc_items[j + 1] = v;
         }
+        // the midpoints in the same order (sc_aux), so a search reads an
+        // item's edge and midpoint independently
+        for (int i = s0; i < s1; ++i) {
+          const int j = sc_items[i];
+          const V3<T> mj = T(0.5) * (sc_at(sc_pos, j) + sc_at(sc_pos, j + 1));
+          sc_aux[3 * i] = mj.x;
+          sc_aux[3 * i + 1] = mj.y;
+          sc_aux[3 * i + 2] = mj.z;
+        }
       }
       __syncthreads();
     }
     const T margin = a.self_margin + skin;
-    // a partner's midpoint is within h_e + h_max + 2 r_max + margin of the
+    // A partner's midpoint is within h_e + h_max + 2 r_max + margin of the
     // edge's own (segment distance >= midpoint distance minus both
-    // half-lengths); the slack keeps every pair the exact test accepts
+    // half-lengths); the slack keeps every pair the exact test accepts.
+    // Each edge looks for partners above it only (j - e > K_ex), so every
+    // pair is met once, by its lower edge.  The search only lists the pairs
+    // that pass the midpoint test (LDS past the hash, then the rod's cidx
+    // block, which is free until the filter); the exact tests then run
+    // round-robin over that list, so no lane waits on another's.
     const T h_max = T(0.5) * fsqrt(l2);
     const int64_t M = sc_M;
-    int nlo[C], nhi[C];
+    int* cand = sc_items + NV;
+    const int capc = sc_cache_bytes / (int)sizeof(int) - (2 * SC_HT + 4 + NV) > 0
+                         ? sc_cache_bytes / (int)sizeof(int) - (2 * SC_HT + 4 + NV)
+                         : 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      nlo[c] = nhi[c] = 0;
-      if (!evalid(c)) continue;
       const int e = gi(c);
-      int* lo_out = g_trilo + sc_off_lo(e, M);
-      const int cap_lo = M - e > 0 ? (int)(M - e) : 0;
-      V3<T> P = sc_at(sc_pos, e), Q = sc_at(sc_pos, e + 1);
-      V3<T> m = T(0.5) * (P + Q);
-      V3<T> PQ = Q - P;
+      const int jmin = e + a.k_ex + 1;
+      // every lane runs the loops (no early exit) so the wave's slot
+      // allocations see all its lanes; lanes without work find nothing
+      const bool act = evalid(c) && jmin < N - 1;
+      const V3<T> m = mid[c];
+      const V3<T> PQ = act ? sc_at(sc_pos, e + 1) - sc_at(sc_pos, e) : zero3<T>();
       const T reach = (T(0.5) * fsqrt(dot(PQ, PQ)) + h_max + cell0) * T(1.0001) + T(1e-6);
-      const T reach2 = reach * reach;
-      const int cx = sc_cell(m.x * ig), cy = sc_cell(m.y * ig), cz = sc_cell(m.z * ig);
-      for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int kk = sc_key(cx + dx, cy + dy, cz + dz);
-            const int q1 = sc_hstart[kk + 1];
-            for (int q = sc_hstart[kk]; q < q1; ++q) {
-              const int j = sc_items[q];
-              if (!(j - e > a.k_ex || e - j > a.k_ex)) continue;
-              V3<T> mm = T(0.5) * (sc_at(sc_pos, j) + sc_at(sc_pos, j + 1)) - m;
-              if (!(dot(mm, mm) < reach2)) continue;
-              if (!sc_near(e, j, margin)) continue;
-              if (j > e) {
-                if (nlo[c] < cap_lo) lo_out[nlo[c]++] = j; else sc_flags |= 2;
-              } else {
-                ++nhi[c];
-              }
-            }
+      const T reach2 = act ? reach * reach : T(-1);
+      // the 27 cells around the edge's cell: block coordinates, residues and
+      // hash terms per axis, so a cell's bucket takes a few operations
+      int rx[3], ry[3], rz[3];
+      unsigned hx[3], hy[3], hz[3];
+      {
+        const int cc[3] = {sc_cell(m.x * ig), sc_cell(m.y * ig), sc_cell(m.z * ig)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int bx = floor_div3(cc[0] + k - 1), by = floor_div3(cc[1] + k - 1),
+                    bz = floor_div3(cc[2] + k - 1);
+          rx[k] = cc[0] + k - 1 - 3 * bx;
+          ry[k] = 3 * (cc[1] + k - 1 - 3 * by);
+          rz[k] = 9 * (cc[2] + k - 1 - 3 * bz);
+          hx[k] = (unsigned)bx * SC_H1;
+          hy[k] = (unsigned)by * SC_H2;
+          hz[k] = (unsigned)bz * SC_H3;
+        }
+      }
+      // two items per round: their loads are independent (edge and midpoint
+      // of a bucket slot), the second clamped into the bucket
+#pragma unroll 1
+      for (int d = 0; d < 27; ++d) {
+        const int ix = d % 3, iy = (d / 3) % 3, iz = d / 9;
+        const int kk = (int)((hx[ix] ^ hy[iy] ^ hz[iz]) & (unsigned)(SC_G - 1)) * 27 + rx[ix] +
+                       ry[iy] + rz[iz];
+        const int q1 = act ? sc_hstart[kk + 1] : 0;
+        for (int q = act ? sc_hstart[kk] : 0; q < q1; q += 2) {
+          const int qb = q + 1 < q1 ? q + 1 : q;
+          const int ja = sc_items[q], jb = sc_items[qb];
+          const V3<T> ma = sc_at(sc_aux, q) - m, mb = sc_at(sc_aux, qb) - m;
+          const bool pa = ja >= jmin && dot(ma, ma) < reach2;
+          const bool pb = q + 1 < q1 && jb >= jmin && dot(mb, mb) < reach2;
+          const int sa = wave_alloc(ncand, pa), sb = wave_alloc(ncand, pb);
+          if (pa) {
+            if (sa < capc) cand[sa] = (e << 16) | ja; else g_cidx[sa] = (e << 16) | ja;
           }
-      // partners in increasing order
+          if (pb) {
+            if (sb < capc) cand[sb] = (e << 16) | jb; else g_cidx[sb] = (e << 16) | jb;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const int nc = *ncand;
+      for (int k = tl; k < nc; k += TL) {
+        const int v = k < capc ? cand[k] : g_cidx[k];
+        const int e = v >> 16, j = v & 0xffff;
+        if (!sc_near(e, j, margin)) continue;
+        const int slot = atomicAdd(&sc_slo[e], 1);
+        if (slot < M - e) g_trilo[sc_off_lo(e, M) + slot] = j; else sc_flags |= 2;
+        atomicAdd(&sc_cnt[j], 1);
+      }
+    }
+    __syncthreads();
+    // each lane's lower lists: in increasing order (their fill order is that
+    // of the atomics); counts of both kinds
+    int nlo[C], nhi[C], slo = 0, shi = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int e = gi(c);
+      nlo[c] = evalid(c) ? sc_slo[e] : 0;
+      nhi[c] = sc_cnt[e];
+      sc_cnt[e] = 0;   // fill counters of the upper-edge lists
+      slo += nlo[c];
+      shi += nhi[c];
+      int* lo_out = g_trilo + sc_off_lo(e, M);
       for (int i = 1; i < nlo[c]; ++i) {
         const int v = lo_out[i];
         int j = i - 1;
@@ -1322,13 +1404,6 @@ struct Rod {
         }
         lo_out[j + 1] = v;
       }
-    }
-    int slo = 0, shi = 0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      slo += nlo[c];
-      shi += nhi[c];
-      sc_cnt[gi(c)] = 0;   // fill counters of the upper-edge lists
     }
     int elo, ehi, tlo, thi;
     sc_scan2(slo, shi, elo, ehi, tlo, thi);
@@ -1343,7 +1418,7 @@ struct Rod {
       sc_slo[NV] = tlo;
       sc_shi[NV] = thi;
     }
-    if (tlo != thi) sc_flags |= 2;   // the two directions of the search must agree
+    if (tlo != thi) sc_flags |= 2;   // every pair has one lower and one upper edge
     sc_S = tlo;
     __syncthreads();
     // compact superset; each pair also takes a place in its upper edge's list
@@ -1505,21 +1580,18 @@ struct Rod {
   __device__ __forceinline__ void sc_gather_fwd(int e, V3<T>& dA, V3<T>& dB) const {
     dA = dB = zero3<T>();
     const T wa = sc_w[e], wb = sc_w[e + 1];
-    const int k1 = sc_lo[e + 1];
-    for (int k = sc_lo[e]; k < k1; ++k) {
-      const T* r = sc_rec(k);
+    // one loop over both runs, so a wave runs as long as its edge with the
+    // most pairs: the lower-edge pairs (weights s, sign +) first, then the
+    // upper-edge pairs (weights u, sign -)
+    const int k0 = sc_lo[e], nl = sc_lo[e + 1] - k0;
+    const int q0 = sc_hi[e] - nl, n = nl + sc_hi[e + 1] - sc_hi[e];
+    for (int i = 0; i < n; ++i) {
+      const bool lo = i < nl;
+      const T* r = sc_rec(lo ? k0 + i : g_hidx[q0 + i]);
       const V3<T> kn = mk(r[0], r[1], r[2]);
-      const T s = r[3], im = r[5];
-      dA += (wa * (T(1) - s) * im) * kn;
-      dB += (wb * s * im) * kn;
-    }
-    const int q1 = sc_hi[e + 1];
-    for (int q = sc_hi[e]; q < q1; ++q) {
-      const T* r = sc_rec(g_hidx[q]);
-      const V3<T> kn = mk(r[0], r[1], r[2]);
-      const T u = r[4], im = r[5];
-      dA -= (wa * (T(1) - u) * im) * kn;
-      dB -= (wb * u * im) * kn;
+      const T t = lo ? r[3] : r[4], im = lo ? r[5] : -r[5];
+      dA += (wa * (T(1) - t) * im) * kn;
+      dB += (wb * t * im) * kn;
     }
   }
   // adjoint records (four vertex adjoints, lower edge's first) from rec
@@ -1527,17 +1599,13 @@ struct Rod {
   __device__ __forceinline__ void sc_gather_adj(int e, const T* base, V3<T>& gA,
                                                 V3<T>& gB) const {
     gA = gB = zero3<T>();
-    const int k1 = sc_lo[e + 1];
-    for (int k = sc_lo[e]; k < k1; ++k) {
-      const T* r = base + (int64_t)k * 12;
+    const int k0 = sc_lo[e], nl = sc_lo[e + 1] - k0;
+    const int q0 = sc_hi[e] - nl, n = nl + sc_hi[e + 1] - sc_hi[e];
+    for (int i = 0; i < n; ++i) {
+      const bool lo = i < nl;
+      const T* r = base + (int64_t)(lo ? k0 + i : g_hidx[q0 + i]) * 12 + (lo ? 0 : 6);
       gA += get3(r, 0);
       gB += get3(r, 3);
-    }
-    const int q1 = sc_hi[e + 1];
-    for (int q = sc_hi[e]; q < q1; ++q) {
-      const T* r = base + (int64_t)g_hidx[q] * 12;
-      gA += get3(r, 6);
-      gB += get3(r, 9);
     }
   }
 
@@ -2525,7 +2593,8 @@ __device__ __forceinline__ size_t xchg_bytes() { return W > 1 ? 2 * W * XK * siz
 
 // Forward: n_steps steps of every rod of the work list, the rod resident in
 // registers the whole time.  TAPE: store every substep-start state.  SC:
-// self-contact support (hash, partner lists and staging buffers in LDS).
+// self-contact (position staging and the pair-record cache in LDS, the
+// neighbour lists and pair lists in the rod's global pair block).
 template <typename T, int C, int W, bool TAPE, bool SC, bool TW, bool BD>
 __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];

@@ -13,10 +13,12 @@
 
 namespace rods {
 
-// hash buckets of the broadphase grid: 64 groups of 27 (SC_NKEY) are used,
-// the table is padded to a multiple of every team size
-constexpr int SC_NKEY = 64 * 27;
-constexpr int SC_HT = 2048;
+// hash buckets of the broadphase grid: G groups of 27 keys, the table
+// padded to a multiple of the team size (sc_groups, sc_table)
+__host__ __device__ constexpr int sc_groups(int tsize, int nv) { return tsize == 4 && nv >= 512 ? 256 : 64; }
+__host__ __device__ constexpr int sc_table(int tsize, int nv, int tl) {
+  return (27 * sc_groups(tsize, nv) + tl - 1) / tl * tl;
+}
 
 // one candidate pair, lower edge first (edge indices of a self-contact
 // rod, at most 1023, fit 16 bits)
@@ -321,17 +323,21 @@ __device__ __forceinline__ T pair_friction_vjp(V3<T> P1, V3<T> Q1, V3<T> P2, V3<
 
 // Bucket of grid cell (ix, iy, iz): cells are grouped in blocks of 3x3x3;
 // the cell's place in its block picks one of 27 residues and a
-// multiplicative hash of the block one of 64 groups.  Two cells of any
-// 3x3x3 neighbourhood differ by at most 2 along every axis, so their
-// residues (and keys) differ: a search over the 27 cells around a cell
-// visits every bucket at most once and finds every edge at most once.
-// Coordinates are clamped to +-2^20 cells beforehand.
+// multiplicative hash of the block one of G groups (a power of two).  Two
+// cells of any 3x3x3 neighbourhood differ by at most 2 along every axis, so
+// their residues (and keys) differ: a search over the 27 cells around a
+// cell visits every bucket at most once and finds every edge at most once.
+// Blocks that share a group share buckets, so more groups mean fewer
+// unrelated edges in a search.  Coordinates are clamped to +-2^20 cells
+// beforehand.
 __device__ __forceinline__ int floor_div3(int i) { return i >= 0 ? i / 3 : -((2 - i) / 3); }
+constexpr unsigned SC_H1 = 73856093u, SC_H2 = 19349663u, SC_H3 = 83492791u;
+template <int G>
 __device__ __forceinline__ int sc_key(int ix, int iy, int iz) {
   const int bx = floor_div3(ix), by = floor_div3(iy), bz = floor_div3(iz);
   const int res = (ix - 3 * bx) + 3 * (iy - 3 * by) + 9 * (iz - 3 * bz);
-  const unsigned g = ((unsigned)bx * 73856093u ^ (unsigned)by * 19349663u ^
-                      (unsigned)bz * 83492791u) & 63u;
+  const unsigned g = ((unsigned)bx * SC_H1 ^ (unsigned)by * SC_H2 ^ (unsigned)bz * SC_H3) &
+                     (unsigned)(G - 1);
   return (int)g * 27 + res;
 }
 template <typename T>
