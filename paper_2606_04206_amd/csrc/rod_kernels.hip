@@ -595,14 +595,14 @@ struct Rod {
   float* sc_vc;   // the adjoint's recorded per-vertex counts
   int *sc_cnt, *sc_fcnt, *sc_hcnt, *sc_hstart, *sc_items, *sc_lo, *sc_hi, *sc_slo, *sc_shi,
       *sc_tmp;
-  int *g_hdr, *g_trilo, *g_hidx, *g_suphi, *g_cidx;
+  int *g_hdr, *g_trilo, *g_hpos, *g_suphi, *g_cidx;
   SPair *g_pairs, *g_sup;
-  // the substep's pair arrays: g_pairs, g_hidx, g_d0, g_d0b and g_rec point
+  // the substep's pair arrays: g_pairs, g_hpos, g_d0, g_d0b and g_rec point
   // either into the rod's global block (gb_*) or, when the substep's pairs
   // fit, into the LDS left over past the fixed layout (the hash, dead after
   // a build, and the rest of the workgroup's allocation); g_rec2 (the
   // adjoint's friction position adjoints) stays global
-  int* gb_hidx;
+  int* gb_hpos;
   SPair* gb_pairs;
   T *gb_d0, *gb_d0b, *gb_rec, *g_rec2;
   unsigned char* sc_cache;
@@ -993,10 +993,11 @@ struct Rod {
   // scratch (sized for every admissible pair: none is ever dropped), in one
   // compact list sorted by the lower edge.  Every sweep over the pairs deals
   // them round-robin to the team's lanes, so each pair is evaluated once and
-  // the work is even across lanes; a pair's result goes to its record, and
-  // each lane then gathers the records of the pairs that touch its own
-  // edges in a fixed order (lower-edge pairs in list order, then upper-edge
-  // pairs in the order of hidx), so every sum is deterministic.
+  // the work is even across lanes; a pair's result goes to its records (one
+  // half for each of its two edges), and each lane then gathers the records
+  // of the pairs that touch its own edges in a fixed order (lower-edge pairs
+  // in list order, then upper-edge pairs in upper-edge order), so every sum
+  // is deterministic.
   //
   // LDS: staging (positions, velocities, adjoints), statics, per-vertex
   // counts of active pairs (this pass, first pass, adjoint's recorded
@@ -1049,7 +1050,7 @@ struct Rod {
     g_suphi = reinterpret_cast<int*>(g + pb.suphi);
     g_cidx = reinterpret_cast<int*>(g + pb.cidx);
     g_pairs = gb_pairs = reinterpret_cast<SPair*>(g + pb.pairs);
-    g_hidx = gb_hidx = reinterpret_cast<int*>(g + pb.hidx);
+    g_hpos = gb_hpos = reinterpret_cast<int*>(g + pb.hpos);
     g_d0 = gb_d0 = reinterpret_cast<T*>(g + pb.d0);
     g_d0b = gb_d0b = reinterpret_cast<T*>(g + pb.d0b);
     g_rec = gb_rec = reinterpret_cast<T*>(g + pb.rec);
@@ -1486,7 +1487,7 @@ struct Rod {
     if (tot <= (sc_cache_bytes - (int)sizeof(T)) / per) {
       unsigned char* c = sc_cache;
       g_pairs = reinterpret_cast<SPair*>(c); c += sizeof(SPair) * tot;
-      g_hidx = reinterpret_cast<int*>(c); c += sizeof(int) * tot;
+      g_hpos = reinterpret_cast<int*>(c); c += sizeof(int) * tot;
       c = sc_cache + (c - sc_cache + sizeof(T) - 1) / sizeof(T) * sizeof(T);
       g_d0 = reinterpret_cast<T*>(c); c += sizeof(T) * tot;
       if (adj) {
@@ -1496,7 +1497,7 @@ struct Rod {
       g_rec = reinterpret_cast<T*>(c);
     } else {
       g_pairs = gb_pairs;
-      g_hidx = gb_hidx;
+      g_hpos = gb_hpos;
       g_d0 = gb_d0;
       g_d0b = gb_d0b;
       g_rec = gb_rec;
@@ -1549,7 +1550,7 @@ struct Rod {
       const int q1 = sc_shi[e + 1];
       for (int q = sc_shi[e]; q < q1; ++q) {
         const int k = g_cidx[g_suphi[q]];
-        if (k >= 0) g_hidx[o++] = k;
+        if (k >= 0) g_hpos[k] = o++;
       }
       if (o != sc_hi[e] + nhi[c]) sc_flags |= 2;
     }
@@ -1570,40 +1571,57 @@ struct Rod {
     const T m = (T)(a0 > a1 ? a0 : a1);
     return m > T(1) ? m : T(1);
   }
-  // Per-pair records (sc_rv values at g_rec[k * rv]) and the fixed-order
-  // gather of the pairs touching an own edge: its pairs as lower edge (a
-  // contiguous run of the list), then as upper edge (its run of g_hidx, in
-  // list order).  Inactive pairs have zero records.
-  __device__ __forceinline__ T* sc_rec(int k) const { return g_rec + (int64_t)k * sc_rv; }
-  // forward records (k n or dv_t, s, u, reciprocal divisor): the
-  // corrections of own edge e's two vertices, summed
+  // Per-pair records: the lower edge's half (sc_rv / 2 values) at the
+  // pair's place k in the list, the upper edge's half at its place in
+  // upper-edge order (g_hpos[k]) after all lower halves; rec2 likewise.
+  // Each own edge then sums its lower-edge run and its upper-edge run of
+  // records, both contiguous, in a fixed order.
+  __device__ __forceinline__ T* sc_rlo(T* base, int k) const {
+    return base + (int64_t)k * (sc_rv / 2);
+  }
+  __device__ __forceinline__ T* sc_rhi(T* base, int k) const {
+    return base + ((int64_t)sc_P + g_hpos[k]) * (sc_rv / 2);
+  }
+  // forward records (k n or dv_t, the edge's parameter s or u, reciprocal
+  // divisor): the corrections of own edge e's two vertices, summed
   __device__ __forceinline__ void sc_gather_fwd(int e, V3<T>& dA, V3<T>& dB) const {
     dA = dB = zero3<T>();
     const T wa = sc_w[e], wb = sc_w[e + 1];
-    // one loop over both runs, so a wave runs as long as its edge with the
-    // most pairs: the lower-edge pairs (weights s, sign +) first, then the
-    // upper-edge pairs (weights u, sign -)
-    const int k0 = sc_lo[e], nl = sc_lo[e + 1] - k0;
-    const int q0 = sc_hi[e] - nl, n = nl + sc_hi[e + 1] - sc_hi[e];
-    for (int i = 0; i < n; ++i) {
-      const bool lo = i < nl;
-      const T* r = sc_rec(lo ? k0 + i : g_hidx[q0 + i]);
+    const int RL = sc_rv / 2;   // 5 in the forward kernels, 6 in the adjoint's replay
+    const int k1 = sc_lo[e + 1];
+    for (int k = sc_lo[e]; k < k1; ++k) {
+      const T* r = g_rec + (int64_t)k * RL;
       const V3<T> kn = mk(r[0], r[1], r[2]);
-      const T t = lo ? r[3] : r[4], im = lo ? r[5] : -r[5];
-      dA += (wa * (T(1) - t) * im) * kn;
-      dB += (wb * t * im) * kn;
+      const T s = r[3], im = r[4];
+      dA += (wa * (T(1) - s) * im) * kn;
+      dB += (wb * s * im) * kn;
+    }
+    const T* rh = g_rec + (int64_t)sc_P * RL;
+    const int q1 = sc_hi[e + 1];
+    for (int q = sc_hi[e]; q < q1; ++q) {
+      const T* r = rh + (int64_t)q * RL;
+      const V3<T> kn = mk(r[0], r[1], r[2]);
+      const T u = r[3], im = r[4];
+      dA -= (wa * (T(1) - u) * im) * kn;
+      dB -= (wb * u * im) * kn;
     }
   }
-  // adjoint records (four vertex adjoints, lower edge's first) from rec
-  // (off = 0) or rec2: the sums for own edge e's two vertices
+  // adjoint records (the two vertex adjoints of the edge; the adjoint
+  // kernel's halves are 6 values) from rec or rec2: the sums for own edge
+  // e's two vertices
   __device__ __forceinline__ void sc_gather_adj(int e, const T* base, V3<T>& gA,
                                                 V3<T>& gB) const {
     gA = gB = zero3<T>();
-    const int k0 = sc_lo[e], nl = sc_lo[e + 1] - k0;
-    const int q0 = sc_hi[e] - nl, n = nl + sc_hi[e + 1] - sc_hi[e];
-    for (int i = 0; i < n; ++i) {
-      const bool lo = i < nl;
-      const T* r = base + (int64_t)(lo ? k0 + i : g_hidx[q0 + i]) * 12 + (lo ? 0 : 6);
+    const int k1 = sc_lo[e + 1];
+    for (int k = sc_lo[e]; k < k1; ++k) {
+      const T* r = base + (int64_t)k * 6;
+      gA += get3(r, 0);
+      gB += get3(r, 3);
+    }
+    const T* rh = base + (int64_t)sc_P * 6;
+    const int q1 = sc_hi[e + 1];
+    for (int q = sc_hi[e]; q < q1; ++q) {
+      const T* r = rh + (int64_t)q * 6;
       gA += get3(r, 0);
       gB += get3(r, 3);
     }
@@ -1631,12 +1649,13 @@ struct Rod {
       PairGeo<T> g = sc_pair(sc_pos, pr.lo, pr.hi);
       if (first) g_d0[k] = g.act ? g.d : T(0);
       const T kk = g.act ? fdiv(g.d, g.W) : T(0);
-      T* r = sc_rec(k);
-      r[0] = kk * g.n.x;
-      r[1] = kk * g.n.y;
-      r[2] = kk * g.n.z;
-      r[3] = g.cp.s;
-      r[4] = g.cp.u;
+      const V3<T> kn = kk * g.n;
+      T* rl = sc_rlo(g_rec, k);
+      T* rh = sc_rhi(g_rec, k);
+      put3(rl, 0, kn);
+      rl[3] = g.cp.s;
+      put3(rh, 0, kn);
+      rh[3] = g.cp.u;
       if (g.act) {
         ++st_act;
         atomicAdd(&sc_cnt[pr.lo], 1);
@@ -1649,7 +1668,9 @@ struct Rod {
     // sweep 2: the pair's divisor, from the completed counts
     for (int k = tl; k < sc_P; k += TL) {
       const SPair pr = g_pairs[k];
-      sc_rec(k)[5] = frcp(sc_divisor(sc_cnt, pr.lo, pr.hi));
+      const T im = frcp(sc_divisor(sc_cnt, pr.lo, pr.hi));
+      sc_rlo(g_rec, k)[4] = im;
+      sc_rhi(g_rec, k)[4] = im;
     }
     if (first) {
 #pragma unroll
@@ -1704,11 +1725,14 @@ struct Rod {
           iW = frcp(f.g.W * sc_divisor(sc_fcnt, lo, hi));
         }
       }
-      T* r = sc_rec(k);
-      put3(r, 0, dvt);
-      r[3] = s;
-      r[4] = u;
-      r[5] = iW;
+      T* rl = sc_rlo(g_rec, k);
+      T* rh = sc_rhi(g_rec, k);
+      put3(rl, 0, dvt);
+      rl[3] = s;
+      rl[4] = iW;
+      put3(rh, 0, dvt);
+      rh[3] = u;
+      rh[4] = iW;
     }
     __syncthreads();
     V3<T> dA[C], dB[C];
@@ -1758,10 +1782,12 @@ struct Rod {
         }
       }
       g_d0b[k] = d0b;
-      T* o = sc_rec(k);
-      put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, b2); put3(o, 9, b3);
-      T* o2 = g_rec2 + (int64_t)k * 12;
-      put3(o2, 0, q0); put3(o2, 3, q1); put3(o2, 6, q2); put3(o2, 9, q3);
+      T* ol = sc_rlo(g_rec, k);
+      T* oh = sc_rhi(g_rec, k);
+      put3(ol, 0, b0); put3(ol, 3, b1); put3(oh, 0, b2); put3(oh, 3, b3);
+      ol = sc_rlo(g_rec2, k);
+      oh = sc_rhi(g_rec2, k);
+      put3(ol, 0, q0); put3(ol, 3, q1); put3(oh, 0, q2); put3(oh, 3, q3);
     }
     __syncthreads();
     V3<T> vA[C], vB[C], xA[C], xB[C];
@@ -1816,8 +1842,9 @@ struct Rod {
                            d0b, b0, b1, b2, b3);
         }
       }
-      T* o = sc_rec(k);
-      put3(o, 0, b0); put3(o, 3, b1); put3(o, 6, b2); put3(o, 9, b3);
+      T* ol = sc_rlo(g_rec, k);
+      T* oh = sc_rhi(g_rec, k);
+      put3(ol, 0, b0); put3(ol, 3, b1); put3(oh, 0, b2); put3(oh, 3, b3);
     }
     __syncthreads();
     V3<T> cA[C], cB[C];

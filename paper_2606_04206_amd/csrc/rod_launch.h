@@ -8,7 +8,7 @@ namespace rods {
 
 // which: 0 = forward, 1 = forward writing the substep tape, 2 = adjoint
 // SC: rods with self-contact (their pair scratch in a.pblk / a.pblk_off,
-//     blocks laid out by sc_block with SC_RV_FWD values per pair record
+//     blocks laid out by sc_block with SC_RV_FWD values per pair of records
 //     for kinds 0 and 1, SC_RV_ADJ for kind 2)
 // GT: the adjoint keeps a substep's projection iterates in the rod's block
 //     of global scratch (sc_tape/sc_off) rather than in LDS (implied by SC)

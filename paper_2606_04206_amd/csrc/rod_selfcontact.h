@@ -26,10 +26,15 @@ struct alignas(4) SPair {
   short lo, hi;
 };
 
-// values of a pair's record: forward kernels 6 (k n, s, u and the
-// reciprocal divisor, from which both edges' corrections follow), the
-// adjoint 12 (the adjoints of the four vertices' positions or velocities)
-constexpr int SC_RV_FWD = 6, SC_RV_ADJ = 12;
+// values per pair of the per-pair records, in two halves: the lower edge's
+// half at the pair's place in the list, the upper edge's half at the pair's
+// place in upper-edge order, so each edge gathers both kinds from contiguous
+// runs.  Forward kernels 2 x 5 (k n, the edge's closest-point parameter s
+// or u, the reciprocal divisor); the adjoint 2 x 6 (the adjoints of the
+// edge's two vertices)
+constexpr int SC_RV_FWD = 10, SC_RV_ADJ = 12;
+static_assert(SC_RV_ADJ / 2 == 6 && SC_RV_ADJ / 2 >= SC_RV_FWD / 2,
+              "the adjoint's record halves hold six values and a forward half");
 
 // Largest number of admissible pairs (j - i > k_ex) among the n - 1 edges of
 // a rod of n vertices: the pair scratch has room for all of them, so no
@@ -53,13 +58,12 @@ __host__ __device__ inline int64_t sc_off_hi(int64_t e, int64_t k_ex) {
 // slots), the compact superset (sup, sorted by lower and then upper edge),
 // per edge the sorted superset indices of the pairs it is the upper edge of
 // (suphi), and each superset pair's place in the substep's list or -1
-// (cidx); the substep's compact pair list (sorted likewise), per edge the
-// indices of the pairs it is the upper edge of (hidx), the first-pass
-// depths d0, their adjoints d0b, rv values of per-pair results, and (the
-// adjoint's blocks, rv = SC_RV_ADJ) 12 more per pair for the position
-// adjoints of friction
+// (cidx); the substep's compact pair list (sorted likewise), each pair's
+// place in upper-edge order (hpos), the first-pass depths d0, their
+// adjoints d0b, rv values of per-pair records, and (the adjoint's blocks,
+// rv = SC_RV_ADJ) 12 more per pair for the position adjoints of friction
 struct PairBlock {
-  int64_t trilo, sup, suphi, cidx, pairs, hidx, d0, d0b, rec, rec2, bytes;
+  int64_t trilo, sup, suphi, cidx, pairs, hpos, d0, d0b, rec, rec2, bytes;
 };
 __host__ __device__ inline int64_t sc_align(int64_t b) { return (b + 255) / 256 * 256; }
 __host__ __device__ inline PairBlock sc_block(int n, int k_ex, int tsize, int rv) {
@@ -71,7 +75,7 @@ __host__ __device__ inline PairBlock sc_block(int n, int k_ex, int tsize, int rv
   b.suphi = o; o = sc_align(o + 4 * P);
   b.cidx = o;  o = sc_align(o + 4 * P);
   b.pairs = o; o = sc_align(o + 4 * P);
-  b.hidx = o;  o = sc_align(o + 4 * P);
+  b.hpos = o;  o = sc_align(o + 4 * P);
   b.d0 = o;    o = sc_align(o + (int64_t)tsize * P);
   b.d0b = o;   o = sc_align(o + (int64_t)tsize * P);
   b.rec = o;   o = sc_align(o + (int64_t)tsize * rv * P);
