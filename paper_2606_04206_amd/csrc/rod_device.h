@@ -129,6 +129,14 @@ __device__ __forceinline__ T wave_sum(T v) {
   return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
 }
 
+// a product the compiler may not fuse into a following add (kept where a
+// value must round exactly as it does when computed in another lane)
+template <typename T>
+__device__ __forceinline__ T mul_nc(T a, T b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
 // slots for the active lanes of a wave whose pred holds: consecutive
 // entries of the LDS counter *ctr in lane order, one atomic per wave (the
 // leader's); -1 where pred is false
@@ -207,6 +215,42 @@ struct Team {
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = r[k];
+  }
+  // both directions with one barrier: a[k] <- a[k] of team lane - 1 (0
+  // before the team's start), b[k] <- b[k] of team lane + 1 (0 past its end)
+  template <int KA, int KB>
+  __device__ __forceinline__ void swap(T (&a)[KA], T (&b)[KB]) {
+    static_assert(KA + KB <= XK, "exchange group too large");
+    T ra[KA], rb[KB];
+#pragma unroll
+    for (int k = 0; k < KA; ++k) ra[k] = dpp_from_prev(a[k]);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) rb[k] = dpp_from_next(b[k]);
+    if constexpr (W > 1) {
+      T* buf2 = buf + pp * (W * XK);
+      if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < KA; ++k) buf2[wave * XK + k] = a[k];
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k) buf2[wave * XK + KA + k] = b[k];
+      }
+      __syncthreads();
+      if (lane == 0 && wave > 0) {
+#pragma unroll
+        for (int k = 0; k < KA; ++k) ra[k] = buf2[(wave - 1) * XK + k];
+      }
+      if (lane == 63 && wave + 1 < W) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k) rb[k] = buf2[(wave + 1) * XK + KA + k];
+      }
+      pp ^= 1;
+    }
+#pragma unroll
+    for (int k = 0; k < KA; ++k) a[k] = ra[k];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) b[k] = rb[k];
   }
   // v[k] <- sum of v[k] over the team, in every lane (K <= XK): wave_sum in
   // each wave, then the W wave sums through LDS in wave order, so every

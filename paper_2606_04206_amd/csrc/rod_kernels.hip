@@ -623,6 +623,10 @@ struct Rod {
   T b, sig, rc, mu, e, K;
   T w[C], rest[C], lbar[C], ks[C], rad[C];
   T aj[C], ak[C];   // projection ratios w_j/W, w_k/W of the edge starting at vertex c
+  // multi-wave teams: the previous lane's last edge (rest length, ratios,
+  // edge vector at the predicted positions), which both of its lanes project
+  T restp, ajp, akp;
+  V3<T> E0p;
   T coef[C], ilbar[C];   // b / l_bar and 1 / l_bar at interior vertices, else 0
   // the forward (no recording) carries a substep's end geometry into the
   // next substep: the same values edges() and prev_edge() would recompute
@@ -727,6 +731,13 @@ struct Rod {
         tcoef[c] = ivalid(c) ? a.Gt[rod] * T(3.14159265358979323846) * r2 * r2 / T(2) * ilbar[c]
                              : T(0);
       }
+    }
+    if constexpr (W > 1) {
+      T q[3] = {rest[C - 1], aj[C - 1], ak[C - 1]};
+      X.prev(q);
+      restp = q[0];
+      ajp = q[1];
+      akp = q[2];
     }
   }
 
@@ -880,6 +891,11 @@ struct Rod {
         E0[c] = evalid(c) ? (c < C - 1 ? p0[c + 1] : mk(pn[0], pn[1], pn[2])) - p0[c]
                           : mk(T(1), T(0), T(0));
     }
+    if constexpr (W > 1) {
+      T ep[3] = {E0[C - 1].x, E0[C - 1].y, E0[C - 1].z};
+      X.prev(ep);
+      E0p = mk(ep[0], ep[1], ep[2]);
+    }
     for (int it = 0; it < a.n_iters; ++it) {
       if (inext) project_iter<REC>(X, E0, dl, lds_tape, it);
       if constexpr (SC) {
@@ -913,19 +929,38 @@ struct Rod {
       T il = proj_edge(c, E0[c], dl[c], dl[c + 1], D);
       if constexpr (REC) tape_put(lds_tape, it, c, D, il);
     }
-    // the lane's last (black) edge reaches into the next lane: project it
-    // here and send the next lane its endpoint's move
-    T dn[3] = {dl[0].x, dl[0].y, dl[0].z};
-    X.next(dn);
-    D = E0[C - 1] + (mk(dn[0], dn[1], dn[2]) - dl[C - 1]);
-    T il = frsq(dot(D, D));
-    T sc = T(1) - rest[C - 1] * il;
-    dl[C - 1] += (sc * aj[C - 1]) * D;
-    if constexpr (REC) tape_put(lds_tape, it, C - 1, D, il);
-    const T mk_ = -(sc * ak[C - 1]);
-    T mv[3] = {mk_ * D.x, mk_ * D.y, mk_ * D.z};
-    X.prev(mv);
-    dl[0] += mk(mv[0], mv[1], mv[2]);
+    // the lane's last (black) edge reaches into the next lane.  One wave:
+    // project it here and send the next lane its endpoint's move.  Several
+    // waves (a barrier per exchange): both lanes of the edge project it from
+    // the same operands, after one exchange in both directions.
+    if constexpr (W == 1) {
+      T dn[3] = {dl[0].x, dl[0].y, dl[0].z};
+      X.next(dn);
+      D = E0[C - 1] + (mk(dn[0], dn[1], dn[2]) - dl[C - 1]);
+      T il = frsq(dot(D, D));
+      T sc = T(1) - rest[C - 1] * il;
+      dl[C - 1] += (sc * aj[C - 1]) * D;
+      if constexpr (REC) tape_put(lds_tape, it, C - 1, D, il);
+      const T mk_ = -(sc * ak[C - 1]);
+      T mv[3] = {mk_ * D.x, mk_ * D.y, mk_ * D.z};
+      X.prev(mv);
+      dl[0] += mk(mv[0], mv[1], mv[2]);
+    } else {
+      T up[3] = {dl[C - 1].x, dl[C - 1].y, dl[C - 1].z};
+      T dn[3] = {dl[0].x, dl[0].y, dl[0].z};
+      X.swap(up, dn);
+      D = E0[C - 1] + (mk(dn[0], dn[1], dn[2]) - dl[C - 1]);
+      const T il = frsq(dot(D, D));
+      const T sc = T(1) - rest[C - 1] * il;
+      const V3<T> Dp = E0p + (dl[0] - mk(up[0], up[1], up[2]));
+      const T ilp = frsq(dot(Dp, Dp));
+      const T scp = T(1) - restp * ilp;
+      const T mk_ = -(scp * akp);
+      const V3<T> mv = mk(mul_nc(mk_, Dp.x), mul_nc(mk_, Dp.y), mul_nc(mk_, Dp.z));
+      dl[C - 1] += (sc * aj[C - 1]) * D;
+      if constexpr (REC) tape_put(lds_tape, it, C - 1, D, il);
+      if (tl > 0) dl[0] += mv;
+    }
   }
 
   __device__ __forceinline__ void tape_load(const T* tape, int it, Q4<T> (&q)[C]) const {
@@ -962,16 +997,29 @@ struct Rod {
 
   __device__ void project_iter_vjp(Team<T, W>& X, V3<T> (&pb)[C], const Q4<T> (&rec)[C]) const {
     // the cross-lane black edge: its far endpoint's adjoint comes from the
-    // next lane, the edge adjoint goes back to it
-    T an[3] = {pb[0].x, pb[0].y, pb[0].z};
-    X.next(an);
+    // next lane, the edge adjoint goes back to it (several waves: both
+    // lanes evaluate it, after one exchange in both directions)
     const Q4<T>& q = rec[C - 1];
-    V3<T> Db = project_edge_vjp(mk(q.x, q.y, q.z), q.w, aj[C - 1], ak[C - 1], rest[C - 1],
-                                pb[C - 1], mk(an[0], an[1], an[2]));
-    pb[C - 1] -= Db;
-    T s[3] = {Db.x, Db.y, Db.z};
-    X.prev(s);
-    pb[0] += mk(s[0], s[1], s[2]);
+    if constexpr (W == 1) {
+      T an[3] = {pb[0].x, pb[0].y, pb[0].z};
+      X.next(an);
+      V3<T> Db = project_edge_vjp(mk(q.x, q.y, q.z), q.w, aj[C - 1], ak[C - 1], rest[C - 1],
+                                  pb[C - 1], mk(an[0], an[1], an[2]));
+      pb[C - 1] -= Db;
+      T s[3] = {Db.x, Db.y, Db.z};
+      X.prev(s);
+      pb[0] += mk(s[0], s[1], s[2]);
+    } else {
+      T up[7] = {pb[C - 1].x, pb[C - 1].y, pb[C - 1].z, q.x, q.y, q.z, q.w};
+      T an[3] = {pb[0].x, pb[0].y, pb[0].z};
+      X.swap(up, an);
+      const V3<T> Db = project_edge_vjp(mk(q.x, q.y, q.z), q.w, aj[C - 1], ak[C - 1],
+                                        rest[C - 1], pb[C - 1], mk(an[0], an[1], an[2]));
+      const V3<T> Dbp = project_edge_vjp(mk(up[3], up[4], up[5]), up[6], ajp, akp, restp,
+                                         mk(up[0], up[1], up[2]), pb[0]);
+      pb[C - 1] -= Db;
+      if (tl > 0) pb[0] += Dbp;
+    }
 #pragma unroll
     for (int c = 1; c < C - 1; c += 2) {   // black edges inside the lane
       V3<T> db = project_edge_vjp(mk(rec[c].x, rec[c].y, rec[c].z), rec[c].w, aj[c], ak[c],
