@@ -217,6 +217,19 @@ int rods_curvature(RodsHandle* h, const void* x, const void* d1, void* kappa,
  * Does not record.  Safe to capture in a HIP graph. */
 int rods_step(RodsHandle* h, const void* grasp_vel, rods_stream_t stream);
 
+/* rods_step, also logging the step's discrete decisions (the branches of
+ * Section 3.1's plastic update, Section 3.2's contact test and App. A.1's
+ * self-collision test) for parity checks: branch (device) [V] uint32 per
+ * vertex, for the step's last substep: bit0 the vertex yielded (strict
+ * |kappa_el| > sigma_y l_bar); bit 1 + k rigid contact was active with
+ * primitive k of the rod's scene (f > f_thresh and v_n < 0; k < 15); bits
+ * 16-23 the number of self-contact pairs with positive depth touching the
+ * vertex in the first projection pass (saturated at 255).  Rows of padding
+ * are not written.  The kernels are those of rods_step.  ROD_EINVAL for a
+ * NULL branch. */
+int rods_step_branches(RodsHandle* h, const void* grasp_vel, uint32_t* branch,
+                       rods_stream_t stream);
+
 /* Same as rods_step, replayed from a HIP graph of the step's kernel launches
  * (captured on the first call and after rods_autotune or rods_set_plain; the
  * graph works on the handle's own buffers).  The action is copied into the

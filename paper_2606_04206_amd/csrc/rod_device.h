@@ -347,6 +347,11 @@ struct RodArgs {
                             // pair-passes, pairs in friction
   int32_t sc_lds;           // self-contact launches: dynamic LDS bytes (the host's
                             // offer; the launch sets the amount it allocates)
+  uint32_t* branch;         // [V] (nullable) discrete decisions of each vertex's last
+                            // forward substep: bit0 yield, bit 1 + k rigid contact
+                            // with primitive k of the rod (k < 15), bits 16-23 the
+                            // active self-contact pairs at the vertex in the first
+                            // projection pass (at most 255)
   int32_t* status;          // [R] bit0 non-finite, bit1 pair bookkeeping fault, bit2 stretched edge
   // twist degree of freedom (rods with the twist flag; edge rows)
   const T* Gt;              // [R] twisting modulus

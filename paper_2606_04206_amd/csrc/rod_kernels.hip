@@ -1963,6 +1963,10 @@ struct Rod {
     const T h = a.h;
     const T ih = T(1) / h;
     const V3<T> g = mk(a.gx, a.gy, a.gz);
+    // discrete decisions of this substep, for the optional branch log
+    uint32_t bits[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) bits[c] = 0u;
     // S2 forces at x with frames fixed
     V3<T> t[C];
     T l[C], il[C];
@@ -2092,7 +2096,9 @@ struct Rod {
         if (!(BD && dyn && a.bw[k] > T(0))) {
 #pragma unroll
           for (int c = 0; c < C; ++c)
-            if (w[c] > T(0)) contact_one(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, v[c]);
+            if (w[c] > T(0) &&
+                contact_one(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, v[c]) && k - p0 < 15)
+              bits[c] |= 2u << (k - p0);
         } else {
           T* bk = bs + (k - p0) * NB_VALS;
           pr.a = V3<T>{bk[0], bk[1], bk[2]};
@@ -2103,8 +2109,10 @@ struct Rod {
             if (w[c] > T(0)) {
               const V3<T> vin = v[c];
               V3<T> n;
-              if (contact_moving(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, Vb, Om, v[c], n) &&
-                  !REC) {
+              const bool hit =
+                  contact_moving(pr, x[c], rad[c], mu, e, a.eps_s, a.f_thresh, Vb, Om, v[c], n);
+              if (hit && k - p0 < 15) bits[c] |= 2u << (k - p0);
+              if (hit && !REC) {
                 const V3<T> dp = (T(1) / w[c]) * (v[c] - vin);
                 const V3<T> lm = cross(pr.r * n, dp);
                 acc[0] += dp.x; acc[1] += dp.y; acc[2] += dp.z;
@@ -2151,6 +2159,15 @@ struct Rod {
     }
     // S7 projections
     if ((flags & FLAG_INEXT) || self_on) project<REC>(a, X, p0, dl, lds_tape);
+    if constexpr (SC) {
+      if (self_on && a.n_iters > 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int n1 = sc_fcnt[gi(c)];
+          bits[c] |= (uint32_t)(n1 < 255 ? n1 : 255) << 16;
+        }
+      }
+    }
     // S8 velocity update from the corrections
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -2236,7 +2253,13 @@ struct Rod {
         }
         kr0[c] += phi * e0;
         kr1[c] += phi * e1;
+        if (y) bits[c] |= 1u;
       }
+    }
+    if (!REC && a.branch) {
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (vvalid(c)) a.branch[v0 + gi(c)] = bits[c];
     }
   }
 

@@ -679,9 +679,10 @@ struct Impl : HandleBase {
     return ROD_OK;
   }
 
-  int step(const T* u, hipStream_t st) {
+  int step(const T* u, hipStream_t st, uint32_t* branch = nullptr) {
     RodArgs<T> a = args(st);
     a.u = u;
+    a.branch = branch;
     a.act_stride = 0;
     a.spa = 1;
     a.step_off = 0;
@@ -1274,6 +1275,16 @@ int rods_step(RodsHandle* h, const void* grasp_vel, rods_stream_t stream) {
     using T = std::remove_pointer_t<decltype(I->x)>;
     if (I->G > 0 && !grasp_vel) return (int)ROD_EINVAL;
     return I->step((const T*)grasp_vel, (hipStream_t)stream);
+  });
+}
+
+int rods_step_branches(RodsHandle* h, const void* grasp_vel, uint32_t* branch,
+                       rods_stream_t stream) {
+  if (!h || !branch) return ROD_EINVAL;
+  return dispatch(h, [&](auto* I) {
+    using T = std::remove_pointer_t<decltype(I->x)>;
+    if (I->G > 0 && !grasp_vel) return (int)ROD_EINVAL;
+    return I->step((const T*)grasp_vel, (hipStream_t)stream, branch);
   });
 }
 

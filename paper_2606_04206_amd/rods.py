@@ -45,7 +45,8 @@ class RodsAdam(ctypes.Structure):
 EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "rods_get_state",
            "rods_set_twist", "rods_get_twist", "rods_set_bodies", "rods_get_bodies",
            "rods_set_body_adjoint", "rods_get_body_adjoint", "rods_set_params", "rods_get_params",
-           "rods_optimize", "rods_curvature", "rods_step", "rods_step_graph", "rods_rollout",
+           "rods_optimize", "rods_curvature", "rods_step", "rods_step_branches", "rods_step_graph",
+           "rods_rollout",
            "rods_backward",
            "rods_loss_mse", "rods_status", "rods_bins", "rods_autotune", "rods_set_launch_shape",
            "rods_set_plain",
@@ -88,6 +89,7 @@ def load():
         "rods_curvature": ([vp, vp, vp, vp, vp], c_int32),
         "rods_step": ([vp, vp, vp], c_int32),
         "rods_step_graph": ([vp, vp, vp], c_int32),
+        "rods_step_branches": ([vp, vp, vp, vp], c_int32),
         "rods_rollout": ([vp, c_int32, vp, vp, c_int32, vp], c_int32),
         "rods_backward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], c_int32),
         "rods_loss_mse": ([vp, vp, vp, vp, vp, vp], c_int32),
@@ -309,9 +311,16 @@ class RodsHandle:
                "rods_curvature")
         return k
 
-    def step(self, u):
+    def step(self, u, branches=None):
+        """One step; with `branches` (an int32 CUDA tensor [V]) the step's
+        discrete decisions are logged there (rods_step_branches)."""
         _require(u, (self.R, self.G, 3), self.dtype, "grasp_vel")
-        _check(self._lib.rods_step(self._h, _ptr(u), _stream()), "rods_step")
+        if branches is None:
+            _check(self._lib.rods_step(self._h, _ptr(u), _stream()), "rods_step")
+        else:
+            _require(branches, (self.V,), torch.int32, "branches")
+            _check(self._lib.rods_step_branches(self._h, _ptr(u), _ptr(branches), _stream()),
+                   "rods_step_branches")
 
     def step_graph(self, u):
         _require(u, (self.R, self.G, 3), self.dtype, "grasp_vel")
