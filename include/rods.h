@@ -70,8 +70,8 @@ enum {
  * edge carries a twist angle theta^j of its material frame against the
  * reference frame and an angular rate, stepped by the same symplectic Euler
  * as the vertices under -dU/dtheta (twisting energy U_t with zero rest
- * twist, bending energy through the material frames).  Not combined with
- * ROD_FLAG_SELF; rods of up to 1024 vertices. */
+ * twist, bending energy through the material frames).  May be combined
+ * with ROD_FLAG_SELF; rods of up to 1024 vertices. */
 #define ROD_FLAG_TWIST 8
 
 enum { ROD_PRIM_PLANE = 0, ROD_PRIM_SPHERE = 1, ROD_PRIM_CAPSULE = 2 };

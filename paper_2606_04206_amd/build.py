@@ -22,6 +22,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 UNITS = [("rod_kernels.hip", [], "rod_kernels.o"),
          ("rod_kernels.hip", ["-DRODS_TU=1"], "rod_kernels_twist.o"),
          ("rod_kernels.hip", ["-DRODS_TU=2"], "rod_kernels_sc.o"),
+         ("rod_kernels.hip", ["-DRODS_TU=3"], "rod_kernels_sctw.o"),
          ("rod_optim.hip", [], "rod_optim.o"),
          ("rod_loss.hip", [], "rod_loss.o"),
          ("rods_api.cpp", [], "rods_api.o")]

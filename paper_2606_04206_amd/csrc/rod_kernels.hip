@@ -8,9 +8,10 @@
 // iteration of the inextensibility projection needs exactly one neighbour
 // exchange pair (positions to the left, corrections to the right).
 //
-// The file is compiled three times: RODS_TU = 1 instantiates the kernels of
+// The file is compiled four times: RODS_TU = 1 instantiates the kernels of
 // rods with the twist degree of freedom, RODS_TU = 2 those of rods with
-// self-contact, the default everything else.
+// self-contact, RODS_TU = 3 those of rods with both, the default everything
+// else.
 //
 // Physics (DLO-Lab, Section 3.1 and Appendix A.1): bending forces of the
 // discrete elastic rod with frames held fixed, stretching forces for
@@ -2752,7 +2753,6 @@ __global__ __launch_bounds__(64 * W) void k_forward(RodArgs<T> a) {
 template <typename T, int C, int W, bool SC, bool GT, bool TW, bool BD>
 __global__ __launch_bounds__(64 * W) void k_adjoint(RodArgs<T> a) {
   static_assert(GT || !SC, "self-contact keeps the iterates in global scratch");
-  static_assert(!(SC && TW), "no kernels for twist with self-contact");
   extern __shared__ __align__(16) unsigned char smem[];
   Team<T, W> X;
   X.init(reinterpret_cast<T*>(smem));
@@ -3022,7 +3022,7 @@ static hipError_t launch_shape(int which, bool gt, const RodArgs<T>& a, int n_bl
   } else if (which == 1) {
     go(k_forward<T, C, W, true, SC, TW, BD>);
   } else if constexpr (SC) {
-    go(k_adjoint<T, C, W, true, true, false, false>);
+    go(k_adjoint<T, C, W, true, true, TW, false>);
   } else {
     if (gt) go(k_adjoint<T, C, W, false, true, TW, BD>);
     else go(k_adjoint<T, C, W, false, false, TW, BD>);
@@ -3080,6 +3080,24 @@ template hipError_t launch_rods_sc<double>(int, int, int, const RodArgs<double>&
                                            hipStream_t);
 template size_t sc_lds_bytes<float>(int, int);
 template size_t sc_lds_bytes<double>(int, int);
+#elif RODS_TU == 3
+// Rods with the twist degree of freedom and self-contact: two vertices per
+// lane, 1-8 waves (this translation unit instantiates only these kernels).
+template <typename T>
+hipError_t launch_rods_sc_twist(int which, int C, int W, const RodArgs<T>& a, int n_blocks,
+                                hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  if (C != 2) return hipErrorInvalidValue;
+  if (W == 1) return launch_shape<T, 2, 1, true, true>(which, true, a, n_blocks, st);
+  if (W == 2) return launch_shape<T, 2, 2, true, true>(which, true, a, n_blocks, st);
+  if (W == 4) return launch_shape<T, 2, 4, true, true>(which, true, a, n_blocks, st);
+  if (W == 8) return launch_shape<T, 2, 8, true, true>(which, true, a, n_blocks, st);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_rods_sc_twist<float>(int, int, int, const RodArgs<float>&, int,
+                                                hipStream_t);
+template hipError_t launch_rods_sc_twist<double>(int, int, int, const RodArgs<double>&, int,
+                                                 hipStream_t);
 #else
 template <typename T>
 hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<T>& a,

@@ -545,6 +545,7 @@ struct Impl : HandleBase {
 
   static hipError_t launch_bin(int which, const Bin& bn, int C, int W, bool gt,
                                const RodArgs<T>& a, int n, hipStream_t st) {
+    if (bn.tw && bn.sc) return rods::launch_rods_sc_twist<T>(which, C, W, a, n, st);
     if (bn.tw) return rods::launch_rods_twist<T>(which, C, W, gt, a, n, st);
     if (bn.bd) return rods::launch_rods_bodies<T>(which, C, W, gt, a, n, st);
     return rods::launch_rods<T>(which, C, W, bn.sc, gt, a, n, st);
@@ -1026,9 +1027,9 @@ static int validate(const RodsDesc* d) {
     int fl = (int)p[ROD_P_FLAGS];
     if (fl < 0 || fl > 15) return ROD_EINVAL;
     if (fl & ROD_FLAG_TWIST) {
-      // twisting rods: no self-contact kernels, two vertices per lane
-      if ((fl & ROD_FLAG_SELF) || !d->twist_inv_inertia || !(p[ROD_P_G] >= 0) ||
-          shapes_for(n, d->precision, false, true).empty())
+      // twisting rods: two vertices per lane
+      if (!d->twist_inv_inertia || !(p[ROD_P_G] >= 0) ||
+          shapes_for(n, d->precision, (fl & ROD_FLAG_SELF) != 0, true).empty())
         return ROD_EINVAL;
       for (int i = d->vert_offsets[r]; i < d->vert_offsets[r + 1] - 1; ++i)
         if (!(d->twist_inv_inertia[i] >= 0)) return ROD_EINVAL;
