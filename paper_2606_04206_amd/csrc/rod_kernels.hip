@@ -3031,8 +3031,9 @@ static hipError_t launch_shape(int which, bool gt, const RodArgs<T>& a, int n_bl
 }
 
 #if RODS_TU == 1
-// Rods with the twist degree of freedom: two vertices per lane, no
-// self-contact (this translation unit instantiates only these kernels).
+// Rods with the twist degree of freedom: two vertices per lane, without
+// self-contact, with and without moving rigid bodies (this translation unit
+// instantiates only these kernels).
 template <typename T>
 hipError_t launch_rods_twist(int which, int C, int W, bool GT, const RodArgs<T>& a,
                              int n_blocks, hipStream_t st) {
@@ -3044,6 +3045,22 @@ hipError_t launch_rods_twist(int which, int C, int W, bool GT, const RodArgs<T>&
   if (W == 8) return launch_shape<T, 2, 8, false, true>(which, GT, a, n_blocks, st);
   return hipErrorInvalidValue;
 }
+// ... and those with moving rigid bodies too (a.bw set)
+template <typename T>
+hipError_t launch_rods_twist_bodies(int which, int C, int W, bool GT, const RodArgs<T>& a,
+                                    int n_blocks, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  if (C != 2 || !a.bw) return hipErrorInvalidValue;
+  if (W == 1) return launch_shape<T, 2, 1, false, true, true>(which, GT, a, n_blocks, st);
+  if (W == 2) return launch_shape<T, 2, 2, false, true, true>(which, GT, a, n_blocks, st);
+  if (W == 4) return launch_shape<T, 2, 4, false, true, true>(which, GT, a, n_blocks, st);
+  if (W == 8) return launch_shape<T, 2, 8, false, true, true>(which, GT, a, n_blocks, st);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_rods_twist_bodies<float>(int, int, int, bool, const RodArgs<float>&,
+                                                    int, hipStream_t);
+template hipError_t launch_rods_twist_bodies<double>(int, int, int, bool,
+                                                     const RodArgs<double>&, int, hipStream_t);
 template hipError_t launch_rods_twist<float>(int, int, int, bool, const RodArgs<float>&, int,
                                              hipStream_t);
 template hipError_t launch_rods_twist<double>(int, int, int, bool, const RodArgs<double>&, int,

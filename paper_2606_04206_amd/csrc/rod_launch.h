@@ -29,6 +29,10 @@ hipError_t launch_rods_sc_twist(int which, int C, int W, const RodArgs<T>& a, in
 template <typename T>
 hipError_t launch_rods_twist(int which, int C, int W, bool GT, const RodArgs<T>& a,
                              int n_blocks, hipStream_t st);
+// rods with the twist degree of freedom and moving rigid bodies (C = 2)
+template <typename T>
+hipError_t launch_rods_twist_bodies(int which, int C, int W, bool GT, const RodArgs<T>& a,
+                                    int n_blocks, hipStream_t st);
 // rods with moving rigid bodies (C = 2, no self-contact or twist; a.bw set)
 template <typename T>
 hipError_t launch_rods_bodies(int which, int C, int W, bool GT, const RodArgs<T>& a,

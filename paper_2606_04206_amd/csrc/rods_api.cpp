@@ -546,6 +546,7 @@ struct Impl : HandleBase {
   static hipError_t launch_bin(int which, const Bin& bn, int C, int W, bool gt,
                                const RodArgs<T>& a, int n, hipStream_t st) {
     if (bn.tw && bn.sc) return rods::launch_rods_sc_twist<T>(which, C, W, a, n, st);
+    if (bn.tw && bn.bd) return rods::launch_rods_twist_bodies<T>(which, C, W, gt, a, n, st);
     if (bn.tw) return rods::launch_rods_twist<T>(which, C, W, gt, a, n, st);
     if (bn.bd) return rods::launch_rods_bodies<T>(which, C, W, gt, a, n, st);
     return rods::launch_rods<T>(which, C, W, bn.sc, gt, a, n, st);
@@ -1045,7 +1046,7 @@ static int validate(const RodsDesc* d) {
       if (d->prims[k].type < 0 || d->prims[k].type > 2) return ROD_EINVAL;
     if (d->prim_inv_mass) {
       // moving bodies: spheres, on rods of at most NB_MAX primitives without
-      // self-contact or twist
+      // self-contact
       for (int r = 0; r < d->n_rods; ++r) {
         bool moving = false;
         for (int k = d->prim_offsets[r]; k < d->prim_offsets[r + 1]; ++k) {
@@ -1060,7 +1061,7 @@ static int validate(const RodsDesc* d) {
         }
         const int fl = (int)d->rod_params[(size_t)r * ROD_NPARAM + ROD_P_FLAGS];
         if (moving && (d->prim_offsets[r + 1] - d->prim_offsets[r] > rods::NB_MAX ||
-                       (fl & (ROD_FLAG_SELF | ROD_FLAG_TWIST))))
+                       (fl & ROD_FLAG_SELF)))
           return ROD_EINVAL;
       }
     }
