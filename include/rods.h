@@ -121,8 +121,8 @@ typedef struct {
                                  sphere a moving rigid body (two-way coupling, Section
                                  3.2, Rigid Body), 0 keeps it static; NULL: every
                                  primitive is static.  A rod with a moving body has
-                                 at most 16 primitives and no ROD_FLAG_SELF (it may
-                                 have ROD_FLAG_TWIST). */
+                                 at most 16 primitives and not both ROD_FLAG_SELF
+                                 and ROD_FLAG_TWIST. */
   const double* prim_inv_inertia; /* (host) [P] inverse moment of inertia (isotropic,
                                  e.g. 5/(2 M R^2) for a solid sphere); read where
                                  prim_inv_mass > 0, may be NULL when prim_inv_mass is */

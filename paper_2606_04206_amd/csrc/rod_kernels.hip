@@ -3004,8 +3004,13 @@ static hipError_t launch_shape(int which, bool gt, const RodArgs<T>& a, int n_bl
   RodArgs<T> b = a;
   if constexpr (SC) {
     // the pair cache takes whatever more the host offers (one workgroup
-    // per CU either way)
-    if ((size_t)a.sc_lds > lds) lds = (size_t)a.sc_lds;
+    // per CU either way), less the moving bodies' blocks
+    size_t offer = (size_t)a.sc_lds;
+    if constexpr (BD) {
+      const size_t bl = body_lds_bytes<T>() + 16;
+      offer = offer > bl ? offer - bl : 0;
+    }
+    if (offer > lds) lds = offer;
     b.sc_lds = (int32_t)lds;
   }
   if constexpr (BD) {
@@ -3022,7 +3027,7 @@ static hipError_t launch_shape(int which, bool gt, const RodArgs<T>& a, int n_bl
   } else if (which == 1) {
     go(k_forward<T, C, W, true, SC, TW, BD>);
   } else if constexpr (SC) {
-    go(k_adjoint<T, C, W, true, true, TW, false>);
+    go(k_adjoint<T, C, W, true, true, TW, BD>);
   } else {
     if (gt) go(k_adjoint<T, C, W, false, true, TW, BD>);
     else go(k_adjoint<T, C, W, false, false, TW, BD>);
@@ -3067,8 +3072,9 @@ template hipError_t launch_rods_twist<double>(int, int, int, bool, const RodArgs
                                               hipStream_t);
 #elif RODS_TU == 2
 // Rods with self-contact: FP32 teams of two vertices per lane and 1-8 waves
-// or four vertices per lane and 4 waves, FP64 teams of two vertices per lane
-// (this translation unit instantiates only these kernels).
+// or four vertices per lane and 4 waves, FP64 teams of two vertices per lane;
+// with moving rigid bodies two vertices per lane (this translation unit
+// instantiates only these kernels).
 template <typename T>
 hipError_t launch_rods_sc(int which, int C, int W, const RodArgs<T>& a, int n_blocks,
                           hipStream_t st) {
@@ -3082,6 +3088,22 @@ hipError_t launch_rods_sc(int which, int C, int W, const RodArgs<T>& a, int n_bl
   }
   return hipErrorInvalidValue;
 }
+// ... and those with moving rigid bodies too (two vertices per lane)
+template <typename T>
+hipError_t launch_rods_sc_bodies(int which, int C, int W, const RodArgs<T>& a, int n_blocks,
+                                 hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  if (C != 2 || !a.bw) return hipErrorInvalidValue;
+  if (W == 1) return launch_shape<T, 2, 1, true, false, true>(which, true, a, n_blocks, st);
+  if (W == 2) return launch_shape<T, 2, 2, true, false, true>(which, true, a, n_blocks, st);
+  if (W == 4) return launch_shape<T, 2, 4, true, false, true>(which, true, a, n_blocks, st);
+  if (W == 8) return launch_shape<T, 2, 8, true, false, true>(which, true, a, n_blocks, st);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_rods_sc_bodies<float>(int, int, int, const RodArgs<float>&, int,
+                                                 hipStream_t);
+template hipError_t launch_rods_sc_bodies<double>(int, int, int, const RodArgs<double>&, int,
+                                                  hipStream_t);
 template <typename T>
 size_t sc_lds_bytes(int C, int W) {
   size_t xb = W > 1 ? 2 * W * XK * sizeof(T) : 0;

@@ -21,6 +21,10 @@ hipError_t launch_rods_sc(int which, int C, int W, const RodArgs<T>& a, int n_bl
                           hipStream_t st);
 template <typename T>
 size_t sc_lds_bytes(int C, int W);
+// rods with self-contact and moving rigid bodies (C = 2, a.bw set)
+template <typename T>
+hipError_t launch_rods_sc_bodies(int which, int C, int W, const RodArgs<T>& a, int n_blocks,
+                                 hipStream_t st);
 // rods with the twist degree of freedom and self-contact (C = 2)
 template <typename T>
 hipError_t launch_rods_sc_twist(int which, int C, int W, const RodArgs<T>& a, int n_blocks,

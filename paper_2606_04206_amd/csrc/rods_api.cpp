@@ -547,6 +547,7 @@ struct Impl : HandleBase {
                                const RodArgs<T>& a, int n, hipStream_t st) {
     if (bn.tw && bn.sc) return rods::launch_rods_sc_twist<T>(which, C, W, a, n, st);
     if (bn.tw && bn.bd) return rods::launch_rods_twist_bodies<T>(which, C, W, gt, a, n, st);
+    if (bn.sc && bn.bd) return rods::launch_rods_sc_bodies<T>(which, C, W, a, n, st);
     if (bn.tw) return rods::launch_rods_twist<T>(which, C, W, gt, a, n, st);
     if (bn.bd) return rods::launch_rods_bodies<T>(which, C, W, gt, a, n, st);
     return rods::launch_rods<T>(which, C, W, bn.sc, gt, a, n, st);
@@ -1045,8 +1046,8 @@ static int validate(const RodsDesc* d) {
     for (int k = 0; k < P; ++k)
       if (d->prims[k].type < 0 || d->prims[k].type > 2) return ROD_EINVAL;
     if (d->prim_inv_mass) {
-      // moving bodies: spheres, on rods of at most NB_MAX primitives without
-      // self-contact
+      // moving bodies: spheres, on rods of at most NB_MAX primitives, not on
+      // rods with both self-contact and twist
       for (int r = 0; r < d->n_rods; ++r) {
         bool moving = false;
         for (int k = d->prim_offsets[r]; k < d->prim_offsets[r + 1]; ++k) {
@@ -1061,7 +1062,8 @@ static int validate(const RodsDesc* d) {
         }
         const int fl = (int)d->rod_params[(size_t)r * ROD_NPARAM + ROD_P_FLAGS];
         if (moving && (d->prim_offsets[r + 1] - d->prim_offsets[r] > rods::NB_MAX ||
-                       (fl & ROD_FLAG_SELF)))
+                       (fl & (ROD_FLAG_SELF | ROD_FLAG_TWIST)) ==
+                           (ROD_FLAG_SELF | ROD_FLAG_TWIST)))
           return ROD_EINVAL;
       }
     }
