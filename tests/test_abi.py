@@ -79,7 +79,7 @@ def test_strerror_and_invalid_descriptions():
 
 def test_moving_body_descriptions_are_validated():
     """Moving bodies are spheres with a non-negative inverse inertia, on rods
-    of at most 16 primitives without self-contact or twist; the checks run
+    of at most 16 primitives without both self-contact and twist; the checks run
     before any device call."""
     lib = R.load()
     h = ctypes.c_void_p()
@@ -119,8 +119,7 @@ def test_moving_body_descriptions_are_validated():
            desc([1], [1.0], [-1.0]),                      # negative inverse inertia
            desc([1], [-1.0], [1.0]),                      # negative inverse mass
            desc([1] * 17, [1.0] * 17, [1.0] * 17),        # too many primitives
-           desc([1], [1.0], [1.0], flags=1 | 4),          # with self-contact
-           desc([1], [1.0], [1.0], flags=1 | 8)]          # with twist
+           desc([1], [1.0], [1.0], flags=1 | 4 | 8)]      # with self-contact and twist
     for d in bad:
         assert lib.rods_create(ctypes.byref(d), ctypes.byref(h)) == -1
 
