@@ -21,6 +21,13 @@ substeps):
   S9  self-friction on velocities
   S10 frames: d1 <- R(t_old -> t_new) d1
   S11 plasticity: rest-curvature return map (App. A.1, Bending Plasticity)
+
+Parity unpinned: the soft blend of S4 for 0 < f < 1, v <- (1 - f) v + f v_res
+(the paper says only that the contact is soft "rather than" hard), and with
+it the size of a capsule's response inside the soft band.  The pins fix the
+blend's limits (f = 1: the sliding block's stopping distance, the falling
+rod coming to rest; f below the threshold: no response) and the capsule's
+SDF normal (finite differences), not the interpolation in between.
 """
 import numpy as np
 

@@ -195,3 +195,46 @@ def test_every_launch_shape_agrees_to_rounding(precision):
         with pytest.raises(RodsError):
             h.set_launch_shape(b, C, W)     # too big, too small, not built, no bin, no C
     assert [x[:2] for x in h.bins()] == default
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+def test_initial_frames_vertical_first_edges(precision):
+    """The initial-frame rule's two branches on the GPU (rods_set_state
+    without frames): rods whose first edge is exactly vertical, tilted by
+    5e-7 (inside the 1e-6 threshold: reference axis x) and by 2e-6 (outside
+    it: axis z), then bending away, against the oracle.  FP64 within 1e-12
+    of the oracle's frames; FP32 frames from FP32 positions within 1e-5,
+    except the 2e-6 tilt, whose z-branch frame is ill-conditioned (a
+    normalised difference of vectors 2e-6 apart) and is only checked to be
+    unit and perpendicular to its edge (to 1e-5: FP32 transport over 15
+    edges)."""
+    from oracle.geometry import init_frames, edges
+    wl = make_workload(2, steps=2, sizes=[16, 16, 16])
+    x = np.asarray(wl.x0, np.float64).copy()
+    for r, tilt in enumerate((0.0, 5e-7, 2e-6)):
+        a, b = wl.rod_range(r)
+        s = np.arange(b - a) * 0.01
+        x[a:b] = np.stack([tilt * s + 0.05 * np.maximum(s - 0.05, 0) ** 2,
+                           np.full(b - a, 0.1 * r), 0.3 + s], axis=1)
+    dt = torch.float32 if precision == 4 else torch.float64
+    npdt = np.float32 if precision == 4 else np.float64
+    x = x.astype(npdt).astype(np.float64)
+    h = _handle(wl, precision=precision, max_steps=2)
+    h.set_state(to_dev(x, dt), to_dev(np.zeros_like(x), dt))
+    d1 = h.get_state()[3].double().cpu().numpy()
+    for r in range(3):
+        a, b = wl.rod_range(r)
+        ref = init_frames(x[a:b][None])[0]
+        got = d1[a:b - 1]
+        _, _, t = edges(x[a:b][None])
+        if precision == 8:
+            assert np.abs(got - ref).max() <= 1e-12, (r, np.abs(got - ref).max())
+        elif r < 2:
+            assert np.abs(got - ref).max() <= 1e-5, (r, np.abs(got - ref).max())
+        # FP32 transport along the rod carries about 1e-7 per edge; the z
+        # branch at a 2e-6 tilt loses digits as 1e-16 / 2e-6 in FP64 too
+        tol = 1e-5 if precision == 4 else (1e-12 if r < 2 else 1e-9)
+        assert np.abs(np.linalg.norm(got, axis=-1) - 1).max() <= tol
+        assert np.abs(np.einsum("ij,ij->i", got, t[0])).max() <= tol
+        if r == 0:
+            np.testing.assert_allclose(got[0], [1.0, 0.0, 0.0], atol=1e-7)

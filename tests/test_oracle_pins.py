@@ -319,6 +319,30 @@ def test_frames_stay_orthonormal_and_adapted():
     assert np.abs(dot(st.d1, t)).max() < 1e-12
 
 
+def test_initial_frames_fall_back_to_x_for_a_vertical_first_edge():
+    """Initial-frame rule: with the first edge along z the reference axis is
+    x, so d1^0 = x exactly; a first edge within 1e-6 of z takes the same
+    branch and gives x projected off the edge; one just outside it uses z.
+    Parallel transport along a straight vertical rod keeps d1 = x."""
+    n = 12
+    x = np.zeros((1, n, 3))
+    x[0, :, 2] = 0.01 * np.arange(n)
+    d1 = init_frames(x)
+    np.testing.assert_array_equal(d1[0], np.tile([1.0, 0.0, 0.0], (n - 1, 1)))
+    for eps, branch_x in ((5e-7, True), (2e-6, False)):
+        y = x.copy()
+        y[0, 1:, 0] = eps * 0.01 * np.arange(1, n)     # tilt about y by ~eps
+        _, _, t = edges(y)
+        d = init_frames(y)[0, 0]
+        a = np.array([1.0, 0.0, 0.0]) if branch_x else np.array([0.0, 0.0, 1.0])
+        ref = a - np.dot(a, t[0, 0]) * t[0, 0]
+        np.testing.assert_allclose(d, ref / np.linalg.norm(ref), rtol=0, atol=1e-15)
+        # d is a normalised difference of vectors |a x t| apart: rounding of
+        # 1e-16 relative becomes 1e-16 / |a x t| in its orthogonality
+        tol = 1e-15 / np.linalg.norm(np.cross(a, t[0, 0]))
+        assert abs(np.dot(d, t[0, 0])) < tol and abs(np.linalg.norm(d) - 1) < 1e-15
+
+
 # ---------------------------------------------------------------- rigid contact
 
 PLANE = (0, np.zeros(3), np.array([0, 0, 1.0]), 0.0)
