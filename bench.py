@@ -328,7 +328,7 @@ def survey(cids, opt_iters):
             _survey_optimize(opt_iters)
             continue
         wl = make_workload(cid)
-        n = {2: 500, 4: 100, 5: 100, 6: 1000, 7: 1000}.get(cid, 100)
+        n = {2: 500, 4: 500, 5: 2000, 6: 1000, 7: 1000}.get(cid, 100)
         K = wl.sim.ckpt_every
         x0, v0 = _dev(wl.x0, f32), _dev(wl.v0, f32)
         h = RodsHandle(wl, precision=4, max_steps=max(n, K), ckpt_every=K)
