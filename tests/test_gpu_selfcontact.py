@@ -98,7 +98,7 @@ def test_selfcontact_step_parity_1024():
         assert rel_err(gather_state(wl, [r], out).x, ref.x) <= max(1e-4, 2 * spread), (r, spread)
 
 
-def judge_blocks(blocks, tol, min_well):
+def check_gradient_blocks(blocks, tol, min_well):
     """Gradient blocks through self-contact, each (label, err, spread): err
     is the GPU's relative error against the oracle, spread the largest
     relative change of the oracle's own result when its inputs are moved by
@@ -131,7 +131,7 @@ def test_selfcontact_rollout_gradients():
     wherever the oracle's own result moves by at most 2e-4 when every
     checkpoint is moved by the FP32 error one step accumulates (3e-7
     relative: the GPU's state after one step differs from the FP64 oracle's
-    by 2.6e-7), judged by judge_blocks, with at least 6 of the 18 blocks
+    by 2.6e-7), held to check_gradient_blocks, with at least 6 of the 18 blocks
     held to 1e-3.  On this batch the oracle's own x0 gradient moves by 6e-1
     on one rod and by 1e-2 on another under such a change (contact and
     yield ties, near-parallel segments)."""
@@ -176,4 +176,4 @@ def test_selfcontact_rollout_gradients():
                            max(rel_err(o, ref) for o in alt)))
     for name, got, ref, k in (("b", gg["b"], bb, 1), ("sigma", gg["sigma"], sb, 2)):
         blocks.append((name, rel_err(got, ref), max(rel_err(o[k], ref) for o in alts)))
-    judge_blocks(blocks, 1e-3, 6)
+    check_gradient_blocks(blocks, 1e-3, 6)

@@ -209,11 +209,11 @@ def test_fp32_rollout_gradients_1024():
     checkpoint every step, differentiated along the GPU's own trajectory
     (the oracle's checkpoints are the GPU's states, its seed the GPU's loss
     gradient): gradients w.r.t. grasp velocities and initial positions per
-    rod and w.r.t. b and sigma_y judged by judge_blocks (within 1e-3 where
+    rod and w.r.t. b and sigma_y held to check_gradient_blocks (within 1e-3 where
     the oracle's own result moves by at most 2e-4 when every checkpoint is
     moved by one step's FP32 error, 3e-7 relative; here mostly it moves by
     more: the x0 gradients by 6e-4 to 6e-3, from contact and yield ties)."""
-    from tests.test_gpu_selfcontact import judge_blocks
+    from tests.test_gpu_selfcontact import check_gradient_blocks
     n, K = 2, 1
     wl = make_workload(5, steps=n, pitch=0.011, noise=NOISE, n_vert=1024, n_rods=2)
     wl.rod_params[:, 4] = 0.5
@@ -255,4 +255,4 @@ def test_fp32_rollout_gradients_1024():
                            max(rel_err(o, ref) for o in alt)))
     for name, got, ref, k in (("b", gg["b"], bb, 1), ("sigma", gg["sigma"], sb, 2)):
         blocks.append((name, rel_err(got, ref), max(rel_err(o[k], ref) for o in alts)))
-    judge_blocks(blocks, 1e-3, 1)
+    check_gradient_blocks(blocks, 1e-3, 1)
