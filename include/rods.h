@@ -271,6 +271,27 @@ int rods_backward(RodsHandle* h, const void* dL_dxT, const void* dL_dvT, void* d
  * rule-derived frames. */
 int rods_frames_vjp(RodsHandle* h, const void* x0, void* dL_dx0, rods_stream_t stream);
 
+/* Reference frames of closed rods (App. A.1, Loop Topology), without a
+ * handle.  A closed rod of N >= 3 vertices x_0 .. x_{N-1} has N edges:
+ * e^j = x_{j+1} - x_j and the closing edge e^{N-1} = x_0 - x_{N-1}.  The
+ * first edge's frame follows the open-rod rule (from z, or x for an edge
+ * within 1e-6 of the z axis); parallel transport carries it edge by edge to
+ * the last edge and across the closing joint back onto t^0, where it makes
+ * the holonomy angle psi_H with the first frame (counter-clockwise about
+ * t^0, in (-pi, pi]); edge j's frame is then turned about t^j by
+ * -psi_H j / N, leaving the same mismatch -psi_H / N at every joint.
+ * vert_offsets: device int32 [n_rods + 1], the CSR layout above with every
+ * rod closed; x: device [V][3] of `precision` (4 float, 8 double); d1:
+ * device [V][3] output, edge j of rod r in row vert_offsets[r] + j (all N
+ * rows used); psi: device [n_rods] output or NULL.  The caller owns every
+ * buffer; nothing is allocated.  The offsets are copied to the host and the
+ * stream synchronised once to check them.  ROD_EINVAL for a NULL input or
+ * output, n_rods < 0 or a rod of fewer than 3 vertices, ROD_EDTYPE for
+ * another precision, ROD_EHIP for a failed copy or launch.  Consecutive
+ * edges must not be antiparallel (the minimal rotation is undefined). */
+int rods_loop_frames(const int32_t* vert_offsets, int32_t n_rods, int32_t precision,
+                     const void* x, void* d1, void* psi, rods_stream_t stream);
+
 /* Number of the handle's current recording: each recorded rods_rollout
  * gets the next number (1, 2, ...); 0 when there is none (a call that
  * clears the recording: rods_set_state, rods_set_params, rods_step, an

@@ -25,6 +25,7 @@ UNITS = [("rod_kernels.hip", [], "rod_kernels.o"),
          ("rod_kernels.hip", ["-DRODS_TU=3"], "rod_kernels_sctw.o"),
          ("rod_optim.hip", [], "rod_optim.o"),
          ("rod_loss.hip", [], "rod_loss.o"),
+         ("rod_loop.hip", [], "rod_loop.o"),
          ("rods_api.cpp", [], "rods_api.o")]
 
 

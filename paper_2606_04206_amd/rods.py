@@ -52,7 +52,7 @@ EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "ro
            "rods_set_plain",
            "rods_set_profiling", "rods_profile", "rods_selftest_exchange",
            "rods_loss_mse_static", "rods_sc_pairs", "rods_sc_stats", "rods_recording",
-           "rods_frames_vjp"]
+           "rods_frames_vjp", "rods_loop_frames"]
 
 _lib = None
 
@@ -107,6 +107,7 @@ def load():
         "rods_sc_stats": ([vp, POINTER(ctypes.c_int64), c_int32, vp], c_int32),
         "rods_recording": ([vp], ctypes.c_int64),
         "rods_frames_vjp": ([vp, vp, vp, vp], c_int32),
+        "rods_loop_frames": ([vp, c_int32, c_int32, vp, vp, vp, vp], c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -434,6 +435,24 @@ def selftest_exchange():
 
 
 LOSS_STATIC_MAX_RODS = 65536
+
+
+def loop_frames(vert_offsets, x):
+    """Reference frames of closed rods (rods_loop_frames): vert_offsets is a
+    device int32 tensor [R+1], x [V][3] float32 or float64 on the device.
+    Returns (d1 [V][3], psi_H [R])."""
+    R = vert_offsets.numel() - 1
+    V = x.shape[0]
+    _require(vert_offsets, (R + 1,), torch.int32, "vert_offsets")
+    _require(x, (V, 3), x.dtype, "x")
+    if R > 0 and int(vert_offsets[-1]) != V:
+        raise RodsError(f"vert_offsets: the last offset must be the vertex count {V}")
+    prec = {torch.float32: 4, torch.float64: 8}.get(x.dtype, 0)
+    d1 = torch.empty(V, 3, dtype=x.dtype, device=x.device)
+    psi = torch.empty(max(R, 0), dtype=x.dtype, device=x.device)
+    _check(load().rods_loop_frames(_ptr(vert_offsets), int(R), int(prec), _ptr(x), _ptr(d1),
+                                   _ptr(psi), _stream()), "rods_loop_frames")
+    return d1, psi
 
 
 def loss_mse_static(vert_offsets, x, target, want_grad=True):
