@@ -22,10 +22,14 @@ Readings (the passage fixes neither):
   positive counter-clockwise about t^0, in (-pi, pi].  With that sign the
   rotation by phi^j leaves the same joint mismatch -psi_H / N at every joint,
   the closing one included.
+
+loop_frames_vjp takes those steps back in reverse order (the reference-axis
+choice of the first frame is piecewise constant, so it passes no adjoint).
 """
 import numpy as np
 
 from .geometry import cross, dot, norm, re, transport
+from .adjoint import transport_vjp
 
 
 def loop_edges(x):
@@ -36,19 +40,44 @@ def loop_edges(x):
     return e, ell, e / ell[..., None]
 
 
-def first_frame(t0):
-    """The frame of edge 0 from its tangent [3] (the open-rod rule)."""
+def _axis(t0):
     a = np.array([0.0, 0.0, 1.0], dtype=t0.dtype)
     if re(norm(cross(t0, a))) < 1e-6:
         a = np.array([1.0, 0.0, 0.0], dtype=t0.dtype)
+    return a
+
+
+def first_frame(t0):
+    """The frame of edge 0 from its tangent [3] (the open-rod rule)."""
+    a = _axis(t0)
     d = a - dot(a, t0) * t0
     return d / norm(d)
+
+
+def first_frame_vjp(t0, g):
+    """Adjoint of first_frame: the tangent adjoint that the frame adjoint g
+    induces (d = a - (a.t0) t0, then d / |d|)."""
+    a = _axis(t0)
+    d = a - dot(a, t0) * t0
+    nd = norm(d)
+    u = d / nd
+    d_b = (g - u * dot(u, g)) / nd
+    return -dot(a, t0) * d_b - dot(d_b, t0) * a
+
+
+def atan2(s, c):
+    """arctan2 that also takes complex-step inputs (first order in the
+    imaginary parts, which is all a complex-step derivative reads)."""
+    if not (np.iscomplexobj(s) or np.iscomplexobj(c)):
+        return np.arctan2(s, c)
+    sr, cr = np.real(s), np.real(c)
+    return np.arctan2(sr, cr) + 1j * (cr * np.imag(s) - sr * np.imag(c)) / (sr * sr + cr * cr)
 
 
 def signed_angle(a, b, axis):
     """Angle from a to b, both perpendicular to the unit axis, positive
     counter-clockwise about it; in (-pi, pi]."""
-    return np.arctan2(dot(cross(a, b), axis), dot(a, b))
+    return atan2(dot(cross(a, b), axis), dot(a, b))
 
 
 def rotate_about(d, t, phi):
@@ -72,3 +101,50 @@ def loop_frames(x):
         psi[bi] = signed_angle(dh[bi, 0], back, t[bi, 0])
     phi = -psi[:, None] * np.arange(N)[None, :] / N
     return rotate_about(dh, t, phi), dh, psi
+
+
+def loop_frames_vjp(x, d1_b, psi_b=None):
+    """Adjoint of loop_frames: the position adjoint [B,N,3] induced by the
+    frame adjoint d1_b [B,N,3] and the angle adjoint psi_b [B] (or None)."""
+    e, ell, t = loop_edges(x)
+    d1, dh, psi = loop_frames(x)
+    B, N, _ = t.shape
+    j = np.arange(N)
+    phi = -psi[:, None] * j[None, :] / N
+    co, si = np.cos(phi)[..., None], np.sin(phi)[..., None]
+    # d1 = cos(phi) dh + sin(phi) t x dh
+    dh_b = co * d1_b + si * cross(d1_b, t)
+    t_b = si * cross(dh, d1_b)
+    phi_b = dot(d1_b, -si * dh + co * cross(t, dh))
+    ps_b = np.sum(phi_b * (-j[None, :] / N), axis=-1)
+    if psi_b is not None:
+        ps_b = ps_b + psi_b
+    x_b = np.zeros_like(x, dtype=np.result_type(x, d1_b))
+    for bi in range(B):
+        tb = t_b[bi].copy()
+        gh = dh_b[bi].copy()
+        t0, d0 = t[bi, 0], dh[bi, 0]
+        # psi = atan2(s, c), s = t0.(d0 x back), c = d0.back
+        back = transport(dh[bi, N - 1], t[bi, N - 1], t0)
+        sv, cv = dot(cross(d0, back), t0), dot(d0, back)
+        s_b = ps_b[bi] * cv / (sv * sv + cv * cv)
+        c_b = -ps_b[bi] * sv / (sv * sv + cv * cv)
+        gh[0] += s_b * cross(back, t0) + c_b * back
+        back_b = s_b * cross(t0, d0) + c_b * d0
+        tb[0] += s_b * cross(d0, back)
+        # back = transport of dh^{N-1} across the closing joint onto t0
+        v_b, ta_b, tb_b = transport_vjp(dh[bi, N - 1], t[bi, N - 1], t0, back_b)
+        gh[N - 1] += v_b
+        tb[N - 1] += ta_b
+        tb[0] += tb_b
+        # dh^k = transport of dh^{k-1} from t^{k-1} to t^k, last joint first
+        for k in range(N - 1, 0, -1):
+            v_b, ta_b, tb_b = transport_vjp(dh[bi, k - 1], t[bi, k - 1], t[bi, k], gh[k])
+            gh[k - 1] += v_b
+            tb[k - 1] += ta_b
+            tb[k] += tb_b
+        tb[0] += first_frame_vjp(t0, gh[0])
+        # t = e / |e|, e^k = x_{k+1} - x_k (the closing edge onto x_0)
+        e_b = (tb - t[bi] * dot(t[bi], tb)[:, None]) / ell[bi][:, None]
+        x_b[bi] += np.roll(e_b, 1, axis=0) - e_b
+    return x_b

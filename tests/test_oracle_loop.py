@@ -19,13 +19,18 @@
   and every frame keeps its angle with the plane's normal.
 * The uncorrected frames of the first N-1 edges equal the open-rod rule on
   the same vertices.
+* The adjoint (loop_frames_vjp): complex-step dot-product tests of the whole
+  rule (frames and psi_H) on knots, warped rings and random curves of 3 to
+  80 vertices; central differences of the same directional derivatives; and
+  psi_H's invariance under rigid rotations, which makes the torque of its
+  position gradient, sum x_i x dpsi/dx_i, vanish.
 """
 import numpy as np
 import pytest
 from scipy.spatial.transform import Rotation
 
 from oracle.geometry import init_frames
-from oracle.loop import loop_edges, loop_frames
+from oracle.loop import loop_edges, loop_frames, loop_frames_vjp
 
 
 def wrap(a):
@@ -139,3 +144,45 @@ def test_uncorrected_frames_extend_the_open_rod_rule():
     for x in (saddle(33), trefoil(20), fourier(57, seed=3)):
         _, dh, _ = loop_frames(x[None])
         np.testing.assert_allclose(dh[0, :-1], init_frames(x[None])[0], rtol=0, atol=1e-15)
+
+
+def _cotangents(x, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=x.shape), rng.normal(size=1), rng.normal(size=x.shape))
+
+
+def _directional(x, d1_b, psi_b, dx, h):
+    """sum d1_b . d1 + psi_b psi_H along x + h dx (h complex: complex step)."""
+    d1, _, psi = loop_frames((x + h * dx)[None])
+    return np.sum(d1_b * d1[0]) + psi_b[0] * psi[0]
+
+
+@pytest.mark.parametrize("name,curve", CURVES)
+@pytest.mark.parametrize("n", [3, 8, 80])
+def test_adjoint_complex_step(name, curve, n):
+    x = curve(n)
+    d1_b, psi_b, dx = _cotangents(x, n)
+    xb = loop_frames_vjp(x[None], d1_b[None], psi_b)[0]
+    h = 1e-30
+    cs = np.imag(_directional(x, d1_b, psi_b, dx, 1j * h)) / h
+    assert abs(cs - np.sum(xb * dx)) <= 1e-10 * max(abs(cs), 1.0), (cs, np.sum(xb * dx))
+
+
+@pytest.mark.parametrize("name,curve", CURVES)
+def test_adjoint_central_differences(name, curve):
+    x = curve(20)
+    d1_b, psi_b, dx = _cotangents(x, 7)
+    xb = loop_frames_vjp(x[None], d1_b[None], psi_b)[0]
+    h = 1e-7 * np.abs(x).max()
+    fd = (_directional(x, d1_b, psi_b, dx, h) - _directional(x, d1_b, psi_b, dx, -h)) / (2 * h)
+    assert abs(fd - np.sum(xb * dx)) <= 1e-6 * max(abs(fd), 1.0), (fd, np.sum(xb * dx))
+
+
+@pytest.mark.parametrize("name,curve", CURVES)
+def test_holonomy_gradient_has_no_torque(name, curve):
+    x = curve(30) + np.array([0.3, -0.2, 0.5])
+    xb = loop_frames_vjp(x[None], np.zeros((1, 30, 3)), np.ones(1))[0]
+    assert np.linalg.norm(xb) > 1e-3
+    np.testing.assert_allclose(xb.sum(axis=0), 0.0, atol=1e-9 * np.linalg.norm(xb))
+    torque = np.cross(x, xb).sum(axis=0)
+    assert np.linalg.norm(torque) <= 1e-9 * np.linalg.norm(xb) * np.abs(x).max()
