@@ -292,6 +292,18 @@ int rods_frames_vjp(RodsHandle* h, const void* x0, void* dL_dx0, rods_stream_t s
 int rods_loop_frames(const int32_t* vert_offsets, int32_t n_rods, int32_t precision,
                      const void* x, void* d1, void* psi, rods_stream_t stream);
 
+/* Adjoint of rods_loop_frames (the rule of App. A.1, Loop Topology, taken
+ * back step by step; its reference-axis choice is piecewise constant):
+ * dL_dx [V][3] (device, output, overwritten) from the frame adjoint dL_dd1
+ * [V][3] and the angle adjoint dL_dpsi [n_rods] (device; NULL for none) at
+ * positions x [V][3].  Layouts, precision, offsets and error codes as for
+ * rods_loop_frames; dL_dx must not alias x or dL_dd1.  Nothing is
+ * allocated: dL_dx's rows hold the transported frames until their adjoint
+ * is final. */
+int rods_loop_frames_vjp(const int32_t* vert_offsets, int32_t n_rods, int32_t precision,
+                         const void* x, const void* dL_dd1, const void* dL_dpsi, void* dL_dx,
+                         rods_stream_t stream);
+
 /* Number of the handle's current recording: each recorded rods_rollout
  * gets the next number (1, 2, ...); 0 when there is none (a call that
  * clears the recording: rods_set_state, rods_set_params, rods_step, an

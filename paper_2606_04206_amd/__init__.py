@@ -5,7 +5,7 @@ rods.py.  There is no CPU fallback: without the built library every call
 raises.
 """
 from .rods import (RodsHandle, RodsRollout, RodsError, load, selftest_exchange, loop_frames,
-                   EXPORTS, LIB_PATH)
+                   loop_frames_vjp, EXPORTS, LIB_PATH)
 
 __all__ = ["RodsHandle", "RodsRollout", "RodsError", "load", "selftest_exchange", "loop_frames",
-           "EXPORTS", "LIB_PATH"]
+           "loop_frames_vjp", "EXPORTS", "LIB_PATH"]

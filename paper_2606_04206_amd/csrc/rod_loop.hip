@@ -2,7 +2,7 @@
 // parallel-transported around the loop, the holonomy angle psi_H left at the
 // closing joint is measured against the first frame, and edge j's frame is
 // turned about its tangent by -psi_H j / N, so that every joint carries the
-// same share of it.
+// same share of it.  Also the adjoint of that rule.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -19,6 +19,29 @@ __device__ __forceinline__ V3<T> loop_transport(V3<T> v, V3<T> ta, V3<T> tb) {
   V3<T> bb = cross(ta, tb);
   T c = dot(ta, tb);
   return c * v + cross(bb, v) + fdiv(dot(bb, v), T(1) + c) * bb;
+}
+
+// adjoint of loop_transport: returns v's adjoint, adds ta's and tb's
+template <typename T>
+__device__ __forceinline__ V3<T> loop_transport_vjp(V3<T> v, V3<T> ta, V3<T> tb, V3<T> yb,
+                                                    V3<T>& tab, V3<T>& tbb) {
+  V3<T> bb = cross(ta, tb);
+  T c = dot(ta, tb);
+  T opc = T(1) + c, bv = dot(bb, v), by = dot(bb, yb);
+  V3<T> vb = c * yb - cross(bb, yb) + (by / opc) * bb;
+  T cb = dot(v, yb) - bv * by / (opc * opc);
+  V3<T> b_b = cross(v, yb) + (T(1) / opc) * (bv * yb + by * v);
+  tab += cross(tb, b_b) + cb * tb;
+  tbb += cross(b_b, ta) + cb * ta;
+  return vb;
+}
+
+// reference axis of the first frame: z, or x for a first edge along z
+template <typename T>
+__device__ __forceinline__ V3<T> loop_axis(V3<T> t0) {
+  V3<T> az = mk(T(0), T(0), T(1));
+  V3<T> c = cross(t0, az);
+  return sqrt(dot(c, c)) < T(1e-6) ? mk(T(1), T(0), T(0)) : az;
 }
 
 // unit tangent of edge j of the closed rod starting at vertex v0 (edge N-1
@@ -40,10 +63,8 @@ __global__ void k_loop_frames(const int32_t* voff, int R, const T* x, T* d1, T* 
   if (r >= R) return;
   int v0 = voff[r], N = voff[r + 1] - v0;
   V3<T> t0 = loop_tangent(x, v0, N, 0);
-  // first frame: the open-rod rule (z, or x for a first edge along z)
-  V3<T> az = mk(T(0), T(0), T(1));
-  V3<T> c = cross(t0, az);
-  V3<T> av = sqrt(dot(c, c)) < T(1e-6) ? mk(T(1), T(0), T(0)) : az;
+  // first frame: the open-rod rule
+  V3<T> av = loop_axis(t0);
   V3<T> d0 = av - dot(av, t0) * t0;
   d0 = (T(1) / sqrt(dot(d0, d0))) * d0;
   put3(d1, 3 * v0, d0);
@@ -66,12 +87,119 @@ __global__ void k_loop_frames(const int32_t* voff, int R, const T* x, T* d1, T* 
   }
 }
 
+// Adjoint of the rule, one thread per closed rod.  xb's rows hold the
+// transported frames until each row's adjoint is final: the reverse walk
+// over the joints (last first) reads the frames of rows j and j-1 at joint
+// j, then edge j's adjoint is complete and rows j and j+1 take their share
+// of it; the closing edge's share of row 0 waits in registers until row 0's
+// frame has been read for the last time.
+template <typename T>
+__global__ void k_loop_frames_vjp(const int32_t* voff, int R, const T* x, const T* d1b,
+                                  const T* psib, T* xb) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  int v0 = voff[r], N = voff[r + 1] - v0;
+  V3<T> t0 = loop_tangent(x, v0, N, 0);
+  V3<T> av = loop_axis(t0);
+  V3<T> d0 = av - dot(av, t0) * t0;
+  d0 = (T(1) / sqrt(dot(d0, d0))) * d0;
+  put3(xb, 3 * v0, d0);
+  V3<T> d = d0, t = t0;
+  for (int j = 1; j < N; ++j) {
+    V3<T> tn = loop_tangent(x, v0, N, j);
+    d = loop_transport(d, t, tn);
+    put3(xb, 3 * (v0 + j), d);
+    t = tn;
+  }
+  V3<T> back = loop_transport(d, t, t0);
+  T sv = dot(cross(d0, back), t0), cv = dot(d0, back);
+  T ps = atan2(sv, cv);
+  // psi_H's adjoint: its own plus that of every edge's rotation angle
+  T psb = psib ? psib[r] : T(0);
+  for (int j = 1; j < N; ++j) {
+    T phi = -ps * T(j) / T(N);
+    T s = sin(phi), co = cos(phi);
+    V3<T> tj = loop_tangent(x, v0, N, j);
+    V3<T> dh = get3(xb, 3 * (v0 + j));
+    V3<T> g = get3(d1b, 3 * (v0 + j));
+    T phib = dot(g, co * cross(tj, dh) - s * dh);
+    psb -= phib * T(j) / T(N);
+  }
+  // psi_H = atan2(t0.(d0 x back), d0.back)
+  T den = sv * sv + cv * cv;
+  T sb = psb * cv / den, cb = -psb * sv / den;
+  V3<T> g0 = sb * cross(back, t0) + cb * back;
+  V3<T> backb = sb * cross(t0, d0) + cb * d0;
+  V3<T> t0b = sb * cross(d0, back);
+  // the closing transport, then the joints from the last to the first
+  V3<T> tnb = zero3<T>();
+  V3<T> carry = loop_transport_vjp(d, t, t0, backb, tnb, t0b);
+  V3<T> eclose = zero3<T>();
+  for (int j = N - 1; j >= 1; --j) {
+    int k = j + 1 == N ? 0 : j + 1;
+    V3<T> e = get3(x, 3 * (v0 + k)) - get3(x, 3 * (v0 + j));
+    T ell = sqrt(dot(e, e));
+    V3<T> tj = (T(1) / ell) * e;
+    T phi = -ps * T(j) / T(N);
+    T s = sin(phi), co = cos(phi);
+    V3<T> dh = get3(xb, 3 * (v0 + j));
+    V3<T> g = get3(d1b, 3 * (v0 + j));
+    V3<T> gh = carry + co * g + s * cross(g, tj);
+    V3<T> tjb = tnb + s * cross(dh, g);
+    V3<T> tpb = zero3<T>();
+    carry = loop_transport_vjp(get3(xb, 3 * (v0 + j - 1)), loop_tangent(x, v0, N, j - 1), tj,
+                               gh, tpb, tjb);
+    V3<T> eb = (T(1) / ell) * (tjb - dot(tj, tjb) * tj);
+    if (j == N - 1)
+      eclose = eb;
+    else
+      put3(xb, 3 * (v0 + j + 1), get3(xb, 3 * (v0 + j + 1)) + eb);
+    put3(xb, 3 * (v0 + j), -eb);
+    tnb = tpb;
+  }
+  // edge 0: no rotation (phi = 0), the first frame's construction
+  V3<T> gh = carry + get3(d1b, 3 * v0) + g0;
+  T nd0;
+  {
+    V3<T> dd = av - dot(av, t0) * t0;
+    nd0 = sqrt(dot(dd, dd));
+  }
+  V3<T> db = (T(1) / nd0) * (gh - dot(d0, gh) * d0);
+  t0b += tnb - dot(av, t0) * db - dot(db, t0) * av;
+  V3<T> e0 = get3(x, 3 * (v0 + 1)) - get3(x, 3 * v0);
+  T ell0 = sqrt(dot(e0, e0));
+  V3<T> eb0 = (T(1) / ell0) * (t0b - dot(t0, t0b) * t0);
+  put3(xb, 3 * (v0 + 1), get3(xb, 3 * (v0 + 1)) + eb0);
+  put3(xb, 3 * v0, eclose - eb0);
+}
+
 template <typename T>
 hipError_t launch_loop_frames(const int32_t* voff, int R, const T* x, T* d1, T* psi,
                               hipStream_t st) {
   hipLaunchKernelGGL(k_loop_frames<T>, dim3((R + 63) / 64), dim3(64), 0, st, voff, R, x, d1,
                      psi);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_loop_frames_vjp(const int32_t* voff, int R, const T* x, const T* d1b,
+                                  const T* psib, T* xb, hipStream_t st) {
+  hipLaunchKernelGGL(k_loop_frames_vjp<T>, dim3((R + 63) / 64), dim3(64), 0, st, voff, R, x,
+                     d1b, psib, xb);
+  return hipGetLastError();
+}
+
+// copies the offsets to the host and checks them: a loop needs three vertices
+static int check_loop_offsets(const int32_t* voff, int R, hipStream_t st) {
+  std::vector<int32_t> off(R + 1);
+  if (hipMemcpyAsync(off.data(), voff, sizeof(int32_t) * (R + 1), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return ROD_EHIP;
+  if (off[0] < 0) return ROD_EINVAL;
+  for (int r = 0; r < R; ++r)
+    if (off[r + 1] - off[r] < 3) return ROD_EINVAL;
+  return ROD_OK;
 }
 
 }  // namespace rods
@@ -82,15 +210,8 @@ extern "C" int rods_loop_frames(const int32_t* vert_offsets, int32_t n_rods, int
   if (precision != 4 && precision != 8) return ROD_EDTYPE;
   if (n_rods == 0) return ROD_OK;
   hipStream_t st = (hipStream_t)stream;
-  // the offsets are validated on the host: a loop needs three vertices
-  std::vector<int32_t> off(n_rods + 1);
-  if (hipMemcpyAsync(off.data(), vert_offsets, sizeof(int32_t) * (n_rods + 1),
-                     hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return ROD_EHIP;
-  if (off[0] < 0) return ROD_EINVAL;
-  for (int r = 0; r < n_rods; ++r)
-    if (off[r + 1] - off[r] < 3) return ROD_EINVAL;
+  int e = rods::check_loop_offsets(vert_offsets, n_rods, st);
+  if (e) return e;
   hipError_t he;
   if (precision == 4)
     he = rods::launch_loop_frames<float>(vert_offsets, n_rods, (const float*)x, (float*)d1,
@@ -98,5 +219,26 @@ extern "C" int rods_loop_frames(const int32_t* vert_offsets, int32_t n_rods, int
   else
     he = rods::launch_loop_frames<double>(vert_offsets, n_rods, (const double*)x, (double*)d1,
                                           (double*)psi, st);
+  return he == hipSuccess ? ROD_OK : ROD_EHIP;
+}
+
+extern "C" int rods_loop_frames_vjp(const int32_t* vert_offsets, int32_t n_rods,
+                                    int32_t precision, const void* x, const void* dL_dd1,
+                                    const void* dL_dpsi, void* dL_dx, rods_stream_t stream) {
+  if (!vert_offsets || !x || !dL_dd1 || !dL_dx || n_rods < 0) return ROD_EINVAL;
+  if (precision != 4 && precision != 8) return ROD_EDTYPE;
+  if (n_rods == 0) return ROD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  int e = rods::check_loop_offsets(vert_offsets, n_rods, st);
+  if (e) return e;
+  hipError_t he;
+  if (precision == 4)
+    he = rods::launch_loop_frames_vjp<float>(vert_offsets, n_rods, (const float*)x,
+                                             (const float*)dL_dd1, (const float*)dL_dpsi,
+                                             (float*)dL_dx, st);
+  else
+    he = rods::launch_loop_frames_vjp<double>(vert_offsets, n_rods, (const double*)x,
+                                              (const double*)dL_dd1, (const double*)dL_dpsi,
+                                              (double*)dL_dx, st);
   return he == hipSuccess ? ROD_OK : ROD_EHIP;
 }
