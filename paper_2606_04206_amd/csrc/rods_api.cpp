@@ -136,6 +136,7 @@ struct Impl : HandleBase {
   int64_t rec_gen = 0, rec_count = 0;
   int n_rec = 0;
   int plain = 0;
+  bool concurrent_bins = true;
   // graph of one step (all size bins) over the handle's own buffers
   hipStream_t cap_stream = nullptr;
   // backward pipelining: the tape of segment s-1 is replayed on side_stream
@@ -150,6 +151,12 @@ struct Impl : HandleBase {
   T* tape_for(int seg) const { return (plain || !tape2) ? tape : ((seg & 1) ? tape2 : tape); }
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_start = nullptr, ev_tape[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
+  // size bins after the first run on streams of their own (default
+  // priority), forked from and joined back to the caller's stream, so that
+  // one bin's last, partly filled round of workgroups overlaps the others
+  std::vector<hipStream_t> bin_streams;
+  std::vector<hipEvent_t> bin_done;
+  hipEvent_t ev_fork = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   T* u_step = nullptr;
@@ -163,7 +170,9 @@ struct Impl : HandleBase {
     drop_graph();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (side_stream) (void)hipStreamDestroy(side_stream);
-    for (hipEvent_t e : {ev_start, ev_tape[0], ev_tape[1], ev_adj[0], ev_adj[1]})
+    for (hipStream_t s : bin_streams) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : bin_done) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {ev_start, ev_tape[0], ev_tape[1], ev_adj[0], ev_adj[1], ev_fork})
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
@@ -448,8 +457,14 @@ struct Impl : HandleBase {
     HIPCHK(hipMemset(status, 0, sizeof(int32_t) * R));
     HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking));
-    for (hipEvent_t* ev : {&ev_start, &ev_tape[0], &ev_tape[1], &ev_adj[0], &ev_adj[1]})
+    for (hipEvent_t* ev : {&ev_start, &ev_tape[0], &ev_tape[1], &ev_adj[0], &ev_adj[1], &ev_fork})
       HIPCHK(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+    for (size_t i = 1; i < bins.size(); ++i) {
+      bin_streams.push_back(nullptr);
+      HIPCHK(hipStreamCreateWithFlags(&bin_streams.back(), hipStreamNonBlocking));
+      bin_done.push_back(nullptr);
+      HIPCHK(hipEventCreateWithFlags(&bin_done.back(), hipEventDisableTiming));
+    }
     {
       // second tape buffer, if the device has room for it
       const size_t bytes = sizeof(T) * (size_t)std::min(d.ckpt_every, std::max(1, d.max_steps)) *
@@ -561,10 +576,28 @@ struct Impl : HandleBase {
       a.sc_stats = sc_stats + 8 * (size_t)R;
     }
     if (!plain) {
-      for (const Bin& bn : bins) {
+      // The bins touch disjoint rods.  They run concurrently except on the
+      // backward's replay stream (whose work already overlaps the adjoint,
+      // and which must not queue behind it on shared bin streams) and
+      // under graph capture (a captured step stays one chain).
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      HIPCHK(hipStreamIsCapturing(st, &cs));
+      const bool fork = concurrent_bins && bins.size() > 1 && st != side_stream &&
+                        cs == hipStreamCaptureStatusNone;
+      if (fork) HIPCHK(hipEventRecord(ev_fork, st));
+      for (size_t i = 0; i < bins.size(); ++i) {
+        const Bin& bn = bins[i];
         a.rods = bin_rods + bn.off;
-        HIPCHK(launch_bin(which, bn, bn.C, bn.W, bn.gt, a, bn.n, st));
+        hipStream_t s = st;
+        if (fork && i > 0) {
+          s = bin_streams[i - 1];
+          HIPCHK(hipStreamWaitEvent(s, ev_fork, 0));
+        }
+        HIPCHK(launch_bin(which, bn, bn.C, bn.W, bn.gt, a, bn.n, s));
+        if (fork && i > 0) HIPCHK(hipEventRecord(bin_done[i - 1], s));
       }
+      if (fork)
+        for (size_t i = 1; i < bins.size(); ++i) HIPCHK(hipStreamWaitEvent(st, bin_done[i - 1], 0));
       return ROD_OK;
     }
     // plain path: one rod per launch, one step per launch

@@ -493,6 +493,27 @@ def loss_mse_static(vert_offsets, x, target, want_grad=True):
     return loss, g
 
 
+class LoopFrames(torch.autograd.Function):
+    """(d1, psi_H) = reference frames of closed rods at x (rods_loop_frames);
+    backward runs rods_loop_frames_vjp.  vert_offsets is a device int32
+    tensor [R+1] and gets no gradient."""
+
+    @staticmethod
+    def forward(ctx, vert_offsets, x):
+        xc = x.detach().contiguous()
+        d1, psi = loop_frames(vert_offsets, xc)
+        ctx.save_for_backward(vert_offsets, xc)
+        return d1, psi
+
+    @staticmethod
+    def backward(ctx, d1_b, psi_b):
+        vert_offsets, x = ctx.saved_tensors
+        if d1_b is None:
+            d1_b = torch.zeros_like(x)
+        psi_b = None if psi_b is None else psi_b.contiguous()
+        return None, loop_frames_vjp(vert_offsets, x, d1_b.contiguous(), psi_b)
+
+
 class RodsRollout(torch.autograd.Function):
     """x_T = rollout(x0, v0, U; b, sigma_y) through librods; backward runs the
     library's checkpointed adjoint.  The initial frames come from x0 by the
