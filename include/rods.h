@@ -420,7 +420,8 @@ int rods_autotune(RodsHandle* h, int32_t n_steps, rods_stream_t stream);
 
 /* Pins size bin `bin` (the order of rods_bins) to a launch shape of
  * vertices_per_lane (C) and waves (W) per rod, overriding the default or
- * the autotuner's choice.  Legal shapes: C = 2 or 4 and W = 1, 2, 4 or 8
+ * the autotuner's choice.  Legal shapes: C = 2 or 4 and W = 1, 2, 4 or 8,
+ * and W = 3 with C = 2 on rods without self-contact, twist or moving bodies,
  * with a team (64 W C vertices) that holds the bin's largest rod and is at
  * most twice the bin's smallest legal team (the tape and scratch are sized
  * for that); C = 2 for FP64, twisting rods and rods with moving bodies; no

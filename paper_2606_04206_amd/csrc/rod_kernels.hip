@@ -3147,6 +3147,7 @@ hipError_t launch_rods(int which, int C, int W, bool SC, bool GT, const RodArgs<
   if (C == CC && W == WW) return launch_shape<T, CC, WW, false>(which, GT, a, n_blocks, st);
   RODS_SHAPE(2, 1)
   RODS_SHAPE(2, 2)
+  RODS_SHAPE(2, 3)
   RODS_SHAPE(2, 4)
   RODS_SHAPE(2, 8)
   if constexpr (sizeof(T) == 4) {

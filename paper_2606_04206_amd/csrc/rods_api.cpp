@@ -43,16 +43,22 @@ static bool sc_shape_ok(int C, int W) {
   return (C == 2 && (W == 1 || W == 2 || W == 4 || W == 8)) || (C == 4 && W == 4);
 }
 
+// three-wave teams exist for two vertices per lane on rods without
+// self-contact, twist or moving bodies (257-384 vertices then fill three
+// quarters of a four-wave team's SIMDs)
+static bool w3_ok(int C, bool sc, bool tw) { return C == 2 && !sc && !tw; }
+
 // legal launch shapes for a rod of n vertices, smallest team first
 static std::vector<std::pair<int, int>> shapes_for(int n, int prec, bool sc = false,
                                                    bool tw = false) {
   std::vector<std::pair<int, int>> out;
   const int Cs[2] = {2, 4};
-  const int Ws[4] = {1, 2, 4, 8};
+  const int Ws[5] = {1, 2, 3, 4, 8};
   for (int C : Cs) {
     if ((prec == 8 || tw) && C != 2) continue;
     for (int W : Ws) {
       if (sc && !sc_shape_ok(C, W)) continue;
+      if (W == 3 && !w3_ok(C, sc, tw)) continue;
       if (64 * W * C >= n) {
         out.push_back({C, W});
         break;
@@ -939,7 +945,8 @@ struct Impl : HandleBase {
   // the bin's largest rod and is at most twice its smallest legal team (the
   // tape and scratch are sized for that), and its LDS fits
   bool shape_legal(const Bin& bn, int C, int W) const {
-    if (!(C == 2 || C == 4) || !(W == 1 || W == 2 || W == 4 || W == 8)) return false;
+    if (!(C == 2 || C == 4) || !(W == 1 || W == 2 || W == 3 || W == 4 || W == 8)) return false;
+    if (W == 3 && !w3_ok(C, bn.sc, bn.tw || bn.bd)) return false;
     const int nmax = bin_nmax(bn);
     auto sh = shapes_for(nmax, prec, bn.sc, bn.tw || bn.bd);
     if (sh.empty()) return false;
@@ -990,7 +997,7 @@ struct Impl : HandleBase {
     for (Bin& bn : bins) {
       std::vector<std::pair<int, int>> cand;
       const int Cs[2] = {2, 4};
-      const int Ws[4] = {1, 2, 4, 8};
+      const int Ws[5] = {1, 2, 3, 4, 8};
       for (int C : Cs)
         for (int W : Ws)
           if (shape_legal(bn, C, W)) cand.push_back({C, W});

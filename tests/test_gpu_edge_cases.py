@@ -56,7 +56,7 @@ def test_ragged_sizes_step_parity(precision, tol):
         full = [a.astype(np.float32).astype(np.float64) for a in full]
     dt = _dt(precision)
     h = _handle(wl, precision, max_steps=1)
-    assert sorted(b[:2] for b in h.bins()) == [(2, 1), (2, 2), (2, 4), (2, 8)]
+    assert sorted(b[:2] for b in h.bins()) == [(2, 1), (2, 2), (2, 3), (2, 4), (2, 8)]
     h.set_state(*(to_dev(a, dt) for a in full))
     h.step(to_dev(wl.actions[0], dt))
     after = [t.double().cpu().numpy() for t in h.get_state()]
@@ -169,11 +169,12 @@ def test_every_launch_shape_agrees_to_rounding(precision):
         out = {k: v.double().cpu().numpy() for k, v in h.backward(g, n_steps=n).items()}
         out["xT"] = xT.double().cpu().numpy()
         return out
-    default = [(2, 1), (2, 2), (2, 4)]
+    default = [(2, 1), (2, 2), (2, 3), (2, 4)]
     if precision == 4:
-        variants = [[(4, 1), (4, 1), (4, 2)], [(2, 2), (2, 4), (2, 8)], [(2, 1), (4, 2), (4, 4)]]
+        variants = [[(4, 1), (4, 1), (4, 2), (4, 2)], [(2, 2), (2, 4), (2, 4), (2, 8)],
+                    [(2, 1), (4, 2), (2, 3), (4, 4)]]
     else:
-        variants = [[(2, 2), (2, 4), (2, 8)]]
+        variants = [[(2, 2), (2, 4), (2, 4), (2, 8)]]
     ref = run(default)
     for shapes in variants:
         got = run(shapes)
@@ -191,9 +192,9 @@ def test_every_launch_shape_agrees_to_rounding(precision):
     for k in ref:
         np.testing.assert_array_equal(again[k], ref[k])
     h = _handle(wl, precision, max_steps=n, ckpt_every=K)
-    for b, C, W in ((0, 2, 4), (1, 2, 1), (2, 4, 8), (3, 2, 1), (0, 3, 1)):
+    for b, C, W in ((0, 2, 4), (1, 2, 1), (2, 2, 2), (3, 4, 8), (3, 4, 3), (4, 2, 1), (0, 3, 1)):
         with pytest.raises(RodsError):
-            h.set_launch_shape(b, C, W)     # too big, too small, not built, no bin, no C
+            h.set_launch_shape(b, C, W)     # too big, too small x2, not built x2, no bin, no C
     assert [x[:2] for x in h.bins()] == default
 
 
