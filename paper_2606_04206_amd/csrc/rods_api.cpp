@@ -583,13 +583,12 @@ struct Impl : HandleBase {
     }
     if (!plain) {
       // The bins touch disjoint rods.  They run concurrently except on the
-      // backward's replay stream (whose work already overlaps the adjoint,
-      // and which must not queue behind it on shared bin streams) and
-      // under graph capture (a captured step stays one chain).
-      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      HIPCHK(hipStreamIsCapturing(st, &cs));
-      const bool fork = concurrent_bins && bins.size() > 1 && st != side_stream &&
-                        cs == hipStreamCaptureStatusNone;
+      // backward's replay stream, whose work already overlaps the adjoint
+      // and which must not queue behind it on shared bin streams.  Under
+      // graph capture the bin streams join the capture through the fork
+      // event and leave it through their completion events, so the graph
+      // holds the same fork and join.
+      const bool fork = concurrent_bins && bins.size() > 1 && st != side_stream;
       if (fork) HIPCHK(hipEventRecord(ev_fork, st));
       for (size_t i = 0; i < bins.size(); ++i) {
         const Bin& bn = bins[i];
