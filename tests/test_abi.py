@@ -136,3 +136,24 @@ def test_new_entry_points_refuse_a_null_handle():
     assert lib.rods_set_twist(None, None, None, None) == -1
     assert lib.rods_get_twist(None, None, None, None) == -1
     assert lib.rods_optimize(None, None, 1, None, None, None, None, None, None, None, None) == -1
+
+
+def test_loop_frame_calls_check_arguments_before_the_device():
+    """rods_loop_frames and rods_loop_frames_vjp (closed-rod frames, App. A.1
+    Loop Topology) refuse null buffers and a negative rod count with
+    ROD_EINVAL and another precision with ROD_EDTYPE, and return at once for
+    an empty batch, all before any HIP call."""
+    lib = R.load()
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.rods_loop_frames(None, 1, 8, p, p, None, None) == -1
+    assert lib.rods_loop_frames(p, 1, 8, None, p, None, None) == -1
+    assert lib.rods_loop_frames(p, 1, 8, p, None, None, None) == -1
+    assert lib.rods_loop_frames(p, -1, 8, p, p, None, None) == -1
+    assert lib.rods_loop_frames(p, 1, 2, p, p, None, None) == -5
+    assert lib.rods_loop_frames(p, 0, 4, p, p, None, None) == 0
+    assert lib.rods_loop_frames_vjp(None, 1, 8, p, p, None, p, None) == -1
+    assert lib.rods_loop_frames_vjp(p, 1, 8, p, None, None, p, None) == -1
+    assert lib.rods_loop_frames_vjp(p, 1, 8, p, p, None, None, None) == -1
+    assert lib.rods_loop_frames_vjp(p, 1, 16, p, p, None, p, None) == -5
+    assert lib.rods_loop_frames_vjp(p, 0, 8, p, p, None, p, None) == 0

@@ -63,3 +63,24 @@ def test_subset_keeps_rows_and_scene():
         np.testing.assert_array_equal(sub.prim_type[sub.prim_offsets[k]:sub.prim_offsets[k + 1]],
                                       wl.prim_type[wl.prim_offsets[r]:wl.prim_offsets[r + 1]])
         np.testing.assert_array_equal(sub.actions[:, k], wl.actions[:, r])
+
+
+def test_closed_curves_batch():
+    """Closed curves (synth.loops): CSR offsets match the sizes, the kinds
+    come in turn, the same seed gives the same batch, no vertex repeats its
+    neighbour (the closing edge included) and no two consecutive edges are
+    antiparallel."""
+    from synth.loops import closed_batch, KINDS
+    sizes = [3, 5, 16, 64, 301]
+    x, off, kinds = closed_batch(sizes, seed=4)
+    assert list(np.diff(off)) == sizes and off[0] == 0 and len(x) == off[-1]
+    assert kinds == [KINDS[i % len(KINDS)] for i in range(len(sizes))]
+    x2, _, _ = closed_batch(sizes, seed=4)
+    np.testing.assert_array_equal(x, x2)
+    for r in range(len(sizes)):
+        c = x[off[r]:off[r + 1]]
+        e = np.roll(c, -1, axis=0) - c
+        ell = np.linalg.norm(e, axis=-1)
+        assert ell.min() > 1e-4
+        t = e / ell[:, None]
+        assert (1 + np.sum(t * np.roll(t, -1, axis=0), axis=-1)).min() > 1e-2
