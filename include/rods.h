@@ -412,7 +412,10 @@ int rods_sc_stats(RodsHandle* h, int64_t* out, int32_t reset, rods_stream_t stre
 int rods_bins(RodsHandle* h, int32_t* out, int32_t max_bins);
 
 /* Times every legal launch shape of every size bin on a short forward run
- * and keeps the fastest.  For a given shape results are bitwise repeatable;
+ * and keeps the fastest.  The bins are tuned one after another, each
+ * candidate timed on the whole batch with every bin launched as a step
+ * launches them (concurrently), so that a shape that frees compute units
+ * for the other bins can win.  For a given shape results are bitwise repeatable;
  * across shapes they agree to rounding (each shape is its own kernel
  * instantiation, whose multiply-adds the compiler may fuse differently).  Saves
  * and restores the state; synchronises the stream. */

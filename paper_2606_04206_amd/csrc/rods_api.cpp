@@ -993,6 +993,14 @@ struct Impl : HandleBase {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // Coordinate descent over the bins: each candidate shape of a bin is
+    // timed on a forward run of the whole batch, every bin launched as a
+    // real step launches them (concurrently), with the bins before it at
+    // their chosen shapes and those after it at their current ones, so a
+    // shape that frees SIMDs for the other bins can win.
+    const int plain0 = plain;
+    plain = 0;
+    int err = ROD_OK;
     for (Bin& bn : bins) {
       std::vector<std::pair<int, int>> cand;
       const int Cs[2] = {2, 4};
@@ -1003,27 +1011,33 @@ struct Impl : HandleBase {
       float best = 1e30f;
       std::pair<int, int> bestk{bn.C, bn.W};
       for (auto cw : cand) {
+        bn.C = cw.first;
+        bn.W = cw.second;
+        bn.gt = global_tape(bn.C, bn.W, bn.sc);
         RodArgs<T> a = args(st);
         a.x = sx; a.v = sv; a.kb = skb; a.d1 = sd1;   // time on the scratch copy
         a.th = sth; a.om = som;
         a.body = sbody;
         a.u = u0; a.act_stride = 0; a.spa = 1; a.step_off = 0; a.n_steps = n_steps;
-        a.rods = bin_rods + bn.off;
-        HIPCHK(launch_bin(0, bn, cw.first, cw.second, false, a, bn.n, st));   // warm
-        HIPCHK(hipEventRecord(e0, st));
-        HIPCHK(launch_bin(0, bn, cw.first, cw.second, false, a, bn.n, st));
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if ((err = launch_all_(0, a, st)) ||                                  // warm
+            (err = hipEventRecord(e0, st) == hipSuccess ? ROD_OK : ROD_EHIP) ||
+            (err = launch_all_(0, a, st)) ||
+            (err = hipEventRecord(e1, st) == hipSuccess ? ROD_OK : ROD_EHIP) ||
+            (err = hipEventSynchronize(e1) == hipSuccess ? ROD_OK : ROD_EHIP) ||
+            (err = hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? ROD_OK : ROD_EHIP))
+          break;
         if (ms < best) { best = ms; bestk = cw; }
       }
       bn.C = bestk.first;
       bn.W = bestk.second;
       bn.gt = global_tape(bn.C, bn.W, bn.sc);
+      if (err) break;
     }
+    plain = plain0;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (err) return err;
     // the tape layouts depend on the shapes
     std::vector<int64_t> toff_h, soff_h;
     layout_offsets(toff_h, soff_h);
