@@ -148,3 +148,19 @@ def loop_frames_vjp(x, d1_b, psi_b=None):
         e_b = (tb - t[bi] * dot(t[bi], tb)[:, None]) / ell[bi][:, None]
         x_b[bi] += np.roll(e_b, 1, axis=0) - e_b
     return x_b
+
+
+def loop_material_curvature(x, d1):
+    """Material curvature kappa_i (App. A.1, Bending) at every vertex of
+    closed rods x [B,N,3] with edge frames d1 [B,N,3]: vertex i joins edge
+    i-1 (the closing edge N-1 for i = 0) and edge i, with
+    (kappa b)_i = 2 t^{i-1} x t^i / (1 + t^{i-1}.t^i) and
+    kappa_i = ((kappa b)_i . (d2^{i-1} + d2^i)/2, (kappa b)_i . (d1^{i-1} + d1^i)/2),
+    d2 = t x d1, the component order of the open-rod form.  Returns [B,N,2]."""
+    _, _, t = loop_edges(x)
+    tp = np.roll(t, 1, axis=-2)
+    kb = 2.0 * cross(tp, t) / (1.0 + dot(tp, t))[..., None]
+    d2 = cross(t, d1)
+    a1 = 0.5 * (np.roll(d2, 1, axis=-2) + d2)
+    a2 = 0.5 * (np.roll(d1, 1, axis=-2) + d1)
+    return np.stack([dot(kb, a1), dot(kb, a2)], axis=-1)

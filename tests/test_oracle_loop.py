@@ -19,6 +19,12 @@
   and every frame keeps its angle with the plane's normal.
 * The uncorrected frames of the first N-1 edges equal the open-rod rule on
   the same vertices.
+* Material curvature of closed rods: at the interior vertices it equals the
+  open-rod form on the same vertices and frames; a regular N-gon in the
+  xy-plane, whose frames are the plane's normal, has kappa = (0, 2 tan(pi/N))
+  up to one sign at every vertex, the two closing vertices included (the
+  turning angle of a regular polygon is 2 pi / N); a cyclic shift of the
+  vertices and frames shifts kappa.
 * The adjoint (loop_frames_vjp): complex-step dot-product tests of the whole
   rule (frames and psi_H) on knots, warped rings and random curves of 3 to
   80 vertices; central differences of the same directional derivatives; and
@@ -29,8 +35,8 @@ import numpy as np
 import pytest
 from scipy.spatial.transform import Rotation
 
-from oracle.geometry import init_frames
-from oracle.loop import loop_edges, loop_frames, loop_frames_vjp
+from oracle.geometry import init_frames, material_curvature, edges
+from oracle.loop import loop_edges, loop_frames, loop_frames_vjp, loop_material_curvature
 
 
 def wrap(a):
@@ -186,3 +192,28 @@ def test_holonomy_gradient_has_no_torque(name, curve):
     np.testing.assert_allclose(xb.sum(axis=0), 0.0, atol=1e-9 * np.linalg.norm(xb))
     torque = np.cross(x, xb).sum(axis=0)
     assert np.linalg.norm(torque) <= 1e-9 * np.linalg.norm(xb) * np.abs(x).max()
+
+
+@pytest.mark.parametrize("name,curve", CURVES)
+def test_loop_curvature_matches_the_open_form_inside(name, curve):
+    x = curve(40)
+    d1, _, _ = loop_frames(x[None])
+    k = loop_material_curvature(x[None], d1)[0]
+    _, _, t = edges(x[None])
+    ko = material_curvature(t, d1[:, :-1])[0]
+    np.testing.assert_allclose(k[1:-1], ko[1:-1], rtol=0, atol=1e-12)
+    for s in (1, 13):
+        ks = loop_material_curvature(np.roll(x, s, axis=0)[None], np.roll(d1, s, axis=1))[0]
+        np.testing.assert_allclose(ks, np.roll(k, s, axis=0), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [3, 8, 50])
+def test_regular_polygon_curvature(n):
+    s = 2 * np.pi * np.arange(n) / n
+    x = np.stack([0.05 * np.cos(s), 0.05 * np.sin(s), np.full(n, 0.2)], -1)
+    d1, _, psi = loop_frames(x[None])
+    np.testing.assert_allclose(np.abs(d1[0, :, 2]), 1.0, atol=1e-14)
+    k = loop_material_curvature(x[None], d1)[0]
+    np.testing.assert_allclose(k[:, 0], 0.0, atol=1e-13)
+    np.testing.assert_allclose(np.abs(k[:, 1]), 2 * np.tan(np.pi / n), rtol=1e-13)
+    assert np.all(np.sign(k[:, 1]) == np.sign(k[0, 1]))
