@@ -304,6 +304,18 @@ int rods_loop_frames_vjp(const int32_t* vert_offsets, int32_t n_rods, int32_t pr
                          const void* x, const void* dL_dd1, const void* dL_dpsi, void* dL_dx,
                          rods_stream_t stream);
 
+/* Material curvature (App. A.1, Bending) at every vertex of closed rods:
+ * vertex i joins edge i-1 (the closing edge N-1 for i = 0) and edge i, with
+ * (kappa b)_i = 2 t^{i-1} x t^i / (1 + t^{i-1}.t^i) and kappa_i =
+ * ((kappa b)_i . (d2^{i-1} + d2^i)/2, (kappa b)_i . (d1^{i-1} + d1^i)/2),
+ * d2 = t x d1 (the component order of rods_curvature).  x [V][3] and the
+ * edge frames d1 [V][3] (as rods_loop_frames writes them) in, kappa [V][2]
+ * out, all device buffers of `precision` that the caller owns; offsets and
+ * error codes as for rods_loop_frames.  Passing kappa of a closed shape as a
+ * rest curvature makes that shape the rest shape. */
+int rods_loop_curvature(const int32_t* vert_offsets, int32_t n_rods, int32_t precision,
+                        const void* x, const void* d1, void* kappa, rods_stream_t stream);
+
 /* Number of the handle's current recording: each recorded rods_rollout
  * gets the next number (1, 2, ...); 0 when there is none (a call that
  * clears the recording: rods_set_state, rods_set_params, rods_step, an

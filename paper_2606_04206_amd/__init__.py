@@ -5,7 +5,7 @@ rods.py.  There is no CPU fallback: without the built library every call
 raises.
 """
 from .rods import (RodsHandle, RodsRollout, LoopFrames, RodsError, load, selftest_exchange, loop_frames,
-                   loop_frames_vjp, EXPORTS, LIB_PATH)
+                   loop_frames_vjp, loop_curvature, EXPORTS, LIB_PATH)
 
 __all__ = ["RodsHandle", "RodsRollout", "LoopFrames", "RodsError", "load", "selftest_exchange", "loop_frames",
-           "loop_frames_vjp", "EXPORTS", "LIB_PATH"]
+           "loop_frames_vjp", "loop_curvature", "EXPORTS", "LIB_PATH"]

@@ -2,7 +2,8 @@
 // parallel-transported around the loop, the holonomy angle psi_H left at the
 // closing joint is measured against the first frame, and edge j's frame is
 // turned about its tangent by -psi_H j / N, so that every joint carries the
-// same share of it.  Also the adjoint of that rule.
+// same share of it.  Also the adjoint of that rule, and the material
+// curvature of closed rods (App. A.1, Bending, with the closing edge).
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -173,6 +174,25 @@ __global__ void k_loop_frames_vjp(const int32_t* voff, int R, const T* x, const 
   put3(xb, 3 * v0, eclose - eb0);
 }
 
+// Material curvature at every vertex of closed rods: vertex i joins edge
+// i-1 (the closing edge for i = 0) and edge i.  One workgroup per rod, its
+// lanes striding over the vertices, so the loads of a wave are contiguous.
+template <typename T>
+__global__ void k_loop_curvature(const int32_t* voff, const T* x, const T* d1, T* kappa) {
+  const int r = blockIdx.x;
+  const int v0 = voff[r], N = voff[r + 1] - v0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const int ip = i == 0 ? N - 1 : i - 1;
+    const V3<T> tp = loop_tangent(x, v0, N, ip), t = loop_tangent(x, v0, N, i);
+    const V3<T> kb = (T(2) / (T(1) + dot(tp, t))) * cross(tp, t);
+    const V3<T> dp = get3(d1, 3 * (v0 + ip)), d = get3(d1, 3 * (v0 + i));
+    const V3<T> a1 = T(0.5) * (cross(tp, dp) + cross(t, d));
+    const V3<T> a2 = T(0.5) * (dp + d);
+    kappa[2 * (v0 + i)] = dot(kb, a1);
+    kappa[2 * (v0 + i) + 1] = dot(kb, a2);
+  }
+}
+
 template <typename T>
 hipError_t launch_loop_frames(const int32_t* voff, int R, const T* x, T* d1, T* psi,
                               hipStream_t st) {
@@ -186,6 +206,13 @@ hipError_t launch_loop_frames_vjp(const int32_t* voff, int R, const T* x, const 
                                   const T* psib, T* xb, hipStream_t st) {
   hipLaunchKernelGGL(k_loop_frames_vjp<T>, dim3((R + 63) / 64), dim3(64), 0, st, voff, R, x,
                      d1b, psib, xb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_loop_curvature(const int32_t* voff, int R, const T* x, const T* d1, T* kappa,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_loop_curvature<T>, dim3(R), dim3(128), 0, st, voff, x, d1, kappa);
   return hipGetLastError();
 }
 
@@ -240,5 +267,24 @@ extern "C" int rods_loop_frames_vjp(const int32_t* vert_offsets, int32_t n_rods,
     he = rods::launch_loop_frames_vjp<double>(vert_offsets, n_rods, (const double*)x,
                                               (const double*)dL_dd1, (const double*)dL_dpsi,
                                               (double*)dL_dx, st);
+  return he == hipSuccess ? ROD_OK : ROD_EHIP;
+}
+
+extern "C" int rods_loop_curvature(const int32_t* vert_offsets, int32_t n_rods, int32_t precision,
+                                   const void* x, const void* d1, void* kappa,
+                                   rods_stream_t stream) {
+  if (!vert_offsets || !x || !d1 || !kappa || n_rods < 0) return ROD_EINVAL;
+  if (precision != 4 && precision != 8) return ROD_EDTYPE;
+  if (n_rods == 0) return ROD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  int e = rods::check_loop_offsets(vert_offsets, n_rods, st);
+  if (e) return e;
+  hipError_t he;
+  if (precision == 4)
+    he = rods::launch_loop_curvature<float>(vert_offsets, n_rods, (const float*)x,
+                                            (const float*)d1, (float*)kappa, st);
+  else
+    he = rods::launch_loop_curvature<double>(vert_offsets, n_rods, (const double*)x,
+                                             (const double*)d1, (double*)kappa, st);
   return he == hipSuccess ? ROD_OK : ROD_EHIP;
 }

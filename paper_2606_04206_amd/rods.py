@@ -52,7 +52,8 @@ EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "ro
            "rods_set_plain",
            "rods_set_profiling", "rods_profile", "rods_selftest_exchange",
            "rods_loss_mse_static", "rods_sc_pairs", "rods_sc_stats", "rods_recording",
-           "rods_frames_vjp", "rods_loop_frames", "rods_loop_frames_vjp"]
+           "rods_frames_vjp", "rods_loop_frames", "rods_loop_frames_vjp",
+           "rods_loop_curvature"]
 
 _lib = None
 
@@ -109,6 +110,7 @@ def load():
         "rods_frames_vjp": ([vp, vp, vp, vp], c_int32),
         "rods_loop_frames": ([vp, c_int32, c_int32, vp, vp, vp, vp], c_int32),
         "rods_loop_frames_vjp": ([vp, c_int32, c_int32, vp, vp, vp, vp, vp], c_int32),
+        "rods_loop_curvature": ([vp, c_int32, c_int32, vp, vp, vp, vp], c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -473,6 +475,24 @@ def loop_frames_vjp(vert_offsets, x, d1_b, psi_b=None):
                                        _ptr(d1_b), _ptr(psi_b), _ptr(xb), _stream()),
            "rods_loop_frames_vjp")
     return xb
+
+
+def loop_curvature(vert_offsets, x, d1):
+    """Material curvature at every vertex of closed rods
+    (rods_loop_curvature): x and d1 [V][3] on the device.  Returns kappa
+    [V][2]."""
+    R = vert_offsets.numel() - 1
+    V = x.shape[0]
+    _require(vert_offsets, (R + 1,), torch.int32, "vert_offsets")
+    _require(x, (V, 3), x.dtype, "x")
+    _require(d1, (V, 3), x.dtype, "d1")
+    if R > 0 and int(vert_offsets[-1]) != V:
+        raise RodsError(f"vert_offsets: the last offset must be the vertex count {V}")
+    prec = {torch.float32: 4, torch.float64: 8}.get(x.dtype, 0)
+    kappa = torch.empty(V, 2, dtype=x.dtype, device=x.device)
+    _check(load().rods_loop_curvature(_ptr(vert_offsets), int(R), int(prec), _ptr(x), _ptr(d1),
+                                      _ptr(kappa), _stream()), "rods_loop_curvature")
+    return kappa
 
 
 def loss_mse_static(vert_offsets, x, target, want_grad=True):

@@ -139,8 +139,8 @@ def test_new_entry_points_refuse_a_null_handle():
 
 
 def test_loop_frame_calls_check_arguments_before_the_device():
-    """rods_loop_frames and rods_loop_frames_vjp (closed-rod frames, App. A.1
-    Loop Topology) refuse null buffers and a negative rod count with
+    """rods_loop_frames, rods_loop_frames_vjp and rods_loop_curvature
+    (closed rods, App. A.1 Loop Topology and Bending) refuse null buffers and a negative rod count with
     ROD_EINVAL and another precision with ROD_EDTYPE, and return at once for
     an empty batch, all before any HIP call."""
     lib = R.load()
@@ -157,3 +157,7 @@ def test_loop_frame_calls_check_arguments_before_the_device():
     assert lib.rods_loop_frames_vjp(p, 1, 8, p, p, None, None, None) == -1
     assert lib.rods_loop_frames_vjp(p, 1, 16, p, p, None, p, None) == -5
     assert lib.rods_loop_frames_vjp(p, 0, 8, p, p, None, p, None) == 0
+    assert lib.rods_loop_curvature(p, 1, 8, p, None, p, None) == -1
+    assert lib.rods_loop_curvature(p, 1, 8, p, p, None, None) == -1
+    assert lib.rods_loop_curvature(p, 1, 2, p, p, p, None) == -5
+    assert lib.rods_loop_curvature(p, 0, 4, p, p, p, None) == 0

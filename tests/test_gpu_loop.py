@@ -12,6 +12,8 @@ absolute; psi_H, radians), FP32 within 2e-5 with unit, orthogonal frames to
 The adjoint (rods_loop_frames_vjp) against the oracle's on the same batch
 with seeded cotangents on the frames and on psi_H: FP64 within 1e-10
 relative per rod, FP32 within 1e-4, and with the angle's cotangent alone.
+The material curvature at every vertex (rods_loop_curvature), from the
+oracle's frames: FP64 within 1e-12, FP32 within 1e-5, relative per rod.
 Through torch.autograd (LoopFrames), torch.autograd.gradcheck's central
 differences of the GPU forward agree with the GPU adjoint in FP64.
 """
@@ -20,7 +22,8 @@ import pytest
 import torch
 
 from synth.loops import closed_batch
-from oracle.loop import loop_frames as oracle_loop_frames, loop_frames_vjp as oracle_vjp
+from oracle.loop import (loop_frames as oracle_loop_frames, loop_frames_vjp as oracle_vjp,
+                         loop_material_curvature as oracle_curvature)
 
 pytestmark = pytest.mark.gpu
 SIZES = [3, 4, 5, 7, 16, 63, 64, 65, 128, 257, 301, 1024]
@@ -153,3 +156,24 @@ def test_autograd_gradcheck():
     d1, psi = LoopFrames.apply(offs, xt)
     (psi.sum() + (d1 * d1.detach().flip(0)).sum()).backward()
     assert xt.grad is not None and torch.isfinite(xt.grad).all()
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_curvature_matches_oracle(precision):
+    from paper_2606_04206_amd import loop_curvature
+    x, off, kinds = _batch()
+    npdt = np.float64 if precision == 8 else np.float32
+    dt = torch.float64 if precision == 8 else torch.float32
+    xin = x.astype(npdt).astype(np.float64)
+    d1, _ = _oracle(xin, off)
+    d1 = d1.astype(npdt).astype(np.float64)
+    got = loop_curvature(torch.tensor(off, device="cuda"), torch.tensor(xin, dtype=dt, device="cuda"),
+                         torch.tensor(d1, dtype=dt, device="cuda")).double().cpu().numpy()
+    tol = 1e-12 if precision == 8 else 1e-5
+    for r in range(len(off) - 1):
+        a, b = off[r], off[r + 1]
+        ref = oracle_curvature(xin[None, a:b], d1[None, a:b])[0]
+        err = np.linalg.norm(got[a:b] - ref) / np.linalg.norm(ref)
+        print(f"rod {r} ({kinds[r]}, {b - a} vertices): |kappa| {np.linalg.norm(ref):.3e}, "
+              f"rel err {err:.1e}", flush=True)
+        assert err <= tol, (r, err)
