@@ -164,3 +164,35 @@ def loop_material_curvature(x, d1):
     a1 = 0.5 * (np.roll(d2, 1, axis=-2) + d2)
     a2 = 0.5 * (np.roll(d1, 1, axis=-2) + d1)
     return np.stack([dot(kb, a1), dot(kb, a2)], axis=-1)
+
+
+def loop_material_curvature_vjp(x, d1, kappa_b):
+    """Adjoint of loop_material_curvature: the position adjoint [B,N,3] and
+    the frame adjoint [B,N,3] that kappa_b [B,N,2] induces, the frames taken
+    as independent inputs."""
+    _, ell, t = loop_edges(x)
+    tp = np.roll(t, 1, axis=-2)
+    dp = np.roll(d1, 1, axis=-2)
+    c = cross(tp, t)
+    chi = 1.0 + dot(tp, t)
+    kb = 2.0 * c / chi[..., None]
+    a1 = 0.5 * (cross(tp, dp) + cross(t, d1))
+    a2 = 0.5 * (dp + d1)
+    g1, g2 = kappa_b[..., 0:1], kappa_b[..., 1:2]
+    kb_b = g1 * a1 + g2 * a2
+    w = 0.5 * g1 * kb                 # adjoint of tp x dp and of t x d
+    # vertex i's adjoints of its incoming edge (i-1) and its outgoing edge (i)
+    tp_b = cross(dp, w)
+    dp_b = 0.5 * g2 * kb + cross(w, tp)
+    t_b = cross(d1, w)
+    d_b = 0.5 * g2 * kb + cross(w, t)
+    c_b = (2.0 / chi)[..., None] * kb_b
+    chi_b = -dot(kb, kb_b) / chi
+    tp_b = tp_b + cross(t, c_b) + chi_b[..., None] * t
+    t_b = t_b + cross(c_b, tp) + chi_b[..., None] * tp
+    # edge j collects from vertex j (as outgoing) and vertex j+1 (as incoming)
+    te_b = t_b + np.roll(tp_b, -1, axis=-2)
+    d1_b = d_b + np.roll(dp_b, -1, axis=-2)
+    e_b = (te_b - t * dot(t, te_b)[..., None]) / ell[..., None]
+    x_b = np.roll(e_b, 1, axis=-2) - e_b
+    return x_b, d1_b

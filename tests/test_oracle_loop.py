@@ -24,7 +24,8 @@
   xy-plane, whose frames are the plane's normal, has kappa = (0, 2 tan(pi/N))
   up to one sign at every vertex, the two closing vertices included (the
   turning angle of a regular polygon is 2 pi / N); a cyclic shift of the
-  vertices and frames shifts kappa.
+  vertices and frames shifts kappa.  Its adjoint passes complex-step
+  dot-product tests in positions and frames together.
 * The adjoint (loop_frames_vjp): complex-step dot-product tests of the whole
   rule (frames and psi_H) on knots, warped rings and random curves of 3 to
   80 vertices; central differences of the same directional derivatives; and
@@ -36,7 +37,8 @@ import pytest
 from scipy.spatial.transform import Rotation
 
 from oracle.geometry import init_frames, material_curvature, edges
-from oracle.loop import loop_edges, loop_frames, loop_frames_vjp, loop_material_curvature
+from oracle.loop import (loop_edges, loop_frames, loop_frames_vjp, loop_material_curvature,
+                         loop_material_curvature_vjp)
 
 
 def wrap(a):
@@ -217,3 +219,19 @@ def test_regular_polygon_curvature(n):
     np.testing.assert_allclose(k[:, 0], 0.0, atol=1e-13)
     np.testing.assert_allclose(np.abs(k[:, 1]), 2 * np.tan(np.pi / n), rtol=1e-13)
     assert np.all(np.sign(k[:, 1]) == np.sign(k[0, 1]))
+
+
+@pytest.mark.parametrize("name,curve", CURVES)
+@pytest.mark.parametrize("n", [3, 9, 60])
+def test_curvature_adjoint_complex_step(name, curve, n):
+    x = curve(n)
+    rng = np.random.default_rng(n + 1)
+    d1, _, _ = loop_frames(x[None])
+    kb_b = rng.normal(size=(1, n, 2))
+    dx, dd = rng.normal(size=x.shape), rng.normal(size=d1[0].shape)
+    xb, db = loop_material_curvature_vjp(x[None], d1, kb_b)
+    h = 1e-30
+    k = loop_material_curvature((x + 1j * h * dx)[None], d1 + 1j * h * dd[None])
+    cs = np.imag(np.sum(kb_b * k)) / h
+    ad = np.sum(xb[0] * dx) + np.sum(db[0] * dd)
+    assert abs(cs - ad) <= 1e-10 * max(abs(cs), 1.0), (cs, ad)
