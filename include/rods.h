@@ -316,6 +316,16 @@ int rods_loop_frames_vjp(const int32_t* vert_offsets, int32_t n_rods, int32_t pr
 int rods_loop_curvature(const int32_t* vert_offsets, int32_t n_rods, int32_t precision,
                         const void* x, const void* d1, void* kappa, rods_stream_t stream);
 
+/* Adjoint of rods_loop_curvature with the frames taken as independent
+ * inputs: dL_dx [V][3] (device, output, overwritten) and dL_dd1 [V][3]
+ * (device, output, overwritten; NULL to skip) from dL_dkappa [V][2] at x
+ * and d1.  Chain dL_dd1 through rods_loop_frames_vjp for frames that come
+ * from x.  Offsets, precision and error codes as for rods_loop_frames; the
+ * outputs must not alias the inputs.  Nothing is allocated. */
+int rods_loop_curvature_vjp(const int32_t* vert_offsets, int32_t n_rods, int32_t precision,
+                            const void* x, const void* d1, const void* dL_dkappa, void* dL_dx,
+                            void* dL_dd1, rods_stream_t stream);
+
 /* Number of the handle's current recording: each recorded rods_rollout
  * gets the next number (1, 2, ...); 0 when there is none (a call that
  * clears the recording: rods_set_state, rods_set_params, rods_step, an

@@ -193,6 +193,66 @@ __global__ void k_loop_curvature(const int32_t* voff, const T* x, const T* d1, T
   }
 }
 
+// Adjoints that vertex v's curvature (kappa b . a1, kappa b . a2), with
+// cotangent g, passes to its incoming edge v-1 (tangent, frame) and to its
+// outgoing edge v.
+template <typename T>
+struct LoopCurvAdj {
+  V3<T> tp_b, dp_b, t_b, d_b;
+};
+
+template <typename T>
+__device__ __forceinline__ LoopCurvAdj<T> loop_curvature_vjp_at(const T* x, const T* d1,
+                                                               const T* kb_b, int v0, int N,
+                                                               int v) {
+  const int vp = v == 0 ? N - 1 : v - 1;
+  const V3<T> tp = loop_tangent(x, v0, N, vp), t = loop_tangent(x, v0, N, v);
+  const V3<T> dp = get3(d1, 3 * (v0 + vp)), d = get3(d1, 3 * (v0 + v));
+  const T g1 = kb_b[2 * (v0 + v)], g2 = kb_b[2 * (v0 + v) + 1];
+  const T chi = T(1) + dot(tp, t);
+  const V3<T> kb = (T(2) / chi) * cross(tp, t);
+  const V3<T> a1 = T(0.5) * (cross(tp, dp) + cross(t, d));
+  const V3<T> a2 = T(0.5) * (dp + d);
+  const V3<T> kbb = g1 * a1 + g2 * a2;   // adjoint of kappa b
+  const V3<T> w = (T(0.5) * g1) * kb;     // adjoint of tp x dp and of t x d
+  const V3<T> cb = (T(2) / chi) * kbb;    // adjoint of tp x t
+  const T chib = -dot(kb, kbb) / chi;     // adjoint of 1 + tp.t
+  LoopCurvAdj<T> r;
+  r.tp_b = cross(dp, w) + cross(t, cb) + chib * t;
+  r.dp_b = (T(0.5) * g2) * kb + cross(w, tp);
+  r.t_b = cross(d, w) + cross(cb, tp) + chib * tp;
+  r.d_b = (T(0.5) * g2) * kb + cross(w, t);
+  return r;
+}
+
+// Adjoint of k_loop_curvature, one workgroup per rod.  The thread of
+// vertex i evaluates the adjoints of vertices i-1, i and i+1, which give
+// the tangent adjoints of edges i-1 and i (hence row i of dL/dx) and the
+// frame adjoint of edge i, so every output row has one writer.
+template <typename T>
+__global__ void k_loop_curvature_vjp(const int32_t* voff, const T* x, const T* d1,
+                                     const T* kb_b, T* xb, T* d1b) {
+  const int r = blockIdx.x;
+  const int v0 = voff[r], N = voff[r + 1] - v0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const int im = i == 0 ? N - 1 : i - 1, ip = i + 1 == N ? 0 : i + 1;
+    const LoopCurvAdj<T> am = loop_curvature_vjp_at(x, d1, kb_b, v0, N, im);
+    const LoopCurvAdj<T> a0 = loop_curvature_vjp_at(x, d1, kb_b, v0, N, i);
+    const LoopCurvAdj<T> ap = loop_curvature_vjp_at(x, d1, kb_b, v0, N, ip);
+    const V3<T> xm = get3(x, 3 * (v0 + im)), xi = get3(x, 3 * (v0 + i));
+    const V3<T> xp = get3(x, 3 * (v0 + ip));
+    // edge i (x_i -> x_{i+1}) and edge i-1 (x_{i-1} -> x_i)
+    const V3<T> ei = xp - xi, em = xi - xm;
+    const T li = sqrt(dot(ei, ei)), lm = sqrt(dot(em, em));
+    const V3<T> ti = (T(1) / li) * ei, tm = (T(1) / lm) * em;
+    const V3<T> gi = a0.t_b + ap.tp_b, gm = am.t_b + a0.tp_b;
+    const V3<T> ebi = (T(1) / li) * (gi - dot(ti, gi) * ti);
+    const V3<T> ebm = (T(1) / lm) * (gm - dot(tm, gm) * tm);
+    put3(xb, 3 * (v0 + i), ebm - ebi);
+    if (d1b) put3(d1b, 3 * (v0 + i), a0.d_b + ap.dp_b);
+  }
+}
+
 template <typename T>
 hipError_t launch_loop_frames(const int32_t* voff, int R, const T* x, T* d1, T* psi,
                               hipStream_t st) {
@@ -213,6 +273,14 @@ template <typename T>
 hipError_t launch_loop_curvature(const int32_t* voff, int R, const T* x, const T* d1, T* kappa,
                                  hipStream_t st) {
   hipLaunchKernelGGL(k_loop_curvature<T>, dim3(R), dim3(128), 0, st, voff, x, d1, kappa);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_loop_curvature_vjp(const int32_t* voff, int R, const T* x, const T* d1,
+                                     const T* kb_b, T* xb, T* d1b, hipStream_t st) {
+  hipLaunchKernelGGL(k_loop_curvature_vjp<T>, dim3(R), dim3(128), 0, st, voff, x, d1, kb_b, xb,
+                     d1b);
   return hipGetLastError();
 }
 
@@ -286,5 +354,27 @@ extern "C" int rods_loop_curvature(const int32_t* vert_offsets, int32_t n_rods, 
   else
     he = rods::launch_loop_curvature<double>(vert_offsets, n_rods, (const double*)x,
                                              (const double*)d1, (double*)kappa, st);
+  return he == hipSuccess ? ROD_OK : ROD_EHIP;
+}
+
+extern "C" int rods_loop_curvature_vjp(const int32_t* vert_offsets, int32_t n_rods,
+                                       int32_t precision, const void* x, const void* d1,
+                                       const void* dL_dkappa, void* dL_dx, void* dL_dd1,
+                                       rods_stream_t stream) {
+  if (!vert_offsets || !x || !d1 || !dL_dkappa || !dL_dx || n_rods < 0) return ROD_EINVAL;
+  if (precision != 4 && precision != 8) return ROD_EDTYPE;
+  if (n_rods == 0) return ROD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  int e = rods::check_loop_offsets(vert_offsets, n_rods, st);
+  if (e) return e;
+  hipError_t he;
+  if (precision == 4)
+    he = rods::launch_loop_curvature_vjp<float>(vert_offsets, n_rods, (const float*)x,
+                                                (const float*)d1, (const float*)dL_dkappa,
+                                                (float*)dL_dx, (float*)dL_dd1, st);
+  else
+    he = rods::launch_loop_curvature_vjp<double>(vert_offsets, n_rods, (const double*)x,
+                                                 (const double*)d1, (const double*)dL_dkappa,
+                                                 (double*)dL_dx, (double*)dL_dd1, st);
   return he == hipSuccess ? ROD_OK : ROD_EHIP;
 }

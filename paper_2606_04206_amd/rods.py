@@ -53,7 +53,7 @@ EXPORTS = ["rods_create", "rods_destroy", "rods_strerror", "rods_set_state", "ro
            "rods_set_profiling", "rods_profile", "rods_selftest_exchange",
            "rods_loss_mse_static", "rods_sc_pairs", "rods_sc_stats", "rods_recording",
            "rods_frames_vjp", "rods_loop_frames", "rods_loop_frames_vjp",
-           "rods_loop_curvature"]
+           "rods_loop_curvature", "rods_loop_curvature_vjp"]
 
 _lib = None
 
@@ -111,6 +111,7 @@ def load():
         "rods_loop_frames": ([vp, c_int32, c_int32, vp, vp, vp, vp], c_int32),
         "rods_loop_frames_vjp": ([vp, c_int32, c_int32, vp, vp, vp, vp, vp], c_int32),
         "rods_loop_curvature": ([vp, c_int32, c_int32, vp, vp, vp, vp], c_int32),
+        "rods_loop_curvature_vjp": ([vp, c_int32, c_int32, vp, vp, vp, vp, vp, vp], c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -495,6 +496,26 @@ def loop_curvature(vert_offsets, x, d1):
     return kappa
 
 
+def loop_curvature_vjp(vert_offsets, x, d1, kappa_b):
+    """Adjoint of loop_curvature (rods_loop_curvature_vjp), the frames taken
+    as independent inputs.  Returns (dL/dx [V][3], dL/dd1 [V][3])."""
+    R = vert_offsets.numel() - 1
+    V = x.shape[0]
+    _require(vert_offsets, (R + 1,), torch.int32, "vert_offsets")
+    _require(x, (V, 3), x.dtype, "x")
+    _require(d1, (V, 3), x.dtype, "d1")
+    _require(kappa_b, (V, 2), x.dtype, "kappa_b")
+    if R > 0 and int(vert_offsets[-1]) != V:
+        raise RodsError(f"vert_offsets: the last offset must be the vertex count {V}")
+    prec = {torch.float32: 4, torch.float64: 8}.get(x.dtype, 0)
+    xb = torch.empty(V, 3, dtype=x.dtype, device=x.device)
+    db = torch.empty(V, 3, dtype=x.dtype, device=x.device)
+    _check(load().rods_loop_curvature_vjp(_ptr(vert_offsets), int(R), int(prec), _ptr(x),
+                                          _ptr(d1), _ptr(kappa_b), _ptr(xb), _ptr(db),
+                                          _stream()), "rods_loop_curvature_vjp")
+    return xb, db
+
+
 def loss_mse_static(vert_offsets, x, target, want_grad=True):
     """rods_loss_mse without a handle (no device allocation inside the
     library): vert_offsets is a device int32 tensor [R+1], x and target
@@ -532,6 +553,24 @@ class LoopFrames(torch.autograd.Function):
             d1_b = torch.zeros_like(x)
         psi_b = None if psi_b is None else psi_b.contiguous()
         return None, loop_frames_vjp(vert_offsets, x, d1_b.contiguous(), psi_b)
+
+
+class LoopCurvature(torch.autograd.Function):
+    """kappa = material curvature of closed rods at (x, d1)
+    (rods_loop_curvature); backward runs rods_loop_curvature_vjp.  Composed
+    with LoopFrames it differentiates the rest curvature of a closed shape."""
+
+    @staticmethod
+    def forward(ctx, vert_offsets, x, d1):
+        xc, dc = x.detach().contiguous(), d1.detach().contiguous()
+        ctx.save_for_backward(vert_offsets, xc, dc)
+        return loop_curvature(vert_offsets, xc, dc)
+
+    @staticmethod
+    def backward(ctx, kappa_b):
+        vert_offsets, x, d1 = ctx.saved_tensors
+        xb, db = loop_curvature_vjp(vert_offsets, x, d1, kappa_b.contiguous())
+        return None, xb, db
 
 
 class RodsRollout(torch.autograd.Function):

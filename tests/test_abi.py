@@ -161,3 +161,7 @@ def test_loop_frame_calls_check_arguments_before_the_device():
     assert lib.rods_loop_curvature(p, 1, 8, p, p, None, None) == -1
     assert lib.rods_loop_curvature(p, 1, 2, p, p, p, None) == -5
     assert lib.rods_loop_curvature(p, 0, 4, p, p, p, None) == 0
+    assert lib.rods_loop_curvature_vjp(p, 1, 8, p, p, None, p, p, None) == -1
+    assert lib.rods_loop_curvature_vjp(p, 1, 8, p, p, p, None, p, None) == -1
+    assert lib.rods_loop_curvature_vjp(p, 1, 2, p, p, p, p, None, None) == -5
+    assert lib.rods_loop_curvature_vjp(p, 0, 8, p, p, p, p, None, None) == 0
