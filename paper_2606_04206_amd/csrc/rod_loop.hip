@@ -54,37 +54,98 @@ __device__ __forceinline__ V3<T> loop_tangent(const T* x, int v0, int N, int j) 
   return (T(1) / sqrt(dot(e, e))) * e;
 }
 
-// One thread per closed rod: the transport around the loop is a chain of
-// dependent rotations, and the rule runs once per rollout.  The transported
-// frames are written to d1 in the first walk and turned in place in the
-// second.
+// unit quaternion (w, v): a rotation; products compose right to left
 template <typename T>
-__global__ void k_loop_frames(const int32_t* voff, int R, const T* x, T* d1, T* psi) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  int v0 = voff[r], N = voff[r + 1] - v0;
-  V3<T> t0 = loop_tangent(x, v0, N, 0);
-  // first frame: the open-rod rule
-  V3<T> av = loop_axis(t0);
+struct LoopQuat {
+  T w;
+  V3<T> v;
+};
+
+// a * b: the rotation b, then a (renormalised, which only removes rounding
+// drift: a product of unit quaternions is a unit quaternion)
+template <typename T>
+__device__ __forceinline__ LoopQuat<T> quat_mul(const LoopQuat<T>& a, const LoopQuat<T>& b) {
+  LoopQuat<T> q{a.w * b.w - dot(a.v, b.v), a.w * b.v + b.w * a.v + cross(a.v, b.v)};
+  const T s = T(1) / sqrt(q.w * q.w + dot(q.v, q.v));
+  return {s * q.w, s * q.v};
+}
+
+// the minimal rotation taking unit ta to unit tb: (1 + ta.tb, ta x tb),
+// normalised (its norm is sqrt(2 (1 + ta.tb)))
+template <typename T>
+__device__ __forceinline__ LoopQuat<T> quat_min_rotation(V3<T> ta, V3<T> tb) {
+  const T c = T(1) + dot(ta, tb);
+  const T s = T(1) / sqrt(T(2) * c);
+  return {s * c, s * cross(ta, tb)};
+}
+
+template <typename T>
+__device__ __forceinline__ V3<T> quat_apply(const LoopQuat<T>& q, V3<T> p) {
+  const V3<T> u = cross(q.v, p);
+  return p + (T(2) * q.w) * u + T(2) * cross(q.v, u);
+}
+
+template <typename T>
+__device__ __forceinline__ LoopQuat<T> quat_shfl_up(const LoopQuat<T>& q, int off) {
+  return {__shfl_up(q.w, off, 64),
+          mk(__shfl_up(q.v.x, off, 64), __shfl_up(q.v.y, off, 64), __shfl_up(q.v.z, off, 64))};
+}
+
+template <typename T>
+__device__ __forceinline__ LoopQuat<T> quat_shfl(const LoopQuat<T>& q, int src) {
+  return {__shfl(q.w, src, 64),
+          mk(__shfl(q.v.x, src, 64), __shfl(q.v.y, src, 64), __shfl(q.v.z, src, 64))};
+}
+
+// One wave per closed rod.  The frame of edge j is the first frame turned
+// by the product of the minimal rotations of joints 1..j; each lane takes a
+// contiguous run of joints, forms its run's product, and a prefix product
+// over the wave's lanes (six shuffle rounds) gives every lane the rotation
+// before its run.  The holonomy angle follows from the whole product and
+// the closing joint's rotation; each lane then writes its edges' frames
+// turned by -psi_H j / N.
+template <typename T>
+__global__ __launch_bounds__(64) void k_loop_frames(const int32_t* voff, const T* x, T* d1,
+                                                     T* psi) {
+  const int r = blockIdx.x, lane = threadIdx.x;
+  const int v0 = voff[r], N = voff[r + 1] - v0;
+  const int K = (N - 1 + 63) / 64;                    // joints per lane
+  const int j0 = 1 + lane * K, j1 = min(N, 1 + (lane + 1) * K);
+  const LoopQuat<T> one{T(1), zero3<T>()};
+  // this lane's run of joints j0 .. j1-1 (joint j turns edge j-1 onto edge j)
+  LoopQuat<T> run = one;
+  for (int j = j0; j < j1; ++j)
+    run = quat_mul(quat_min_rotation(loop_tangent(x, v0, N, j - 1), loop_tangent(x, v0, N, j)),
+                   run);
+  // inclusive prefix product over the lanes, later runs on the left
+  LoopQuat<T> inc = run;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const LoopQuat<T> lo = quat_shfl_up(inc, off);
+    if (lane >= off) inc = quat_mul(inc, lo);
+  }
+  LoopQuat<T> before = quat_shfl_up(inc, 1);
+  if (lane == 0) before = one;
+  const LoopQuat<T> all = quat_shfl(inc, 63);
+  const V3<T> t0 = loop_tangent(x, v0, N, 0);
+  const V3<T> av = loop_axis(t0);
   V3<T> d0 = av - dot(av, t0) * t0;
   d0 = (T(1) / sqrt(dot(d0, d0))) * d0;
-  put3(d1, 3 * v0, d0);
-  V3<T> d = d0, t = t0;
-  for (int j = 1; j < N; ++j) {
-    V3<T> tn = loop_tangent(x, v0, N, j);
-    d = loop_transport(d, t, tn);
-    put3(d1, 3 * (v0 + j), d);
-    t = tn;
+  const V3<T> tl = loop_tangent(x, v0, N, N - 1);
+  const V3<T> back = quat_apply(quat_min_rotation(tl, t0), quat_apply(all, d0));
+  const T ps = atan2(dot(cross(d0, back), t0), dot(d0, back));
+  if (lane == 0) {
+    put3(d1, 3 * v0, d0);
+    if (psi) psi[r] = ps;
   }
-  V3<T> back = loop_transport(d, t, t0);
-  T ps = atan2(dot(cross(d0, back), t0), dot(d0, back));
-  if (psi) psi[r] = ps;
-  for (int j = 1; j < N; ++j) {
-    T phi = -ps * T(j) / T(N);
-    T s = sin(phi), co = cos(phi);
-    V3<T> tj = loop_tangent(x, v0, N, j);
-    V3<T> dh = get3(d1, 3 * (v0 + j));
-    put3(d1, 3 * (v0 + j), co * dh + s * cross(tj, dh));
+  LoopQuat<T> cur = before;
+  for (int j = j0; j < j1; ++j) {
+    const V3<T> tj = loop_tangent(x, v0, N, j);
+    cur = quat_mul(quat_min_rotation(loop_tangent(x, v0, N, j - 1), tj), cur);
+    const V3<T> dh = quat_apply(cur, d0);
+    const T phi = -ps * T(j) / T(N);
+    const T sn = sin(phi), co = cos(phi);
+    put3(d1, 3 * (v0 + j), co * dh + sn * cross(tj, dh));
   }
 }
 
@@ -256,8 +317,7 @@ __global__ void k_loop_curvature_vjp(const int32_t* voff, const T* x, const T* d
 template <typename T>
 hipError_t launch_loop_frames(const int32_t* voff, int R, const T* x, T* d1, T* psi,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_loop_frames<T>, dim3((R + 63) / 64), dim3(64), 0, st, voff, R, x, d1,
-                     psi);
+  hipLaunchKernelGGL(k_loop_frames<T>, dim3(R), dim3(64), 0, st, voff, x, d1, psi);
   return hipGetLastError();
 }
 

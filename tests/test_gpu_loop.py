@@ -6,7 +6,7 @@ A ragged batch of rings, warped rings, trefoil knots and random smooth
 closed curves (3 to 1024 vertices, seeded), plus a ring whose first edge
 runs along z (the first frame then starts from x), and the 1024 x 128 batch
 of the benchmark's rod shape as closed loops.  FP64 within 1e-12 (frames,
-absolute; psi_H, radians), FP32 within 2e-5 with unit, orthogonal frames to
+absolute; psi_H, radians), FP32 within 5e-6 with unit, orthogonal frames to
 1e-5.  Invalid offsets and precisions are refused.
 
 The adjoint (rods_loop_frames_vjp) against the oracle's on the same batch
@@ -77,7 +77,7 @@ def test_ragged_batch_matches_oracle(precision):
     assert np.abs(rpsi).max() < np.pi - 1e-3
     assert np.abs(rpsi).max() > 0.5
     d1, psi = _gpu(xin, off, dt)
-    tol = 1e-12 if precision == 8 else 2e-5
+    tol = 1e-12 if precision == 8 else 5e-6
     for r in range(len(off) - 1):
         a, b = off[r], off[r + 1]
         err = np.abs(d1[a:b] - ref[a:b]).max()
